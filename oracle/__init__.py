@@ -1,0 +1,38 @@
+"""FP64 CPU oracle for template-matching orientation mapping.
+
+TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import, call or execute anything in this
+package. The GPU library never routes through it, and it imports nothing from
+the GPU library (a test checks both directions).
+
+What it computes is the paper's indexation procedure (Section 2.2) written
+out plainly, in float64, one function per step:
+
+* ``intensity_transform64`` - gamma correction and constant subtraction of
+  the experimental pattern (Section 2.2, discussion of the limitations of Q;
+  Section 4.3 for the unit-intensity / subtract-constant workflow);
+* ``polar64`` - polar resampling of a pattern about the direct-beam centre
+  (Section 2.2, Fig. 2 c);
+* ``template_pixels64`` - template spots rounded to integer polar pixels,
+  mirrored templates by reflection across y = 0 (Section 2.2, Fig. 2 d);
+* ``scores64`` / ``match_exact64`` - the correlation index Q of Eq. (1) at
+  every in-plane shift with wraparound, and its maximum per template
+  (Section 2.2, Fig. 2 e);
+* ``topn64`` - sort and keep the N best templates (Section 2.2, end);
+* ``prefilter64`` - azimuthally integrated pre-filter of the library
+  (Section 2.2, Fig. 3).
+
+Readings where the paper is silent are stated in each function.
+"""
+from .polar import (polar_coords64, bilinear64, intensity_transform64,
+                    polar64, norm64, profile64)
+from .library import template_pixels64, OracleLibrary
+from .match import scores64, match_exact64, topn64, index_pattern64, index_batch64
+from .prefilter import radial_profiles64, prefilter64, index_pattern_prefiltered64
+
+__all__ = [
+    "polar_coords64", "bilinear64", "intensity_transform64", "polar64", "norm64",
+    "profile64", "template_pixels64", "OracleLibrary", "scores64", "match_exact64",
+    "topn64", "index_pattern64", "index_batch64", "radial_profiles64", "prefilter64",
+    "index_pattern_prefiltered64",
+]

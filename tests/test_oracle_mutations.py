@@ -1,0 +1,135 @@
+"""Planted mistakes in the oracle (on the CPU) must each fail at least one pin.
+
+Each case monkeypatches one oracle function with a plausible bug (a swapped
+axis, a wrong sign, a dropped term, a wrong tie rule) and runs the pins that
+should catch it."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.library as olibmod
+import oracle.match as omatch
+import oracle.polar as opolar
+import test_oracle_pins as pins
+
+
+def _swapped_coords(R, n_theta, r0, dr, cx, cy):
+    x, y = _orig_coords(R, n_theta, r0, dr, cx, cy)
+    return cy + (x - cx), cx + (y - cy)          # x and y exchanged
+
+
+_orig_coords = opolar.polar_coords64
+
+
+def _clockwise_coords(R, n_theta, r0, dr, cx, cy):
+    x, y = _orig_coords(R, n_theta, r0, dr, cx, cy)
+    return x, 2 * cy - y                         # angle measured the other way
+
+
+def _bilinear_transposed(img, x, y):
+    x0, y0 = np.floor(x), np.floor(y)
+    fx, fy = x - x0, y - y0
+    xi, yi = x0.astype(np.int64), y0.astype(np.int64)
+    p = opolar._pixel
+    return ((1 - fx) * (1 - fy) * p(img, yi, xi) + fy * (1 - fx) * p(img, yi, xi + 1)
+            + (1 - fy) * fx * p(img, yi + 1, xi) + fx * fy * p(img, yi + 1, xi + 1))
+
+
+_orig_num = omatch._numerators
+
+
+def _num_wrong_sign(P, lib, t_lo, t_hi):
+    # slides the template the other way: P[j, k - s]
+    return _orig_num(P[:, ::-1][:, np.r_[len(P[0]) - 1, 0:len(P[0]) - 1]], lib, t_lo, t_hi)
+
+
+def _num_no_wrap(P, lib, t_lo, t_hi):
+    Pz = np.concatenate([P, np.zeros_like(P)], axis=1)
+    n = P.shape[1]
+    a, b = lib.starts[t_lo], lib.starts[t_hi]
+    out = np.zeros((t_hi - t_lo, n))
+    s = np.arange(n)
+    g = Pz[lib.J[a:b, None], lib.K[a:b, None] + s[None, :]] * lib.Wt[a:b, None]
+    np.add.at(out, lib.tid[a:b] - t_lo, g)
+    return out
+
+
+_orig_tp = olibmod.template_pixels64
+
+
+def _tp_mirror_not_reflected(kx, ky, intensity, offsets, px_per, R, n_theta, r0=0.0, dr=1.0,
+                             mirror=True, unit=False, keep_direct_beam=False):
+    base = _orig_tp(kx, ky, intensity, offsets, px_per, R, n_theta, r0, dr, False, unit,
+                    keep_direct_beam)
+    return base + base if mirror else base
+
+
+def _tp_no_merge(kx, ky, intensity, offsets, px_per, R, n_theta, r0=0.0, dr=1.0,
+                 mirror=True, unit=False, keep_direct_beam=False):
+    out = []
+    offsets = np.asarray(offsets)
+    for sign in ((1.0, -1.0) if mirror else (1.0,)):
+        for t in range(len(offsets) - 1):
+            a, b = offsets[t], offsets[t + 1]
+            x, y = np.asarray(kx[a:b]), sign * np.asarray(ky[a:b])
+            w = np.ones(b - a) if unit else np.asarray(intensity[a:b], dtype=float)
+            keep = ~((x == 0) & (y == 0)) | keep_direct_beam
+            j = np.rint((px_per * np.hypot(x, y) - r0) / dr)
+            k = np.mod(np.rint(np.arctan2(y, x) * n_theta / (2 * np.pi)), n_theta)
+            keep &= (j >= 0) & (j < R)
+            out.append((j[keep].astype(int), k[keep].astype(int), w[keep]))   # duplicates kept apart
+    return out
+
+
+def _match_last_max(P, lib, pnorm=None, chunk=512):
+    Q = oracle.scores64(P, lib, pnorm)
+    n = Q.shape[1]
+    arg = n - 1 - np.argmax(Q[:, ::-1], axis=1)
+    return Q[np.arange(len(Q)), arg], arg
+
+
+def _topn_ties_high_index(best, arg, N, templates=None):
+    tids = np.arange(len(best)) if templates is None else np.asarray(templates)
+    order = np.lexsort((-tids, -np.asarray(best)))[:N]
+    return tids[order], np.asarray(arg)[order], np.asarray(best)[order]
+
+
+CASES = [
+    ("x/y swapped in polar coordinates", opolar, "polar_coords64", _swapped_coords,
+     [pins.test_p9_polar_reproduces_bilinear_functions]),
+    ("angle measured clockwise", opolar, "polar_coords64", _clockwise_coords,
+     [pins.test_p9_polar_reproduces_bilinear_functions, pins.test_p6_polar_equals_scipy_map_coordinates]),
+    ("bilinear weights transposed", opolar, "bilinear64", _bilinear_transposed,
+     [pins.test_p6_polar_equals_scipy_map_coordinates]),
+    ("template slid the wrong way", omatch, "_numerators", _num_wrong_sign,
+     [pins.test_p2_cartesian_rotated_template_equals_polar_shift, pins.test_p3_roll_by_one_bin]),
+    ("no wraparound", omatch, "_numerators", _num_no_wrap,
+     [pins.test_p6_numerator_equals_fft_cross_correlation]),
+    ("mirror not reflected", olibmod, "template_pixels64", _tp_mirror_not_reflected,
+     [pins.test_p11_mirror_identity]),
+    ("duplicate spots not merged", olibmod, "template_pixels64", _tp_no_merge,
+     [pins.test_template_pixels_rounding_merge_and_drop]),
+    ("last maximum instead of first", omatch, "match_exact64", _match_last_max,
+     [pins.test_p7_topn_brute_force]),
+    ("ties ranked by higher index", omatch, "topn64", _topn_ties_high_index,
+     [pins.test_p7_topn_brute_force]),
+]
+
+
+@pytest.mark.parametrize("name,mod,attr,bad,tests", CASES, ids=[c[0] for c in CASES])
+def test_planted_mistake_is_caught(monkeypatch, name, mod, attr, bad, tests):
+    monkeypatch.setattr(mod, attr, bad)
+    # functions re-exported at package level or imported into sibling modules
+    for m in (oracle, omatch, pins.oracle):
+        if hasattr(m, attr):
+            monkeypatch.setattr(m, attr, bad)
+    import oracle.prefilter as opre
+    if hasattr(opre, attr):
+        monkeypatch.setattr(opre, attr, bad)
+    caught = 0
+    for t in tests:
+        try:
+            t()
+        except AssertionError:
+            caught += 1
+    assert caught >= 1, f"planted mistake '{name}' passed every pin"

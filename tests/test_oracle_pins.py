@@ -1,0 +1,408 @@
+"""Pins of the FP64 oracle to facts that do not come from the oracle itself:
+closed forms, brute force on tiny inputs, library routines (scipy, numpy.fft),
+invariances and the paper's own numbers. CPU only."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle
+import synth
+from conftest import small_library
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _lib(R=32, n_theta=72, n=12, seed=0, mirror=True, unit=False, px_per=30.0):
+    lib = small_library(n, seed)
+    return lib, oracle.OracleLibrary.build(lib, px_per, R, n_theta, mirror=mirror, unit=unit)
+
+
+def _dense_template(olib, t):
+    D = np.zeros((olib.R, olib.n_theta))
+    a, b = olib.starts[t], olib.starts[t + 1]
+    D[olib.J[a:b], olib.K[a:b]] = olib.Wt[a:b]
+    return D
+
+
+# ---------------------------------------------------------------- P12 golden
+def test_p12_angular_step_from_paper():
+    """Section 2.2: the in-plane step is 360 degrees over the polar width;
+    a 360-column polar image gives 1 degree (stored fixture)."""
+    with open(os.path.join(GOLDEN, "paper_facts.json")) as f:
+        facts = json.load(f)
+    ex = facts["angular_step"]
+    assert 360.0 / ex["polar_width"] == ex["delta_phi1_deg"] == 1.0
+    # the oracle's angle grid: column k sits at 2*pi*k/n_theta
+    x, y = oracle.polar_coords64(2, ex["polar_width"], 0.0, 1.0, 0.0, 0.0)
+    ang = np.degrees(np.arctan2(y[1], x[1]))
+    assert abs(ang[1] - ang[0] - ex["delta_phi1_deg"]) < 1e-12
+    assert facts["prefilter_keep_fraction"]["value"] == 0.1
+
+
+def test_electron_wavelength_200kv():
+    """200 kV electrons (Section 3): relativistic lambda = 0.025079 A."""
+    assert abs(synth.wavelength_A(200.0) - 0.025079) < 5e-7
+
+
+# ---------------------------------------------------------------- P9 analytic polar
+def test_p9_polar_reproduces_bilinear_functions():
+    """Bilinear interpolation reproduces f = a + b x + c y + d x y exactly, so
+    the polar image of such an image is f at the sample points (pins the
+    x = column, y = row, theta from +x to +y conventions)."""
+    H, W = 40, 48
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    a, b, c, d = 0.3, 0.7, -0.45, 0.013
+    img = a + b * xx + c * yy + d * xx * yy
+    R, n_theta, cx, cy = 15, 90, 23.0, 19.0
+    P = oracle.polar64(img, R, n_theta, 0.0, 1.0, cx, cy)
+    r = np.arange(R)[:, None]
+    th = 2 * np.pi * np.arange(n_theta)[None, :] / n_theta
+    X = cx + r * np.cos(th)
+    Y = cy + r * np.sin(th)
+    assert np.allclose(P, a + b * X + c * Y + d * X * Y, rtol=0, atol=1e-11)
+
+
+def test_p9_constant_image_and_radial_rows():
+    img = np.full((64, 64), 2.5)
+    P = oracle.polar64(img, 30, 360)
+    assert np.allclose(P, 2.5, rtol=1e-15, atol=0)
+    # a radially symmetric image sampled at integer radii along the axes
+    yy, xx = np.mgrid[0:64, 0:64].astype(np.float64)
+    img = np.hypot(xx - 32, yy - 32)
+    P = oracle.polar64(img, 30, 360)
+    for k in (0, 90, 180, 270):          # samples fall on pixel centres
+        assert np.allclose(P[:, k], np.arange(30), atol=1e-12)
+
+
+def test_intensity_transform_order():
+    """Clamp, gamma, then subtract (Section 2.2 and Section 4.3)."""
+    x = np.array([-1.0, 0.0, 0.25, 4.0])
+    assert np.allclose(oracle.intensity_transform64(x, 0.5, 0.1), [-0.1, -0.1, 0.4, 1.9])
+    assert np.allclose(oracle.intensity_transform64(x, 1.0, 0.0), x)
+    assert np.allclose(oracle.intensity_transform64(x, 1.0, 1.0), x - 1.0)
+
+
+# ---------------------------------------------------------------- P6 library cross-checks
+def test_p6_polar_equals_scipy_map_coordinates():
+    rng = np.random.default_rng(3)
+    img = rng.standard_normal((50, 60))
+    R, n_theta, cx, cy = 40, 128, 27.5, 24.0      # reaches outside: zero padding
+    P = oracle.polar64(img, R, n_theta, 0.5, 0.9, cx, cy)
+    x, y = oracle.polar_coords64(R, n_theta, 0.5, 0.9, cx, cy)
+    ref = ndimage.map_coordinates(img, [y.ravel(), x.ravel()], order=1,
+                                  mode="grid-constant", cval=0.0).reshape(R, n_theta)
+    assert np.allclose(P, ref, rtol=0, atol=1e-12)
+
+
+def test_p6_numerator_equals_fft_cross_correlation():
+    lib, olib = _lib()
+    rng = np.random.default_rng(4)
+    P = rng.standard_normal((olib.R, olib.n_theta))
+    Q = oracle.scores64(P, olib, pnorm=1.0)
+    for t in range(olib.n_total):
+        D = _dense_template(olib, t)
+        cc = np.fft.irfft(np.conj(np.fft.rfft(D, axis=1)) * np.fft.rfft(P, axis=1),
+                          n=olib.n_theta, axis=1).sum(axis=0)
+        tn = olib.tnorm[t]
+        assert np.allclose(Q[t] * tn, cc, atol=1e-10)
+
+
+def test_p6_prefilter_equals_matmul_and_stable_sort():
+    lib, olib = _lib(n=40, seed=5)
+    rng = np.random.default_rng(6)
+    P = rng.random((olib.R, olib.n_theta))
+    profT = oracle.radial_profiles64(olib)
+    # profile of a base template: dense template summed along theta
+    for t in range(olib.T_base):
+        assert np.allclose(profT[t], _dense_template(olib, t).sum(axis=1))
+    kept, cos = oracle.prefilter64(P.sum(axis=1), profT, 0.25)
+    pP = P.sum(axis=1)
+    ref = (profT @ pP) / (np.linalg.norm(profT, axis=1) * np.linalg.norm(pP))
+    assert np.allclose(cos, ref)
+    order = np.argsort(-ref, kind="stable")[: math.ceil(0.25 * olib.T_base)]
+    assert list(kept) == list(order)
+
+
+# ---------------------------------------------------------------- P1 Cauchy-Schwarz
+@pytest.mark.parametrize("roll", [0, 1, 17, 71])
+def test_p1_template_image_scores_one(roll):
+    lib, olib = _lib()
+    for t in range(olib.n_total):
+        if olib.tnorm[t] == 0:
+            continue
+        P = np.roll(_dense_template(olib, t), roll, axis=1)
+        Q = oracle.scores64(P, olib)
+        assert np.all(np.abs(Q) <= 1.0 + 1e-14)
+        assert abs(Q[t, roll] - 1.0) < 1e-14
+        best, arg = oracle.match_exact64(P, olib)
+        assert abs(best[t] - 1.0) < 1e-14
+        # the first maximising shift of template t is the roll unless the
+        # template is rotationally symmetric (then an earlier shift also fits)
+        D = _dense_template(olib, t)
+        assert np.array_equal(np.roll(D, arg[t], axis=1), P)
+        assert arg[t] <= roll
+
+
+# ---------------------------------------------------------------- P2 brute force, Cartesian
+def test_p2_cartesian_rotated_template_equals_polar_shift():
+    """For every template and shift: rotate the raw spots in Cartesian space
+    by s bins, round each rotated spot to its pixel, sample the raw image at
+    that pixel's Cartesian position with scipy, sum with the merged weights.
+    Must equal the polar-path numerator."""
+    R, n_theta, px = 24, 60, 20.0
+    lib = small_library(8, seed=11, g_max=1.1)
+    olib = oracle.OracleLibrary.build(lib, px, R, n_theta, mirror=False)
+    rng = np.random.default_rng(12)
+    H = W = 56
+    img = rng.random((H, W))
+    cx, cy = 28.0, 27.0
+    P = oracle.polar64(img, R, n_theta, 0.0, 1.0, cx, cy)
+    C = oracle.scores64(P, olib, pnorm=1.0) * olib.tnorm[:, None]
+    for t in range(olib.T_base):
+        a, b = lib["offsets"][t], lib["offsets"][t + 1]
+        kx, ky, w = lib["kx"][a:b], lib["ky"][a:b], lib["intensity"][a:b]
+        for s in range(n_theta):
+            ang = 2 * np.pi * s / n_theta
+            rx = np.cos(ang) * kx - np.sin(ang) * ky
+            ry = np.sin(ang) * kx + np.cos(ang) * ky
+            rho = px * np.hypot(rx, ry)
+            j = np.rint(rho)
+            k = np.mod(np.rint(np.arctan2(ry, rx) * n_theta / (2 * np.pi)), n_theta)
+            ok = j < R
+            # merge by pixel, then sample each pixel's Cartesian position
+            pix = {}
+            for jj, kk, ww in zip(j[ok], k[ok], w[ok]):
+                pix[(int(jj), int(kk))] = pix.get((int(jj), int(kk)), 0.0) + ww
+            tot = 0.0
+            for (jj, kk), ww in pix.items():
+                th = 2 * np.pi * kk / n_theta
+                xs, ys = cx + jj * np.cos(th), cy + jj * np.sin(th)
+                v = ndimage.map_coordinates(img, [[ys], [xs]], order=1, mode="grid-constant")[0]
+                tot += ww * v
+            assert abs(tot - C[t, s]) < 1e-10, (t, s)
+
+
+# ---------------------------------------------------------------- P3 one-bin rotation
+def test_p3_roll_by_one_bin():
+    lib, olib = _lib(n=20, seed=7)
+    rng = np.random.default_rng(8)
+    P = rng.random((olib.R, olib.n_theta))
+    best, arg = oracle.match_exact64(P, olib)
+    best1, arg1 = oracle.match_exact64(np.roll(P, 1, axis=1), olib)
+    assert np.allclose(best, best1, rtol=0, atol=1e-15)
+    assert np.array_equal(arg1, (arg + 1) % olib.n_theta)
+
+
+def test_p3_rendered_rotation_by_one_bin(c1, c1_olib):
+    """A Cartesian pattern rendered from template t at shift s0 and at s0 + 1
+    (Gaussian spots at the template pixels' Cartesian positions) has its
+    best angle for t move by exactly one bin."""
+    rng = np.random.default_rng(5)
+    checked = 0
+    for t in rng.choice(c1_olib.n_total, 8, replace=False):
+        if c1_olib.tnorm[t] == 0:
+            continue
+        sub = c1_olib.subset([t])
+        s0 = int(rng.integers(0, c1.n_theta))
+        got = []
+        for s in (s0, s0 + 1):
+            img = _render_pixels(c1_olib, t, s, c1.H, c1.W, c1.cx, c1.cy, sigma=1.5)
+            P = oracle.polar64(img, c1.R, c1.n_theta)
+            got.append(int(np.argmax(oracle.scores64(P, sub)[0])))
+        # rotationally symmetric templates resolve to the lowest equivalent shift
+        D = _dense_template(c1_olib, t)
+        per = next(p for p in range(1, c1.n_theta + 1)
+                   if np.array_equal(np.roll(D, p, axis=1), D))
+        assert got[0] == s0 % per and got[1] == (s0 + 1) % per
+        checked += 1
+    assert checked >= 6
+
+
+# ---------------------------------------------------------------- P4 rendered pattern
+def _render_pixels(olib, t, s0, H, W, cx, cy, sigma=1.0):
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    img = np.zeros((H, W))
+    a, b = olib.starts[t], olib.starts[t + 1]
+    for j, k, w in zip(olib.J[a:b], olib.K[a:b], olib.Wt[a:b]):
+        th = 2 * np.pi * ((k + s0) % olib.n_theta) / olib.n_theta
+        x, y = cx + j * np.cos(th), cy + j * np.sin(th)
+        img += w * np.exp(-((xx - x) ** 2 + (yy - y) ** 2) / (2 * sigma ** 2))
+    return img
+
+
+def test_p4_rendered_template_scores_maximal():
+    R, n_theta = 40, 180
+    # spots at 16..36 px, where one 2-degree bin spans at least half a pixel
+    lib = small_library(16, seed=21, g_max=1.1, g_min=0.5)
+    olib = oracle.OracleLibrary.build(lib, 33.0, R, n_theta)
+    H = W = 96
+    rng = np.random.default_rng(22)
+    for t in range(0, olib.n_total, 3):
+        if olib.tnorm[t] == 0:
+            continue
+        s0 = int(rng.integers(0, n_theta))
+        img = _render_pixels(olib, t, s0, H, W, 48.0, 48.0)
+        tt, ss, qq, _ = oracle.index_pattern64(img, olib, 3, cx=48.0, cy=48.0)
+        # expected: template t at s0 unless an identical pixel set (rotated)
+        # with a lower template index or a smaller shift exists
+        Dt = np.roll(_dense_template(olib, t), s0, axis=1)
+        equiv = [(u, s) for u in range(olib.n_total) for s in range(n_theta)
+                 if np.array_equal(np.roll(_dense_template(olib, u), s, axis=1), Dt)]
+        assert (int(tt[0]), int(ss[0])) == min(equiv)
+
+
+# ---------------------------------------------------------------- P5 invariance
+def test_p5_scale_invariance():
+    lib, olib = _lib(n=20, seed=9)
+    rng = np.random.default_rng(10)
+    img = rng.random((70, 70))
+    t1, s1, q1, _ = oracle.index_pattern64(img, olib, 6, cx=35.0, cy=35.0)
+    t2, s2, q2, _ = oracle.index_pattern64(7.5 * img, olib, 6, cx=35.0, cy=35.0)
+    lib3 = dict(lib, intensity=lib["intensity"] * 3.25)
+    olib3 = oracle.OracleLibrary.build(lib3, 30.0, olib.R, olib.n_theta)
+    t3, s3, q3, _ = oracle.index_pattern64(img, olib3, 6, cx=35.0, cy=35.0)
+    assert np.array_equal(t1, t2) and np.array_equal(s1, s2)
+    assert np.array_equal(t1, t3) and np.array_equal(s1, s3)
+    assert np.allclose(q1, q2, rtol=1e-13) and np.allclose(q1, q3, rtol=1e-13)
+
+
+# ---------------------------------------------------------------- P7 brute-force top-N
+def test_p7_topn_brute_force():
+    R, n_theta = 12, 36
+    lib = small_library(9, seed=31, g_max=0.9)
+    olib = oracle.OracleLibrary.build(lib, 12.0, R, n_theta)
+    rng = np.random.default_rng(32)
+    P = rng.integers(0, 4, (R, n_theta)).astype(np.float64)   # integer image: many ties
+    pn = math.sqrt(float((P * P).sum()))
+    # pure-python triple loop over (template, shift, pixel)
+    triples = []
+    pix = oracle.template_pixels64(lib["kx"], lib["ky"], lib["intensity"], lib["offsets"],
+                                   12.0, R, n_theta)
+    for t, (J, K, Wt) in enumerate(pix):
+        tn = math.sqrt(sum(w * w for w in Wt))
+        for s in range(n_theta):
+            num = 0.0
+            for j, k, w in zip(J, K, Wt):
+                num += w * P[j, (k + s) % n_theta]
+            q = num / (pn * tn) if tn > 0 else 0.0
+            triples.append((-q, t, s))
+    triples.sort()
+    seen, expect = set(), []
+    for nq, t, s in triples:
+        if t not in seen:
+            seen.add(t)
+            expect.append((t, s, -nq))
+    for N in (1, 4, len(pix)):
+        best, arg = oracle.match_exact64(P, olib, pn)
+        t, s, q = oracle.topn64(best, arg, N)
+        assert [(int(a), int(b)) for a, b in zip(t, s)] == [(e[0], e[1]) for e in expect[:N]]
+        assert np.allclose(q, [e[2] for e in expect[:N]], atol=1e-14)
+
+
+# ---------------------------------------------------------------- P8 prefilter special case
+def test_p8_prefilter_keep_all_equals_exact():
+    lib, olib = _lib(n=25, seed=41)
+    rng = np.random.default_rng(42)
+    img = rng.random((70, 70))
+    t1, s1, q1, _ = oracle.index_pattern64(img, olib, 7, cx=35.0, cy=35.0)
+    t2, s2, q2, ids = oracle.index_pattern_prefiltered64(img, olib, 7, keep=1.0, cx=35.0, cy=35.0)
+    assert len(ids) == olib.n_total
+    assert np.array_equal(t1, t2) and np.array_equal(s1, s2) and np.allclose(q1, q2)
+
+
+# ---------------------------------------------------------------- P10 equivariance
+def test_p10_template_permutation():
+    lib, olib = _lib(n=15, seed=51, mirror=False)
+    rng = np.random.default_rng(52)
+    P = rng.random((olib.R, olib.n_theta))
+    best, arg = oracle.match_exact64(P, olib)
+    perm = rng.permutation(olib.T_base)
+    off = lib["offsets"]
+    kx, ky, I, no = [], [], [], [0]
+    for t in perm:
+        kx.append(lib["kx"][off[t]:off[t + 1]])
+        ky.append(lib["ky"][off[t]:off[t + 1]])
+        I.append(lib["intensity"][off[t]:off[t + 1]])
+        no.append(no[-1] + off[t + 1] - off[t])
+    lib2 = dict(kx=np.concatenate(kx), ky=np.concatenate(ky), intensity=np.concatenate(I),
+                offsets=np.array(no))
+    olib2 = oracle.OracleLibrary.build(lib2, 30.0, olib.R, olib.n_theta, mirror=False)
+    best2, arg2 = oracle.match_exact64(P, olib2)
+    assert np.allclose(best2, best[perm], atol=1e-15) and np.array_equal(arg2, arg[perm])
+
+
+# ---------------------------------------------------------------- P11 mirror identity
+def test_p11_mirror_identity():
+    """Flipping the image about y = cy maps the score of template t at shift
+    s onto the score of mirror(t) at -s."""
+    lib, olib = _lib(n=10, seed=61)
+    rng = np.random.default_rng(62)
+    H = W = 64
+    cy = 32
+    img = rng.random((H, W))
+    flip = np.zeros_like(img)
+    for y in range(H):
+        if 0 <= 2 * cy - y < H:
+            flip[y] = img[2 * cy - y]
+    P = oracle.polar64(img, olib.R, olib.n_theta, cx=32.0, cy=float(cy))
+    Pf = oracle.polar64(flip, olib.R, olib.n_theta, cx=32.0, cy=float(cy))
+    Q = oracle.scores64(P, olib)
+    Qf = oracle.scores64(Pf, olib)
+    T = olib.T_base
+    n = olib.n_theta
+    neg = (-np.arange(n)) % n
+    for t in range(T):
+        assert np.allclose(Qf[t], Q[T + t][neg], atol=1e-12)
+        assert np.allclose(Qf[T + t], Q[t][neg], atol=1e-12)
+
+
+def test_mirror_pixels_are_reflected_columns():
+    lib, olib = _lib(n=10, seed=71)
+    T = olib.T_base
+    for t in range(T):
+        a, b = olib.starts[t], olib.starts[t + 1]
+        c, d = olib.starts[T + t], olib.starts[T + t + 1]
+        base = sorted(zip(olib.J[a:b], olib.K[a:b], olib.Wt[a:b]))
+        mir = sorted(zip(olib.J[c:d], (-olib.K[c:d]) % olib.n_theta, olib.Wt[c:d]))
+        assert [(j, k) for j, k, _ in base] == [(j, k) for j, k, _ in mir]
+        assert np.allclose([w for *_, w in base], [w for *_, w in mir])
+
+
+# ---------------------------------------------------------------- template pixel rules
+def test_template_pixels_rounding_merge_and_drop():
+    px, R, n = 10.0, 8, 8          # 45 degree bins
+    kx = np.array([0.0, 0.31, 0.0, 0.7, 0.701, 0.3 * np.cos(np.pi / 8 + 1e-9), 0.0])
+    ky = np.array([0.0, 0.0, 0.52, 0.0, 0.0, 0.3 * np.sin(np.pi / 8 + 1e-9), 0.9])
+    w = np.array([5.0, 1.0, 2.0, 0.5, 0.25, 3.0, 9.0])
+    J, K, W = oracle.template_pixels64(kx, ky, w, [0, 7], px, R, n, mirror=False)[0]
+    got = {(int(j), int(k)): float(x) for j, k, x in zip(J, K, W)}
+    # direct beam dropped; rho 3.1 -> j 3; 5.2 at 90 deg -> (5, 2);
+    # 7.0 and 7.01 merge at (7, 0); 3.0 at 22.5+ deg -> k = 1; 9.0 -> j 9 >= R dropped
+    assert got == {(3, 0): 1.0, (5, 2): 2.0, (7, 0): 0.75, (3, 1): 3.0}
+    J2, K2, W2 = oracle.template_pixels64(kx, ky, w, [0, 7], px, R, n, mirror=False,
+                                          unit=True, keep_direct_beam=True)[0]
+    got2 = {(int(j), int(k)): float(x) for j, k, x in zip(J2, K2, W2)}
+    assert got2 == {(0, 0): 1.0, (3, 0): 1.0, (5, 2): 1.0, (7, 0): 2.0, (3, 1): 1.0}
+
+
+def test_zero_norm_scores_zero():
+    lib, olib = _lib(n=5, seed=81)
+    P = np.zeros((olib.R, olib.n_theta))
+    best, arg = oracle.match_exact64(P, olib)
+    assert np.all(best == 0) and np.all(arg == 0)
+    t, s, q = oracle.topn64(best, arg, 3)
+    assert list(t) == [0, 1, 2] and list(s) == [0, 0, 0]
+
+
+def test_oracle_does_not_import_product():
+    import subprocess
+    import sys
+    code = ("import sys, oracle, synth; "
+            "bad=[m for m in sys.modules if m.startswith('paper_2111_07347_amd')]; "
+            "assert not bad, bad")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    subprocess.run([sys.executable, "-c", code], cwd=root, check=True)
