@@ -1,0 +1,257 @@
+/*
+ * tm.h - C ABI of libtm, template-matching orientation mapping on MI355X (gfx950).
+ *
+ * The library indexes 4D-STEM diffraction patterns against a library of
+ * simulated templates, following Cautaerts et al., "Free, flexible and fast:
+ * orientation mapping using the multi-core and GPU-accelerated template
+ * matching capabilities in the Python-based open source 4D-STEM analysis
+ * toolbox Pyxem" (Ultramicroscopy; arXiv 2111.07347):
+ *
+ *   - a template is a list of Bragg spots (kx, ky) with intensities, one per
+ *     out-of-plane orientation (Section 2.1);
+ *   - each pattern is resampled to polar coordinates about the direct beam
+ *     (Section 2.2, Fig. 2 c);
+ *   - every template, and its mirror across y = 0, is slid along the
+ *     azimuthal axis with wraparound and scored at every shift by the
+ *     correlation index Q of Eq. (1), with template spots rounded to integer
+ *     polar pixels (Section 2.2, Fig. 2 d-e);
+ *   - the best Q per template and its angle are kept and the N best
+ *     templates are returned per pattern (Section 2.2, end);
+ *   - optionally the library is first pre-filtered by correlating
+ *     azimuthally integrated profiles (Section 2.2, Fig. 3).
+ *
+ * Conventions shared by every call
+ *   - Template indices: base templates are 0..T-1; with mirrors enabled the
+ *     mirror of base template t has index T + t, so T' = 2T.
+ *   - Angles are bins s in [0, n_theta); the in-plane rotation in degrees is
+ *     s * 360 / n_theta (Section 2.2: 360 polar columns give 1 degree).
+ *     Shift s means the template read at polar column (k + s) mod n_theta,
+ *     i.e. the template rotated counter-clockwise (from +x toward +y, x being
+ *     the image column and y the image row) by s bins.
+ *   - Scores are Q of Eq. (1) as float32.
+ *   - Device buffers are owned by the caller (e.g. torch tensors); the
+ *     library only reads or writes them during the work it enqueues.
+ *   - Every call that touches the device enqueues its work asynchronously on
+ *     the given HIP stream (NULL = the default stream) and returns; results
+ *     are valid once that stream has synchronised. Arguments are validated
+ *     before anything is enqueued.
+ *   - Every call returns a tm_status. Nothing aborts or throws across the
+ *     ABI. On failure tm_last_error() describes the cause (per thread).
+ *   - With no HIP device present, every call that needs one returns
+ *     TM_ENODEV.
+ */
+#ifndef TM_H
+#define TM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TM_OK = 0,
+    TM_EINVAL = -1,          /* an argument is invalid (null, out of range, mismatched) */
+    TM_ENOMEM = -2,          /* device or host allocation failed */
+    TM_EHIP = -3,            /* a HIP runtime call failed; message in tm_last_error() */
+    TM_ENODEV = -4,          /* no HIP device is available */
+    TM_EUNSUPPORTED = -5,    /* valid request the library does not implement */
+    TM_ENOMEM_BUDGET = -6    /* request larger than a caller-given memory budget */
+} tm_status;
+
+typedef enum { TM_U16 = 0, TM_F32 = 1 } tm_dtype;
+
+typedef enum {
+    TM_PREC_FP32 = 0,        /* plain float32 */
+    TM_PREC_BF16 = 1,
+    TM_PREC_FP16 = 2,
+    TM_PREC_FP8 = 3          /* e4m3 with per-template scale */
+} tm_precision;
+
+/* Polar sampling grid (Section 2.2, Fig. 2 c).
+ *   radii   r_j = r0 + j*dr, j in [0, R)                   (pixels)
+ *   angles  theta_k = 2*pi*k/n_theta, k in [0, n_theta)
+ *   sample  (x, y) = (cx + r_j cos theta_k, cy + r_j sin theta_k), where x is
+ *           the image column and y the image row (pixel (row i, column j)
+ *           sits at x = j, y = i), (cx, cy) is the direct-beam centre.
+ * interp: 1 = bilinear with zero padding outside the image (default),
+ *         0 = nearest pixel (round half to even), zero outside.
+ * Limits: 1 <= R <= 4096, 64 <= n_theta <= 768, dr > 0. */
+typedef struct {
+    int32_t R;
+    int32_t n_theta;
+    double r0;
+    double dr;
+    double cx;
+    double cy;
+    int32_t interp;
+} tm_polar_grid;
+
+/* Library flags. */
+enum {
+    TM_LIB_MIRROR = 1u,            /* add mirrored templates (Section 2.2, Fig. 2 f) */
+    TM_LIB_UNIT_INTENSITY = 2u,    /* all spot weights 1 (Section 4.3) */
+    TM_LIB_KEEP_DIRECT_BEAM = 4u   /* keep spots at (0, 0); dropped by default */
+};
+
+/* Options of tm_match_batch. A NULL options pointer means the plain float32
+ * path: every template scored exactly.
+ *   prefilter_keep    fraction f of base templates kept by the azimuthal
+ *                     pre-filter (Section 2.2, Fig. 3), 0 = no pre-filter;
+ *                     the kept ceil(f*T) base templates (and their mirrors)
+ *                     are then scored exactly in float32.
+ *   prefilter_prec    arithmetic of the pre-filter's profile correlation
+ *                     (FP32, BF16, FP16 or FP8 on the matrix cores with
+ *                     float32 accumulation).
+ *   reserved          must be zero. */
+typedef struct {
+    double prefilter_keep;
+    int32_t prefilter_prec;
+    int32_t reserved[7];
+} tm_match_opts;
+
+typedef struct tm_library tm_library;   /* opaque; immutable after load */
+
+/* Largest N accepted by tm_match_batch and tm_topn. */
+#define TM_MAX_N 64
+
+/* tm_load_library - build a device-resident template library.
+ *
+ * Section 2.1: each template is a list of Bragg spots (kx, ky)_i in
+ * reciprocal-space units (1/Angstrom) with intensities I_i; the library is a
+ * list of templates. Section 2.2: spot polar coordinates are rounded to the
+ * nearest integer pixel of the polar grid; mirrors reflect spots across
+ * y = 0; template norms are precomputed so Eq. (1) becomes a dot product.
+ *
+ * Per spot, in float64 on the host (one-time set-up):
+ *   rho = px_per_inv_angstrom * hypot(kx, ky)
+ *   j   = rint((rho - grid->r0) / grid->dr)                (half to even)
+ *   k   = rint(atan2(ky, kx) * n_theta / (2 pi)) mod n_theta
+ *   spots with j outside [0, R) are dropped; spots at (0, 0) are dropped
+ *   unless TM_LIB_KEEP_DIRECT_BEAM; spots of one template falling on the
+ *   same (j, k) are merged by summing their weights (weight = intensity, or
+ *   1 with TM_LIB_UNIT_INTENSITY); ||T|| = sqrt(sum of merged weights^2);
+ *   device weights are w / ||T|| rounded to float32. A mirror uses
+ *   (j, (-k) mod n_theta).
+ *
+ * Arguments
+ *   kx, ky, intensity  host float64 arrays of length offsets[n_templates],
+ *                      read during the call only.
+ *   offsets            host int64 array [n_templates + 1], CSR offsets
+ *                      (offsets[0] = 0, non-decreasing).
+ *   n_templates        T >= 1 base templates.
+ *   px_per_inv_angstrom  detector calibration (pixels per 1/Angstrom), > 0.
+ *   grid               polar grid the patterns will be resampled on (R,
+ *                      n_theta, r0, dr are used; cx, cy, interp are not).
+ *   flags              TM_LIB_* bits.
+ *   hip_stream         stream used for the uploads; the call synchronises it
+ *                      before returning.
+ *   out                receives the handle; free with tm_free_library.
+ * Errors: TM_EINVAL (null pointer, T < 1, bad offsets, bad grid),
+ *         TM_ENOMEM, TM_EHIP, TM_ENODEV. On error *out is set to NULL. */
+int tm_load_library(const double* kx, const double* ky, const double* intensity,
+                    const int64_t* offsets, int32_t n_templates,
+                    double px_per_inv_angstrom, const tm_polar_grid* grid, uint32_t flags,
+                    void* hip_stream, tm_library** out);
+
+/* tm_free_library - release a library's device memory. The caller must make
+ * sure no enqueued work still uses it (synchronise the streams first).
+ * NULL is accepted and ignored. */
+int tm_free_library(tm_library* lib);
+
+/* tm_library_info - sizes of a loaded library (any pointer may be NULL).
+ *   n_templates_total  T' (2T with mirrors)
+ *   n_spots            merged polar pixels over all T' templates
+ *   device_bytes       device memory held by the handle */
+int tm_library_info(const tm_library* lib, int32_t* n_templates_total, int64_t* n_spots,
+                    size_t* device_bytes);
+
+/* tm_polar_transform - intensity transform, polar resampling, norms and
+ * azimuthal profiles of a batch of patterns (Section 2.2: gamma correction
+ * and constant subtraction of the pattern; polar transform about the
+ * direct-beam centre; Eq. (1) image norm; Fig. 3 azimuthal integration).
+ *
+ *   x~ = (gamma != 1 ? max(x, 0)^gamma : x) - subtract   per Cartesian pixel
+ *   P[b, j, k] = interp(x~_b; sample point of (j, k))    zero outside image
+ *   norm_out[b] = sqrt(sum_{j,k} P[b,j,k]^2)              float64 sum
+ *   profile_out[j*B + b] = sum_k P[b, j, k]               float64 sum, stored float32
+ *
+ * Arguments
+ *   patterns     device, [B, H, W] row-major, uint16 or float32 (dtype).
+ *   B, H, W      B >= 0 (0 is a no-op), 1 <= H, W <= 32767.
+ *   grid         sampling grid (all fields used).
+ *   gamma        > 0; 1 disables the power (and the clamp at zero).
+ *   subtract     constant removed after the power.
+ *   polar_out    device, [B, R, n_theta] float32, written.
+ *   norm_out     device, [B] float64, written.
+ *   profile_out  device, [R, B] float32 (note: radius-major), or NULL.
+ * Polar look-up tables (float64-built base pixel and float32 fractions) are
+ * built on first use for each (H, W, grid) and cached for the process.
+ * Errors: TM_EINVAL (null required pointer, bad sizes or grid, gamma <= 0),
+ *         TM_EHIP, TM_ENODEV, TM_ENOMEM. */
+int tm_polar_transform(const void* patterns, tm_dtype dtype, int32_t B, int32_t H, int32_t W,
+                       const tm_polar_grid* grid, float gamma, float subtract,
+                       float* polar_out, double* norm_out, float* profile_out,
+                       void* hip_stream);
+
+/* tm_match_batch - score every template of lib against every pattern at every
+ * in-plane shift and keep the N best templates per pattern (Eq. 1; Section
+ * 2.2: sliding with wraparound, best Q and angle per template, top-N).
+ *
+ *   Q(b, t, s) = sum_{(j,k,w) in t} w * P[b, j, (k+s) mod n_theta]
+ *                / (norms[b] * ||T_t||)           (0 if either norm is 0)
+ *   best(b, t) = max_s Q, angle = smallest maximising s
+ *   top rows: N distinct templates by best descending, ties to the lower
+ *   template index, each with its best angle. Accumulation is float32 in a
+ *   fixed order per (pattern, template), independent of the batch.
+ *
+ * Arguments
+ *   lib          loaded library; its grid defines R and n_theta.
+ *   polar        device, [B, R, n_theta] float32 (tm_polar_transform output).
+ *   norms        device, [B] float64 image norms.
+ *   profiles     device, [R, B] float32 azimuthal profiles; required only
+ *                when opts->prefilter_keep > 0, else may be NULL.
+ *   B            >= 0 (0 is a no-op).
+ *   opts         NULL for the plain path, or options (see tm_match_opts).
+ *   N            1 <= N <= min(TM_MAX_N, T'); with a pre-filter, N must not
+ *                exceed the number of kept templates.
+ *   top_template, top_angle  device, [B, N] int32, written, best first.
+ *   top_score    device, [B, N] float32, written.
+ *   best_score   device, [B, T'] float32 per-template best Q, or NULL.
+ *   best_angle   device, [B, T'] int16 per-template best angle, or NULL;
+ *                best_score and best_angle must be both NULL or both set,
+ *                and are only available without pre-filter.
+ * Errors: TM_EINVAL, TM_EUNSUPPORTED (unknown options), TM_EHIP, TM_ENODEV. */
+int tm_match_batch(const tm_library* lib, const float* polar, const double* norms,
+                   const float* profiles, int32_t B, const tm_match_opts* opts, int32_t N,
+                   int32_t* top_template, int32_t* top_angle, float* top_score,
+                   float* best_score, int16_t* best_angle, void* hip_stream);
+
+/* tm_topn - sort per-template best scores and keep the N best per pattern
+ * (Section 2.2, end: the list of correlations can be sorted and the N best
+ * matching templates queried).
+ *
+ * Arguments
+ *   best_score   device, [B, T] float32.
+ *   best_angle   device, [B, T] int16.
+ *   B, T, N      B >= 0, T >= 1, 1 <= N <= min(TM_MAX_N, T).
+ *   top_template, top_angle  device, [B, N] int32, written.
+ *   top_score    device, [B, N] float32, written.
+ * Order: score descending, ties to the lower template index.
+ * Errors: TM_EINVAL, TM_EHIP, TM_ENODEV. */
+int tm_topn(const float* best_score, const int16_t* best_angle, int32_t B, int32_t T, int32_t N,
+            int32_t* top_template, int32_t* top_angle, float* top_score, void* hip_stream);
+
+/* tm_last_error - message of the last failing call on this thread ("" if
+ * none). The pointer stays valid until the next call on the same thread. */
+const char* tm_last_error(void);
+
+/* tm_version - library version string, e.g. "tm 0.1.0 gfx950". */
+const char* tm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TM_H */

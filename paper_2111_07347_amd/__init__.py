@@ -1,0 +1,290 @@
+"""MI355X-native template-matching orientation mapping (Pyxem method,
+arXiv 2111.07347), Python binding of libtm.
+
+Argument marshalling only: every step runs in libtm's HIP kernels. PyTorch
+provides device memory and the current HIP stream. Names follow the C ABI in
+include/tm.h:
+
+    grid = PolarGrid(R=128, n_theta=360, cx=128.0, cy=128.0)
+    lib = Library(kx, ky, intensity, offsets, px_per_inv_angstrom, grid)
+    polar, norms, prof = polar_transform(patterns, grid)
+    top_t, top_s, top_q = match_batch(lib, polar, norms, N=5)
+    top_t, top_s, top_q = topn(best_score, best_angle, N=5)
+
+The library must have been built (``python -m paper_2111_07347_amd.build``);
+importing without it raises ImportError. There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtm.so")
+
+TM_OK, TM_EINVAL, TM_ENOMEM, TM_EHIP, TM_ENODEV, TM_EUNSUPPORTED, TM_ENOMEM_BUDGET = (
+    0, -1, -2, -3, -4, -5, -6)
+TM_U16, TM_F32 = 0, 1
+TM_PREC_FP32, TM_PREC_BF16, TM_PREC_FP16, TM_PREC_FP8 = 0, 1, 2, 3
+TM_LIB_MIRROR, TM_LIB_UNIT_INTENSITY, TM_LIB_KEEP_DIRECT_BEAM = 1, 2, 4
+TM_MAX_N = 64
+
+EXPORTED = ("tm_load_library", "tm_free_library", "tm_library_info", "tm_polar_transform",
+            "tm_match_batch", "tm_topn", "tm_last_error", "tm_version")
+
+
+class TMError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where} failed with status {code}: {msg}")
+        self.code = code
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_int32), ("n_theta", ctypes.c_int32), ("r0", ctypes.c_double),
+                ("dr", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+                ("interp", ctypes.c_int32)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("prefilter_keep", ctypes.c_double), ("prefilter_prec", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2111_07347_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D, F = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                         ctypes.c_float)
+    sig = {
+        "tm_load_library": [P, P, P, P, I32, D, ctypes.POINTER(_Grid), ctypes.c_uint32, P,
+                            ctypes.POINTER(P)],
+        "tm_free_library": [P],
+        "tm_library_info": [P, P, P, P],
+        "tm_polar_transform": [P, ctypes.c_int, I32, I32, I32, ctypes.POINTER(_Grid), F, F, P, P,
+                               P, P],
+        "tm_match_batch": [P, P, P, P, I32, ctypes.POINTER(_Opts), I32, P, P, P, P, P, P],
+        "tm_topn": [P, P, I32, I32, I32, P, P, P, P],
+        "tm_last_error": [],
+        "tm_version": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name in ("tm_last_error", "tm_version") else ctypes.c_int
+    return lib
+
+
+_lib = _load()
+
+
+def version() -> str:
+    return _lib.tm_version().decode()
+
+
+def last_error() -> str:
+    return _lib.tm_last_error().decode()
+
+
+def _check(code: int, where: str):
+    if code != TM_OK:
+        raise TMError(code, where, last_error())
+
+
+@dataclass(frozen=True)
+class PolarGrid:
+    """Polar sampling grid: r_j = r0 + j*dr, theta_k = 2 pi k / n_theta, about
+    (cx, cy) in pixel-index coordinates (x = column, y = row)."""
+    R: int
+    n_theta: int = 360
+    cx: float = 0.0
+    cy: float = 0.0
+    r0: float = 0.0
+    dr: float = 1.0
+    interp: str = "bilinear"
+
+    def _c(self) -> _Grid:
+        if self.interp not in ("bilinear", "nearest"):
+            raise ValueError(f"interp must be 'bilinear' or 'nearest', not {self.interp!r}")
+        return _Grid(int(self.R), int(self.n_theta), float(self.r0), float(self.dr),
+                     float(self.cx), float(self.cy), 1 if self.interp == "bilinear" else 0)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream) -> int:
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _require(t, name, dtype, shape=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device (cuda) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+class Library:
+    """Device-resident template library (tm_load_library).
+
+    kx, ky, intensity: spot coordinates (1/Angstrom) and intensities of all
+    templates concatenated; offsets: CSR offsets [T+1]."""
+
+    def __init__(self, kx, ky, intensity, offsets, px_per_inv_angstrom: float, grid: PolarGrid,
+                 mirror: bool = True, unit_intensity: bool = False,
+                 keep_direct_beam: bool = False, stream=None):
+        kx = np.ascontiguousarray(kx, dtype=np.float64)
+        ky = np.ascontiguousarray(ky, dtype=np.float64)
+        inten = np.ascontiguousarray(intensity, dtype=np.float64)
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        if not (len(kx) == len(ky) == len(inten) == int(off[-1])):
+            raise ValueError("kx, ky, intensity must all have offsets[-1] entries")
+        flags = ((TM_LIB_MIRROR if mirror else 0) | (TM_LIB_UNIT_INTENSITY if unit_intensity else 0)
+                 | (TM_LIB_KEEP_DIRECT_BEAM if keep_direct_beam else 0))
+        self.grid = grid
+        self.T = len(off) - 1
+        self.mirror = mirror
+        h = ctypes.c_void_p()
+        g = grid._c()
+        _check(_lib.tm_load_library(kx.ctypes.data, ky.ctypes.data, inten.ctypes.data,
+                                    off.ctypes.data, self.T, float(px_per_inv_angstrom),
+                                    ctypes.byref(g), flags, _stream_ptr(stream), ctypes.byref(h)),
+               "tm_load_library")
+        self._h = h
+
+    @property
+    def handle(self) -> int:
+        return self._h.value
+
+    def info(self):
+        tt, ns, db = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_size_t()
+        _check(_lib.tm_library_info(self._h, ctypes.byref(tt), ctypes.byref(ns), ctypes.byref(db)),
+               "tm_library_info")
+        return {"n_templates_total": tt.value, "n_spots": ns.value, "device_bytes": db.value}
+
+    @property
+    def n_total(self) -> int:
+        return self.info()["n_templates_total"]
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.tm_free_library(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def polar_transform(patterns, grid: PolarGrid, gamma: float = 1.0, subtract: float = 0.0,
+                    polar_out=None, norm_out=None, profile_out=None, want_profile: bool = True,
+                    stream=None):
+    """tm_polar_transform on a [B, H, W] uint16/float32 device tensor.
+    Returns (polar [B, R, n_theta] f32, norms [B] f64, profiles [R, B] f32 or None)."""
+    torch = _torch()
+    if patterns.dtype == torch.float32:
+        dt = TM_F32
+    elif patterns.dtype in (torch.uint16, torch.int16):
+        dt = TM_U16
+    else:
+        raise TypeError("patterns must be float32 or uint16")
+    if patterns.dim() != 3:
+        raise ValueError("patterns must be [B, H, W]")
+    if not patterns.is_cuda or not patterns.is_contiguous():
+        raise ValueError("patterns must be a contiguous device tensor")
+    B, H, W = patterns.shape
+    dev = patterns.device
+    if polar_out is None:
+        polar_out = torch.empty((B, grid.R, grid.n_theta), dtype=torch.float32, device=dev)
+    if norm_out is None:
+        norm_out = torch.empty((B,), dtype=torch.float64, device=dev)
+    if profile_out is None and want_profile:
+        profile_out = torch.empty((grid.R, B), dtype=torch.float32, device=dev)
+    _require(polar_out, "polar_out", torch.float32, (B, grid.R, grid.n_theta))
+    _require(norm_out, "norm_out", torch.float64, (B,))
+    if profile_out is not None:
+        _require(profile_out, "profile_out", torch.float32, (grid.R, B))
+    g = grid._c()
+    _check(_lib.tm_polar_transform(_ptr(patterns), dt, B, H, W, ctypes.byref(g), float(gamma),
+                                   float(subtract), _ptr(polar_out), _ptr(norm_out),
+                                   _ptr(profile_out), _stream_ptr(stream)), "tm_polar_transform")
+    return polar_out, norm_out, profile_out
+
+
+def _opts(prefilter_keep: float, prefilter_prec: int):
+    if prefilter_keep == 0.0:
+        return None
+    o = _Opts()
+    o.prefilter_keep = float(prefilter_keep)
+    o.prefilter_prec = int(prefilter_prec)
+    return o
+
+
+def match_batch(lib: Library, polar, norms, N: int, profiles=None, prefilter_keep: float = 0.0,
+                prefilter_prec: int = TM_PREC_FP32, with_best: bool = False, out=None,
+                stream=None):
+    """tm_match_batch. Returns (top_template [B,N] i32, top_angle [B,N] i32,
+    top_score [B,N] f32) and, with with_best, also (best_score [B,T'] f32,
+    best_angle [B,T'] i16)."""
+    torch = _torch()
+    B = polar.shape[0]
+    _require(polar, "polar", torch.float32, (B, lib.grid.R, lib.grid.n_theta))
+    _require(norms, "norms", torch.float64, (B,))
+    if profiles is not None:
+        _require(profiles, "profiles", torch.float32, (lib.grid.R, B))
+    dev = polar.device
+    if out is None:
+        out = (torch.empty((B, N), dtype=torch.int32, device=dev),
+               torch.empty((B, N), dtype=torch.int32, device=dev),
+               torch.empty((B, N), dtype=torch.float32, device=dev))
+    tt, ts, tq = out
+    _require(tt, "top_template", torch.int32, (B, N))
+    _require(ts, "top_angle", torch.int32, (B, N))
+    _require(tq, "top_score", torch.float32, (B, N))
+    bq = bs = None
+    if with_best:
+        Tn = lib.n_total
+        bq = torch.empty((B, Tn), dtype=torch.float32, device=dev)
+        bs = torch.empty((B, Tn), dtype=torch.int16, device=dev)
+    o = _opts(prefilter_keep, prefilter_prec)
+    _check(_lib.tm_match_batch(lib._h, _ptr(polar), _ptr(norms), _ptr(profiles), B,
+                               ctypes.byref(o) if o is not None else None, int(N), _ptr(tt),
+                               _ptr(ts), _ptr(tq), _ptr(bq), _ptr(bs), _stream_ptr(stream)),
+           "tm_match_batch")
+    return (tt, ts, tq, bq, bs) if with_best else (tt, ts, tq)
+
+
+def topn(best_score, best_angle, N: int, stream=None):
+    """tm_topn on [B, T] scores/angles. Returns (template, angle, score) [B, N]."""
+    torch = _torch()
+    B, T = best_score.shape
+    _require(best_score, "best_score", torch.float32, (B, T))
+    _require(best_angle, "best_angle", torch.int16, (B, T))
+    dev = best_score.device
+    tt = torch.empty((B, N), dtype=torch.int32, device=dev)
+    ts = torch.empty((B, N), dtype=torch.int32, device=dev)
+    tq = torch.empty((B, N), dtype=torch.float32, device=dev)
+    _check(_lib.tm_topn(_ptr(best_score), _ptr(best_angle), B, T, int(N), _ptr(tt), _ptr(ts),
+                        _ptr(tq), _stream_ptr(stream)), "tm_topn")
+    return tt, ts, tq

@@ -439,44 +439,26 @@ def make_patterns(cfg: Config | int, lib: dict, indices) -> np.ndarray:
 
 
 def _worker(args):
-    cid, lib, lo, hi, shm_name, shape, dtype = args
-    from multiprocessing import shared_memory
-    shm = shared_memory.SharedMemory(name=shm_name)
-    try:
-        arr = np.ndarray(shape, dtype=dtype, buffer=shm.buf)
-        cfg = CONFIGS[cid]
-        for i in range(lo, hi):
-            arr[i] = make_pattern(cfg, lib, i)
-    finally:
-        shm.close()
-    return hi - lo
+    cid, lib, lo, hi = args
+    return lo, make_patterns(CONFIGS[cid], lib, range(lo, hi))
 
 
 def make_patterns_parallel(cfg: Config | int, lib: dict, n: int, workers: int = 8,
                            out: np.ndarray | None = None) -> np.ndarray:
-    """Patterns 0..n-1 generated by a process pool into shared memory; same
-    bytes as make_patterns(cfg, lib, range(n))."""
+    """Patterns 0..n-1 generated by a process pool; same bytes as
+    make_patterns(cfg, lib, range(n))."""
     import multiprocessing as mp
-    from multiprocessing import shared_memory
     if isinstance(cfg, int):
         cfg = CONFIGS[cfg]
     dt = np.float32 if cfg.dtype == "f32" else np.uint16
-    shape = (n, cfg.H, cfg.W)
-    nbytes = int(np.prod(shape)) * np.dtype(dt).itemsize
-    shm = shared_memory.SharedMemory(create=True, size=max(nbytes, 1))
-    try:
-        step = max(1, (n + workers * 4 - 1) // (workers * 4))
-        jobs = [(cfg.cid, lib, lo, min(n, lo + step), shm.name, shape, dt)
-                for lo in range(0, n, step)]
-        ctx = mp.get_context("fork")
-        with ctx.Pool(workers) as pool:
-            for _ in pool.imap_unordered(_worker, jobs):
-                pass
-        arr = np.ndarray(shape, dtype=dt, buffer=shm.buf)
-        if out is None:
-            out = np.empty(shape, dtype=dt)
-        out[...] = arr
+    if out is None:
+        out = np.empty((n, cfg.H, cfg.W), dtype=dt)
+    if workers <= 1 or n < 64:
+        out[...] = make_patterns(cfg, lib, range(n))
         return out
-    finally:
-        shm.close()
-        shm.unlink()
+    step = 128
+    jobs = [(cfg.cid, lib, lo, min(n, lo + step)) for lo in range(0, n, step)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        for lo, arr in pool.imap_unordered(_worker, jobs):
+            out[lo:lo + len(arr)] = arr
+    return out

@@ -1,0 +1,277 @@
+"""GPU parity: libtm's HIP path against the FP64 oracle on seeded inputs.
+
+Runs only on an MI355X (marked gpu). Every case prints its name, seed and
+shape before touching the GPU."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import small_library
+from parity import PatternRef, check_topn, scores_close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2111_07347_amd as tm
+    return tm
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _grid_for(tm, cfg):
+    return tm.PolarGrid(R=cfg.R, n_theta=cfg.n_theta, cx=cfg.cx, cy=cfg.cy)
+
+
+def _olib(lib, cfg, **kw):
+    return oracle.OracleLibrary.build(lib, synth.px_per_inv_A(cfg), cfg.R, cfg.n_theta, **kw)
+
+
+def _run(tm, lib_np, imgs, grid, px_per, N, gamma=1.0, subtract=0.0, with_best=False,
+         mirror=True, unit=False):
+    import torch
+    lib = tm.Library(lib_np["kx"], lib_np["ky"], lib_np["intensity"], lib_np["offsets"], px_per,
+                     grid, mirror=mirror, unit_intensity=unit)
+    x = torch.from_numpy(np.ascontiguousarray(imgs)).cuda()
+    polar, norms, prof = tm.polar_transform(x, grid, gamma, subtract)
+    out = tm.match_batch(lib, polar, norms, N, with_best=with_best)
+    torch.cuda.synchronize()
+    res = [o.cpu().numpy() for o in out]
+    return lib, polar.cpu().numpy(), norms.cpu().numpy(), prof.cpu().numpy(), res
+
+
+# --------------------------------------------------------------------------- polar
+def _polar_close(got, ref, img):
+    scale = max(1.0, float(np.abs(img).max()))
+    assert np.allclose(got, ref, rtol=2e-6, atol=2e-6 * scale), float(np.abs(got - ref).max())
+
+
+def test_polar_c1(tm, c1, c1_lib):
+    _say("polar c1 B=64 128x128 R=64")
+    import torch
+    imgs = synth.make_patterns(c1, c1_lib, range(64))
+    grid = _grid_for(tm, c1)
+    polar, norms, prof = tm.polar_transform(torch.from_numpy(imgs).cuda(), grid)
+    polar, norms, prof = polar.cpu().numpy(), norms.cpu().numpy(), prof.cpu().numpy()
+    for b in range(64):
+        P = oracle.polar64(imgs[b], c1.R, c1.n_theta)
+        _polar_close(polar[b], P, imgs[b])
+        assert abs(norms[b] - oracle.norm64(P)) <= 1e-6 * oracle.norm64(P)
+        pr = oracle.profile64(P)
+        assert np.allclose(prof[:, b], pr, rtol=1e-5, atol=1e-5 * np.abs(pr).max())
+
+
+@pytest.mark.parametrize("case", ["gamma_sub", "nearest", "offcentre_pad", "u16", "r0dr", "ragged"])
+def test_polar_options(tm, case):
+    import torch
+    rng = np.random.default_rng(sum(map(ord, case)))
+    H, W, R, nt = 70, 90, 40, 180
+    kw = dict(gamma=1.0, subtract=0.0)
+    gk = dict(R=R, n_theta=nt, cx=45.0, cy=35.0)
+    imgs = rng.random((3, H, W)).astype(np.float32) * 5.0
+    if case == "gamma_sub":
+        imgs -= 1.0   # negative pixels: the clamp matters
+        kw = dict(gamma=0.5, subtract=0.3)
+    elif case == "nearest":
+        gk["interp"] = "nearest"
+    elif case == "offcentre_pad":
+        gk.update(cx=20.3, cy=61.7, R=60)   # many samples outside the image
+    elif case == "u16":
+        imgs = rng.integers(0, 60000, (3, H, W)).astype(np.uint16)
+    elif case == "r0dr":
+        gk.update(r0=2.5, dr=0.75)
+    elif case == "ragged":
+        imgs = rng.random((1, 33, 47)).astype(np.float32)
+        H, W = 33, 47
+        gk.update(R=30, n_theta=97, cx=23.2, cy=16.9)
+    _say("polar option", case, imgs.shape, gk, kw)
+    grid = tm.PolarGrid(**gk)
+    x = torch.from_numpy(imgs).cuda()
+    polar, norms, prof = tm.polar_transform(x, grid, **kw)
+    polar, norms = polar.cpu().numpy(), norms.cpu().numpy()
+    interp = gk.get("interp", "bilinear")
+    for b in range(len(imgs)):
+        P = oracle.polar64(imgs[b].astype(np.float64), gk["R"], gk["n_theta"], gk.get("r0", 0.0),
+                           gk.get("dr", 1.0), gk["cx"], gk["cy"], kw["gamma"], kw["subtract"],
+                           interp)
+        _polar_close(polar[b], P, imgs[b].astype(np.float64))
+        assert abs(norms[b] - oracle.norm64(P)) <= 1e-6 * oracle.norm64(P) + 1e-9
+
+
+# --------------------------------------------------------------------------- match
+def test_match_c1_full(tm, c1, c1_lib, c1_olib):
+    _say("match c1 full B=64 T'=600 N=5")
+    imgs = synth.make_patterns(c1, c1_lib, range(64))
+    grid = _grid_for(tm, c1)
+    _, polar, norms, _, (tt, ts, tq, bq, bs) = _run(tm, c1_lib, imgs, grid,
+                                                     synth.px_per_inv_A(c1), 5, with_best=True)
+    exact_contract = exact_tight = 0
+    for b in range(64):
+        P = oracle.polar64(imgs[b], c1.R, c1.n_theta)
+        ref = PatternRef(P, c1_olib)
+        exact_contract += check_topn(ref, tt[b], ts[b], tq[b], margin=1e-4, tight=False)
+        exact_tight += check_topn(ref, tt[b], ts[b], tq[b], margin=1e-4, tight=True)
+        # per-template best scores and angles for every template
+        assert scores_close(bq[b], ref.best).all()
+        srt = np.sort(ref.Q, axis=1)
+        am = srt[:, -1] - srt[:, -2]
+        clear = am > 2 * np.maximum(1e-5 * np.abs(ref.best), 1e-7) * 2
+        assert np.array_equal(bs[b][clear], ref.arg[clear])
+    _say("exact ranks: contract", exact_contract, "tight", exact_tight)
+    assert exact_tight >= 64 * 5 * 0.5
+
+
+def test_topn_standalone_matches_sort(tm):
+    import torch
+    rng = np.random.default_rng(7)
+    for B, T, N in ((3, 1000, 5), (2, 70, 64), (5, 4001, 10), (1, 1, 1), (4, 257, 17)):
+        _say("topn", B, T, N)
+        q = rng.integers(0, 50, (B, T)).astype(np.float32) / 7.0   # many exact ties
+        s = rng.integers(0, 360, (B, T)).astype(np.int16)
+        tt, ts, tq = tm.topn(torch.from_numpy(q).cuda(), torch.from_numpy(s).cuda(), N)
+        tt, ts, tq = tt.cpu().numpy(), ts.cpu().numpy(), tq.cpu().numpy()
+        for b in range(B):
+            order = np.lexsort((np.arange(T), -q[b].astype(np.float64)))[:N]
+            assert np.array_equal(tt[b], order)
+            assert np.array_equal(ts[b], s[b][order])
+            assert np.array_equal(tq[b], q[b][order])
+
+
+def test_match_best_then_topn_equals_fused(tm, c1, c1_lib):
+    _say("fused top-N == tm_topn(best arrays), c1")
+    import torch
+    imgs = synth.make_patterns(c1, c1_lib, range(16))
+    grid = _grid_for(tm, c1)
+    _, _, _, _, (tt, ts, tq, bq, bs) = _run(tm, c1_lib, imgs, grid, synth.px_per_inv_A(c1), 7,
+                                            with_best=True)
+    t2, s2, q2 = tm.topn(torch.from_numpy(bq).cuda(), torch.from_numpy(bs).cuda(), 7)
+    assert np.array_equal(tt, t2.cpu().numpy()) and np.array_equal(ts, s2.cpu().numpy())
+    assert np.array_equal(tq, q2.cpu().numpy())
+
+
+@pytest.mark.parametrize("n_theta", [64, 90, 180, 361, 720])
+def test_match_theta_widths(tm, n_theta):
+    R = 40
+    lib = small_library(30, seed=n_theta, max_spots=12, g_max=1.1, g_min=0.3)
+    px = 33.0
+    rng = np.random.default_rng(n_theta)
+    imgs = rng.random((5, 96, 96)).astype(np.float32)
+    _say("theta width", n_theta, "R", R, imgs.shape)
+    grid = tm.PolarGrid(R=R, n_theta=n_theta, cx=48.0, cy=48.0)
+    olib = oracle.OracleLibrary.build(lib, px, R, n_theta)
+    _, _, _, _, (tt, ts, tq, bq, bs) = _run(tm, lib, imgs, grid, px, 6, with_best=True)
+    for b in range(5):
+        P = oracle.polar64(imgs[b], R, n_theta, cx=48.0, cy=48.0)
+        ref = PatternRef(P, olib)
+        check_topn(ref, tt[b], ts[b], tq[b], margin=1e-4, tight=True)
+        assert scores_close(bq[b], ref.best).all()
+
+
+def test_match_multiband_synthetic(tm):
+    """Spots spread over most of 128 rows: the library is processed in LDS
+    bands with per-wave accumulators held across bands."""
+    R, nt = 128, 360
+    lib = small_library(300, seed=99, max_spots=40, g_max=1.2, g_min=0.05)
+    px = (R - 4) / 1.2
+    rng = np.random.default_rng(100)
+    imgs = rng.random((6, 256, 256)).astype(np.float32)
+    _say("multi-band synthetic T=300 R=128", imgs.shape)
+    grid = tm.PolarGrid(R=R, n_theta=nt, cx=128.0, cy=128.0)
+    olib = oracle.OracleLibrary.build(lib, px, R, nt)
+    tml, _, _, _, (tt, ts, tq, bq, bs) = _run(tm, lib, imgs, grid, px, 8, with_best=True)
+    for b in range(6):
+        P = oracle.polar64(imgs[b], R, nt)
+        ref = PatternRef(P, olib)
+        check_topn(ref, tt[b], ts[b], tq[b], margin=1e-4, tight=True)
+        assert scores_close(bq[b], ref.best).all()
+
+
+def test_match_c3_library_multiband(tm):
+    """The 20 000-template orthorhombic library (93 touched rows) on three
+    patterns of the precision-form scan."""
+    cfg = synth.CONFIGS[3]
+    lib = synth.make_library(3)
+    imgs = synth.make_patterns(cfg, lib, [0, 4096, 16383])
+    _say("c3 library, 3 patterns, T'=40000")
+    grid = _grid_for(tm, cfg)
+    olib = _olib(lib, cfg)
+    _, _, _, _, (tt, ts, tq) = _run(tm, lib, imgs, grid, synth.px_per_inv_A(cfg), 5)
+    for b in range(3):
+        P = oracle.polar64(imgs[b], cfg.R, cfg.n_theta)
+        ref = PatternRef(P, olib)
+        check_topn(ref, tt[b], ts[b], tq[b], margin=1e-4, tight=True)
+
+
+def test_batch_independence_and_determinism(tm, c1, c1_lib):
+    _say("batch independence c1")
+    imgs = synth.make_patterns(c1, c1_lib, range(40))
+    grid = _grid_for(tm, c1)
+    px = synth.px_per_inv_A(c1)
+    _, _, _, _, full = _run(tm, c1_lib, imgs, grid, px, 5)
+    _, _, _, _, again = _run(tm, c1_lib, imgs, grid, px, 5)
+    for a, b in zip(full, again):
+        assert np.array_equal(a, b)
+    for i in (0, 17, 39):
+        _, _, _, _, one = _run(tm, c1_lib, imgs[i:i + 1], grid, px, 5)
+        for a, b in zip(full, one):
+            assert np.array_equal(a[i], b[0])
+    # permuting the batch permutes the results
+    perm = np.random.default_rng(3).permutation(40)
+    _, _, _, _, pr = _run(tm, c1_lib, imgs[perm], grid, px, 5)
+    for a, b in zip(full, pr):
+        assert np.array_equal(a[perm], b)
+
+
+def test_edge_cases(tm, c1, c1_lib, c1_olib):
+    import torch
+    grid = _grid_for(tm, c1)
+    px = synth.px_per_inv_A(c1)
+    # all-zero pattern: every Q is 0, templates ranked by index at angle 0
+    _say("edge: zero pattern")
+    z = np.zeros((2, c1.H, c1.W), dtype=np.float32)
+    _, _, norms, _, (tt, ts, tq) = _run(tm, c1_lib, z, grid, px, 5)
+    assert np.all(norms == 0)
+    assert np.array_equal(tt, np.tile(np.arange(5), (2, 1))) and np.all(ts == 0) and np.all(tq == 0)
+    # N = T' (complete ordering) on a small library
+    _say("edge: N = T'")
+    lib = small_library(20, seed=5, g_max=1.1, g_min=0.2)
+    olib = oracle.OracleLibrary.build(lib, px, c1.R, c1.n_theta)
+    imgs = synth.make_patterns(c1, c1_lib, [3])
+    _, _, _, _, (tt, ts, tq) = _run(tm, lib, imgs, grid, px, olib.n_total)
+    ref = PatternRef(oracle.polar64(imgs[0], c1.R, c1.n_theta), olib)
+    check_topn(ref, tt[0], ts[0], tq[0], margin=1e-4, tight=True)
+    # templates whose spots all fall outside the grid, or only the direct beam
+    _say("edge: empty templates, no mirrors, unit intensities")
+    lib2 = dict(kx=np.array([5.0, 0.0, 0.3, 0.1]), ky=np.array([5.0, 0.0, 0.2, -0.4]),
+                intensity=np.array([1.0, 1.0, 0.5, 2.0]),
+                offsets=np.array([0, 1, 2, 4], dtype=np.int64))
+    olib2 = oracle.OracleLibrary.build(lib2, px, c1.R, c1.n_theta, mirror=False, unit=True)
+    _, _, _, _, (tt, ts, tq) = _run(tm, lib2, imgs, grid, px, 3, mirror=False, unit=True)
+    ref = PatternRef(oracle.polar64(imgs[0], c1.R, c1.n_theta), olib2)
+    check_topn(ref, tt[0], ts[0], tq[0], margin=1e-4, tight=True)
+    # B = 0 is a no-op
+    _say("edge: B = 0")
+    tml = tm.Library(c1_lib["kx"], c1_lib["ky"], c1_lib["intensity"], c1_lib["offsets"], px, grid)
+    e = torch.empty((0, c1.H, c1.W), dtype=torch.float32, device="cuda")
+    polar, norms, prof = tm.polar_transform(e, grid)
+    tt, ts, tq = tm.match_batch(tml, polar, norms, 5)
+    assert tt.shape == (0, 5)
+    # invalid N is rejected before launch
+    with pytest.raises(tm.TMError):
+        tm.match_batch(tml, polar, norms, tml.n_total + 1)
+
+
+def test_library_info(tm, c1, c1_lib, c1_olib):
+    grid = _grid_for(tm, c1)
+    lib = tm.Library(c1_lib["kx"], c1_lib["ky"], c1_lib["intensity"], c1_lib["offsets"],
+                     synth.px_per_inv_A(c1), grid)
+    info = lib.info()
+    assert info["n_templates_total"] == c1_olib.n_total
+    assert info["n_spots"] == len(c1_olib.J)
+    assert info["device_bytes"] > 0
