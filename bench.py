@@ -47,6 +47,11 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--cpu-procs", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-grouping", action="store_true",
+                    help="score every template on its own (no shared-pixel groups)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy three times (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
 
 
@@ -72,6 +77,14 @@ def main():
               file=sys.stderr)
         return 2
     import torch
+    if a.calibrate_copy:
+        src_t = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst_t = torch.empty_like(src_t)
+        for _ in range(3):
+            dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": src_t.numel() * 4, "launches": 3}))
+        return 0
     import paper_2111_07347_amd as tm
     import synth
 
@@ -89,8 +102,10 @@ def main():
 
     grid = tm.PolarGrid(R=cfg.R, n_theta=cfg.n_theta, cx=cfg.cx, cy=cfg.cy)
     px = synth.px_per_inv_A(cfg)
-    lib = tm.Library(lib_np["kx"], lib_np["ky"], lib_np["intensity"], lib_np["offsets"], px, grid)
+    lib = tm.Library(lib_np["kx"], lib_np["ky"], lib_np["intensity"], lib_np["offsets"], px, grid,
+                     grouping=not a.no_grouping)
     info = lib.info()
+    layout = lib.layout()
     x = torch.from_numpy(imgs).to(dev)
     del imgs
     polar = torch.empty((B, cfg.R, cfg.n_theta), dtype=torch.float32, device=dev)
@@ -186,6 +201,7 @@ def main():
             "B": B, "H": cfg.H, "W": cfg.W, "R": cfg.R, "n_theta": cfg.n_theta,
             "templates": cfg.n_templates, "templates_with_mirrors": info["n_templates_total"],
             "template_pixels": n_spots, "top_n": N, "path": "plain fp32",
+            "library_layout": layout,
             "parallelism": "single GPU",
         },
         "roofline": roofline,

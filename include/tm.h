@@ -92,7 +92,11 @@ typedef struct {
 enum {
     TM_LIB_MIRROR = 1u,            /* add mirrored templates (Section 2.2, Fig. 2 f) */
     TM_LIB_UNIT_INTENSITY = 2u,    /* all spot weights 1 (Section 4.3) */
-    TM_LIB_KEEP_DIRECT_BEAM = 4u   /* keep spots at (0, 0); dropped by default */
+    TM_LIB_KEEP_DIRECT_BEAM = 4u,  /* keep spots at (0, 0); dropped by default */
+    TM_LIB_NO_GROUPING = 8u        /* score every template on its own; by default
+                                      templates sharing polar pixels are scored
+                                      together (same results up to float32
+                                      summation order) */
 };
 
 /* Options of tm_match_batch. A NULL options pointer means the plain float32
@@ -166,6 +170,18 @@ int tm_free_library(tm_library* lib);
  *   device_bytes       device memory held by the handle */
 int tm_library_info(const tm_library* lib, int32_t* n_templates_total, int64_t* n_spots,
                     size_t* device_bytes);
+
+/* tm_library_layout - how a loaded library is laid out for the match kernel
+ * (any pointer may be NULL).
+ *   group      templates scored together per group (1 = no grouping)
+ *   n_bands    LDS bands the touched polar rows are split into (1 = all at once)
+ *   n_rows     polar rows touched by any template
+ *   n_records  union pixels stored over all groups and bands
+ *   row_width  floats per LDS row: n_theta + 64*ceil(n_theta/64) - 1 (wide rows,
+ *              no wrap handling) or n_theta + 63 (narrow rows, wrap handled
+ *              per pixel) */
+int tm_library_layout(const tm_library* lib, int32_t* group, int32_t* n_bands, int32_t* n_rows,
+                      int64_t* n_records, int32_t* row_width);
 
 /* tm_polar_transform - intensity transform, polar resampling, norms and
  * azimuthal profiles of a batch of patterns (Section 2.2: gamma correction

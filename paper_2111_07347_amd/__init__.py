@@ -11,7 +11,7 @@ include/tm.h:
     top_t, top_s, top_q = match_batch(lib, polar, norms, N=5)
     top_t, top_s, top_q = topn(best_score, best_angle, N=5)
 
-The library must have been built (``python -m paper_2111_07347_amd.build``);
+The library must have been built (``python paper_2111_07347_amd/build.py``);
 importing without it raises ImportError. There is no CPU fallback.
 """
 from __future__ import annotations
@@ -29,10 +29,11 @@ TM_OK, TM_EINVAL, TM_ENOMEM, TM_EHIP, TM_ENODEV, TM_EUNSUPPORTED, TM_ENOMEM_BUDG
     0, -1, -2, -3, -4, -5, -6)
 TM_U16, TM_F32 = 0, 1
 TM_PREC_FP32, TM_PREC_BF16, TM_PREC_FP16, TM_PREC_FP8 = 0, 1, 2, 3
-TM_LIB_MIRROR, TM_LIB_UNIT_INTENSITY, TM_LIB_KEEP_DIRECT_BEAM = 1, 2, 4
+TM_LIB_MIRROR, TM_LIB_UNIT_INTENSITY, TM_LIB_KEEP_DIRECT_BEAM, TM_LIB_NO_GROUPING = 1, 2, 4, 8
 TM_MAX_N = 64
 
-EXPORTED = ("tm_load_library", "tm_free_library", "tm_library_info", "tm_polar_transform",
+EXPORTED = ("tm_load_library", "tm_free_library", "tm_library_info", "tm_library_layout",
+            "tm_polar_transform",
             "tm_match_batch", "tm_topn", "tm_last_error", "tm_version")
 
 
@@ -56,7 +57,7 @@ class _Opts(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
-                          "`python -m paper_2111_07347_amd.build`")
+                          "`python paper_2111_07347_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     P, I32, I64, D, F = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
                          ctypes.c_float)
@@ -65,6 +66,7 @@ def _load():
                             ctypes.POINTER(P)],
         "tm_free_library": [P],
         "tm_library_info": [P, P, P, P],
+        "tm_library_layout": [P, P, P, P, P, P],
         "tm_polar_transform": [P, ctypes.c_int, I32, I32, I32, ctypes.POINTER(_Grid), F, F, P, P,
                                P, P],
         "tm_match_batch": [P, P, P, P, I32, ctypes.POINTER(_Opts), I32, P, P, P, P, P, P],
@@ -73,6 +75,9 @@ def _load():
         "tm_version": [],
     }
     for name, args in sig.items():
+        if not hasattr(lib, name):
+            raise ImportError(f"{LIB_PATH} lacks {name}: it is stale, rebuild it with "
+                              "`python paper_2111_07347_amd/build.py`")
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_char_p if name in ("tm_last_error", "tm_version") else ctypes.c_int
@@ -151,7 +156,7 @@ class Library:
 
     def __init__(self, kx, ky, intensity, offsets, px_per_inv_angstrom: float, grid: PolarGrid,
                  mirror: bool = True, unit_intensity: bool = False,
-                 keep_direct_beam: bool = False, stream=None):
+                 keep_direct_beam: bool = False, grouping: bool = True, stream=None):
         kx = np.ascontiguousarray(kx, dtype=np.float64)
         ky = np.ascontiguousarray(ky, dtype=np.float64)
         inten = np.ascontiguousarray(intensity, dtype=np.float64)
@@ -159,7 +164,8 @@ class Library:
         if not (len(kx) == len(ky) == len(inten) == int(off[-1])):
             raise ValueError("kx, ky, intensity must all have offsets[-1] entries")
         flags = ((TM_LIB_MIRROR if mirror else 0) | (TM_LIB_UNIT_INTENSITY if unit_intensity else 0)
-                 | (TM_LIB_KEEP_DIRECT_BEAM if keep_direct_beam else 0))
+                 | (TM_LIB_KEEP_DIRECT_BEAM if keep_direct_beam else 0)
+                 | (0 if grouping else TM_LIB_NO_GROUPING))
         self.grid = grid
         self.T = len(off) - 1
         self.mirror = mirror
@@ -180,6 +186,15 @@ class Library:
         _check(_lib.tm_library_info(self._h, ctypes.byref(tt), ctypes.byref(ns), ctypes.byref(db)),
                "tm_library_info")
         return {"n_templates_total": tt.value, "n_spots": ns.value, "device_bytes": db.value}
+
+    def layout(self):
+        g, nb, nr, rw = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        rec = ctypes.c_int64()
+        _check(_lib.tm_library_layout(self._h, ctypes.byref(g), ctypes.byref(nb), ctypes.byref(nr),
+                                      ctypes.byref(rec), ctypes.byref(rw)), "tm_library_layout")
+        n_theta = self.grid.n_theta
+        return {"group": g.value, "n_bands": nb.value, "n_rows": nr.value, "n_records": rec.value,
+                "row_width": rw.value, "narrow": rw.value == n_theta + 63}
 
     @property
     def n_total(self) -> int:

@@ -1,6 +1,6 @@
 """Build libtm.so (HIP kernels + C ABI) for gfx950, in-tree.
 
-    python -m paper_2111_07347_amd.build [--jobs N] [--verbose]
+    python paper_2111_07347_amd/build.py [--jobs N] [--verbose]
 
 Every HIP source under csrc/ is compiled with hipcc for gfx950 and linked
 into paper_2111_07347_amd/libtm.so next to this file. Packed FP32 vector
@@ -39,9 +39,14 @@ def hipcc() -> str:
     return exe
 
 
+# Per-source extra flags. The match kernel never produces NaNs (finite
+# patterns and weights), so NaN-quieting around fmaxf is dropped there.
+EXTRA = {"tm_match.hip": ["-fno-honor-nans"]}
+
+
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc(), *COMMON, "-c", src, "-o", obj]
+    cmd = [hipcc(), *COMMON, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

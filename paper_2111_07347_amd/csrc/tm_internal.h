@@ -37,10 +37,14 @@ constexpr int kWave = 64;
 // Number of 64-lane shift slots per lane for a given polar width.
 inline int slots_for(int n_theta) { return (n_theta + kWave - 1) / kWave; }
 
-// Width of an LDS polar row: n_theta columns plus a wraparound halo long
+// LDS polar row widths. Wide: n_theta columns plus a wraparound halo long
 // enough that lane l of slot k reading column (k0 + l + 64 k) never wraps
-// (k0 < n_theta, l < 64, k < K).
-inline int lds_row_width(int n_theta) { return n_theta + kWave * slots_for(n_theta) - 1; }
+// (k0 < n_theta, l < 64, k < K). Narrow: a halo of one wave, enough for any
+// read of 64 consecutive columns starting below n_theta.
+inline int wide_row_width(int n_theta) { return n_theta + kWave * slots_for(n_theta) - 1; }
+inline int narrow_row_width(int n_theta) { return n_theta + kWave - 1; }
+// Narrow rows are used up to this many slots (n_theta <= 384).
+constexpr int kMaxNarrowSlots = 6;
 
 }  // namespace tmlib
 
@@ -58,13 +62,21 @@ struct tm_library {
     int32_t n_bands = 0;
     int32_t band_rows = 0;      // max rows per band
     int32_t row_width = 0;      // LDS row width in floats
+    bool narrow = false;        // narrow rows with per-pixel wrap classes
+    int32_t n_cls = 1;          // record classes per (group, band): K if narrow, else 1
     int64_t n_spots = 0;        // merged pixels over all T' templates
+    int32_t group = 1;          // templates per group (1 or 3)
+    int32_t n_groups = 0;
+    int64_t n_records = 0;      // union pixels over all groups and bands
 
     // device arrays
     int32_t* d_rows = nullptr;      // [n_rows] global row of each touched row
     int32_t* d_band_off = nullptr;  // [n_bands + 1] first touched-row index of each band
-    uint2* d_spots = nullptr;       // [n_spots] (LDS float offset within band, weight bits)
-    int32_t* d_seg = nullptr;       // [Tp * (n_bands + 1)] spot ranges per (template, band)
+    uint32_t* d_recs = nullptr;     // [n_records * (group + 1)]: LDS float offset within the
+                                    // band, then one float32 weight per group member
+    int32_t* d_seg = nullptr;       // [n_groups * n_bands * n_cls + 1] first record of each
+                                    // (group, band, class) segment; the next entry ends it
+    int32_t* d_members = nullptr;   // [n_groups * group] template index of each member, -1 = none
     float* d_prof = nullptr;        // [T, R] radial profiles of base templates (float32)
     float* d_prof_norm = nullptr;   // [T] L2 norm of each profile (float32 of float64)
     size_t device_bytes = 0;

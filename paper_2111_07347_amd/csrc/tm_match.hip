@@ -14,15 +14,19 @@
 //   * Lanes are shifts: lane l, slot k holds C(l + 64 k); a spot costs one
 //     address add, K = ceil(n_theta / 64) conflict-free ds_read_b32 (64
 //     consecutive floats each) and K FMAs with the spot weight from SGPRs.
-//   * Template spots (offset, weight) are streamed with scalar loads.
+//   * Templates that share polar pixels are scored together in groups of G:
+//     the library stores per group one record per union pixel (LDS offset
+//     and one weight per member, zero if the member lacks the pixel), so a
+//     pixel shared by several members is read from LDS once and feeds G*K
+//     FMAs. Records are streamed with scalar loads.
 //   * Per template the wave takes the lane-wise maximum and skips the rest
 //     unless some lane beats the wave's current N-th best score (the
 //     common case once the running list fills). Only then does it do the
 //     cross-lane reduction and the first-maximum search, and insert into a
 //     per-wave top-N held in lanes 0..N-1.
 //   * When the touched rows exceed the LDS budget, they are processed in
-//     bands: each wave keeps G templates' accumulators in registers while
-//     the workgroup streams the bands through LDS.
+//     bands: each wave keeps M groups' accumulators in registers while the
+//     workgroup streams the bands through LDS.
 //   * At the end the waves' lists are merged by wave 0 in LDS.
 //
 // Ranking order is Q descending, ties to the lower template index; within a
@@ -38,27 +42,90 @@
 
 namespace {
 
-constexpr int kMatchThreads = 512;
-constexpr int kWaves = kMatchThreads / 64;
+// Waves per workgroup: 8 when several workgroups share a CU, 16 when one
+// workgroup holds (nearly) all of a CU's LDS.
+constexpr int kWavesShared = 8;
+constexpr int kWavesWhole = 16;
+constexpr size_t kWholeCuLds = 80 * 1024;
 
-template <int K>
-__device__ __forceinline__ void finalize(const float (&acc)[K], float lastpen, int t, int lane,
-                                         float invP, int N, tmlib::TopState& st, bool write_all,
-                                         float* __restrict__ best_q, short* __restrict__ best_s,
-                                         size_t best_off) {
-    // lane-wise maximum over valid slots (only the last slot can be partial)
-    float m = (K == 1) ? acc[0] + lastpen : acc[0];
+// One union pixel of a group: LDS float offset within the band, then one
+// weight per group member.
+template <int G>
+struct Rec {
+    uint32_t off;
+    float w[G];
+};
+
+// Accumulate records [i0, i1): every lane adds w * P[col + lane + 64 k] for
+// its K shift slots. Slots k < CLS read from the pixel's column, the others
+// (narrow rows only) one period back, where the row's wraparound continues.
+template <int K, int G, int CLS>
+__device__ __forceinline__ void accumulate(const Rec<G>* __restrict__ rec, int i0, int i1,
+                                           const float* lds, int lane, int n_theta,
+                                           float (&acc)[G][K]) {
+    int i = i0;
+    // four records per step: their scalar loads and LDS reads are all in
+    // flight before the first FMA
+    for (; i + 4 <= i1; i += 4) {
+        Rec<G> r[4];
+        float v[4][K];
 #pragma unroll
-    for (int k = 1; k < K; ++k) m = fmaxf(m, (k == K - 1) ? acc[k] + lastpen : acc[k]);
-    const float q = m * invP;
-    if (!write_all && !tmlib::ballot(q > st.thr)) return;
-    const float wm = tmlib::wave_max(m);
+        for (int u = 0; u < 4; ++u) r[u] = rec[i + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float* pa = lds + r[u].off + lane;
+            const float* pb = pa - n_theta;
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[u][k] = (k < CLS) ? pa[64 * k] : pb[64 * k];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int k = 0; k < K; ++k) acc[g][k] = fmaf(r[u].w[g], v[u][k], acc[g][k]);
+    }
+    for (; i < i1; ++i) {
+        const Rec<G> r = rec[i];
+        const float* pa = lds + r.off + lane;
+        const float* pb = pa - n_theta;
+        float v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = (k < CLS) ? pa[64 * k] : pb[64 * k];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[g][k] = fmaf(r.w[g], v[k], acc[g][k]);
+    }
+}
+
+// Records of one (group, band): one segment on wide rows, K class segments
+// (CLS = 1..K) on narrow rows.
+template <int K, int G, bool NARROW, int CLS = 1>
+__device__ __forceinline__ void accumulate_segments(const Rec<G>* __restrict__ rec,
+                                                    const int* __restrict__ sg, const float* lds,
+                                                    int lane, int n_theta, float (&acc)[G][K]) {
+    if constexpr (!NARROW) {
+        accumulate<K, G, K>(rec, sg[0], sg[1], lds, lane, n_theta, acc);
+    } else {
+        accumulate<K, G, CLS>(rec, sg[CLS - 1], sg[CLS], lds, lane, n_theta, acc);
+        if constexpr (CLS < K) accumulate_segments<K, G, true, CLS + 1>(rec, sg, lds, lane, n_theta, acc);
+    }
+}
+
+// Full reduction of one template whose lane maximum may enter the list: the
+// wave maximum, its first (smallest) shift, and the insertion.
+template <int K>
+__device__ __forceinline__ void finalize_slow(const float (&acc)[K], float mx, int t, int lane,
+                                              float invP, int N, tmlib::TopState& st,
+                                              bool write_all, float* __restrict__ best_q,
+                                              short* __restrict__ best_s, size_t best_off) {
+    const float wm = tmlib::wave_max(mx);
     int s = 0;
     bool found = false;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const float v = (k == K - 1) ? acc[k] + lastpen : acc[k];
-        const unsigned long long msk = tmlib::ballot(v == wm);
+        const unsigned long long msk = tmlib::ballot(acc[k] == wm);
         if (!found && msk) {
             s = 64 * k + __ffsll(static_cast<long long>(msk)) - 1;
             found = true;
@@ -69,27 +136,36 @@ __device__ __forceinline__ void finalize(const float (&acc)[K], float lastpen, i
         best_q[best_off + t] = Q;
         best_s[best_off + t] = static_cast<short>(s);
     }
-    if (!(Q > st.thr)) return;
-    tmlib::topn_insert(st, Q, t, s, lane, N);
+    if (tmlib::topn_beats(st, Q, t)) tmlib::topn_insert(st, Q, t, s, lane, N);
 }
 
-template <int K, int G>
-__global__ void __launch_bounds__(kMatchThreads)
+template <int K>
+__device__ __forceinline__ float lane_max(const float (&acc)[K]) {
+    float m = acc[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k) m = fmaxf(m, acc[k]);
+    return m;
+}
+
+template <int K, int G, int M, bool NARROW, int NW>
+__global__ void __launch_bounds__(NW * 64)
 match_kernel(const float* __restrict__ polar, const double* __restrict__ norms, int R,
              int n_theta, const int* __restrict__ rows, const int* __restrict__ band_off,
-             int n_bands, int row_width, const uint2* __restrict__ spots,
-             const int* __restrict__ seg, int Tp, int N, int* __restrict__ top_t,
-             int* __restrict__ top_s, float* __restrict__ top_q, float* __restrict__ best_q,
-             short* __restrict__ best_s) {
+             int n_bands, int row_width, const uint32_t* __restrict__ recs,
+             const int* __restrict__ seg, const int* __restrict__ members, int n_groups, int Tp,
+             int N, int* __restrict__ top_t, int* __restrict__ top_s, float* __restrict__ top_q,
+             float* __restrict__ best_q, short* __restrict__ best_s) {
     extern __shared__ float lds[];
+    constexpr int NCLS = NARROW ? K : 1;
     const int b = blockIdx.x;
     const int lane = threadIdx.x & 63;
     const int wave = tmlib::uniform(threadIdx.x >> 6);
     const float* src = polar + static_cast<size_t>(b) * R * n_theta;
+    const Rec<G>* rec = reinterpret_cast<const Rec<G>*>(recs);
 
     auto stage = [&](int band) {
         const int r0 = band_off[band], r1 = band_off[band + 1];
-        for (int r = r0 + wave; r < r1; r += kWaves) {
+        for (int r = r0 + wave; r < r1; r += NW) {
             const float* row = src + static_cast<size_t>(rows[r]) * n_theta;
             float* dst = lds + (r - r0) * row_width;
             for (int c = lane; c < row_width; c += 64) {
@@ -102,22 +178,33 @@ match_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
 
     const double pn = norms[b];
     const float invP = pn > 0.0 ? static_cast<float>(1.0 / pn) : 0.0f;
-    const float lastpen = (64 * (K - 1) + lane < n_theta) ? 0.0f : -INFINITY;
+    // the last slot of lanes past n_theta holds no shift: start it at -inf
+    const float lastinit = (64 * (K - 1) + lane < n_theta) ? 0.0f : -INFINITY;
     const bool write_all = best_q != nullptr;
     const size_t best_off = static_cast<size_t>(b) * Tp;
-    tmlib::TopState st{-INFINITY, INT_MAX, 0, 0, -INFINITY};
+    tmlib::TopState st = tmlib::topn_init();
 
     if (n_bands == 1) {
         stage(0);
         __syncthreads();
     }
-    for (int c0 = 0; c0 < Tp; c0 += kWaves * G) {
-        const int tb = c0 + wave * G;
-        float acc[G][K];
+    for (int c0 = 0; c0 < n_groups; c0 += NW * M) {
+        const int gb = c0 + wave * M;
+        int mem[M][G];
 #pragma unroll
-        for (int g = 0; g < G; ++g)
+        for (int m = 0; m < M; ++m)
 #pragma unroll
-            for (int k = 0; k < K; ++k) acc[g][k] = 0.0f;
+            for (int g = 0; g < G; ++g)
+                mem[m][g] = (gb + m < n_groups) ? members[static_cast<size_t>(gb + m) * G + g] : -1;
+        float acc[M][G][K];
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+#pragma unroll
+                for (int k = 0; k < K - 1; ++k) acc[m][g][k] = 0.0f;
+                acc[m][g][K - 1] = lastinit;
+            }
         for (int band = 0; band < n_bands; ++band) {
             if (n_bands > 1) {
                 __syncthreads();
@@ -125,59 +212,95 @@ match_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
                 __syncthreads();
             }
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int t = tb + g;
-                if (t < Tp) {
-                    const int* sg = seg + static_cast<size_t>(t) * (n_bands + 1) + band;
-                    const int i0 = sg[0], i1 = sg[1];
-                    for (int i = i0; i < i1; ++i) {
-                        const uint2 sp = spots[i];
-                        const float w = __uint_as_float(sp.y);
-                        const float* p = lds + sp.x + lane;
-#pragma unroll
-                        for (int k = 0; k < K; ++k) acc[g][k] = fmaf(w, p[64 * k], acc[g][k]);
-                    }
+            for (int m = 0; m < M; ++m) {
+                const int grp = gb + m;
+                if (grp < n_groups) {
+                    const int* sg = seg + (static_cast<size_t>(grp) * n_bands + band) * NCLS;
+                    accumulate_segments<K, G, NARROW>(rec, sg, lds, lane, n_theta, acc[m]);
                 }
             }
         }
+        // a template needs the full reduction only if some lane's maximum
+        // can enter the wave's list; test all members before branching
+        float mx[M][G];
+        unsigned long long any = 0;
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int t = tb + g;
-            if (t < Tp)
-                finalize<K>(acc[g], lastpen, t, lane, invP, N, st, write_all, best_q, best_s,
-                            best_off);
-        }
+        for (int m = 0; m < M; ++m)
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                mx[m][g] = lane_max<K>(acc[m][g]);
+                const int t = mem[m][g];
+                const float q = mx[m][g] * invP;
+                const bool tie_wins = t < st.thr_t;
+                const bool hit = tie_wins ? (q >= st.thr) : (q > st.thr);
+                any |= (t >= 0) ? tmlib::ballot(hit) : 0ull;
+            }
+        if (!any && !write_all) continue;
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int t = mem[m][g];
+                if (t < 0) continue;
+                const float q = mx[m][g] * invP;
+                if (!write_all && !tmlib::ballot(tmlib::topn_beats(st, q, t))) continue;
+                finalize_slow<K>(acc[m][g], mx[m][g], t, lane, invP, N, st, write_all, best_q,
+                                 best_s, best_off);
+            }
     }
 
     __syncthreads();
-    tmlib::topn_merge_write<kWaves>(st, lds, wave, lane, N, top_t + static_cast<size_t>(b) * N,
-                                 top_s + static_cast<size_t>(b) * N,
-                                 top_q + static_cast<size_t>(b) * N);
+    tmlib::topn_merge_write<NW>(st, lds, wave, lane, N, top_t + static_cast<size_t>(b) * N,
+                                    top_s + static_cast<size_t>(b) * N,
+                                    top_q + static_cast<size_t>(b) * N);
 }
 
 using MatchFn = void (*)(const float*, const double*, int, int, const int*, const int*, int, int,
-                         const uint2*, const int*, int, int, int*, int*, float*, float*, short*);
+                         const uint32_t*, const int*, const int*, int, int, int, int*, int*,
+                         float*, float*, short*);
 
-template <int K>
-MatchFn pick(bool multi) {
-    if (!multi) return match_kernel<K, 1>;
-    return K <= 6 ? match_kernel<K, 8> : match_kernel<K, 4>;
+// Groups held per wave while rows stream through LDS in bands.
+template <int K, int G>
+constexpr int multi_groups() { return G == 3 ? (K <= 6 ? 2 : 1) : (K <= 6 ? 8 : 4); }
+
+template <int K, int NW>
+MatchFn pick(int G, bool multi, bool narrow) {
+    if constexpr (K <= tmlib::kMaxNarrowSlots) {
+        if (narrow) {
+            if (G == 3) return multi ? match_kernel<K, 3, multi_groups<K, 3>(), true, NW>
+                                     : match_kernel<K, 3, 1, true, NW>;
+            return multi ? match_kernel<K, 1, multi_groups<K, 1>(), true, NW>
+                         : match_kernel<K, 1, 1, true, NW>;
+        }
+        if (multi) return nullptr;   // multi-band libraries with K <= 6 use narrow rows
+    } else {
+        if (narrow) return nullptr;
+        if (multi) return G == 3 ? match_kernel<K, 3, multi_groups<K, 3>(), false, NW>
+                                 : match_kernel<K, 1, multi_groups<K, 1>(), false, NW>;
+    }
+    return G == 3 ? match_kernel<K, 3, 1, false, NW> : match_kernel<K, 1, 1, false, NW>;
 }
 
-MatchFn select_kernel(int K, bool multi) {
+template <int K>
+MatchFn pick_nw(int G, bool multi, bool narrow, int nw) {
+    return nw == kWavesWhole ? pick<K, kWavesWhole>(G, multi, narrow)
+                             : pick<K, kWavesShared>(G, multi, narrow);
+}
+
+MatchFn select_kernel(int K, int G, bool multi, bool narrow, int nw) {
     switch (K) {
-        case 1: return pick<1>(multi);
-        case 2: return pick<2>(multi);
-        case 3: return pick<3>(multi);
-        case 4: return pick<4>(multi);
-        case 5: return pick<5>(multi);
-        case 6: return pick<6>(multi);
-        case 7: return pick<7>(multi);
-        case 8: return pick<8>(multi);
-        case 9: return pick<9>(multi);
-        case 10: return pick<10>(multi);
-        case 11: return pick<11>(multi);
-        case 12: return pick<12>(multi);
+        case 1: return pick_nw<1>(G, multi, narrow, nw);
+        case 2: return pick_nw<2>(G, multi, narrow, nw);
+        case 3: return pick_nw<3>(G, multi, narrow, nw);
+        case 4: return pick_nw<4>(G, multi, narrow, nw);
+        case 5: return pick_nw<5>(G, multi, narrow, nw);
+        case 6: return pick_nw<6>(G, multi, narrow, nw);
+        case 7: return pick_nw<7>(G, multi, narrow, nw);
+        case 8: return pick_nw<8>(G, multi, narrow, nw);
+        case 9: return pick_nw<9>(G, multi, narrow, nw);
+        case 10: return pick_nw<10>(G, multi, narrow, nw);
+        case 11: return pick_nw<11>(G, multi, narrow, nw);
+        case 12: return pick_nw<12>(G, multi, narrow, nw);
         default: return nullptr;
     }
 }
@@ -222,19 +345,21 @@ extern "C" int tm_match_batch(const tm_library* lib, const float* polar, const d
 
     const int K = tmlib::slots_for(lib->n_theta);
     const bool multi = lib->n_bands > 1;
-    MatchFn fn = select_kernel(K, multi);
-    if (!fn) { tmlib::set_error("n_theta=%d not supported", lib->n_theta); return TM_EUNSUPPORTED; }
     const size_t pattern_bytes = static_cast<size_t>(std::max(lib->band_rows, 1)) * lib->row_width * sizeof(float);
-    const size_t merge_bytes = tmlib::topn_merge_bytes(kWaves, N);
+    const int nw = (!multi && pattern_bytes > kWholeCuLds) ? kWavesWhole : kWavesShared;
+    MatchFn fn = select_kernel(K, lib->group, multi, lib->narrow, nw);
+    if (!fn) { tmlib::set_error("n_theta=%d not supported", lib->n_theta); return TM_EUNSUPPORTED; }
+    const size_t merge_bytes = tmlib::topn_merge_bytes(nw, N);
     const size_t lds_bytes = std::max(pattern_bytes, merge_bytes);
     TM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                static_cast<int>(lds_bytes)));
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    hipLaunchKernelGGL(fn, dim3(B), dim3(kMatchThreads), lds_bytes, s, polar, norms, lib->R,
+    hipLaunchKernelGGL(fn, dim3(B), dim3(nw * 64), lds_bytes, s, polar, norms, lib->R,
                        lib->n_theta, lib->d_rows, lib->d_band_off, lib->n_bands, lib->row_width,
-                       lib->d_spots, lib->d_seg, lib->Tp, N, top_template, top_angle, top_score,
-                       best_score, reinterpret_cast<short*>(best_angle));
+                       lib->d_recs, lib->d_seg, lib->d_members, lib->n_groups, lib->Tp, N,
+                       top_template, top_angle, top_score, best_score,
+                       reinterpret_cast<short*>(best_angle));
     TM_HIP(hipGetLastError());
     return TM_OK;
 }

@@ -3,17 +3,24 @@
 // Fig. 2 c for the polar image; Eq. (1) for the image norm; Fig. 3 for the
 // azimuthal integral used by the pre-filter).
 //
-// Geometry is computed once per (H, W, grid) on the host in float64 and
-// cached on the device as a look-up table: per polar sample the integer base
-// pixel (x0, y0) = floor(x), floor(y) (or the nearest pixel) and the float32
-// fractions (x - x0, y - y0). The kernel then only gathers and blends, so the
-// float32 device path never recomputes cos/sin.
+// Sample coordinates are formed in float64 on the device from per-column
+// cos/sin tables built on the host (x = cx + r_j cos theta_k with separately
+// rounded multiply and add, bit-identical to the host's computation), then
+// split into the base pixel and float32 fractions; the float32 path never
+// evaluates trigonometry.
 //
-// Kernel layout: one workgroup per pattern, 8 waves; wave w owns polar rows
-// w, w + 8, ...; lane l owns columns l, l + 64, ... of the row, so the polar
-// writes are coalesced along theta. Row sums (profile) are reduced across the
-// wave in float64; the float64 sum of squares is reduced wave by wave and
-// then across waves in a fixed order, so norms are bit-reproducible.
+// Kernel layout: one workgroup per pattern, 16 waves. The polar grid is cut
+// into blocks (angular sectors, and radial bands if needed) whose bilinear
+// tap footprint, clipped to the image plus a one-pixel zero ring, fits the
+// LDS budget; for a centred grid these are the four quadrants. Per block the
+// footprint is staged into LDS with coalesced row loads, the intensity
+// transform applied once per pixel and out-of-image pixels set to zero, so
+// the tap reads need no bounds checks. Half-waves own polar rows and their
+// lanes consecutive columns, so the polar writes are coalesced along theta.
+// Each lane accumulates float64 partial row sums (profile) and squares
+// (norm) in registers across blocks; rows are reduced once per half-wave and
+// the squares per wave and then across waves in a fixed order, so norms and
+// profiles are bit-reproducible.
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -33,116 +40,290 @@ struct LutKey {
     }
 };
 
-struct Lut {
-    short2* xy = nullptr;   // [R * n_theta] base pixel (x0, y0)
-    float2* f = nullptr;    // [R * n_theta] fractions (fx, fy)
+// One block of the polar grid: rows [j0, j1) x columns [k0, k1), with the
+// footprint box [x_lo, x_lo + bw) x [y_lo, y_lo + bh) staged in LDS with a
+// row pitch >= bw chosen so that a wave's taps along an arc spread over the
+// LDS banks.
+struct PolarBlock {
+    int j0, j1, k0, k1;
+    int x_lo, y_lo, bw, bh, pitch;
 };
+
+struct Lut {
+    PolarBlock* blocks = nullptr;   // device [n_blocks]
+    double2* cs = nullptr;          // device [n_theta] (cos theta_k, sin theta_k)
+    int n_blocks = 0;
+    int lds_floats = 0;             // max over blocks of bw * bh + bw + 2
+};
+
+// LDS budget for one block's footprint (two workgroups per CU).
+constexpr size_t kBoxBytes = 76 * 1024;
 
 std::mutex g_lut_mu;
 std::map<LutKey, Lut> g_luts;
+
+// Base pixel of a sample, computed exactly as the kernel does.
+struct Sample { int x0, y0; };
+
+// LDS row pitch for a block: among bw .. bw + 31 the one that minimises the
+// mean worst-bank load of the four taps over each half-wave of consecutive
+// columns (32 banks of 4 bytes; equal addresses broadcast), within the LDS
+// budget.
+template <typename BaseFn, typename InFn>
+int choose_pitch(const PolarBlock& B, BaseFn base_pixel, InFn inside, size_t max_floats) {
+    int best_p = B.bw;
+    double best_c = 1e30;
+    std::vector<int> addr;
+    for (int p = B.bw; p < B.bw + 32; ++p) {
+        if (static_cast<size_t>(p) * B.bh + p + 2 > max_floats) break;
+        double cost = 0.0;
+        for (int j = B.j0; j < B.j1; ++j) {
+            for (int k = B.k0; k < B.k1; k += 32) {
+                const int k_end = std::min(B.k1, k + 32);
+                for (int tap = 0; tap < 4; ++tap) {
+                    addr.clear();
+                    for (int kk = k; kk < k_end; ++kk) {
+                        const Sample q = base_pixel(j, kk);
+                        if (!inside(q)) continue;
+                        addr.push_back((q.y0 - B.y_lo + (tap >> 1)) * p + (q.x0 - B.x_lo + (tap & 1)));
+                    }
+                    std::sort(addr.begin(), addr.end());
+                    addr.erase(std::unique(addr.begin(), addr.end()), addr.end());
+                    int bank[32] = {0}, worst = 0;
+                    for (int a : addr) worst = std::max(worst, ++bank[a & 31]);
+                    cost += worst;
+                }
+            }
+        }
+        if (cost < best_c) { best_c = cost; best_p = p; }
+    }
+    return best_p;
+}
 
 int get_lut(const LutKey& key, hipStream_t s, Lut& out) {
     std::lock_guard<std::mutex> lock(g_lut_mu);
     auto it = g_luts.find(key);
     if (it != g_luts.end()) { out = it->second; return TM_OK; }
-    const size_t n = static_cast<size_t>(key.R) * key.n_theta;
-    std::vector<short2> xy(n);
-    std::vector<float2> f(n);
+    const int R = key.R, nt = key.n_theta;
+    std::vector<double2> cs(nt);
     const double two_pi = 2.0 * M_PI;
-    for (int j = 0; j < key.R; ++j) {
+    for (int k = 0; k < nt; ++k) {
+        const double th = two_pi * k / nt;
+        cs[k] = make_double2(std::cos(th), std::sin(th));
+    }
+    auto base_pixel = [&](int j, int k) {
         const double r = key.r0 + key.dr * j;
-        for (int k = 0; k < key.n_theta; ++k) {
-            const double th = two_pi * k / key.n_theta;
-            const double x = key.cx + r * std::cos(th);
-            const double y = key.cy + r * std::sin(th);
-            double x0, y0, fx, fy;
-            if (key.interp == 1) {
-                x0 = std::floor(x); y0 = std::floor(y);
-                fx = x - x0; fy = y - y0;
-            } else {
-                x0 = std::nearbyint(x); y0 = std::nearbyint(y);
-                fx = 0.0; fy = 0.0;
+        const double x = key.cx + r * cs[k].x;
+        const double y = key.cy + r * cs[k].y;
+        double x0 = key.interp == 1 ? std::floor(x) : std::nearbyint(x);
+        double y0 = key.interp == 1 ? std::floor(y) : std::nearbyint(y);
+        x0 = std::fmin(std::fmax(x0, -4.0), 40000.0);
+        y0 = std::fmin(std::fmax(y0, -4.0), 40000.0);
+        return Sample{static_cast<int>(x0), static_cast<int>(y0)};
+    };
+    // a sample contributes iff its 2x2 footprint touches the image
+    auto inside = [&](const Sample& q) {
+        return q.x0 >= -1 && q.x0 <= key.W - 1 && q.y0 >= -1 && q.y0 <= key.H - 1;
+    };
+    // smallest sector / band split whose every footprint box fits the budget
+    std::vector<PolarBlock> blocks;
+    const size_t max_floats = kBoxBytes / sizeof(float);
+    int lds_floats = 0;
+    for (int sk = 4, sj = 1;;) {
+        blocks.clear();
+        lds_floats = 0;
+        bool fits = true;
+        for (int bj = 0; bj < sj && fits; ++bj) {
+            for (int bk = 0; bk < sk && fits; ++bk) {
+                PolarBlock B{};
+                B.j0 = R * bj / sj; B.j1 = R * (bj + 1) / sj;
+                B.k0 = nt * bk / sk; B.k1 = nt * (bk + 1) / sk;
+                if (B.j0 == B.j1 || B.k0 == B.k1) continue;
+                int xl = INT32_MAX, xh = INT32_MIN, yl = INT32_MAX, yh = INT32_MIN;
+                for (int j = B.j0; j < B.j1; ++j)
+                    for (int k = B.k0; k < B.k1; ++k) {
+                        const Sample q = base_pixel(j, k);
+                        if (!inside(q)) continue;
+                        xl = std::min(xl, q.x0); xh = std::max(xh, q.x0 + 1);
+                        yl = std::min(yl, q.y0); yh = std::max(yh, q.y0 + 1);
+                    }
+                if (xl > xh) { xl = xh = yl = yh = 0; }   // block entirely outside
+                B.x_lo = xl; B.y_lo = yl; B.bw = xh - xl + 1; B.bh = yh - yl + 1;
+                B.pitch = choose_pitch(B, base_pixel, inside, max_floats);
+                const size_t need = static_cast<size_t>(B.pitch) * B.bh + B.pitch + 2;
+                if (need > max_floats) fits = false;
+                lds_floats = std::max(lds_floats, static_cast<int>(need));
+                blocks.push_back(B);
             }
-            // samples far outside the image read nothing: clamp to a
-            // position whose four taps are all out of range
-            x0 = std::fmin(std::fmax(x0, -2.0), 32767.0);
-            y0 = std::fmin(std::fmax(y0, -2.0), 32767.0);
-            xy[static_cast<size_t>(j) * key.n_theta + k] =
-                make_short2(static_cast<short>(x0), static_cast<short>(y0));
-            f[static_cast<size_t>(j) * key.n_theta + k] =
-                make_float2(static_cast<float>(fx), static_cast<float>(fy));
         }
+        if (fits) break;
+        if (sk < nt / 8) sk *= 2; else if (sj < R) sj *= 2;
+        else { tmlib::set_error("polar grid too large for the LDS blocking"); return TM_EUNSUPPORTED; }
     }
     Lut L;
-    hipError_t e = hipMalloc(&L.xy, n * sizeof(short2));
-    if (e == hipSuccess) e = hipMalloc(&L.f, n * sizeof(float2));
-    if (e != hipSuccess) {
-        hipFree(L.xy);
-        hipFree(L.f);
-        tmlib::set_error("polar LUT allocation failed: %s", hipGetErrorString(e));
+    L.n_blocks = static_cast<int>(blocks.size());
+    L.lds_floats = lds_floats;
+    hipError_t err = hipMalloc(&L.blocks, blocks.size() * sizeof(PolarBlock));
+    if (err == hipSuccess) err = hipMalloc(&L.cs, nt * sizeof(double2));
+    if (err != hipSuccess) {
+        hipFree(L.blocks); hipFree(L.cs);
+        tmlib::set_error("polar table allocation failed: %s", hipGetErrorString(err));
         return TM_ENOMEM;
     }
-    TM_HIP(hipMemcpyAsync(L.xy, xy.data(), n * sizeof(short2), hipMemcpyHostToDevice, s));
-    TM_HIP(hipMemcpyAsync(L.f, f.data(), n * sizeof(float2), hipMemcpyHostToDevice, s));
+    TM_HIP(hipMemcpyAsync(L.blocks, blocks.data(), blocks.size() * sizeof(PolarBlock), hipMemcpyHostToDevice, s));
+    TM_HIP(hipMemcpyAsync(L.cs, cs.data(), nt * sizeof(double2), hipMemcpyHostToDevice, s));
     TM_HIP(hipStreamSynchronize(s));   // host staging must outlive the copies
     g_luts[key] = L;
     out = L;
     return TM_OK;
 }
 
-template <typename Tin>
-__device__ __forceinline__ float tap(const Tin* __restrict__ img, int H, int W, int x, int y,
-                                     bool pw, float gamma, float sub) {
-    if (x < 0 || x >= W || y < 0 || y >= H) return 0.0f;   // zero padding
-    float v = static_cast<float>(img[y * W + x]);
-    if (pw) v = powf(fmaxf(v, 0.0f), gamma);
-    return v - sub;
+constexpr int kPolarThreads = 1024;
+constexpr int kPolarWaves = kPolarThreads / 64;
+constexpr int kRowsPerStep = 2 * kPolarWaves;   // each half-wave owns one row per step
+constexpr int kRowSteps = 4;                    // rows held per half-wave: a group of 128
+constexpr int kRowGroup = kRowsPerStep * kRowSteps;
+constexpr int kStageUnroll = 8;                 // independent loads in flight per thread
+
+// Sum over the 32 lanes of a half-wave (fixed tree, identical in every lane
+// of the half).
+__device__ __forceinline__ double half_wave_sum(double v) {
+#pragma unroll
+    for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m, 32);
+    return v;
 }
 
-constexpr int kPolarThreads = 512;
-
-template <typename Tin>
+// One workgroup per pattern. Rows are processed in groups of 128: for each
+// group every block's footprint is staged and its samples of the group's rows
+// are resampled. Half-wave h of wave w owns rows g0 + 32 i + 2 w + h (i < 4)
+// and its 32 lanes walk the block's columns, so stores are 128-byte runs and
+// each lane keeps float64 partial row sums in registers across blocks; a row
+// is reduced across its half-wave once.
+template <typename Tin, bool BILINEAR>
 __global__ void __launch_bounds__(kPolarThreads)
 polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
-             const short2* __restrict__ lut_xy, const float2* __restrict__ lut_f, int R,
-             int n_theta, float gamma, float sub, float* __restrict__ polar,
+             const PolarBlock* __restrict__ blocks, int n_blocks,
+             const double2* __restrict__ cs, double r0, double dr, double cx, double cy,
+             int R, int n_theta, float gamma, float sub, float* __restrict__ polar,
              double* __restrict__ norm_out, float* __restrict__ prof_out) {
-    __shared__ double partial[kPolarThreads / 64];
+    extern __shared__ double smem[];
+    double* partial = smem;                                   // [waves]
+    float* box = reinterpret_cast<float*>(smem + kPolarWaves);
     const int b = blockIdx.x;
-    const int lane = threadIdx.x & 63;
-    const int wave = tmlib::uniform(threadIdx.x >> 6);
-    const int nw = kPolarThreads / 64;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int half = lane >> 5;
+    const int col = lane & 31;
+    const int wave = tmlib::uniform(tid >> 6);
     const bool pw = gamma != 1.0f;
     const Tin* img = patterns + static_cast<size_t>(b) * H * W;
     float* out = polar + static_cast<size_t>(b) * R * n_theta;
     double sq = 0.0;
-    for (int j = wave; j < R; j += nw) {
-        double rs = 0.0;
-        for (int k = lane; k < n_theta; k += 64) {
-            const int i = j * n_theta + k;
-            const short2 p = lut_xy[i];
-            const float2 fr = lut_f[i];
-            const int x0 = p.x, y0 = p.y;
-            const float fx = fr.x, fy = fr.y;
-            const float p00 = tap(img, H, W, x0, y0, pw, gamma, sub);
-            const float p01 = tap(img, H, W, x0 + 1, y0, pw, gamma, sub);
-            const float p10 = tap(img, H, W, x0, y0 + 1, pw, gamma, sub);
-            const float p11 = tap(img, H, W, x0 + 1, y0 + 1, pw, gamma, sub);
-            const float gx = 1.0f - fx, gy = 1.0f - fy;
-            const float v = gx * gy * p00 + fx * gy * p01 + gx * fy * p10 + fx * fy * p11;
-            out[i] = v;
-            rs += static_cast<double>(v);
-            sq += static_cast<double>(v) * static_cast<double>(v);
+    for (int g0 = 0; g0 < R; g0 += kRowGroup) {
+        double rs[kRowSteps];
+#pragma unroll
+        for (int i = 0; i < kRowSteps; ++i) rs[i] = 0.0;
+        for (int bi = 0; bi < n_blocks; ++bi) {
+            const PolarBlock blk = blocks[bi];
+            if (blk.j1 <= g0 || blk.j0 >= g0 + kRowGroup) continue;   // uniform
+            const int bw = blk.bw, pitch = blk.pitch, total = blk.bw * blk.bh;
+            __syncthreads();
+            // stage the footprint (transform once per pixel, zero outside the
+            // image); element i = tid + 1024 m walks the box row-major, eight
+            // loads in flight per thread before the stores
+            {
+                const int step_y = kPolarThreads / bw, step_x = kPolarThreads - step_y * bw;
+                int yy = tid / bw, xx = tid - yy * bw;
+                for (int base = tid; base < total; base += kPolarThreads * kStageUnroll) {
+                    float v[kStageUnroll];
+                    int dst[kStageUnroll];
+                    bool in[kStageUnroll];
+#pragma unroll
+                    for (int u = 0; u < kStageUnroll; ++u) {
+                        const int y = blk.y_lo + yy, x = blk.x_lo + xx;
+                        const bool live = base + u * kPolarThreads < total;
+                        in[u] = live && y >= 0 && y < H && x >= 0 && x < W;
+                        dst[u] = live ? yy * pitch + xx : -1;
+                        v[u] = in[u] ? static_cast<float>(img[y * W + x]) : 0.0f;
+                        xx += step_x;
+                        yy += step_y;
+                        if (xx >= bw) { xx -= bw; ++yy; }
+                    }
+#pragma unroll
+                    for (int u = 0; u < kStageUnroll; ++u) {
+                        float t = v[u];
+                        if (in[u]) {
+                            if (pw) t = powf(fmaxf(t, 0.0f), gamma);
+                            t -= sub;
+                        }
+                        if (dst[u] >= 0) box[dst[u]] = t;
+                    }
+                }
+            }
+            const int zero_slot = pitch * blk.bh;   // pitch + 2 zeros follow the box
+            for (int i = tid; i < pitch + 2; i += kPolarThreads) box[zero_slot + i] = 0.0f;
+            __syncthreads();
+            const int nk = blk.k1 - blk.k0;
+            const int bwm = max(bw - 2, 0), bhm = max(blk.bh - 2, 0);
+            for (int c0 = 0; c0 < nk; c0 += 32) {
+                const int kk = c0 + col;
+                const bool col_ok = kk < nk;
+                const double2 c = cs[blk.k0 + (col_ok ? kk : 0)];
+#pragma unroll
+                for (int i = 0; i < kRowSteps; ++i) {
+                    const int j = g0 + i * kRowsPerStep + 2 * wave + half;
+                    if (!(col_ok && j >= blk.j0 && j < blk.j1)) continue;
+                    // x = cx + r cos, y = cy + r sin, multiply and add rounded
+                    // separately (no FMA contraction), exactly as the host
+                    // computed the footprint
+                    double r, x, y;
+                    {
+#pragma clang fp contract(off)
+                        r = r0 + dr * static_cast<double>(j);
+                        x = cx + r * c.x;
+                        y = cy + r * c.y;
+                    }
+                    const double xf = BILINEAR ? floor(x) : rint(x);
+                    const double yf = BILINEAR ? floor(y) : rint(y);
+                    const int x0 = static_cast<int>(fmin(fmax(xf, -4.0), 40000.0));
+                    const int y0 = static_cast<int>(fmin(fmax(yf, -4.0), 40000.0));
+                    const bool in = x0 >= -1 && x0 <= W - 1 && y0 >= -1 && y0 <= H - 1;
+                    // the clamp keeps every read inside the staged box
+                    const int o = in ? min(max(y0 - blk.y_lo, 0), bhm) * pitch +
+                                           min(max(x0 - blk.x_lo, 0), bwm)
+                                     : zero_slot;
+                    float v;
+                    if (BILINEAR) {
+                        const float fx = in ? static_cast<float>(x - xf) : 0.0f;
+                        const float fy = in ? static_cast<float>(y - yf) : 0.0f;
+                        const float p00 = box[o], p01 = box[o + 1];
+                        const float p10 = box[o + pitch], p11 = box[o + pitch + 1];
+                        const float gx = 1.0f - fx, gy = 1.0f - fy;
+                        v = gx * gy * p00 + fx * gy * p01 + gx * fy * p10 + fx * fy * p11;
+                    } else {
+                        v = box[o];
+                    }
+                    out[j * n_theta + blk.k0 + kk] = v;
+                    const double vd = static_cast<double>(v);
+                    rs[i] += vd;
+                    sq += vd * vd;
+                }
+            }
         }
-        rs = tmlib::wave_sum(rs);
-        if (prof_out && lane == 0) prof_out[static_cast<size_t>(j) * B + b] = static_cast<float>(rs);
+        // one reduction per row of the group
+#pragma unroll
+        for (int i = 0; i < kRowSteps; ++i) {
+            const double t = half_wave_sum(rs[i]);
+            const int j = g0 + i * kRowsPerStep + 2 * wave + half;
+            if (prof_out && col == 0 && j < R) prof_out[static_cast<size_t>(j) * B + b] = static_cast<float>(t);
+        }
     }
     sq = tmlib::wave_sum(sq);
     if (lane == 0) partial[wave] = sq;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += partial[w];
+        for (int w = 0; w < kPolarWaves; ++w) s += partial[w];
         norm_out[b] = sqrt(s);
     }
 }
@@ -173,15 +354,25 @@ extern "C" int tm_polar_transform(const void* patterns, tm_dtype dtype, int32_t 
     LutKey key{dev, H, W, grid->R, grid->n_theta, grid->interp, grid->r0, grid->dr, grid->cx, grid->cy};
     Lut lut;
     if (int r = get_lut(key, s, lut)) return r;
+    const size_t lds = static_cast<size_t>(kPolarWaves) * sizeof(double) +
+                       static_cast<size_t>(lut.lds_floats) * sizeof(float);
+    auto launch = [&](auto fn, auto ptr) -> int {
+        TM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+        hipLaunchKernelGGL(fn, dim3(B), dim3(kPolarThreads), lds, s, ptr, B, H, W, lut.blocks,
+                           lut.n_blocks, lut.cs, grid->r0, grid->dr, grid->cx, grid->cy, grid->R,
+                           grid->n_theta, gamma, subtract, polar_out, norm_out, profile_out);
+        return TM_OK;
+    };
+    int r = TM_OK;
     if (dtype == TM_F32) {
-        polar_kernel<float><<<B, kPolarThreads, 0, s>>>(
-            static_cast<const float*>(patterns), B, H, W, lut.xy, lut.f, grid->R, grid->n_theta,
-            gamma, subtract, polar_out, norm_out, profile_out);
+        const float* p = static_cast<const float*>(patterns);
+        r = grid->interp ? launch(polar_kernel<float, true>, p) : launch(polar_kernel<float, false>, p);
     } else {
-        polar_kernel<uint16_t><<<B, kPolarThreads, 0, s>>>(
-            static_cast<const uint16_t*>(patterns), B, H, W, lut.xy, lut.f, grid->R,
-            grid->n_theta, gamma, subtract, polar_out, norm_out, profile_out);
+        const uint16_t* p = static_cast<const uint16_t*>(patterns);
+        r = grid->interp ? launch(polar_kernel<uint16_t, true>, p) : launch(polar_kernel<uint16_t, false>, p);
     }
+    if (r) return r;
     TM_HIP(hipGetLastError());
     return TM_OK;
 }

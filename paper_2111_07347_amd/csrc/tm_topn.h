@@ -14,14 +14,25 @@ struct TopState {
     float q;     // lanes < cnt: entry score
     int t, s;    // entry template and angle
     int cnt;     // entries held (uniform)
-    float thr;   // score to beat (uniform); -inf until the list is full
+    float thr;   // N-th entry's score (uniform); -inf until the list is full
+    int thr_t;   // N-th entry's template (uniform); INT_MAX until full
 };
 
-// Insert (Q, t, s) into a wave's list. Callers pass templates in increasing
-// index order and only when Q beats the threshold, so every held entry with
-// an equal score has a lower index and stays ahead.
+__device__ __forceinline__ TopState topn_init() {
+    return TopState{-INFINITY, INT_MAX, 0, 0, -INFINITY, INT_MAX};
+}
+
+// True if (Q, t) ranks before the list's N-th entry: higher score, or equal
+// score and lower template index.
+__device__ __forceinline__ bool topn_beats(const TopState& st, float Q, int t) {
+    return Q > st.thr || (Q == st.thr && t < st.thr_t);
+}
+
+// Insert (Q, t, s) into a wave's list; callers only insert entries that
+// beat the N-th entry, in any template order.
 __device__ __forceinline__ void topn_insert(TopState& st, float Q, int t, int s, int lane, int N) {
-    const unsigned long long before = ballot(lane < st.cnt && st.q >= Q);
+    const unsigned long long before =
+        ballot(lane < st.cnt && (st.q > Q || (st.q == Q && st.t < t)));
     const int pos = __popcll(before);
     const float uq = __shfl_up(st.q, 1, 64);
     const int ut = __shfl_up(st.t, 1, 64);
@@ -30,6 +41,7 @@ __device__ __forceinline__ void topn_insert(TopState& st, float Q, int t, int s,
     if (lane == pos) { st.q = Q; st.t = t; st.s = s; }
     st.cnt = min(st.cnt + 1, N);
     st.thr = (st.cnt == N) ? __shfl(st.q, N - 1, 64) : -INFINITY;
+    st.thr_t = (st.cnt == N) ? __shfl(st.t, N - 1, 64) : INT_MAX;
 }
 
 inline size_t topn_merge_bytes(int waves, int N) {

@@ -28,19 +28,19 @@ topn_kernel(const float* __restrict__ best_q, const short* __restrict__ best_s, 
     const int hi = static_cast<int>((static_cast<long long>(T) * (wave + 1)) / kTopnWaves);
     const float* q_row = best_q + static_cast<size_t>(b) * T;
     const short* s_row = best_s + static_cast<size_t>(b) * T;
-    tmlib::TopState st{-INFINITY, INT_MAX, 0, 0, -INFINITY};
+    tmlib::TopState st = tmlib::topn_init();
     for (int base = lo; base < hi; base += 64) {
         const int t = base + lane;
         const bool ok = t < hi;
         const float q = ok ? q_row[t] : -INFINITY;
         const int s = ok ? s_row[t] : 0;
-        unsigned long long msk = tmlib::ballot(ok && (st.cnt < N || q > st.thr));
+        unsigned long long msk = tmlib::ballot(ok && (st.cnt < N || tmlib::topn_beats(st, q, t)));
         while (msk) {
             const int l = __ffsll(static_cast<long long>(msk)) - 1;
             msk &= msk - 1;
             const float Q = __shfl(q, l, 64);
             const int S = __shfl(s, l, 64);
-            if (st.cnt < N || Q > st.thr) tmlib::topn_insert(st, Q, base + l, S, lane, N);
+            if (st.cnt < N || tmlib::topn_beats(st, Q, base + l)) tmlib::topn_insert(st, Q, base + l, S, lane, N);
         }
     }
     tmlib::topn_merge_write<kTopnWaves>(st, lds, wave, lane, N, top_t + static_cast<size_t>(b) * N,

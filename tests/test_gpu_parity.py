@@ -34,10 +34,11 @@ def _olib(lib, cfg, **kw):
 
 
 def _run(tm, lib_np, imgs, grid, px_per, N, gamma=1.0, subtract=0.0, with_best=False,
-         mirror=True, unit=False):
+         mirror=True, unit=False, grouping=True):
     import torch
     lib = tm.Library(lib_np["kx"], lib_np["ky"], lib_np["intensity"], lib_np["offsets"], px_per,
-                     grid, mirror=mirror, unit_intensity=unit)
+                     grid, mirror=mirror, unit_intensity=unit, grouping=grouping)
+    _say("layout", lib.layout())
     x = torch.from_numpy(np.ascontiguousarray(imgs)).cuda()
     polar, norms, prof = tm.polar_transform(x, grid, gamma, subtract)
     out = tm.match_batch(lib, polar, norms, N, with_best=with_best)
@@ -105,12 +106,16 @@ def test_polar_options(tm, case):
 
 
 # --------------------------------------------------------------------------- match
-def test_match_c1_full(tm, c1, c1_lib, c1_olib):
-    _say("match c1 full B=64 T'=600 N=5")
+@pytest.mark.parametrize("grouping", [True, False])
+def test_match_c1_full(tm, c1, c1_lib, c1_olib, grouping):
+    _say("match c1 full B=64 T'=600 N=5 grouping", grouping)
     imgs = synth.make_patterns(c1, c1_lib, range(64))
     grid = _grid_for(tm, c1)
-    _, polar, norms, _, (tt, ts, tq, bq, bs) = _run(tm, c1_lib, imgs, grid,
-                                                     synth.px_per_inv_A(c1), 5, with_best=True)
+    lib, polar, norms, _, (tt, ts, tq, bq, bs) = _run(tm, c1_lib, imgs, grid,
+                                                       synth.px_per_inv_A(c1), 5, with_best=True,
+                                                       grouping=grouping)
+    lay = lib.layout()
+    assert lay["group"] == (3 if grouping else 1) and lay["n_bands"] == 1 and not lay["narrow"]
     exact_contract = exact_tight = 0
     for b in range(64):
         P = oracle.polar64(imgs[b], c1.R, c1.n_theta)
@@ -173,35 +178,45 @@ def test_match_theta_widths(tm, n_theta):
         assert scores_close(bq[b], ref.best).all()
 
 
-def test_match_multiband_synthetic(tm):
-    """Spots spread over most of 128 rows: the library is processed in LDS
-    bands with per-wave accumulators held across bands."""
-    R, nt = 128, 360
+@pytest.mark.parametrize("n_theta,grouping", [(360, True), (360, False), (720, True),
+                                              (720, False)])
+def test_match_multiband_synthetic(tm, n_theta, grouping):
+    """Spots spread over most of 128 rows: the rows do not fit LDS at once and
+    stream through it in bands (narrow rows for 360 columns, wide rows for
+    720), each wave holding several groups' accumulators across bands."""
+    R = 128
     lib = small_library(300, seed=99, max_spots=40, g_max=1.2, g_min=0.05)
     px = (R - 4) / 1.2
     rng = np.random.default_rng(100)
     imgs = rng.random((6, 256, 256)).astype(np.float32)
-    _say("multi-band synthetic T=300 R=128", imgs.shape)
-    grid = tm.PolarGrid(R=R, n_theta=nt, cx=128.0, cy=128.0)
-    olib = oracle.OracleLibrary.build(lib, px, R, nt)
-    tml, _, _, _, (tt, ts, tq, bq, bs) = _run(tm, lib, imgs, grid, px, 8, with_best=True)
+    _say("multi-band synthetic T=300 R=128 n_theta", n_theta, "grouping", grouping, imgs.shape)
+    grid = tm.PolarGrid(R=R, n_theta=n_theta, cx=128.0, cy=128.0)
+    olib = oracle.OracleLibrary.build(lib, px, R, n_theta)
+    tml, _, _, _, (tt, ts, tq, bq, bs) = _run(tm, lib, imgs, grid, px, 8, with_best=True,
+                                              grouping=grouping)
+    lay = tml.layout()
+    assert lay["n_bands"] > 1 and lay["narrow"] == (n_theta <= 384)
     for b in range(6):
-        P = oracle.polar64(imgs[b], R, nt)
+        P = oracle.polar64(imgs[b], R, n_theta)
         ref = PatternRef(P, olib)
         check_topn(ref, tt[b], ts[b], tq[b], margin=1e-4, tight=True)
         assert scores_close(bq[b], ref.best).all()
 
 
-def test_match_c3_library_multiband(tm):
-    """The 20 000-template orthorhombic library (93 touched rows) on three
-    patterns of the precision-form scan."""
+@pytest.mark.parametrize("grouping", [True, False])
+def test_match_c3_library(tm, grouping):
+    """The 20 000-template orthorhombic library (93 touched rows, one band of
+    narrow rows) on three patterns of the precision-form scan."""
     cfg = synth.CONFIGS[3]
     lib = synth.make_library(3)
     imgs = synth.make_patterns(cfg, lib, [0, 4096, 16383])
-    _say("c3 library, 3 patterns, T'=40000")
+    _say("c3 library, 3 patterns, T'=40000, grouping", grouping)
     grid = _grid_for(tm, cfg)
     olib = _olib(lib, cfg)
-    _, _, _, _, (tt, ts, tq) = _run(tm, lib, imgs, grid, synth.px_per_inv_A(cfg), 5)
+    tml, _, _, _, (tt, ts, tq) = _run(tm, lib, imgs, grid, synth.px_per_inv_A(cfg), 5,
+                                      grouping=grouping)
+    lay = tml.layout()
+    assert lay["n_bands"] == 1 and lay["narrow"] and lay["group"] == (3 if grouping else 1)
     for b in range(3):
         P = oracle.polar64(imgs[b], cfg.R, cfg.n_theta)
         ref = PatternRef(P, olib)
