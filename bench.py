@@ -55,6 +55,25 @@ def parse():
     return ap.parse_args()
 
 
+def recorded_traffic(cid, kernel_prefix):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    record (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings), or
+    None if the record is missing or any kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_config{cid}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    for f, h in rec["sources"].items():
+        src = os.path.join(ROOT, "paper_2111_07347_amd", "csrc", f)
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != h:
+            return None
+    for k, v in rec["traffic_bytes_per_launch"].items():
+        if k.startswith(kernel_prefix):
+            return v["fetch_bytes"] + v["write_bytes"]
+    return None
+
+
 def oracle_baseline(cfg, lib_np, n_sample, procs):
     """FP64 oracle patterns/s on a bounded sample (patterns p = 0 mod 64)."""
     os.environ.setdefault("OMP_NUM_THREADS", "1")
@@ -157,15 +176,18 @@ def main():
         "peak": LDS_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(match_gbs / LDS_PEAK_GBS, 4),
-        "traffic": None,
-        "work_per_launch": {"fma": macs, "lds_operand_bytes": lds_bytes},
+        "traffic": recorded_traffic(a.config, "match_kernel"),
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+        "work_per_launch": {"fma": macs, "lds_operand_bytes": lds_bytes,
+                            "lds_records": float(B) * layout["n_records"]},
         "alu": {"achieved_tflops": round(2 * macs / (match_ms * 1e-3) / 1e12, 3),
                 "peak_tflops": FMA_PEAK_TFLOPS,
                 "frac": round(2 * macs / (match_ms * 1e-3) / 1e12 / FMA_PEAK_TFLOPS, 4)},
         "polar": {"bound": "hbm", "ms": round(polar_ms, 4),
                   "achieved": round(polar_bytes / (polar_ms * 1e-3) / 1e9, 1),
                   "peak": HBM_PEAK_GBS,
-                  "frac": round(polar_bytes / (polar_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+                  "frac": round(polar_bytes / (polar_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                  "traffic": recorded_traffic(a.config, "polar_kernel")},
     }
 
     ms_per_step = wall / a.steps * 1e3
