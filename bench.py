@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-grouping", action="store_true",
                     help="score every template on its own (no shared-pixel groups)")
+    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp16", "fp8", "none"],
+                    help="arithmetic of the pre-filtered path timed beside the plain path")
+    ap.add_argument("--keep", type=float, default=0.1,
+                    help="fraction of base templates the pre-filter keeps")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy three times (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -192,6 +196,41 @@ def main():
 
     ms_per_step = wall / a.steps * 1e3
     value = B * a.steps / wall
+    plain_top = [o.clone() for o in out]
+
+    # the precision form: pre-filter in reduced precision, exact rescoring
+    prec_path = None
+    if a.precision != "none":
+        def step_p(ev=None):
+            if ev is not None:
+                ev[0].record(stream)
+            tm.polar_transform(x, grid, polar_out=polar, norm_out=norms, profile_out=prof)
+            if ev is not None:
+                ev[1].record(stream)
+            tm.match_batch(lib, polar, norms, N, profiles=prof, prefilter_keep=a.keep,
+                           prefilter_prec=a.precision, out=out)
+            if ev is not None:
+                ev[2].record(stream)
+        for _ in range(a.warmup):
+            step_p()
+        pevs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(a.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(a.steps):
+            step_p(pevs[i])
+        torch.cuda.synchronize()
+        pwall = time.perf_counter() - t0
+        pre_top = [o.clone() for o in out]
+        same_t1 = float((pre_top[0][:, 0] == plain_top[0][:, 0]).float().mean().item())
+        prec_path = {
+            "value": round(B * a.steps / pwall, 1), "unit": "patterns/s",
+            "ms_per_step": round(pwall / a.steps * 1e3, 4),
+            "precision": a.precision, "keep_fraction": a.keep,
+            "prefilter_and_rescore_ms": round(float(np.mean([e[1].elapsed_time(e[2]) for e in pevs])), 4),
+            "top1_agreement_vs_fp32_path": same_t1,
+        }
+        print(f"[bench] precision path {a.precision}: {pwall / a.steps * 1e3:.2f} ms/step, "
+              f"top-1 agreement with the plain path {same_t1:.4f}", file=sys.stderr, flush=True)
 
     cpu = None
     top1 = None
@@ -202,8 +241,11 @@ def main():
                "kind": "oracle",
                "sample": f"{len(idx)} patterns (index = 0 mod {max(1, cfg.B // len(idx))}) of "
                          f"the same workload, FP64 NumPy, {procs} processes"}
-        gt = out[0].cpu().numpy()
+        gt = plain_top[0].cpu().numpy()
         top1 = float(np.mean(gt[idx, 0] == ot[:, 0]))
+        if prec_path is not None:
+            pt = pre_top[0].cpu().numpy()
+            prec_path["top1_agreement_vs_oracle_on_sample"] = float(np.mean(pt[idx, 0] == ot[:, 0]))
 
     line = {
         "metric": METRIC,
@@ -229,6 +271,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "top1_agreement_vs_oracle_on_sample": top1,
+        "precision_path": prec_path,
         "kernel_ms": {"polar_transform": round(polar_ms, 4), "match_kernel": round(match_ms, 4)},
     }
     print(json.dumps(line), flush=True)

@@ -104,7 +104,8 @@ enum {
  *   prefilter_keep    fraction f of base templates kept by the azimuthal
  *                     pre-filter (Section 2.2, Fig. 3), 0 = no pre-filter;
  *                     the kept ceil(f*T) base templates (and their mirrors)
- *                     are then scored exactly in float32.
+ *                     are then scored exactly in float32 (tm_prefilter
+ *                     followed by tm_match_candidates).
  *   prefilter_prec    arithmetic of the pre-filter's profile correlation
  *                     (FP32, BF16, FP16 or FP8 on the matrix cores with
  *                     float32 accumulation).
@@ -243,6 +244,50 @@ int tm_match_batch(const tm_library* lib, const float* polar, const double* norm
                    const float* profiles, int32_t B, const tm_match_opts* opts, int32_t N,
                    int32_t* top_template, int32_t* top_angle, float* top_score,
                    float* best_score, int16_t* best_angle, void* hip_stream);
+
+/* tm_prefilter - the library pre-filter of Section 2.2 (Fig. 3): pattern and
+ * template are integrated over the azimuth and correlated by one matrix
+ * product; the best-correlating templates are kept for the full search.
+ *
+ *   score[b, t] = sum_j prof_T[t, j] * profiles[j*B + b]
+ *
+ * prof_T is template t's radial profile (per polar row, the sum of its merged
+ * pixel weights) scaled to unit length, so ranking a pattern's scores ranks
+ * the cosine between the two profiles. The product runs in `precision`
+ * (TM_PREC_FP32, BF16, FP16 or FP8 e4m3 with every template profile and every
+ * pattern profile scaled to maximum 1) with float32 accumulation. Per pattern
+ * the n_keep base templates with the largest scores are kept, ties to the
+ * lower template index, and written in ascending index order.
+ *
+ * Arguments
+ *   lib        loaded library (its base templates 0..T-1 are ranked; mirrors
+ *              share their base template's profile).
+ *   profiles   device, [R, B] float32 (tm_polar_transform's profile_out).
+ *   B          >= 0 (0 is a no-op).
+ *   n_keep     1 <= n_keep <= T.
+ *   precision  a tm_precision.
+ *   kept       device, [B, n_keep] int32, written.
+ * Scratch of B*T*4 bytes is taken from the stream-ordered allocator.
+ * Errors: TM_EINVAL, TM_ENOMEM, TM_EHIP, TM_ENODEV. */
+int tm_prefilter(const tm_library* lib, const float* profiles, int32_t B, int32_t n_keep,
+                 int32_t precision, int32_t* kept, void* hip_stream);
+
+/* tm_match_candidates - the exact search of tm_match_batch restricted to a
+ * per-pattern candidate list (rescoring after a pre-filter or another coarse
+ * scorer): Q of Eq. (1) at every shift for each listed template, best shift
+ * per template, N best by Q descending, ties to the lower template index.
+ *
+ * Arguments
+ *   candidates device, [B, n_cand] int32 template indices in [0, T') (mirrors
+ *              are T..T'-1); entries outside that range are ignored; a row
+ *              must not list a template twice.
+ *   n_cand     >= 1; 1 <= N <= min(TM_MAX_N, n_cand).
+ *   other arguments as in tm_match_batch.
+ * Errors: TM_EINVAL, TM_EHIP, TM_ENODEV. */
+int tm_match_candidates(const tm_library* lib, const float* polar, const double* norms,
+                        int32_t B, const int32_t* candidates, int32_t n_cand, int32_t N,
+                        int32_t* top_template, int32_t* top_angle, float* top_score,
+                        void* hip_stream);
 
 /* tm_topn - sort per-template best scores and keep the N best per pattern
  * (Section 2.2, end: the list of correlations can be sorted and the N best

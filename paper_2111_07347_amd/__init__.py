@@ -33,8 +33,8 @@ TM_LIB_MIRROR, TM_LIB_UNIT_INTENSITY, TM_LIB_KEEP_DIRECT_BEAM, TM_LIB_NO_GROUPIN
 TM_MAX_N = 64
 
 EXPORTED = ("tm_load_library", "tm_free_library", "tm_library_info", "tm_library_layout",
-            "tm_polar_transform",
-            "tm_match_batch", "tm_topn", "tm_last_error", "tm_version")
+            "tm_polar_transform", "tm_match_batch", "tm_prefilter", "tm_match_candidates",
+            "tm_topn", "tm_last_error", "tm_version")
 
 
 class TMError(RuntimeError):
@@ -70,6 +70,8 @@ def _load():
         "tm_polar_transform": [P, ctypes.c_int, I32, I32, I32, ctypes.POINTER(_Grid), F, F, P, P,
                                P, P],
         "tm_match_batch": [P, P, P, P, I32, ctypes.POINTER(_Opts), I32, P, P, P, P, P, P],
+        "tm_prefilter": [P, P, I32, I32, I32, P, P],
+        "tm_match_candidates": [P, P, P, I32, P, I32, I32, P, P, P, P],
         "tm_topn": [P, P, I32, I32, I32, P, P, P, P],
         "tm_last_error": [],
         "tm_version": [],
@@ -282,12 +284,52 @@ def match_batch(lib: Library, polar, norms, N: int, profiles=None, prefilter_kee
         Tn = lib.n_total
         bq = torch.empty((B, Tn), dtype=torch.float32, device=dev)
         bs = torch.empty((B, Tn), dtype=torch.int16, device=dev)
-    o = _opts(prefilter_keep, prefilter_prec)
+    o = _opts(prefilter_keep, _prec(prefilter_prec))
     _check(_lib.tm_match_batch(lib._h, _ptr(polar), _ptr(norms), _ptr(profiles), B,
                                ctypes.byref(o) if o is not None else None, int(N), _ptr(tt),
                                _ptr(ts), _ptr(tq), _ptr(bq), _ptr(bs), _stream_ptr(stream)),
            "tm_match_batch")
     return (tt, ts, tq, bq, bs) if with_best else (tt, ts, tq)
+
+
+PRECISIONS = {"fp32": TM_PREC_FP32, "bf16": TM_PREC_BF16, "fp16": TM_PREC_FP16, "fp8": TM_PREC_FP8}
+
+
+def _prec(p):
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def prefilter(lib: Library, profiles, n_keep: int, precision="fp32", stream=None):
+    """tm_prefilter: per pattern the n_keep base templates whose radial
+    profile correlates best with the pattern's. Returns [B, n_keep] int32
+    (ascending template indices)."""
+    torch = _torch()
+    R, B = profiles.shape
+    _require(profiles, "profiles", torch.float32, (lib.grid.R, B))
+    kept = torch.empty((B, n_keep), dtype=torch.int32, device=profiles.device)
+    _check(_lib.tm_prefilter(lib._h, _ptr(profiles), B, int(n_keep), _prec(precision), _ptr(kept),
+                             _stream_ptr(stream)), "tm_prefilter")
+    return kept
+
+
+def match_candidates(lib: Library, polar, norms, candidates, N: int, stream=None):
+    """tm_match_candidates: exact search over per-pattern candidate template
+    lists [B, n_cand] (int32). Returns (template, angle, score) [B, N]."""
+    torch = _torch()
+    B = polar.shape[0]
+    _require(polar, "polar", torch.float32, (B, lib.grid.R, lib.grid.n_theta))
+    _require(norms, "norms", torch.float64, (B,))
+    _require(candidates, "candidates", torch.int32)
+    if candidates.shape[0] != B:
+        raise ValueError("candidates must have one row per pattern")
+    dev = polar.device
+    tt = torch.empty((B, N), dtype=torch.int32, device=dev)
+    ts = torch.empty((B, N), dtype=torch.int32, device=dev)
+    tq = torch.empty((B, N), dtype=torch.float32, device=dev)
+    _check(_lib.tm_match_candidates(lib._h, _ptr(polar), _ptr(norms), B, _ptr(candidates),
+                                    candidates.shape[1], int(N), _ptr(tt), _ptr(ts), _ptr(tq),
+                                    _stream_ptr(stream)), "tm_match_candidates")
+    return tt, ts, tq
 
 
 def topn(best_score, best_angle, N: int, stream=None):

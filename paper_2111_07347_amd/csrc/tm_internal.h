@@ -31,6 +31,13 @@ int hip_fail(hipError_t e, const char* what);
 // Shared validation of a tm_polar_grid (TM_OK or TM_EINVAL with a message).
 int validate_grid(const tm_polar_grid* g);
 
+// Pre-filter (azimuthally integrated profiles, Fig. 3): per pattern the n_keep
+// base templates with the highest profile correlation, ties to the lower
+// index, written ascending to items [B, n_items]; with mirrors, entries
+// n_keep.. hold the kept templates' mirrors (t + T). Enqueued on s.
+int prefilter_kept(const tm_library* lib, const float* profiles, int32_t B, int32_t n_keep,
+                   int32_t precision, int32_t* items, int32_t n_items, bool mirror, hipStream_t s);
+
 constexpr int kMaxN = TM_MAX_N;
 constexpr int kWave = 64;
 
@@ -77,8 +84,14 @@ struct tm_library {
     int32_t* d_seg = nullptr;       // [n_groups * n_bands * n_cls + 1] first record of each
                                     // (group, band, class) segment; the next entry ends it
     int32_t* d_members = nullptr;   // [n_groups * group] template index of each member, -1 = none
-    float* d_prof = nullptr;        // [T, R] radial profiles of base templates (float32)
-    float* d_prof_norm = nullptr;   // [T] L2 norm of each profile (float32 of float64)
+    // per-template records and segments (layout of group = 1), used to rescore
+    // candidate lists; null when group == 1 (then d_recs / d_seg serve)
+    uint32_t* d_recs1 = nullptr;
+    int32_t* d_seg1 = nullptr;
+    const uint32_t* recs_single() const { return d_recs1 ? d_recs1 : d_recs; }
+    const int32_t* seg_single() const { return d_seg1 ? d_seg1 : d_seg; }
+    float* d_prof = nullptr;        // [T, R] radial profiles of base templates, unit L2 norm
+    float* d_prof_max = nullptr;    // [T] largest entry of each normalised profile
     size_t device_bytes = 0;
 
     // host copies used for validation and info

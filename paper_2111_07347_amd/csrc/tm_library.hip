@@ -170,9 +170,11 @@ void release(tm_library* L) {
     hipFree(L->d_band_off);
     hipFree(L->d_recs);
     hipFree(L->d_members);
+    hipFree(L->d_recs1);
+    hipFree(L->d_seg1);
     hipFree(L->d_seg);
     hipFree(L->d_prof);
-    hipFree(L->d_prof_norm);
+    hipFree(L->d_prof_max);
     delete L;
 }
 
@@ -311,49 +313,67 @@ extern "C" int tm_load_library(const double* kx, const double* ky, const double*
 
     // 5. records per (group, band, class): union pixel offset + one weight
     // per member (zero when the member lacks the pixel)
-    std::vector<uint32_t> recs;
-    const size_t n_seg = static_cast<size_t>(n_groups) * n_bands * n_cls;
-    std::vector<int32_t> seg(n_seg + 1);
-    struct UEnt { uint64_t key; int g; float w; };
-    std::vector<UEnt> u;   // key = (band << 40 | class << 32 | off), member, weight
-    std::vector<float> w_of;
-    const size_t rec_words = static_cast<size_t>(G) + 1;
-    for (int32_t gi = 0; gi < n_groups; ++gi) {
-        u.clear();
-        for (int g = 0; g < G; ++g) {
-            const int32_t tt = members[static_cast<size_t>(gi) * G + g];
-            if (tt < 0) continue;
-            for (const Spot& s : tsp[tt])
-                u.push_back({(static_cast<uint64_t>(s.band) << 40) |
-                                 (static_cast<uint64_t>(pixel_class(s.off)) << 32) | s.off,
-                             g, s.w});
-        }
-        std::sort(u.begin(), u.end(), [](const UEnt& a, const UEnt& b) {
-            return a.key != b.key ? a.key < b.key : a.g < b.g;
-        });
-        const size_t base = static_cast<size_t>(gi) * n_bands * n_cls;
-        size_t next = 0;   // next segment of this group to open
-        for (size_t i = 0; i < u.size();) {
-            const uint64_t key = u[i].key;
-            const size_t sidx = static_cast<size_t>(key >> 40) * n_cls + ((key >> 32) & 0xff);
-            while (next <= sidx) seg[base + next++] = static_cast<int32_t>(recs.size() / rec_words);
-            w_of.assign(G, 0.0f);
-            for (; i < u.size() && u[i].key == key; ++i) w_of[u[i].g] = u[i].w;
-            recs.push_back(static_cast<uint32_t>(key & 0xffffffffu));
+    auto build_records = [&](int G, const std::vector<int32_t>& members,
+                             std::vector<uint32_t>& recs, std::vector<int32_t>& seg) -> int {
+        const int32_t n_groups = static_cast<int32_t>(members.size() / G);
+        const size_t n_seg = static_cast<size_t>(n_groups) * n_bands * n_cls;
+        recs.clear();
+        seg.assign(n_seg + 1, 0);
+        struct UEnt { uint64_t key; int g; float w; };
+        std::vector<UEnt> u;   // key = (band << 40 | class << 32 | off), member, weight
+        std::vector<float> w_of;
+        const size_t rec_words = static_cast<size_t>(G) + 1;
+        for (int32_t gi = 0; gi < n_groups; ++gi) {
+            u.clear();
             for (int g = 0; g < G; ++g) {
-                uint32_t wb;
-                std::memcpy(&wb, &w_of[g], 4);
-                recs.push_back(wb);
+                const int32_t tt = members[static_cast<size_t>(gi) * G + g];
+                if (tt < 0) continue;
+                for (const Spot& s : tsp[tt])
+                    u.push_back({(static_cast<uint64_t>(s.band) << 40) |
+                                     (static_cast<uint64_t>(pixel_class(s.off)) << 32) | s.off,
+                                 g, s.w});
+            }
+            std::sort(u.begin(), u.end(), [](const UEnt& a, const UEnt& b) {
+                return a.key != b.key ? a.key < b.key : a.g < b.g;
+            });
+            const size_t base = static_cast<size_t>(gi) * n_bands * n_cls;
+            size_t next = 0;   // next segment of this group to open
+            for (size_t i = 0; i < u.size();) {
+                const uint64_t key = u[i].key;
+                const size_t sidx = static_cast<size_t>(key >> 40) * n_cls + ((key >> 32) & 0xff);
+                while (next <= sidx) seg[base + next++] = static_cast<int32_t>(recs.size() / rec_words);
+                w_of.assign(G, 0.0f);
+                for (; i < u.size() && u[i].key == key; ++i) w_of[u[i].g] = u[i].w;
+                recs.push_back(static_cast<uint32_t>(key & 0xffffffffu));
+                for (int g = 0; g < G; ++g) {
+                    uint32_t wb;
+                    std::memcpy(&wb, &w_of[g], 4);
+                    recs.push_back(wb);
+                }
+            }
+            while (next < static_cast<size_t>(n_bands) * n_cls)
+                seg[base + next++] = static_cast<int32_t>(recs.size() / rec_words);
+            if (recs.size() / rec_words > static_cast<size_t>(INT32_MAX)) {
+                tmlib::set_error("library too large");
+                return TM_EINVAL;
             }
         }
-        while (next < static_cast<size_t>(n_bands) * n_cls)
-            seg[base + next++] = static_cast<int32_t>(recs.size() / rec_words);
-        if (recs.size() / rec_words > static_cast<size_t>(INT32_MAX)) { tmlib::set_error("library too large"); return TM_EINVAL; }
+        seg[n_seg] = static_cast<int32_t>(recs.size() / rec_words);
+        return TM_OK;
+    };
+    std::vector<uint32_t> recs, recs1;
+    std::vector<int32_t> seg, seg1;
+    if (int r = build_records(G, members, recs, seg)) return r;
+    // per-template records (one template per "group") for rescoring an
+    // arbitrary candidate list; the same arrays when G = 1
+    if (G != 1) {
+        std::vector<int32_t> ident(Tp);
+        for (int32_t t = 0; t < Tp; ++t) ident[t] = t;
+        if (int r = build_records(1, ident, recs1, seg1)) return r;
     }
-    seg[n_seg] = static_cast<int32_t>(recs.size() / rec_words);
 
     // 6. radial profiles of the base templates, normalised (Fig. 3)
-    std::vector<float> prof(static_cast<size_t>(T) * g.R, 0.0f), prof_norm(T, 0.0f);
+    std::vector<float> prof(static_cast<size_t>(T) * g.R, 0.0f), prof_max(T, 0.0f);
     std::vector<double> acc(g.R);
     for (int32_t t = 0; t < T; ++t) {
         std::fill(acc.begin(), acc.end(), 0.0);
@@ -361,9 +381,13 @@ extern "C" int tm_load_library(const double* kx, const double* ky, const double*
         double s = 0.0;
         for (int j = 0; j < g.R; ++j) s += acc[j] * acc[j];
         s = std::sqrt(s);
-        prof_norm[t] = static_cast<float>(s);
-        for (int j = 0; j < g.R; ++j)
-            prof[static_cast<size_t>(t) * g.R + j] = s > 0.0 ? static_cast<float>(acc[j] / s) : 0.0f;
+        float mx = 0.0f;
+        for (int j = 0; j < g.R; ++j) {
+            const float v = s > 0.0 ? static_cast<float>(acc[j] / s) : 0.0f;
+            prof[static_cast<size_t>(t) * g.R + j] = v;
+            mx = std::max(mx, std::fabs(v));
+        }
+        prof_max[t] = mx;
     }
 
     // 7. upload
@@ -396,8 +420,10 @@ extern "C" int tm_load_library(const double* kx, const double* ky, const double*
     if (!r) r = upload(&L->d_recs, recs, s, bytes);
     if (!r) r = upload(&L->d_seg, seg, s, bytes);
     if (!r) r = upload(&L->d_members, members, s, bytes);
+    if (!r && G != 1) r = upload(&L->d_recs1, recs1, s, bytes);
+    if (!r && G != 1) r = upload(&L->d_seg1, seg1, s, bytes);
     if (!r) r = upload(&L->d_prof, prof, s, bytes);
-    if (!r) r = upload(&L->d_prof_norm, prof_norm, s, bytes);
+    if (!r) r = upload(&L->d_prof_max, prof_max, s, bytes);
     if (!r) {
         hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) r = tmlib::hip_fail(e, "hipStreamSynchronize");

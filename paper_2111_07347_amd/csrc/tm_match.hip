@@ -33,6 +33,7 @@
 // template the smallest maximising shift. Summation order per (pattern,
 // template) is the library's spot order, so results do not depend on the
 // batch.
+#include <algorithm>
 #include <climits>
 #include <cmath>
 
@@ -154,9 +155,14 @@ match_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
              int n_bands, int row_width, const uint32_t* __restrict__ recs,
              const int* __restrict__ seg, const int* __restrict__ members, int n_groups, int Tp,
              int N, int* __restrict__ top_t, int* __restrict__ top_s, float* __restrict__ top_q,
-             float* __restrict__ best_q, short* __restrict__ best_s) {
+             float* __restrict__ best_q, short* __restrict__ best_s,
+             const int* __restrict__ cand) {
     extern __shared__ float lds[];
     constexpr int NCLS = NARROW ? K : 1;
+    // candidate mode (G = 1 only): item i of pattern b is template cand[b, i],
+    // whose records are the per-template segments; ids outside [0, Tp) are
+    // skipped
+    const int* items = cand ? cand + static_cast<size_t>(blockIdx.x) * n_groups : nullptr;
     const int b = blockIdx.x;
     const int lane = threadIdx.x & 63;
     const int wave = tmlib::uniform(threadIdx.x >> 6);
@@ -194,8 +200,18 @@ match_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
 #pragma unroll
         for (int m = 0; m < M; ++m)
 #pragma unroll
-            for (int g = 0; g < G; ++g)
-                mem[m][g] = (gb + m < n_groups) ? members[static_cast<size_t>(gb + m) * G + g] : -1;
+            for (int g = 0; g < G; ++g) {
+                int t = -1;
+                if (gb + m < n_groups) {
+                    if (G == 1 && items) {
+                        t = items[gb + m];
+                        t = (t >= 0 && t < Tp) ? t : -1;
+                    } else {
+                        t = members[static_cast<size_t>(gb + m) * G + g];
+                    }
+                }
+                mem[m][g] = t;
+            }
         float acc[M][G][K];
 #pragma unroll
         for (int m = 0; m < M; ++m)
@@ -213,8 +229,8 @@ match_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
             }
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                const int grp = gb + m;
-                if (grp < n_groups) {
+                const int grp = (G == 1 && items) ? mem[m][0] : (gb + m < n_groups ? gb + m : -1);
+                if (grp >= 0) {
                     const int* sg = seg + (static_cast<size_t>(grp) * n_bands + band) * NCLS;
                     accumulate_segments<K, G, NARROW>(rec, sg, lds, lane, n_theta, acc[m]);
                 }
@@ -257,7 +273,7 @@ match_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
 
 using MatchFn = void (*)(const float*, const double*, int, int, const int*, const int*, int, int,
                          const uint32_t*, const int*, const int*, int, int, int, int*, int*,
-                         float*, float*, short*);
+                         float*, float*, short*, const int*);
 
 // Groups held per wave while rows stream through LDS in bands.
 template <int K, int G>
@@ -305,6 +321,35 @@ MatchFn select_kernel(int K, int G, bool multi, bool narrow, int nw) {
     }
 }
 
+// Launch the match kernel for all templates (cand == nullptr) or for
+// per-pattern candidate lists of n_items template ids (per-template records).
+int launch_match(const tm_library* lib, const float* polar, const double* norms, int32_t B,
+                 int32_t N, int32_t* top_template, int32_t* top_angle, float* top_score,
+                 float* best_score, int16_t* best_angle, const int32_t* cand, int32_t n_items,
+                 hipStream_t s) {
+    const int K = tmlib::slots_for(lib->n_theta);
+    const bool multi = lib->n_bands > 1;
+    const int G = cand ? 1 : lib->group;
+    const size_t pattern_bytes = static_cast<size_t>(std::max(lib->band_rows, 1)) * lib->row_width * sizeof(float);
+    const int nw = (!multi && pattern_bytes > kWholeCuLds) ? kWavesWhole : kWavesShared;
+    MatchFn fn = select_kernel(K, G, multi, lib->narrow, nw);
+    if (!fn) { tmlib::set_error("n_theta=%d not supported", lib->n_theta); return TM_EUNSUPPORTED; }
+    const size_t merge_bytes = tmlib::topn_merge_bytes(nw, N);
+    const size_t lds_bytes = std::max(pattern_bytes, merge_bytes);
+    TM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               static_cast<int>(lds_bytes)));
+    const uint32_t* recs = cand ? lib->recs_single() : lib->d_recs;
+    const int32_t* seg = cand ? lib->seg_single() : lib->d_seg;
+    const int32_t n_groups = cand ? n_items : lib->n_groups;
+    hipLaunchKernelGGL(fn, dim3(B), dim3(nw * 64), lds_bytes, s, polar, norms, lib->R,
+                       lib->n_theta, lib->d_rows, lib->d_band_off, lib->n_bands, lib->row_width,
+                       recs, seg, lib->d_members, n_groups, lib->Tp, N, top_template, top_angle,
+                       top_score, best_score, reinterpret_cast<short*>(best_angle), cand);
+    TM_HIP(hipGetLastError());
+    return TM_OK;
+}
+
 }  // namespace
 
 extern "C" int tm_match_batch(const tm_library* lib, const float* polar, const double* norms,
@@ -323,6 +368,8 @@ extern "C" int tm_match_batch(const tm_library* lib, const float* polar, const d
         tmlib::set_error("best_score and best_angle must be both NULL or both set");
         return TM_EINVAL;
     }
+    double keep = 0.0;
+    int32_t prec = TM_PREC_FP32;
     if (opts) {
         for (int i = 0; i < 7; ++i)
             if (opts->reserved[i]) { tmlib::set_error("tm_match_opts.reserved must be zero"); return TM_EINVAL; }
@@ -330,36 +377,60 @@ extern "C" int tm_match_batch(const tm_library* lib, const float* polar, const d
             tmlib::set_error("prefilter_keep=%g outside [0, 1]", opts->prefilter_keep);
             return TM_EINVAL;
         }
-        if (opts->prefilter_keep > 0.0) {
-            tmlib::set_error("pre-filtered matching is not available in this build");
-            return TM_EUNSUPPORTED;
-        }
+        keep = opts->prefilter_keep;
+        prec = opts->prefilter_prec;
+        if (prec < TM_PREC_FP32 || prec > TM_PREC_FP8) { tmlib::set_error("unknown precision %d", prec); return TM_EINVAL; }
     }
-    (void)profiles;
+    const bool mirror = lib->Tp == 2 * lib->T;
+    int32_t n_keep = 0;
+    if (keep > 0.0) {
+        n_keep = static_cast<int32_t>(std::ceil(keep * lib->T - 1e-9));
+        n_keep = std::max(1, std::min(n_keep, lib->T));
+        const int32_t n_items = mirror ? 2 * n_keep : n_keep;
+        if (N > n_items) { tmlib::set_error("N=%d exceeds the %d kept templates", N, n_items); return TM_EINVAL; }
+        if (best_score) { tmlib::set_error("per-template outputs are not available with a pre-filter"); return TM_EINVAL; }
+        if (!profiles && B > 0) { tmlib::set_error("profiles are required with a pre-filter"); return TM_EINVAL; }
+    }
     if (B == 0) return TM_OK;
     if (!polar || !norms || !top_template || !top_angle || !top_score) {
         tmlib::set_error("polar, norms and top_* outputs must be non-NULL");
         return TM_EINVAL;
     }
     if (int r = tmlib::require_device()) return r;
-
-    const int K = tmlib::slots_for(lib->n_theta);
-    const bool multi = lib->n_bands > 1;
-    const size_t pattern_bytes = static_cast<size_t>(std::max(lib->band_rows, 1)) * lib->row_width * sizeof(float);
-    const int nw = (!multi && pattern_bytes > kWholeCuLds) ? kWavesWhole : kWavesShared;
-    MatchFn fn = select_kernel(K, lib->group, multi, lib->narrow, nw);
-    if (!fn) { tmlib::set_error("n_theta=%d not supported", lib->n_theta); return TM_EUNSUPPORTED; }
-    const size_t merge_bytes = tmlib::topn_merge_bytes(nw, N);
-    const size_t lds_bytes = std::max(pattern_bytes, merge_bytes);
-    TM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               static_cast<int>(lds_bytes)));
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    hipLaunchKernelGGL(fn, dim3(B), dim3(nw * 64), lds_bytes, s, polar, norms, lib->R,
-                       lib->n_theta, lib->d_rows, lib->d_band_off, lib->n_bands, lib->row_width,
-                       lib->d_recs, lib->d_seg, lib->d_members, lib->n_groups, lib->Tp, N,
-                       top_template, top_angle, top_score, best_score,
-                       reinterpret_cast<short*>(best_angle));
-    TM_HIP(hipGetLastError());
-    return TM_OK;
+    if (n_keep == 0)
+        return launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score,
+                            best_score, best_angle, nullptr, 0, s);
+    // pre-filter, then rescore the kept templates (and their mirrors) exactly
+    const int32_t n_items = mirror ? 2 * n_keep : n_keep;
+    int32_t* items = nullptr;
+    TM_HIP(hipMallocAsync(reinterpret_cast<void**>(&items),
+                          static_cast<size_t>(B) * n_items * sizeof(int32_t), s));
+    int r = tmlib::prefilter_kept(lib, profiles, B, n_keep, prec, items, n_items, mirror, s);
+    if (!r) r = launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score,
+                             nullptr, nullptr, items, n_items, s);
+    hipError_t e = hipFreeAsync(items, s);
+    if (!r && e != hipSuccess) r = tmlib::hip_fail(e, "hipFreeAsync");
+    return r;
+}
+
+extern "C" int tm_match_candidates(const tm_library* lib, const float* polar, const double* norms,
+                                   int32_t B, const int32_t* candidates, int32_t n_cand, int32_t N,
+                                   int32_t* top_template, int32_t* top_angle, float* top_score,
+                                   void* hip_stream) {
+    tmlib::clear_error();
+    if (!lib) { tmlib::set_error("library is NULL"); return TM_EINVAL; }
+    if (B < 0 || n_cand < 1) { tmlib::set_error("B=%d, n_cand=%d: need B >= 0, n_cand >= 1", B, n_cand); return TM_EINVAL; }
+    if (N < 1 || N > tmlib::kMaxN || N > n_cand) {
+        tmlib::set_error("N=%d outside [1, min(%d, n_cand=%d)]", N, tmlib::kMaxN, n_cand);
+        return TM_EINVAL;
+    }
+    if (B == 0) return TM_OK;
+    if (!polar || !norms || !candidates || !top_template || !top_angle || !top_score) {
+        tmlib::set_error("polar, norms, candidates and top_* outputs must be non-NULL");
+        return TM_EINVAL;
+    }
+    if (int r = tmlib::require_device()) return r;
+    return launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score, nullptr,
+                        nullptr, candidates, n_cand, static_cast<hipStream_t>(hip_stream));
 }
