@@ -53,6 +53,10 @@ def parse():
                     help="arithmetic of the pre-filtered path timed beside the plain path")
     ap.add_argument("--keep", type=float, default=0.1,
                     help="fraction of base templates the pre-filter keeps")
+    ap.add_argument("--serving-rows", type=int, default=256,
+                    help="scan rows replayed through the serving loop (0 = skip)")
+    ap.add_argument("--serving-distinct", type=int, default=32,
+                    help="distinct generated rows, replayed cyclically")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy three times (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -90,6 +94,49 @@ def oracle_baseline(cfg, lib_np, n_sample, procs):
     t, s, q, _ = oracle.index_batch64(imgs, olib, cfg.N, processes=procs)
     dt = time.perf_counter() - t0
     return idx, (t, s, q), dt
+
+
+def serving_bench(tm, n_rows, n_distinct, workers):
+    """Serving form: scan rows of 256 uint16 patterns arriving every 64 ms
+    (4000 patterns/s), each routed to one of three resident libraries (2000
+    FCC, 8000 HCP, 20000 orthorhombic templates); continuous batching on 4
+    stream slots with a 16 GiB in-flight budget. Returns the paced latency
+    report and the burst-mode throughput."""
+    import multiprocessing as mp
+
+    import torch
+
+    import synth
+    from paper_2111_07347_amd.serve import GpuExecutor, Server, latency_report, run_stream
+    cfg0 = synth.serving_config(0)
+    grid = tm.PolarGrid(R=cfg0.R, n_theta=cfg0.n_theta, cx=cfg0.cx, cy=cfg0.cy)
+    px = synth.px_per_inv_A(cfg0)
+    libs_np = {i: synth.make_library(synth.serving_config(i)) for i in range(3)}
+    libs = {i: tm.Library(l["kx"], l["ky"], l["intensity"], l["offsets"], px, grid)
+            for i, l in libs_np.items()}
+    lib_ids, arrivals = synth.serving_schedule(n_rows)
+    distinct = min(n_distinct, n_rows)
+    with mp.get_context("fork").Pool(workers) as pool:
+        gen = pool.starmap(synth.serving_row, [(r, int(lib_ids[r]), libs_np[int(lib_ids[r])])
+                                               for r in range(distinct)])
+    pinned = [torch.from_numpy(g.view(np.int16)).pin_memory() for g in gen]
+    rows = [pinned[i % distinct] for i in range(n_rows)]
+    rows_lib = [int(lib_ids[i % distinct]) for i in range(n_rows)]
+    out = {"rows": n_rows, "distinct_rows": distinct, "patterns_per_row": synth.SERVING_ROW,
+           "arrival_patterns_per_s": synth.SERVING_ROW / synth.SERVING_INTERVAL_S,
+           "libraries": {i: libs[i].info()["n_templates_total"] for i in libs},
+           "slots": 4, "max_batch_rows": 4, "budget_bytes": 16 << 30, "path": "plain fp32"}
+    # warm up every library once
+    ex = GpuExecutor(libs, grid, N=5, slots=4)
+    srv = Server(ex, budget_bytes=16 << 30, slots=4, max_batch_rows=4)
+    run_stream(srv, rows[:3] * 1, rows_lib[:3], np.zeros(3))
+    for mode, arr in (("paced", arrivals), ("burst", np.zeros(n_rows))):
+        srv = Server(GpuExecutor(libs, grid, N=5, slots=4), budget_bytes=16 << 30, slots=4,
+                     max_batch_rows=4)
+        res = run_stream(srv, rows, rows_lib, arr)
+        out[mode] = latency_report(res)
+        print(f"[bench] serving {mode}: {out[mode]}", file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -247,6 +294,10 @@ def main():
             pt = pre_top[0].cpu().numpy()
             prec_path["top1_agreement_vs_oracle_on_sample"] = float(np.mean(pt[idx, 0] == ot[:, 0]))
 
+    serving = None
+    if a.serving_rows > 0:
+        serving = serving_bench(tm, a.serving_rows, a.serving_distinct, workers)
+
     line = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -272,6 +323,8 @@ def main():
         "cpu_baseline": cpu,
         "top1_agreement_vs_oracle_on_sample": top1,
         "precision_path": prec_path,
+        "serving": serving,
+        "p99_scan_row_latency_ms": (serving or {}).get("paced", {}).get("p99_ms"),
         "kernel_ms": {"polar_transform": round(polar_ms, 4), "match_kernel": round(match_ms, 4)},
     }
     print(json.dumps(line), flush=True)

@@ -462,3 +462,40 @@ def make_patterns_parallel(cfg: Config | int, lib: dict, n: int, workers: int = 
         for lo, arr in pool.imap_unordered(_worker, jobs):
             out[lo:lo + len(arr)] = arr
     return out
+
+
+# --------------------------------------------------------------------------
+# Serving workload: scan rows of 256 uint16 patterns, each routed to one of
+# the resident libraries, arriving at a fixed cadence.
+# --------------------------------------------------------------------------
+SERVING_ROW = 256
+SERVING_INTERVAL_S = SERVING_ROW / 4000.0      # 4000 patterns/s
+
+
+def serving_config(lib_id: int) -> Config:
+    base = CONFIGS[4]
+    return Config(4, f"serving row, library {lib_id}", B=SERVING_ROW, H=base.H, W=base.W,
+                  R=base.R, n_theta=base.n_theta, phases=SERVING_LIBRARIES[lib_id], N=base.N,
+                  dtype="u16", lognormal=True)
+
+
+def serving_schedule(n_rows: int):
+    """(library id per row, arrival offset in seconds per row)."""
+    rng = rng_for(4, 4, 0)
+    lib_ids = rng.integers(0, len(SERVING_LIBRARIES), n_rows)
+    return lib_ids.astype(np.int64), np.arange(n_rows) * SERVING_INTERVAL_S
+
+
+def serving_row(row_id: int, lib_id: int, lib: dict | None = None, workers: int = 1) -> np.ndarray:
+    """Patterns of one scan row: scan indices row_id*256 .. +255 rendered from
+    the row's library."""
+    cfg = serving_config(lib_id)
+    lib = make_library(cfg) if lib is None else lib
+    idx = range(row_id * SERVING_ROW, (row_id + 1) * SERVING_ROW)
+    if workers > 1:
+        import multiprocessing as mp
+        chunks = [list(idx)[i:i + 32] for i in range(0, SERVING_ROW, 32)]
+        with mp.get_context("fork").Pool(workers) as pool:
+            parts = pool.starmap(make_patterns, [(cfg, lib, c) for c in chunks])
+        return np.concatenate(parts)
+    return make_patterns(cfg, lib, idx)

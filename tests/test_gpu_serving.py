@@ -1,0 +1,82 @@
+"""Serving on the GPU: continuous batching of scan rows over three resident
+libraries; each row's result is bit-identical alone and in the mix, and
+agrees with the FP64 oracle. Marked gpu."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import PatternRef, check_topn
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2111_07347_amd as tm
+    from paper_2111_07347_amd.serve import GpuExecutor, Server
+    cfg0 = synth.serving_config(0)
+    grid = tm.PolarGrid(R=cfg0.R, n_theta=cfg0.n_theta, cx=cfg0.cx, cy=cfg0.cy)
+    px = synth.px_per_inv_A(cfg0)
+    libs_np = {i: synth.make_library(synth.serving_config(i)) for i in range(3)}
+    libs = {i: tm.Library(l["kx"], l["ky"], l["intensity"], l["offsets"], px, grid)
+            for i, l in libs_np.items()}
+    n_rows = 6
+    lib_ids, _ = synth.serving_schedule(n_rows)
+    lib_ids = np.array([0, 1, 2, 2, 1, 0])     # every library, repeated
+    # 64 patterns per row keep the oracle checks short
+    rows_np = [synth.serving_row(r, int(lib_ids[r]), libs_np[int(lib_ids[r])])[:64]
+               for r in range(n_rows)]
+    rows = [torch.from_numpy(r.view(np.int16)).pin_memory() for r in rows_np]
+    return tm, GpuExecutor, Server, grid, px, libs_np, libs, lib_ids, rows_np, rows
+
+
+def _serve(setup, order, slots, max_rows, burst=True, keep=0.0):
+    tm, GpuExecutor, Server, grid, px, libs_np, libs, lib_ids, rows_np, rows = setup
+    from paper_2111_07347_amd.serve import run_stream
+    ex = GpuExecutor(libs, grid, N=5, slots=slots, prefilter_keep=keep)
+    srv = Server(ex, budget_bytes=8 << 30, slots=slots, max_batch_rows=max_rows)
+    res = run_stream(srv, [rows[i] for i in order], [lib_ids[i] for i in order],
+                     np.zeros(len(order)) if burst else np.arange(len(order)) * 0.01)
+    assert all(r.error is None for r in res)
+    return {order[r.req_id]: r for r in res}
+
+
+def test_alone_equals_mix(setup):
+    n = len(setup[7])
+    _say("serving: each row alone")
+    alone = {}
+    for i in range(n):
+        alone.update(_serve(setup, [i], slots=1, max_rows=1))
+    _say("serving: all rows mixed, 3 slots, batches of up to 3 rows")
+    mix = _serve(setup, list(range(n)), slots=3, max_rows=3)
+    assert max(r.batch_rows for r in mix.values()) > 1      # batching happened
+    _say("serving: reversed order, paced arrivals")
+    mix2 = _serve(setup, list(reversed(range(n))), slots=2, max_rows=2, burst=False)
+    for i in range(n):
+        for other in (mix[i], mix2[i]):
+            assert np.array_equal(alone[i].top_template, other.top_template)
+            assert np.array_equal(alone[i].top_angle, other.top_angle)
+            assert np.array_equal(alone[i].top_score, other.top_score)
+
+
+def test_serving_matches_oracle(setup):
+    tm, GpuExecutor, Server, grid, px, libs_np, libs, lib_ids, rows_np, rows = setup
+    res = _serve(setup, list(range(len(rows))), slots=3, max_rows=2)
+    for i in (0, 1, 2):           # one row per library
+        lib = libs_np[int(lib_ids[i])]
+        cfg = synth.serving_config(int(lib_ids[i]))
+        olib = oracle.OracleLibrary.build(lib, px, cfg.R, cfg.n_theta)
+        for b in (0, 31):
+            _say("serving oracle check row", i, "library", int(lib_ids[i]), "pattern", b)
+            P = oracle.polar64(rows_np[i][b].astype(np.float64), cfg.R, cfg.n_theta)
+            ref = PatternRef(P, olib)
+            r = res[i]
+            check_topn(ref, r.top_template[b], r.top_angle[b], r.top_score[b], margin=1e-4,
+                       tight=True)
