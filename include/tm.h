@@ -93,14 +93,30 @@ enum {
     TM_LIB_MIRROR = 1u,            /* add mirrored templates (Section 2.2, Fig. 2 f) */
     TM_LIB_UNIT_INTENSITY = 2u,    /* all spot weights 1 (Section 4.3) */
     TM_LIB_KEEP_DIRECT_BEAM = 4u,  /* keep spots at (0, 0); dropped by default */
-    TM_LIB_NO_GROUPING = 8u        /* score every template on its own; by default
+    TM_LIB_NO_GROUPING = 8u,       /* score every template on its own; by default
                                       templates sharing polar pixels are scored
                                       together (same results up to float32
                                       summation order) */
+    TM_LIB_FFT = 16u               /* also keep the templates' spectra along theta
+                                      for the Fourier-route coarse scorer
+                                      (tm_fft_scores; needs an even n_theta) */
 };
 
-/* Options of tm_match_batch. A NULL options pointer means the plain float32
- * path: every template scored exactly.
+/* Coarse scorer and rescoring policy of tm_match_batch. */
+enum {
+    TM_COARSE_NONE = 0,            /* no coarse scorer */
+    TM_COARSE_FFT = 1              /* Fourier route along theta (tm_fft_scores) */
+};
+enum {
+    TM_RESCORE_CERTIFIED = 0,      /* rescore every template the coarse scorer's
+                                      error bound cannot rule out: the result
+                                      is the exact float32 top-N */
+    TM_RESCORE_KEEP = 1            /* rescore a fixed fraction of the templates
+                                      with the best coarse scores */
+};
+
+/* Options of tm_match_batch. A NULL options pointer (or all fields zero)
+ * means the plain float32 path: every template scored exactly.
  *   prefilter_keep    fraction f of base templates kept by the azimuthal
  *                     pre-filter (Section 2.2, Fig. 3), 0 = no pre-filter;
  *                     the kept ceil(f*T) base templates (and their mirrors)
@@ -109,11 +125,29 @@ enum {
  *   prefilter_prec    arithmetic of the pre-filter's profile correlation
  *                     (FP32, BF16, FP16 or FP8 on the matrix cores with
  *                     float32 accumulation).
+ *   coarse            TM_COARSE_NONE, or TM_COARSE_FFT: score every template
+ *                     approximately through the Fourier route (Section 3;
+ *                     tm_fft_scores; the library needs TM_LIB_FFT), then
+ *                     rescore candidates exactly in float32. Exclusive with
+ *                     the pre-filter.
+ *   rescore_policy    with a coarse scorer: TM_RESCORE_CERTIFIED (default)
+ *                     or TM_RESCORE_KEEP.
+ *   rescore_keep      TM_RESCORE_KEEP: fraction of the T' templates rescored
+ *                     (those with the best coarse scores, ties to the lower
+ *                     index). TM_RESCORE_CERTIFIED: largest fraction of T'
+ *                     rescored from the candidate list (0 = 0.1); a pattern
+ *                     whose certified set is larger is scored in full.
+ *   n_rescored        optional device [B] int32 output: templates scored
+ *                     exactly per pattern (T' for a full scan), or NULL.
  *   reserved          must be zero. */
 typedef struct {
     double prefilter_keep;
     int32_t prefilter_prec;
-    int32_t reserved[7];
+    int32_t coarse;
+    int32_t rescore_policy;
+    int32_t reserved;
+    double rescore_keep;
+    int32_t* n_rescored;
 } tm_match_opts;
 
 typedef struct tm_library tm_library;   /* opaque; immutable after load */
@@ -229,6 +263,10 @@ int tm_polar_transform(const void* patterns, tm_dtype dtype, int32_t B, int32_t 
  *   norms        device, [B] float64 image norms.
  *   profiles     device, [R, B] float32 azimuthal profiles; required only
  *                when opts->prefilter_keep > 0, else may be NULL.
+ *                With opts->coarse = TM_COARSE_FFT (certified policy), the
+ *                result equals the plain path's top-N: every template whose
+ *                approximate score, widened by tm_fft_error_bound(), could
+ *                reach the N-th best exact score is rescored exactly.
  *   B            >= 0 (0 is a no-op).
  *   opts         NULL for the plain path, or options (see tm_match_opts).
  *   N            1 <= N <= min(TM_MAX_N, T'); with a pre-filter, N must not
@@ -238,7 +276,8 @@ int tm_polar_transform(const void* patterns, tm_dtype dtype, int32_t B, int32_t 
  *   best_score   device, [B, T'] float32 per-template best Q, or NULL.
  *   best_angle   device, [B, T'] int16 per-template best angle, or NULL;
  *                best_score and best_angle must be both NULL or both set,
- *                and are only available without pre-filter.
+ *                and are only available without pre-filter or coarse
+ *                scorer.
  * Errors: TM_EINVAL, TM_EUNSUPPORTED (unknown options), TM_EHIP, TM_ENODEV. */
 int tm_match_batch(const tm_library* lib, const float* polar, const double* norms,
                    const float* profiles, int32_t B, const tm_match_opts* opts, int32_t N,
@@ -288,6 +327,46 @@ int tm_match_candidates(const tm_library* lib, const float* polar, const double*
                         int32_t B, const int32_t* candidates, int32_t n_cand, int32_t N,
                         int32_t* top_template, int32_t* top_angle, float* top_score,
                         void* hip_stream);
+
+/* tm_fft_scores - approximate best score and angle of every template for every
+ * pattern through the Fourier route (Section 3: the azimuthal sliding is a
+ * circular cross-correlation along theta, evaluated with Fourier transforms).
+ *
+ *   spectra  P^[b, j, k] = sum_theta P[b, j, theta] e^{-2 pi i k theta / n}
+ *            / norms[b], and T^[t, j, k] of template t's merged weights / ||T||,
+ *            frequencies k = 0 .. n/2 (n = n_theta);
+ *   C(k)     = sum_j conj(T^[t, j, k]) P^[b, j, k] (mirror: T^ instead of
+ *            conj(T^));
+ *   Q~(s)    = (1/n) sum_k c_k Re(C(k) e^{2 pi i k s / n}), c_k = 1 at k = 0
+ *            and k = n/2, else 2; approx_score = max_s Q~, approx_angle =
+ *            the smallest maximising s of the computed values.
+ * Exact arithmetic would give Q of Eq. (1). Here the spectra are float16,
+ * the contraction over rows and the inverse transform run on the matrix
+ * cores with float32 accumulation, and C(k) is stored as float16 between
+ * them; |approx_score - best Q| never exceeds tm_fft_error_bound().
+ *
+ * Arguments
+ *   lib           library loaded with TM_LIB_FFT.
+ *   polar, norms  as in tm_match_batch.
+ *   B             >= 0 (0 is a no-op).
+ *   approx_score  device, [B, T'] float32, written.
+ *   approx_angle  device, [B, T'] int16, written, or NULL.
+ * Scratch (spectra of a chunk of patterns; up to about 8 GiB) is taken from
+ * the stream-ordered allocator.
+ * Errors: TM_EINVAL (null pointer, library without TM_LIB_FFT), TM_ENOMEM,
+ *         TM_EHIP, TM_ENODEV. */
+int tm_fft_scores(const tm_library* lib, const float* polar, const double* norms, int32_t B,
+                  float* approx_score, int16_t* approx_angle, void* hip_stream);
+
+/* tm_fft_error_bound - a-priori bound eps with |Q~ - Q32| <= eps for every
+ * template and shift, where Q~ is tm_fft_scores' arithmetic and Q32 the exact
+ * float32 path's score (both for the same float32 polar image). It adds the
+ * worst-case effect of every float16 rounding (spectra, stored C(k), cosine
+ * tables, with subnormals possibly flushed) and of float32 accumulation,
+ * bounded through Parseval's identity, and the float32 path's own error.
+ * The certified rescoring of tm_match_batch relies on it.
+ * Errors: TM_EINVAL (null pointer, library without TM_LIB_FFT). */
+int tm_fft_error_bound(const tm_library* lib, double* eps);
 
 /* tm_topn - sort per-template best scores and keep the N best per pattern
  * (Section 2.2, end: the list of correlations can be sorted and the N best

@@ -20,7 +20,9 @@ out plainly, in float64, one function per step:
   (Section 2.2, Fig. 2 e);
 * ``topn64`` - sort and keep the N best templates (Section 2.2, end);
 * ``prefilter64`` - azimuthally integrated pre-filter of the library
-  (Section 2.2, Fig. 3).
+  (Section 2.2, Fig. 3);
+* ``fft_match64`` - the same in-plane search through Fourier transforms
+  along the azimuth (Section 3, computational cost).
 
 Readings where the paper is silent are stated in each function.
 """
@@ -28,11 +30,12 @@ from .polar import (polar_coords64, bilinear64, intensity_transform64,
                     polar64, norm64, profile64)
 from .library import template_pixels64, OracleLibrary
 from .match import scores64, match_exact64, topn64, index_pattern64, index_batch64
+from .fft import template_images64, fft_numerators64, fft_match64
 from .prefilter import radial_profiles64, prefilter64, index_pattern_prefiltered64
 
 __all__ = [
     "polar_coords64", "bilinear64", "intensity_transform64", "polar64", "norm64",
     "profile64", "template_pixels64", "OracleLibrary", "scores64", "match_exact64",
     "topn64", "index_pattern64", "index_batch64", "radial_profiles64", "prefilter64",
-    "index_pattern_prefiltered64",
+    "index_pattern_prefiltered64", "template_images64", "fft_numerators64", "fft_match64",
 ]

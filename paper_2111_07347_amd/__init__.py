@@ -30,11 +30,14 @@ TM_OK, TM_EINVAL, TM_ENOMEM, TM_EHIP, TM_ENODEV, TM_EUNSUPPORTED, TM_ENOMEM_BUDG
 TM_U16, TM_F32 = 0, 1
 TM_PREC_FP32, TM_PREC_BF16, TM_PREC_FP16, TM_PREC_FP8 = 0, 1, 2, 3
 TM_LIB_MIRROR, TM_LIB_UNIT_INTENSITY, TM_LIB_KEEP_DIRECT_BEAM, TM_LIB_NO_GROUPING = 1, 2, 4, 8
+TM_LIB_FFT = 16
+TM_COARSE_NONE, TM_COARSE_FFT = 0, 1
+TM_RESCORE_CERTIFIED, TM_RESCORE_KEEP = 0, 1
 TM_MAX_N = 64
 
 EXPORTED = ("tm_load_library", "tm_free_library", "tm_library_info", "tm_library_layout",
             "tm_polar_transform", "tm_match_batch", "tm_prefilter", "tm_match_candidates",
-            "tm_topn", "tm_last_error", "tm_version")
+            "tm_fft_scores", "tm_fft_error_bound", "tm_topn", "tm_last_error", "tm_version")
 
 
 class TMError(RuntimeError):
@@ -51,7 +54,9 @@ class _Grid(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("prefilter_keep", ctypes.c_double), ("prefilter_prec", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("coarse", ctypes.c_int32), ("rescore_policy", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("rescore_keep", ctypes.c_double),
+                ("n_rescored", ctypes.c_void_p)]
 
 
 def _load():
@@ -72,6 +77,8 @@ def _load():
         "tm_match_batch": [P, P, P, P, I32, ctypes.POINTER(_Opts), I32, P, P, P, P, P, P],
         "tm_prefilter": [P, P, I32, I32, I32, P, P],
         "tm_match_candidates": [P, P, P, I32, P, I32, I32, P, P, P, P],
+        "tm_fft_scores": [P, P, P, I32, P, P, P],
+        "tm_fft_error_bound": [P, ctypes.POINTER(D)],
         "tm_topn": [P, P, I32, I32, I32, P, P, P, P],
         "tm_last_error": [],
         "tm_version": [],
@@ -158,7 +165,8 @@ class Library:
 
     def __init__(self, kx, ky, intensity, offsets, px_per_inv_angstrom: float, grid: PolarGrid,
                  mirror: bool = True, unit_intensity: bool = False,
-                 keep_direct_beam: bool = False, grouping: bool = True, stream=None):
+                 keep_direct_beam: bool = False, grouping: bool = True, fft: bool = False,
+                 stream=None):
         kx = np.ascontiguousarray(kx, dtype=np.float64)
         ky = np.ascontiguousarray(ky, dtype=np.float64)
         inten = np.ascontiguousarray(intensity, dtype=np.float64)
@@ -167,7 +175,7 @@ class Library:
             raise ValueError("kx, ky, intensity must all have offsets[-1] entries")
         flags = ((TM_LIB_MIRROR if mirror else 0) | (TM_LIB_UNIT_INTENSITY if unit_intensity else 0)
                  | (TM_LIB_KEEP_DIRECT_BEAM if keep_direct_beam else 0)
-                 | (0 if grouping else TM_LIB_NO_GROUPING))
+                 | (0 if grouping else TM_LIB_NO_GROUPING) | (TM_LIB_FFT if fft else 0))
         self.grid = grid
         self.T = len(off) - 1
         self.mirror = mirror
@@ -197,6 +205,13 @@ class Library:
         n_theta = self.grid.n_theta
         return {"group": g.value, "n_bands": nb.value, "n_rows": nr.value, "n_records": rec.value,
                 "row_width": rw.value, "narrow": rw.value == n_theta + 63}
+
+    def fft_error_bound(self) -> float:
+        """tm_fft_error_bound: certified bound on |Q~ - Q32| of the Fourier
+        route (library loaded with fft=True)."""
+        e = ctypes.c_double()
+        _check(_lib.tm_fft_error_bound(self._h, ctypes.byref(e)), "tm_fft_error_bound")
+        return e.value
 
     @property
     def n_total(self) -> int:
@@ -249,21 +264,34 @@ def polar_transform(patterns, grid: PolarGrid, gamma: float = 1.0, subtract: flo
     return polar_out, norm_out, profile_out
 
 
-def _opts(prefilter_keep: float, prefilter_prec: int):
-    if prefilter_keep == 0.0:
+COARSE = {None: TM_COARSE_NONE, "none": TM_COARSE_NONE, "fft": TM_COARSE_FFT}
+RESCORE = {"certified": TM_RESCORE_CERTIFIED, "keep": TM_RESCORE_KEEP}
+
+
+def _opts(prefilter_keep: float, prefilter_prec: int, coarse: int = TM_COARSE_NONE,
+          rescore: int = TM_RESCORE_CERTIFIED, rescore_keep: float = 0.0, n_rescored=None):
+    if prefilter_keep == 0.0 and coarse == TM_COARSE_NONE and n_rescored is None:
         return None
     o = _Opts()
     o.prefilter_keep = float(prefilter_keep)
     o.prefilter_prec = int(prefilter_prec)
+    o.coarse = int(coarse)
+    o.rescore_policy = int(rescore)
+    o.rescore_keep = float(rescore_keep)
+    o.n_rescored = _ptr(n_rescored) or None
     return o
 
 
 def match_batch(lib: Library, polar, norms, N: int, profiles=None, prefilter_keep: float = 0.0,
                 prefilter_prec: int = TM_PREC_FP32, with_best: bool = False, out=None,
-                stream=None):
+                coarse=None, rescore="certified", rescore_keep: float = 0.0,
+                n_rescored=None, stream=None):
     """tm_match_batch. Returns (top_template [B,N] i32, top_angle [B,N] i32,
     top_score [B,N] f32) and, with with_best, also (best_score [B,T'] f32,
-    best_angle [B,T'] i16)."""
+    best_angle [B,T'] i16). coarse="fft" scores every template through the
+    Fourier route first and rescores candidates exactly (rescore="certified"
+    or "keep" with rescore_keep); n_rescored, a [B] int32 device tensor, if
+    given receives the number of templates scored exactly per pattern."""
     torch = _torch()
     B = polar.shape[0]
     _require(polar, "polar", torch.float32, (B, lib.grid.R, lib.grid.n_theta))
@@ -284,7 +312,11 @@ def match_batch(lib: Library, polar, norms, N: int, profiles=None, prefilter_kee
         Tn = lib.n_total
         bq = torch.empty((B, Tn), dtype=torch.float32, device=dev)
         bs = torch.empty((B, Tn), dtype=torch.int16, device=dev)
-    o = _opts(prefilter_keep, _prec(prefilter_prec))
+    if n_rescored is not None:
+        _require(n_rescored, "n_rescored", torch.int32, (B,))
+    o = _opts(prefilter_keep, _prec(prefilter_prec), COARSE[coarse],
+              RESCORE[rescore] if isinstance(rescore, str) else int(rescore), rescore_keep,
+              n_rescored)
     _check(_lib.tm_match_batch(lib._h, _ptr(polar), _ptr(norms), _ptr(profiles), B,
                                ctypes.byref(o) if o is not None else None, int(N), _ptr(tt),
                                _ptr(ts), _ptr(tq), _ptr(bq), _ptr(bs), _stream_ptr(stream)),
@@ -330,6 +362,22 @@ def match_candidates(lib: Library, polar, norms, candidates, N: int, stream=None
                                     candidates.shape[1], int(N), _ptr(tt), _ptr(ts), _ptr(tq),
                                     _stream_ptr(stream)), "tm_match_candidates")
     return tt, ts, tq
+
+
+def fft_scores(lib: Library, polar, norms, with_angle: bool = True, stream=None):
+    """tm_fft_scores: approximate best score (and angle) of every template for
+    every pattern through the Fourier route. Returns ([B, T'] f32, [B, T']
+    i16 or None)."""
+    torch = _torch()
+    B = polar.shape[0]
+    _require(polar, "polar", torch.float32, (B, lib.grid.R, lib.grid.n_theta))
+    _require(norms, "norms", torch.float64, (B,))
+    Tn = lib.n_total
+    q = torch.empty((B, Tn), dtype=torch.float32, device=polar.device)
+    a = torch.empty((B, Tn), dtype=torch.int16, device=polar.device) if with_angle else None
+    _check(_lib.tm_fft_scores(lib._h, _ptr(polar), _ptr(norms), B, _ptr(q), _ptr(a),
+                              _stream_ptr(stream)), "tm_fft_scores")
+    return q, a
 
 
 def topn(best_score, best_angle, N: int, stream=None):

@@ -38,6 +38,44 @@ int validate_grid(const tm_polar_grid* g);
 int prefilter_kept(const tm_library* lib, const float* profiles, int32_t B, int32_t n_keep,
                    int32_t precision, int32_t* items, int32_t n_items, bool mirror, hipStream_t s);
 
+// Exact rescoring launch of the match kernel (tm_match.hip): all templates
+// (cand == nullptr) or per-pattern candidate lists of up to n_items ids;
+// cand_count (optional, [B]) limits each pattern's list; pat_mask (optional,
+// [B]) skips patterns whose entry is 0. Enqueued on s.
+int launch_match(const tm_library* lib, const float* polar, const double* norms, int32_t B,
+                 int32_t N, int32_t* top_template, int32_t* top_angle, float* top_score,
+                 float* best_score, int16_t* best_angle, const int32_t* cand, int32_t n_items,
+                 const int32_t* cand_count, const int32_t* pat_mask, hipStream_t s);
+
+// Top-N over per-template scores [B, T] (tm_topn's kernel); best_angle may be
+// null (angles reported as 0). Enqueued on s.
+int launch_topn(const float* best_score, const int16_t* best_angle, int32_t B, int32_t T,
+                int32_t N, int32_t* top_template, int32_t* top_angle, float* top_score,
+                hipStream_t s);
+
+// Per row of S [B, n], the n_keep largest entries (ties to the lower index),
+// written ascending to items [B, n_keep]. Enqueued on s.
+int select_top(const float* S, int32_t B, int32_t n, int32_t n_keep, int32_t* items,
+               hipStream_t s);
+
+// Template pixel on the polar grid (host, float64 weight).
+struct HostPixel {
+    int32_t j, k;
+    double w;
+};
+
+// Fourier-route data of a library (tm_fft.hip): template spectra, inverse
+// transform tables and the error bound; host pixels are per base template.
+int fft_prepare(tm_library* L, const std::vector<std::vector<HostPixel>>& pix, hipStream_t s,
+                size_t& bytes);
+void fft_release(tm_library* L);
+// Certified or keep-fraction rescoring after the Fourier-route coarse scorer.
+int fft_match(const tm_library* lib, const float* polar, const double* norms, int32_t B,
+              int32_t N, int32_t policy, double keep, int32_t* n_rescored, int32_t* top_template,
+              int32_t* top_angle, float* top_score, hipStream_t s);
+// Fill a device int32 array with a value. Enqueued on s.
+int fill_i32(int32_t* dst, int64_t n, int32_t value, hipStream_t s);
+
 constexpr int kMaxN = TM_MAX_N;
 constexpr int kWave = 64;
 
@@ -93,6 +131,19 @@ struct tm_library {
     float* d_prof = nullptr;        // [T, R] radial profiles of base templates, unit L2 norm
     float* d_prof_max = nullptr;    // [T] largest entry of each normalised profile
     size_t device_bytes = 0;
+
+    // Fourier route (TM_LIB_FFT)
+    bool fft = false;
+    int32_t fft_F = 0;          // frequencies 0..n_theta/2
+    int32_t fft_Fp = 0;         // padded to a multiple of 16 (8 per parity)
+    int32_t fft_Rp = 0;         // polar rows padded to a multiple of 16
+    int32_t fft_Tpad = 0;       // base templates padded to a multiple of 32
+    int32_t fft_Sh = 0;         // shifts of half a turn padded to a multiple of 32
+    int32_t fft_sc = 0;         // power of two applied to C(k) before float16 storage
+    double fft_eps = 0.0;       // certified bound |Q~ - Q32|
+    uint16_t* d_fft_t = nullptr;    // [Fp][2 Tpad][Rp] float16 template spectra (x 2^8)
+    uint16_t* d_fft_w = nullptr;    // [2 parities][Sh][Fp + 8] float16 inverse tables (x 2^12)
+    double* d_fft_dft = nullptr;    // [n_theta][2] cos, sin of 2 pi m / n_theta
 
     // host copies used for validation and info
     std::vector<double> tnorm;      // [Tp]

@@ -30,10 +30,7 @@ constexpr size_t kSharedCuBytes = 76 * 1024;
 constexpr size_t kSingleBandBytes = 158 * 1024;
 constexpr size_t kBandBytes = 76 * 1024;
 
-struct Pixel {
-    int32_t j, k;
-    double w;
-};
+using Pixel = tmlib::HostPixel;
 
 // Merged polar pixels of one template, sorted by (j, k).
 void template_pixels(const double* kx, const double* ky, const double* inten, int64_t a,
@@ -175,6 +172,7 @@ void release(tm_library* L) {
     hipFree(L->d_seg);
     hipFree(L->d_prof);
     hipFree(L->d_prof_max);
+    tmlib::fft_release(L);
     delete L;
 }
 
@@ -193,7 +191,11 @@ extern "C" int tm_load_library(const double* kx, const double* ky, const double*
         tmlib::set_error("px_per_inv_angstrom must be positive and finite");
         return TM_EINVAL;
     }
-    if (flags & ~15u) { tmlib::set_error("unknown library flags 0x%x", flags); return TM_EINVAL; }
+    if (flags & ~31u) { tmlib::set_error("unknown library flags 0x%x", flags); return TM_EINVAL; }
+    if ((flags & TM_LIB_FFT) && (grid->n_theta % 2)) {
+        tmlib::set_error("TM_LIB_FFT needs an even n_theta (got %d)", grid->n_theta);
+        return TM_EUNSUPPORTED;
+    }
     if (offsets[0] != 0) { tmlib::set_error("offsets[0] must be 0"); return TM_EINVAL; }
     for (int32_t t = 0; t < n_templates; ++t)
         if (offsets[t + 1] < offsets[t]) { tmlib::set_error("offsets decrease at template %d", t); return TM_EINVAL; }
@@ -424,6 +426,7 @@ extern "C" int tm_load_library(const double* kx, const double* ky, const double*
     if (!r && G != 1) r = upload(&L->d_seg1, seg1, s, bytes);
     if (!r) r = upload(&L->d_prof, prof, s, bytes);
     if (!r) r = upload(&L->d_prof_max, prof_max, s, bytes);
+    if (!r && (flags & TM_LIB_FFT)) r = tmlib::fft_prepare(L, pix, s, bytes);
     if (!r) {
         hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) r = tmlib::hip_fail(e, "hipStreamSynchronize");

@@ -156,13 +156,17 @@ match_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
              const int* __restrict__ seg, const int* __restrict__ members, int n_groups, int Tp,
              int N, int* __restrict__ top_t, int* __restrict__ top_s, float* __restrict__ top_q,
              float* __restrict__ best_q, short* __restrict__ best_s,
-             const int* __restrict__ cand) {
+             const int* __restrict__ cand, const int* __restrict__ cand_cnt,
+             const int* __restrict__ pat_mask) {
     extern __shared__ float lds[];
     constexpr int NCLS = NARROW ? K : 1;
+    // patterns masked out are left untouched (the whole workgroup returns)
+    if (pat_mask && pat_mask[blockIdx.x] == 0) return;
     // candidate mode (G = 1 only): item i of pattern b is template cand[b, i],
     // whose records are the per-template segments; ids outside [0, Tp) are
-    // skipped
+    // skipped; cand_cnt[b] (optional) limits the row to its first entries
     const int* items = cand ? cand + static_cast<size_t>(blockIdx.x) * n_groups : nullptr;
+    if (cand && cand_cnt) n_groups = min(n_groups, max(0, cand_cnt[blockIdx.x]));
     const int b = blockIdx.x;
     const int lane = threadIdx.x & 63;
     const int wave = tmlib::uniform(threadIdx.x >> 6);
@@ -273,7 +277,7 @@ match_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
 
 using MatchFn = void (*)(const float*, const double*, int, int, const int*, const int*, int, int,
                          const uint32_t*, const int*, const int*, int, int, int, int*, int*,
-                         float*, float*, short*, const int*);
+                         float*, float*, short*, const int*, const int*, const int*);
 
 // Groups held per wave while rows stream through LDS in bands.
 template <int K, int G>
@@ -321,12 +325,15 @@ MatchFn select_kernel(int K, int G, bool multi, bool narrow, int nw) {
     }
 }
 
+}  // namespace
+
 // Launch the match kernel for all templates (cand == nullptr) or for
 // per-pattern candidate lists of n_items template ids (per-template records).
-int launch_match(const tm_library* lib, const float* polar, const double* norms, int32_t B,
-                 int32_t N, int32_t* top_template, int32_t* top_angle, float* top_score,
-                 float* best_score, int16_t* best_angle, const int32_t* cand, int32_t n_items,
-                 hipStream_t s) {
+int tmlib::launch_match(const tm_library* lib, const float* polar, const double* norms, int32_t B,
+                        int32_t N, int32_t* top_template, int32_t* top_angle, float* top_score,
+                        float* best_score, int16_t* best_angle, const int32_t* cand,
+                        int32_t n_items, const int32_t* cand_count, const int32_t* pat_mask,
+                        hipStream_t s) {
     const int K = tmlib::slots_for(lib->n_theta);
     const bool multi = lib->n_bands > 1;
     const int G = cand ? 1 : lib->group;
@@ -345,12 +352,11 @@ int launch_match(const tm_library* lib, const float* polar, const double* norms,
     hipLaunchKernelGGL(fn, dim3(B), dim3(nw * 64), lds_bytes, s, polar, norms, lib->R,
                        lib->n_theta, lib->d_rows, lib->d_band_off, lib->n_bands, lib->row_width,
                        recs, seg, lib->d_members, n_groups, lib->Tp, N, top_template, top_angle,
-                       top_score, best_score, reinterpret_cast<short*>(best_angle), cand);
+                       top_score, best_score, reinterpret_cast<short*>(best_angle), cand,
+                       cand_count, pat_mask);
     TM_HIP(hipGetLastError());
     return TM_OK;
 }
-
-}  // namespace
 
 extern "C" int tm_match_batch(const tm_library* lib, const float* polar, const double* norms,
                               const float* profiles, int32_t B, const tm_match_opts* opts,
@@ -368,11 +374,11 @@ extern "C" int tm_match_batch(const tm_library* lib, const float* polar, const d
         tmlib::set_error("best_score and best_angle must be both NULL or both set");
         return TM_EINVAL;
     }
-    double keep = 0.0;
-    int32_t prec = TM_PREC_FP32;
+    double keep = 0.0, rescore_keep = 0.0;
+    int32_t prec = TM_PREC_FP32, coarse = TM_COARSE_NONE, policy = TM_RESCORE_CERTIFIED;
+    int32_t* n_rescored = nullptr;
     if (opts) {
-        for (int i = 0; i < 7; ++i)
-            if (opts->reserved[i]) { tmlib::set_error("tm_match_opts.reserved must be zero"); return TM_EINVAL; }
+        if (opts->reserved) { tmlib::set_error("tm_match_opts.reserved must be zero"); return TM_EINVAL; }
         if (!(opts->prefilter_keep >= 0.0 && opts->prefilter_keep <= 1.0)) {
             tmlib::set_error("prefilter_keep=%g outside [0, 1]", opts->prefilter_keep);
             return TM_EINVAL;
@@ -380,6 +386,19 @@ extern "C" int tm_match_batch(const tm_library* lib, const float* polar, const d
         keep = opts->prefilter_keep;
         prec = opts->prefilter_prec;
         if (prec < TM_PREC_FP32 || prec > TM_PREC_FP8) { tmlib::set_error("unknown precision %d", prec); return TM_EINVAL; }
+        coarse = opts->coarse;
+        policy = opts->rescore_policy;
+        rescore_keep = opts->rescore_keep;
+        n_rescored = opts->n_rescored;
+        if (coarse != TM_COARSE_NONE && coarse != TM_COARSE_FFT) { tmlib::set_error("unknown coarse scorer %d", coarse); return TM_EINVAL; }
+        if (policy != TM_RESCORE_CERTIFIED && policy != TM_RESCORE_KEEP) { tmlib::set_error("unknown rescore policy %d", policy); return TM_EINVAL; }
+        if (!(rescore_keep >= 0.0 && rescore_keep <= 1.0)) { tmlib::set_error("rescore_keep=%g outside [0, 1]", rescore_keep); return TM_EINVAL; }
+        if (coarse == TM_COARSE_FFT) {
+            if (keep > 0.0) { tmlib::set_error("the pre-filter and the coarse scorer are exclusive"); return TM_EINVAL; }
+            if (!lib->fft) { tmlib::set_error("TM_COARSE_FFT needs a library loaded with TM_LIB_FFT"); return TM_EINVAL; }
+            if (policy == TM_RESCORE_KEEP && !(rescore_keep > 0.0)) { tmlib::set_error("TM_RESCORE_KEEP needs rescore_keep > 0"); return TM_EINVAL; }
+            if (best_score) { tmlib::set_error("per-template outputs are not available with a coarse scorer"); return TM_EINVAL; }
+        }
     }
     const bool mirror = lib->Tp == 2 * lib->T;
     int32_t n_keep = 0;
@@ -398,17 +417,24 @@ extern "C" int tm_match_batch(const tm_library* lib, const float* polar, const d
     }
     if (int r = tmlib::require_device()) return r;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    if (n_keep == 0)
-        return launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score,
-                            best_score, best_angle, nullptr, 0, s);
+    if (coarse == TM_COARSE_FFT)
+        return tmlib::fft_match(lib, polar, norms, B, N, policy, rescore_keep, n_rescored,
+                                top_template, top_angle, top_score, s);
+    if (n_keep == 0) {
+        int r = tmlib::launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score,
+                                    best_score, best_angle, nullptr, 0, nullptr, nullptr, s);
+        if (!r && n_rescored) r = tmlib::fill_i32(n_rescored, B, lib->Tp, s);
+        return r;
+    }
     // pre-filter, then rescore the kept templates (and their mirrors) exactly
     const int32_t n_items = mirror ? 2 * n_keep : n_keep;
     int32_t* items = nullptr;
     TM_HIP(hipMallocAsync(reinterpret_cast<void**>(&items),
                           static_cast<size_t>(B) * n_items * sizeof(int32_t), s));
     int r = tmlib::prefilter_kept(lib, profiles, B, n_keep, prec, items, n_items, mirror, s);
-    if (!r) r = launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score,
-                             nullptr, nullptr, items, n_items, s);
+    if (!r) r = tmlib::launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score,
+                                    nullptr, nullptr, items, n_items, nullptr, nullptr, s);
+    if (!r && n_rescored) r = tmlib::fill_i32(n_rescored, B, n_items, s);
     hipError_t e = hipFreeAsync(items, s);
     if (!r && e != hipSuccess) r = tmlib::hip_fail(e, "hipFreeAsync");
     return r;
@@ -431,6 +457,7 @@ extern "C" int tm_match_candidates(const tm_library* lib, const float* polar, co
         return TM_EINVAL;
     }
     if (int r = tmlib::require_device()) return r;
-    return launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score, nullptr,
-                        nullptr, candidates, n_cand, static_cast<hipStream_t>(hip_stream));
+    return tmlib::launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score, nullptr,
+                               nullptr, candidates, n_cand, nullptr, nullptr,
+                               static_cast<hipStream_t>(hip_stream));
 }

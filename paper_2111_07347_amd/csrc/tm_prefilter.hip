@@ -251,6 +251,13 @@ int tmlib::prefilter_kept(const tm_library* lib, const float* profiles, int32_t 
     return r;
 }
 
+int tmlib::select_top(const float* S, int32_t B, int32_t n, int32_t n_keep, int32_t* items,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(select_kept, dim3(B), dim3(kSelThreads), 0, s, S, n, n_keep, items, n_keep, 0);
+    TM_HIP(hipGetLastError());
+    return TM_OK;
+}
+
 extern "C" int tm_prefilter(const tm_library* lib, const float* profiles, int32_t B,
                             int32_t n_keep, int32_t precision, int32_t* kept, void* hip_stream) {
     tmlib::clear_error();

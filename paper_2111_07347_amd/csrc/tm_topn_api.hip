@@ -27,13 +27,13 @@ topn_kernel(const float* __restrict__ best_q, const short* __restrict__ best_s, 
     const int lo = static_cast<int>((static_cast<long long>(T) * wave) / kTopnWaves);
     const int hi = static_cast<int>((static_cast<long long>(T) * (wave + 1)) / kTopnWaves);
     const float* q_row = best_q + static_cast<size_t>(b) * T;
-    const short* s_row = best_s + static_cast<size_t>(b) * T;
+    const short* s_row = best_s ? best_s + static_cast<size_t>(b) * T : nullptr;
     tmlib::TopState st = tmlib::topn_init();
     for (int base = lo; base < hi; base += 64) {
         const int t = base + lane;
         const bool ok = t < hi;
         const float q = ok ? q_row[t] : -INFINITY;
-        const int s = ok ? s_row[t] : 0;
+        const int s = (ok && best_s) ? s_row[t] : 0;
         unsigned long long msk = tmlib::ballot(ok && (st.cnt < N || tmlib::topn_beats(st, q, t)));
         while (msk) {
             const int l = __ffsll(static_cast<long long>(msk)) - 1;
@@ -50,6 +50,17 @@ topn_kernel(const float* __restrict__ best_q, const short* __restrict__ best_s, 
 
 }  // namespace
 
+int tmlib::launch_topn(const float* best_score, const int16_t* best_angle, int32_t B, int32_t T,
+                       int32_t N, int32_t* top_template, int32_t* top_angle, float* top_score,
+                       hipStream_t s) {
+    const size_t lds = tmlib::topn_merge_bytes(kTopnWaves, N);
+    hipLaunchKernelGGL(topn_kernel, dim3(B), dim3(kTopnThreads), lds, s, best_score,
+                       reinterpret_cast<const short*>(best_angle), T, N, top_template, top_angle,
+                       top_score);
+    TM_HIP(hipGetLastError());
+    return TM_OK;
+}
+
 extern "C" int tm_topn(const float* best_score, const int16_t* best_angle, int32_t B, int32_t T,
                        int32_t N, int32_t* top_template, int32_t* top_angle, float* top_score,
                        void* hip_stream) {
@@ -65,11 +76,6 @@ extern "C" int tm_topn(const float* best_score, const int16_t* best_angle, int32
         return TM_EINVAL;
     }
     if (int r = tmlib::require_device()) return r;
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    const size_t lds = tmlib::topn_merge_bytes(kTopnWaves, N);
-    hipLaunchKernelGGL(topn_kernel, dim3(B), dim3(kTopnThreads), lds, s, best_score,
-                       reinterpret_cast<const short*>(best_angle), T, N, top_template, top_angle,
-                       top_score);
-    TM_HIP(hipGetLastError());
-    return TM_OK;
+    return tmlib::launch_topn(best_score, best_angle, B, T, N, top_template, top_angle, top_score,
+                              static_cast<hipStream_t>(hip_stream));
 }

@@ -71,6 +71,11 @@ def test_load_library_argument_errors(tm):
                              -1.0, ctypes.byref(g), 1, None, ctypes.byref(h)) == tm.TM_EINVAL
     assert L.tm_load_library(kx.ctypes.data, kx.ctypes.data, kx.ctypes.data, off.ctypes.data, 1,
                              10.0, ctypes.byref(g), 64, None, ctypes.byref(h)) == tm.TM_EINVAL
+    # the Fourier route needs an even polar width
+    assert L.tm_load_library(kx.ctypes.data, kx.ctypes.data, kx.ctypes.data, off.ctypes.data, 1,
+                             10.0, ctypes.byref(_grid(tm, n_theta=361)), 1 | tm.TM_LIB_FFT, None,
+                             ctypes.byref(h)) == tm.TM_EUNSUPPORTED
+    assert "even" in tm.last_error()
     bad_off = np.array([0, 3, 2], dtype=np.int64)
     assert L.tm_load_library(kx.ctypes.data, kx.ctypes.data, kx.ctypes.data, bad_off.ctypes.data,
                              2, 10.0, ctypes.byref(g), 1, None, ctypes.byref(h)) == tm.TM_EINVAL
@@ -101,6 +106,9 @@ def test_polar_and_topn_argument_errors(tm):
     assert L.tm_topn(None, None, 0, 10, 3, None, None, None, None) == tm.TM_OK
     assert L.tm_match_batch(None, buf, buf, None, 1, None, 1, buf, buf, buf, None, None,
                             None) == tm.TM_EINVAL
+    e = ctypes.c_double()
+    assert L.tm_fft_error_bound(None, ctypes.byref(e)) == tm.TM_EINVAL
+    assert L.tm_fft_scores(None, buf, buf, 1, buf, None, None) == tm.TM_EINVAL
     assert L.tm_free_library(None) == tm.TM_OK
     assert L.tm_library_info(None, None, None, None) == tm.TM_EINVAL
 

@@ -406,3 +406,53 @@ def test_oracle_does_not_import_product():
             "assert not bad, bad")
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     subprocess.run([sys.executable, "-c", code], cwd=root, check=True)
+
+
+# ------------------------------------------------ Fourier route along theta
+def test_fft_route_numerator_equals_shift_sum_brute_force():
+    """Section 3: the in-plane search is a circular cross-correlation along
+    theta. On a tiny case the Fourier-route numerator must equal the plain
+    double sum over (row, column) of T[j, c] * P[j, (c + s) mod n_theta]."""
+    lib, olib = _lib(R=12, n_theta=20, n=5, seed=11, px_per=9.0)
+    rng = np.random.default_rng(12)
+    P = rng.standard_normal((olib.R, olib.n_theta))
+    C = oracle.fft_numerators64(P, olib, 0, olib.n_total)
+    for t in range(olib.n_total):
+        D = _dense_template(olib, t)
+        for s in range(olib.n_theta):
+            ref = 0.0
+            for j in range(olib.R):
+                for c in range(olib.n_theta):
+                    ref += D[j, c] * P[j, (c + s) % olib.n_theta]
+            assert abs(C[t, s] - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+def test_fft_route_dense_images_and_mirror_reflection():
+    """Dense template images carry exactly the merged weights; the mirror
+    image is the base image reflected k -> -k (Section 2.2, Fig. 2 f)."""
+    lib, olib = _lib(n=10, seed=13)
+    D = oracle.template_images64(olib, 0, olib.n_total)
+    T = olib.T_base
+    for t in range(olib.n_total):
+        assert np.array_equal(D[t], _dense_template(olib, t))
+        assert np.isclose(np.sqrt((D[t] ** 2).sum()), olib.tnorm[t], rtol=1e-15)
+    refl = np.roll(D[:T, :, ::-1], 1, axis=2)        # column k -> (-k) mod n_theta
+    assert np.allclose(D[T:], refl, atol=0)
+
+
+def test_fft_route_matches_direct_search():
+    """The Fourier route reaches the direct search's result: best Q to
+    1e-12 and the same smallest maximising shift wherever the best shift is
+    unique by more than 1e-9."""
+    lib, olib = _lib(n=30, seed=14)
+    rng = np.random.default_rng(15)
+    for trial in range(3):
+        P = rng.random((olib.R, olib.n_theta)) ** 3
+        best_d, arg_d = oracle.match_exact64(P, olib)
+        best_f, arg_f = oracle.fft_match64(P, olib, chunk=7)
+        assert np.allclose(best_f, best_d, rtol=0, atol=1e-12)
+        Q = oracle.scores64(P, olib)
+        for t in range(olib.n_total):
+            q = np.sort(Q[t])[::-1]
+            if q[0] - q[1] > 1e-9:
+                assert arg_f[t] == arg_d[t]
