@@ -46,11 +46,12 @@ constexpr int kScaleT = 8;     // template spectra x 2^8 before float16 rounding
 constexpr int kScaleP = 8;     // pattern spectra x 2^8
 constexpr int kScaleW = 12;    // inverse cosine / sine tables x 2^12
 constexpr int kDftRows = 32;   // polar rows per fft_patterns workgroup
-constexpr int kInvWaves = 8;   // fft_inverse: 4 pair tiles x 2 halves of the shifts
+constexpr int kFwdWaves = 8;   // fft_forward: 2 row blocks x 4 column blocks of 32
+constexpr int kInvWaves = 12;  // fft_inverse: 6 pair tiles x 2 halves of the shifts
 constexpr int kInvTiles = kInvWaves / 2;
 constexpr int kInvMaxBlocks = 3;                // 32-shift blocks per wave per part
 constexpr size_t kInvLdsBudget = 160 * 1024 - 2048;
-constexpr double kChatBudget = 8.0 * 1024 * 1024 * 1024;   // bytes of stored C(k)
+constexpr double kChatBudget = 16.0 * 1024 * 1024 * 1024;  // bytes of stored C(k)
 constexpr int kSelThreads = 256;
 
 // ---------------------------------------------------------------- host side
@@ -216,77 +217,101 @@ fft_patterns(const float* __restrict__ polar, const double* __restrict__ norms, 
     }
 }
 
-// C(k) for a tile of 32 base templates x 64 patterns, all frequencies.
-// Wave w: rows 32 * (w & 1) .. (16 templates x re/im), columns of two
-// 32-column blocks 64 * (w >> 1) .. (2 x 16 patterns x re/im).
+// Linear workgroup id remapped so that consecutive ids on one XCD (hardware
+// ids l, l + 8, l + 16, ...) get consecutive work items: workgroups sharing
+// a template tile then share that XCD's L2.
+__device__ __forceinline__ int xcd_item(int L, int n) {
+    const int q = n / 8, r = n % 8, x = L % 8, slot = L / 8;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + slot;
+}
+
+// C(k) for a tile of 32 base templates x 64 patterns at the four frequencies
+// of one record chunk (one parity). The grid runs chunk-major: all
+// workgroups in flight share one chunk's pattern spectra (L2-resident), and
+// the XCD remap keeps the workgroups of one template tile on one XCD.
+// Per frequency, the workgroup stages the template tile (64 rows: 32
+// templates x re/im) and the pattern tile (128 columns: 64 patterns x re/im)
+// in LDS, in slabs of up to 128 rows j, with rows padded by 16 bytes so that
+// the 16-byte fragment reads of 16 lanes hit distinct banks.
+// Wave w: rows 32 * (w & 1) .. (16 templates x re/im), columns of the
+// 32-column block 32 * (w >> 1) .. (16 patterns x re/im).
 // MFMA 32x32x16 output: lane l holds column l % 32, rows 8 (v / 4) +
 // 4 (l / 32) + v % 4, so a lane has both halves (a, b) of its templates and
 // one half (c or d) of its pattern; lane l ^ 1 has the other half.
-__global__ void __launch_bounds__(256, 2)
+constexpr int kFwdSlab = 128;                  // rows j per LDS slab
+constexpr int kFwdPitch = kFwdSlab + 8;        // halves per LDS row
+constexpr int kFwdRows = 64 + 128;             // template rows + pattern columns
+
+__global__ void __launch_bounds__(kFwdWaves * 64, 4)
 fft_forward(const _Float16* __restrict__ Th, const _Float16* __restrict__ Ph,
             _Float16* __restrict__ Ch, int T, int Tp, int Tpad, int Rp, int Fp, int nbp,
             float resc) {
+    __shared__ _Float16 tile[kFwdRows * kFwdPitch];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int rb = wave & 1, cb0 = (wave >> 1) * 2;
-    const int t0 = blockIdx.y * 32, b0 = blockIdx.x * 64;
+    const int rb = wave & 1, cb0 = wave >> 1;
+    const int n_pt = nbp / 64;
+    const int group = n_pt * (Tpad / 32);
+    const int kc = static_cast<int>(blockIdx.x) / group;          // record chunk: parity, q
+    const int item = xcd_item(static_cast<int>(blockIdx.x) - kc * group, group);
+    const int t0 = (item / n_pt) * 32, b0 = (item % n_pt) * 64;
     const int col = lane & 31, hi = lane >> 5;
     const bool odd = lane & 1;
-    const int Q = Fp / 8, KS = Rp / 16;
+    const int Q = Fp / 8;
+    const int p = kc / Q, q = kc - p * Q;
     const size_t slabA = static_cast<size_t>(2) * Tpad * Rp;
     const size_t slabB = static_cast<size_t>(2) * nbp * Rp;
-    const size_t a_off = static_cast<size_t>(2 * t0 + rb * 32 + col) * Rp + 8 * hi;
-    const size_t b_off = static_cast<size_t>(2 * b0 + cb0 * 32 + col) * Rp + 8 * hi;
     const bool mirror = Tp > T;
-    const size_t chunk_stride = static_cast<size_t>(Tp) * nbp;   // records per chunk
-    for (int p = 0; p < 2; ++p) {
-        for (int q = 0; q < Q; ++q) {
-            uint32_t stage[2][8][4];
+    const _Float16* a_frag = tile + (rb * 32 + col) * kFwdPitch + 8 * hi;
+    const _Float16* b_frag = tile + (64 + cb0 * 32 + col) * kFwdPitch + 8 * hi;
+    uint32_t stage[8][4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int k = p + 8 * q + 2 * e;
-                const _Float16* A = Th + k * slabA + a_off;
-                const _Float16* X = Ph + k * slabB + b_off;
-                f32x16_t acc0 = {}, acc1 = {};
-                for (int ks = 0; ks < KS; ++ks) {
-                    const f16x8_t a = *reinterpret_cast<const f16x8_t*>(A + ks * 16);
-                    const f16x8_t x0 = *reinterpret_cast<const f16x8_t*>(X + ks * 16);
-                    const f16x8_t x1 = *reinterpret_cast<const f16x8_t*>(X + 32 * Rp + ks * 16);
-                    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, x0, acc0, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, x1, acc1, 0, 0, 0);
-                }
-#pragma unroll
-                for (int cb = 0; cb < 2; ++cb) {
-                    const f32x16_t& acc = cb ? acc1 : acc0;
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) {       // i = 2 g + h2, rows 8 g + 4 hi + 2 h2 + {0, 1}
-                        const int v = 4 * (i >> 1) + 2 * (i & 1);
-                        const float own0 = acc[v], own1 = acc[v + 1];   // a x, b x
-                        const float par0 = dpp_xor1(own0), par1 = dpp_xor1(own1);
-                        const float s1 = own0 + par1, s2 = par0 - own1;
-                        const float X_ = odd ? s2 : s1, Y_ = odd ? s1 : s2;
-                        stage[cb][i][e] = pack_half2(X_ * resc, Y_ * resc);
-                    }
-                }
+    for (int e = 0; e < 4; ++e) {
+        const int k = p + 8 * q + 2 * e;
+        const _Float16* A = Th + k * slabA + static_cast<size_t>(2 * t0) * Rp;
+        const _Float16* X = Ph + k * slabB + static_cast<size_t>(2 * b0) * Rp;
+        f32x16_t acc = {};
+        for (int j0 = 0; j0 < Rp; j0 += kFwdSlab) {
+            const int w = min(kFwdSlab, Rp - j0);              // multiple of 16
+            const int vpr = w / 8;                               // 16-byte vectors per row
+            __syncthreads();
+            for (int i = threadIdx.x; i < kFwdRows * vpr; i += kFwdWaves * 64) {
+                const int r = i / vpr, c = i - r * vpr;
+                const _Float16* src = r < 64 ? A + static_cast<size_t>(r) * Rp
+                                             : X + static_cast<size_t>(r - 64) * Rp;
+                *reinterpret_cast<uint4*>(tile + r * kFwdPitch + c * 8) =
+                    *reinterpret_cast<const uint4*>(src + j0 + c * 8);
             }
-            const size_t cbase = static_cast<size_t>(p * Q + q) * chunk_stride;
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-                const int b = b0 + (cb0 + cb) * 16 + (col >> 1);
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int tau = 4 * (i >> 1) + 2 * hi + (i & 1);
-                    const int t = t0 + rb * 16 + tau;
-                    if (t >= T || (odd && !mirror)) continue;
-                    const int tq = odd ? T + t : t;
-                    uint4 v;
-                    v.x = stage[cb][i][0];
-                    v.y = stage[cb][i][1];
-                    v.z = stage[cb][i][2];
-                    v.w = stage[cb][i][3];
-                    *reinterpret_cast<uint4*>(Ch + (cbase + static_cast<size_t>(tq) * nbp + b) * 8) = v;
-                }
+            __syncthreads();
+            for (int ks = 0; ks < w / 16; ++ks) {
+                const f16x8_t a = *reinterpret_cast<const f16x8_t*>(a_frag + ks * 16);
+                const f16x8_t x = *reinterpret_cast<const f16x8_t*>(b_frag + ks * 16);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, x, acc, 0, 0, 0);
             }
         }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {       // i = 2 g + h2, rows 8 g + 4 hi + 2 h2 + {0, 1}
+            const int v = 4 * (i >> 1) + 2 * (i & 1);
+            const float own0 = acc[v], own1 = acc[v + 1];   // a x, b x
+            const float par0 = dpp_xor1(own0), par1 = dpp_xor1(own1);
+            const float s1 = own0 + par1, s2 = par0 - own1;
+            const float X_ = odd ? s2 : s1, Y_ = odd ? s1 : s2;
+            stage[i][e] = pack_half2(X_ * resc, Y_ * resc);
+        }
+    }
+    const size_t cbase = static_cast<size_t>(kc) * Tp * nbp;
+    const int b = b0 + cb0 * 16 + (col >> 1);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int tau = 4 * (i >> 1) + 2 * hi + (i & 1);
+        const int t = t0 + rb * 16 + tau;
+        if (t >= T || (odd && !mirror)) continue;
+        const int tq = odd ? T + t : t;
+        uint4 v;
+        v.x = stage[i][0];
+        v.y = stage[i][1];
+        v.z = stage[i][2];
+        v.w = stage[i][3];
+        *reinterpret_cast<uint4*>(Ch + (cbase + static_cast<size_t>(tq) * nbp + b) * 8) = v;
     }
 }
 
@@ -513,7 +538,7 @@ int fft_scores_impl(const tm_library* L, const float* polar, const double* norms
         hipLaunchKernelGGL(fft_patterns, dim3(nbp, (Rp + kDftRows - 1) / kDftRows), dim3(256),
                            dft_lds, s, polar + c0 * R * n, norms + c0, R, n, F, Fp, Rp, nb,
                            2 * nbp, L->d_fft_dft, Ph);
-        hipLaunchKernelGGL(fft_forward, dim3(nbp / 64, Tpad / 32), dim3(256), 0, s,
+        hipLaunchKernelGGL(fft_forward, dim3((Fp / 4) * (nbp / 64) * (Tpad / 32)), dim3(kFwdWaves * 64), 0, s,
                            reinterpret_cast<const _Float16*>(L->d_fft_t), Ph, Ch, L->T, Tp, Tpad,
                            Rp, Fp, nbp, resc);
         const int n_tiles = Tp * (nbp / 32);
