@@ -55,9 +55,9 @@ def parse():
                     help="fraction of base templates the pre-filter keeps")
     ap.add_argument("--no-fft", action="store_true",
                     help="skip the Fourier-route (coarse + certified rescoring) leg")
-    ap.add_argument("--serving-rows", type=int, default=256,
+    ap.add_argument("--serving-rows", type=int, default=1024,
                     help="scan rows replayed through the serving loop (0 = skip)")
-    ap.add_argument("--serving-distinct", type=int, default=32,
+    ap.add_argument("--serving-distinct", type=int, default=128,
                     help="distinct generated rows, replayed cyclically")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy three times (reference for the "
@@ -84,12 +84,13 @@ def recorded_traffic(cid, kernel_prefix):
     return None
 
 
-def oracle_baseline(cfg, lib_np, n_sample, procs):
-    """FP64 oracle patterns/s on a bounded sample (patterns p = 0 mod 64)."""
+def oracle_baseline(cfg, lib_np, n_sample, procs, B):
+    """FP64 oracle patterns/s on a bounded sample (every (B // n_sample)-th
+    pattern of the batch)."""
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     import oracle
     import synth
-    idx = list(range(0, cfg.B, max(1, cfg.B // n_sample)))[:n_sample]
+    idx = list(range(0, B, max(1, B // n_sample)))[:n_sample]
     imgs = synth.make_patterns(cfg, lib_np, idx)
     olib = oracle.OracleLibrary.build(lib_np, synth.px_per_inv_A(cfg), cfg.R, cfg.n_theta)
     t0 = time.perf_counter()
@@ -197,6 +198,13 @@ def fft_bench(tm, a, lib_np, cfg, grid, px, x, polar, norms, prof, N, B, stream,
     flops = 2.0 * (4.0 * B * (Tp // 2 if Tp == 2 * cfg.n_templates else Tp) * cfg.R * F
                    + B * Tp * F * cfg.n_theta)
     achieved = hbm_bytes / (coarse_ms * 1e-3) / 1e9
+    # measured HBM traffic of one call: per-launch counter record of the three
+    # kernels times the pattern chunks of a call (C(k) kept within 16 GiB)
+    Fp = (F + 15) // 16 * 16
+    bc = max(64, int(16 * 2 ** 30 / (Fp * Tp * 4.0)) // 64 * 64)
+    n_chunks = -(-B // bc)
+    per_launch = [recorded_traffic(a.config, k) for k in ("fft_patterns", "fft_forward", "fft_inverse")]
+    traffic = sum(per_launch) * n_chunks if all(v is not None for v in per_launch) else None
     res = {
         "value": round(B * a.steps / fwall, 1), "unit": "patterns/s",
         "ms_per_step": round(fwall / a.steps * 1e3, 4),
@@ -213,6 +221,7 @@ def fft_bench(tm, a, lib_np, cfg, grid, px, x, polar, norms, prof, N, B, stream,
         "roofline": {"bound": "hbm", "kernels": "fft_patterns + fft_forward + fft_inverse",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "pattern_chunks": n_chunks,
                      "work_per_launch": {"hbm_bytes": hbm_bytes, "mfma_flops": flops},
                      "mfma_tflops": round(flops / (coarse_ms * 1e-3) / 1e12, 1),
                      "mfma_frac_fp16": round(flops / (coarse_ms * 1e-3) / 1e12 / 2500.0, 4)},
@@ -377,10 +386,10 @@ def main():
     top1 = None
     if not a.no_cpu:
         procs = a.cpu_procs or min(16, os.cpu_count() or 1)
-        idx, (ot, os_, oq), dt = oracle_baseline(cfg, lib_np, min(a.cpu_sample, B), procs)
+        idx, (ot, os_, oq), dt = oracle_baseline(cfg, lib_np, min(a.cpu_sample, B), procs, B)
         cpu = {"value": round(len(idx) / dt, 2), "unit": "patterns/s", "cores": procs,
                "kind": "oracle",
-               "sample": f"{len(idx)} patterns (index = 0 mod {max(1, cfg.B // len(idx))}) of "
+               "sample": f"{len(idx)} patterns (index = 0 mod {max(1, B // len(idx))}) of "
                          f"the same workload, FP64 NumPy, {procs} processes"}
         gt = plain_top[0].cpu().numpy()
         top1 = float(np.mean(gt[idx, 0] == ot[:, 0]))

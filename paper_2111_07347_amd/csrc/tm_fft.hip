@@ -45,7 +45,7 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
 constexpr int kScaleT = 8;     // template spectra x 2^8 before float16 rounding
 constexpr int kScaleP = 8;     // pattern spectra x 2^8
 constexpr int kScaleW = 12;    // inverse cosine / sine tables x 2^12
-constexpr int kDftRows = 32;   // polar rows per fft_patterns workgroup
+constexpr int kDftRows = 8;    // polar rows per fft_patterns workgroup (one 16-byte store)
 constexpr int kFwdWaves = 8;   // fft_forward: 2 row blocks x 4 column blocks of 32
 constexpr int kInvWaves = 12;  // fft_inverse: 6 pair tiles x 2 halves of the shifts
 constexpr int kInvTiles = kInvWaves / 2;
@@ -157,15 +157,23 @@ __device__ __forceinline__ uint32_t pack_half2(float lo, float hi) {
            (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, b)) << 16);
 }
 
-// Pattern spectra of one chunk: workgroup (pattern bl, rows j0..j0+31); item
-// (k, 8-row group) sums its rows against cos / sin of 2 pi (k theta mod n)/n
-// in float64, then scales by 2^8/||P|| and rounds to float16.
+// Pattern spectra of one chunk: workgroup (pattern bl, rows j0..j0+7), in
+// float64 by one Cooley-Tukey split n = n1 * n2 (theta = n2 a + b,
+// k = k1 + n1 k2, W(m) = e^{-2 pi i m / n}):
+//   Z[k1][b] = W(k1 b) * sum_a x[n2 a + b] W(n2 a k1)      (n2 DFTs of length n1)
+//   X[k]     = sum_b Z[k1][b] W(n1 b k2)                    (k < F only)
+// then scaled by 2^8/||P|| and rounded to float16. Thread item of the second
+// stage: one frequency for all 8 rows (one 16-byte store per half).
 __global__ void __launch_bounds__(256)
 fft_patterns(const float* __restrict__ polar, const double* __restrict__ norms, int R,
-             int n_theta, int F, int Fp, int Rp, int nb_valid, int ld_cols,
+             int n_theta, int n1, int F, int Fp, int Rp, int nb_valid, int ld_cols,
              const double* __restrict__ dft, _Float16* __restrict__ Ph) {
-    extern __shared__ float xs[];                        // [kDftRows][n_theta]
-    double* cs = reinterpret_cast<double*>(xs + kDftRows * n_theta);   // [n_theta][2]
+    extern __shared__ double smem[];
+    double* cs = smem;                                   // [n_theta][2] cos, sin
+    double* zr = cs + 2 * n_theta;                       // [kDftRows][n_theta] re Z
+    double* zi = zr + kDftRows * n_theta;                // [kDftRows][n_theta] im Z
+    float* xs = reinterpret_cast<float*>(zi + kDftRows * n_theta);   // [kDftRows][n_theta]
+    const int n2 = n_theta / n1;
     const int bl = blockIdx.x;
     const int j0 = blockIdx.y * kDftRows;
     const bool valid = bl < nb_valid;
@@ -174,47 +182,78 @@ fft_patterns(const float* __restrict__ polar, const double* __restrict__ norms, 
         const double pn = norms[bl];
         scale = pn > 0.0 ? 256.0 / pn : 0.0;
     }
-    const float* src = polar + static_cast<size_t>(bl) * R * n_theta;
-    for (int i = threadIdx.x; i < kDftRows * n_theta; i += 256) {
-        const int r = i / n_theta, c = i - r * n_theta;
-        const int j = j0 + r;
-        xs[i] = (valid && j < R) ? src[static_cast<size_t>(j) * n_theta + c] : 0.0f;
-    }
-    for (int i = threadIdx.x; i < 2 * n_theta; i += 256) cs[i] = dft[i];
-    __syncthreads();
-    constexpr int kGroups = kDftRows / 8;
-    for (int it = threadIdx.x; it < Fp * kGroups; it += 256) {
-        const int k = it / kGroups, rg = it - k * kGroups;
-        const int jr = j0 + rg * 8;
-        if (jr >= Rp) continue;
-        double re[8], im[8];
-#pragma unroll
-        for (int r = 0; r < 8; ++r) re[r] = im[r] = 0.0;
-        if (k < F && scale != 0.0 && jr < R) {
-            const float* x = xs + rg * 8 * n_theta;
+    const bool live = scale != 0.0 && j0 < R;
+    if (live) {
+        const float* src = polar + static_cast<size_t>(bl) * R * n_theta;
+        for (int i = threadIdx.x; i < kDftRows * n_theta; i += 256) {
+            const int r = i / n_theta, c = i - r * n_theta;
+            const int j = j0 + r;
+            xs[i] = j < R ? src[static_cast<size_t>(j) * n_theta + c] : 0.0f;
+        }
+        for (int i = threadIdx.x; i < 2 * n_theta; i += 256) cs[i] = dft[i];
+        __syncthreads();
+        // first stage: item (row r, k1, b)
+        for (int it = threadIdx.x; it < kDftRows * n_theta; it += 256) {
+            const int r = it / n_theta, rem = it - r * n_theta;
+            const int k1 = rem / n2, b = rem - k1 * n2;
+            const float* x = xs + r * n_theta + b;
+            double yr = 0.0, yi = 0.0;
+            const int step = n2 * k1;                    // W(n2 a k1), a = 0, 1, ...
             int m = 0;
-            for (int c = 0; c < n_theta; ++c) {
-                const double co = cs[2 * m], si = cs[2 * m + 1];
+            for (int a = 0; a < n1; ++a) {
+                const double v = x[n2 * a];
+                yr = fma(v, cs[2 * m], yr);
+                yi = fma(-v, cs[2 * m + 1], yi);
+                m += step;
+                if (m >= n_theta) m -= n_theta;
+            }
+            const int mt = (k1 * b) % n_theta;           // twiddle W(k1 b)
+            const double c = cs[2 * mt], sn = -cs[2 * mt + 1];
+            zr[it] = yr * c - yi * sn;
+            zi[it] = yr * sn + yi * c;
+        }
+        __syncthreads();
+    }
+    // second stage: item k, all rows
+    for (int k = threadIdx.x; k < Fp; k += 256) {
+        double xr[kDftRows], xi[kDftRows];
 #pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    const double v = x[r * n_theta + c];
-                    re[r] = fma(v, co, re[r]);
-                    im[r] = fma(-v, si, im[r]);
+        for (int r = 0; r < kDftRows; ++r) xr[r] = xi[r] = 0.0;
+        if (live && k < F) {
+            const int k1 = k % n1, k2 = k / n1;
+            const int step = (n1 * k2) % n_theta;        // W(n1 b k2), b = 0, 1, ...
+            int m = 0;
+            for (int b = 0; b < n2; ++b) {
+                const double c = cs[2 * m], sn = -cs[2 * m + 1];
+#pragma unroll
+                for (int r = 0; r < kDftRows; ++r) {
+                    const double ar = zr[r * n_theta + k1 * n2 + b];
+                    const double ai = zi[r * n_theta + k1 * n2 + b];
+                    xr[r] = fma(ar, c, fma(-ai, sn, xr[r]));
+                    xi[r] = fma(ar, sn, fma(ai, c, xi[r]));
                 }
-                m += k;
+                m += step;
                 if (m >= n_theta) m -= n_theta;
             }
         }
         f16x8_t vr, vi;
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            vr[r] = static_cast<_Float16>(static_cast<float>(re[r] * scale));
-            vi[r] = static_cast<_Float16>(static_cast<float>(im[r] * scale));
+            vr[r] = static_cast<_Float16>(static_cast<float>(xr[r] * scale));
+            vi[r] = static_cast<_Float16>(static_cast<float>(xi[r] * scale));
         }
-        _Float16* dst = Ph + (static_cast<size_t>(k) * ld_cols + 2 * bl) * Rp + jr;
+        _Float16* dst = Ph + (static_cast<size_t>(k) * ld_cols + 2 * bl) * Rp + j0;
         *reinterpret_cast<f16x8_t*>(dst) = vr;
         *reinterpret_cast<f16x8_t*>(dst + Rp) = vi;
     }
+}
+
+// Split n = n1 * n2 with n1 the largest divisor not above sqrt(n).
+int dft_split(int n) {
+    int best = 1;
+    for (int d = 1; d * d <= n; ++d)
+        if (n % d == 0) best = d;
+    return best;
 }
 
 // Linear workgroup id remapped so that consecutive ids on one XCD (hardware
@@ -519,7 +558,10 @@ int fft_scores_impl(const tm_library* L, const float* polar, const double* norms
     part_blocks = std::min(part_blocks, NB);
     const int n_parts = (NB + part_blocks - 1) / part_blocks;
     const size_t inv_lds = block_bytes * part_blocks;
-    const size_t dft_lds = static_cast<size_t>(kDftRows) * n * sizeof(float) + 2 * n * sizeof(double);
+    const size_t dft_lds = 2 * static_cast<size_t>(n) * sizeof(double) +
+                           2 * static_cast<size_t>(kDftRows) * n * sizeof(double) +
+                           static_cast<size_t>(kDftRows) * n * sizeof(float);
+    const int n1 = dft_split(n);
     auto inv = St ? fft_inverse<true> : fft_inverse<false>;
     TM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(inv),
                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(inv_lds)));
@@ -535,8 +577,8 @@ int fft_scores_impl(const tm_library* L, const float* polar, const double* norms
     for (int64_t c0 = 0; !r && c0 < B; c0 += bc) {
         const int nb = static_cast<int>(std::min<int64_t>(bc, B - c0));
         const int nbp = (nb + 63) / 64 * 64;
-        hipLaunchKernelGGL(fft_patterns, dim3(nbp, (Rp + kDftRows - 1) / kDftRows), dim3(256),
-                           dft_lds, s, polar + c0 * R * n, norms + c0, R, n, F, Fp, Rp, nb,
+        hipLaunchKernelGGL(fft_patterns, dim3(nbp, Rp / kDftRows), dim3(256),
+                           dft_lds, s, polar + c0 * R * n, norms + c0, R, n, n1, F, Fp, Rp, nb,
                            2 * nbp, L->d_fft_dft, Ph);
         hipLaunchKernelGGL(fft_forward, dim3((Fp / 4) * (nbp / 64) * (Tpad / 32)), dim3(kFwdWaves * 64), 0, s,
                            reinterpret_cast<const _Float16*>(L->d_fft_t), Ph, Ch, L->T, Tp, Tpad,

@@ -157,49 +157,47 @@ select_kept(const float* __restrict__ S, int T, int n_keep, int32_t* __restrict_
         __syncthreads();
     }
     // prefix is the n_keep-th largest key; take every key above it and the
-    // first `need` keys equal to it in index order. Each thread owns a
-    // contiguous slice of indices so the output stays in ascending order.
-    const int per = (T + kSelThreads - 1) / kSelThreads;
-    const int lo = min(T, tid * per), hi = min(T, lo + per);
+    // first `need` keys equal to it in index order. Waves own contiguous
+    // quarters of the row and compact 64 entries at a time with ballots, so
+    // the output stays in ascending order and every pass reads coalesced.
+    constexpr int W = kSelThreads / 64;
+    const int wave = tid >> 6, lane = tid & 63;
+    const unsigned long long lt = (1ull << lane) - 1;
+    const int lo = static_cast<int>((static_cast<long long>(T) * wave) / W);
+    const int hi = static_cast<int>((static_cast<long long>(T) * (wave + 1)) / W);
     int gt = 0, eq = 0;
-    for (int t = lo; t < hi; ++t) {
-        const uint32_t k = fkey(row[t]);
-        gt += k > prefix;
-        eq += k == prefix;
+    for (int base = lo; base < hi; base += 64) {
+        const int t = base + lane;
+        const uint32_t k = t < hi ? fkey(row[t]) : 0u;
+        gt += __popcll(__ballot(t < hi && k > prefix));
+        eq += __popcll(__ballot(t < hi && k == prefix));
     }
-    // exclusive scans of the equal counts, then of the taken counts
-    scan[tid] = eq;
+    if (lane == 0) { scan[2 * wave] = gt; scan[2 * wave + 1] = eq; }
     __syncthreads();
-    for (int off = 1; off < kSelThreads; off <<= 1) {
-        const int v = tid >= off ? scan[tid - off] : 0;
-        __syncthreads();
-        scan[tid] += v;
-        __syncthreads();
+    int eq_before = 0, taken_before = 0;
+    for (int w = 0; w < wave; ++w) {
+        const int e = scan[2 * w + 1];
+        const int take_eq = max(0, min(e, static_cast<int>(need) - eq_before));
+        taken_before += scan[2 * w] + take_eq;
+        eq_before += e;
     }
-    const int eq_before = scan[tid] - eq;
-    const int eq_take = max(0, min(eq, static_cast<int>(need) - eq_before));
-    const int mine = gt + eq_take;
-    __syncthreads();
-    scan[tid] = mine;
-    __syncthreads();
-    for (int off = 1; off < kSelThreads; off <<= 1) {
-        const int v = tid >= off ? scan[tid - off] : 0;
-        __syncthreads();
-        scan[tid] += v;
-        __syncthreads();
-    }
-    int pos = scan[tid] - mine;
-    int taken_eq = 0;
     int32_t* out = items + static_cast<size_t>(b) * n_items;
-    for (int t = lo; t < hi; ++t) {
-        const uint32_t k = fkey(row[t]);
-        bool take = k > prefix;
-        if (k == prefix && taken_eq < eq_take) { take = true; ++taken_eq; }
+    int pos = taken_before, eq_seen = eq_before;
+    for (int base = lo; base < hi; base += 64) {
+        const int t = base + lane;
+        const uint32_t k = t < hi ? fkey(row[t]) : 0u;
+        const bool is_eq = t < hi && k == prefix;
+        const unsigned long long meq = __ballot(is_eq);
+        const bool take = (t < hi && k > prefix) ||
+                          (is_eq && eq_seen + __popcll(meq & lt) < static_cast<int>(need));
+        const unsigned long long mt = __ballot(take);
         if (take) {
-            out[pos] = t;
-            if (mirror_T) out[n_keep + pos] = t + mirror_T;
-            ++pos;
+            const int at = pos + __popcll(mt & lt);
+            out[at] = t;
+            if (mirror_T) out[n_keep + at] = t + mirror_T;
         }
+        pos += __popcll(mt);
+        eq_seen += __popcll(meq);
     }
 }
 

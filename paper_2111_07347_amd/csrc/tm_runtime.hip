@@ -36,6 +36,24 @@ int require_device() {
         set_error("no HIP device available");
         return TM_ENODEV;
     }
+    // Scratch comes from the stream-ordered allocator; keep freed blocks in
+    // the device's default pool instead of returning them to the driver at
+    // every synchronisation, so repeated calls reuse them (once per device).
+    static std::mutex mu;
+    static std::vector<char> pool_set;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0) {
+        std::lock_guard<std::mutex> lock(mu);
+        if (pool_set.size() <= static_cast<size_t>(dev)) pool_set.resize(dev + 1, 0);
+        if (!pool_set[dev]) {
+            pool_set[dev] = 1;
+            hipMemPool_t pool;
+            if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+                uint64_t keep = UINT64_MAX;
+                hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+            }
+        }
+    }
     return TM_OK;
 }
 
