@@ -27,7 +27,7 @@ namespace {
 // LDS budgets: a band small enough for two workgroups per CU, the most a
 // single workgroup may stage, and the band size when rows must be streamed.
 constexpr size_t kSharedCuBytes = 76 * 1024;
-constexpr size_t kSingleBandBytes = 158 * 1024;
+constexpr size_t kSingleBandBytes = 160 * 1024;   // all of a CU's LDS
 constexpr size_t kBandBytes = 76 * 1024;
 
 using Pixel = tmlib::HostPixel;
