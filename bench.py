@@ -57,6 +57,8 @@ def parse():
                     help="config 5: scan rows of 256 patterns streamed (burst)")
     ap.add_argument("--c5-distinct", type=int, default=128,
                     help="config 5: distinct generated rows, replayed cyclically")
+    ap.add_argument("--full-polar", action="store_true",
+                    help="write all R polar rows (default: only the rows the library touches)")
     ap.add_argument("--no-fft", action="store_true",
                     help="skip the Fourier-route (coarse + certified rescoring) leg")
     ap.add_argument("--serving-rows", type=int, default=1024,
@@ -146,7 +148,8 @@ def serving_bench(tm, n_rows, n_distinct, workers):
     return out
 
 
-def fft_bench(tm, a, lib_np, cfg, grid, px, x, polar, norms, prof, N, B, stream, plain_top):
+def fft_bench(tm, a, lib_np, cfg, grid, px, x, polar, norms, prof, N, B, stream, plain_top,
+              plib):
     import torch
     t0 = time.perf_counter()
     flib = tm.Library(lib_np["kx"], lib_np["ky"], lib_np["intensity"], lib_np["offsets"], px,
@@ -163,7 +166,7 @@ def fft_bench(tm, a, lib_np, cfg, grid, px, x, polar, norms, prof, N, B, stream,
     def step_f(ev=None):
         if ev is not None:
             ev[0].record(stream)
-        tm.polar_transform(x, grid, polar_out=polar, norm_out=norms, profile_out=prof)
+        tm.polar_transform(x, grid, polar_out=polar, norm_out=norms, profile_out=prof, lib=plib)
         if ev is not None:
             ev[1].record(stream)
         tm.match_batch(flib, polar, norms, N, coarse="fft", n_rescored=nr, out=out)
@@ -198,8 +201,9 @@ def fft_bench(tm, a, lib_np, cfg, grid, px, x, polar, norms, prof, N, B, stream,
     # MACs of the row contraction (4 real products per base pair, row and
     # frequency) and of the inverse (per pair, F complex terms x n_theta shifts)
     chat_bytes = 2.0 * B * Tp * F * 4
-    hbm_bytes = chat_bytes + B * cfg.R * cfg.n_theta * 4
-    flops = 2.0 * (4.0 * B * (Tp // 2 if Tp == 2 * cfg.n_templates else Tp) * cfg.R * F
+    hbm_bytes = chat_bytes + B * polar.shape[1] * cfg.n_theta * 4
+    n_rows = flib.rows()[0]          # the contraction runs over the touched rows
+    flops = 2.0 * (4.0 * B * (Tp // 2 if Tp == 2 * cfg.n_templates else Tp) * n_rows * F
                    + B * Tp * F * cfg.n_theta)
     achieved = hbm_bytes / (coarse_ms * 1e-3) / 1e9
     # measured HBM traffic of one call: per-launch counter record of the three
@@ -373,7 +377,9 @@ def main():
     layout = lib.layout()
     x = torch.from_numpy(imgs).to(dev)
     del imgs
-    polar = torch.empty((B, cfg.R, cfg.n_theta), dtype=torch.float32, device=dev)
+    plib = None if a.full_polar else lib            # compact polar: the touched rows only
+    n_out_rows = cfg.R if plib is None else lib.rows()[0]
+    polar = torch.empty((B, n_out_rows, cfg.n_theta), dtype=torch.float32, device=dev)
     norms = torch.empty((B,), dtype=torch.float64, device=dev)
     prof = torch.empty((cfg.R, B), dtype=torch.float32, device=dev)
     N = cfg.N
@@ -385,7 +391,7 @@ def main():
     def step(ev=None):
         if ev is not None:
             ev[0].record(stream)
-        tm.polar_transform(x, grid, polar_out=polar, norm_out=norms, profile_out=prof)
+        tm.polar_transform(x, grid, polar_out=polar, norm_out=norms, profile_out=prof, lib=plib)
         if ev is not None:
             ev[1].record(stream)
         tm.match_batch(lib, polar, norms, N, out=out)
@@ -413,7 +419,7 @@ def main():
     macs = float(B) * n_spots * cfg.n_theta
     lds_bytes = 4.0 * macs
     in_bytes = B * cfg.H * cfg.W * x.element_size()
-    polar_bytes = in_bytes + B * cfg.R * cfg.n_theta * 4 + B * 8 + B * cfg.R * 4
+    polar_bytes = in_bytes + B * n_out_rows * cfg.n_theta * 4 + B * 8 + B * cfg.R * 4
     match_gbs = lds_bytes / (match_ms * 1e-3) / 1e9
     roofline = {
         "bound": "lds",
@@ -446,7 +452,7 @@ def main():
         def step_p(ev=None):
             if ev is not None:
                 ev[0].record(stream)
-            tm.polar_transform(x, grid, polar_out=polar, norm_out=norms, profile_out=prof)
+            tm.polar_transform(x, grid, polar_out=polar, norm_out=norms, profile_out=prof, lib=plib)
             if ev is not None:
                 ev[1].record(stream)
             tm.match_batch(lib, polar, norms, N, profiles=prof, prefilter_keep=a.keep,
@@ -480,7 +486,7 @@ def main():
     fft_path = None
     if not a.no_fft:
         fft_path = fft_bench(tm, a, lib_np, cfg, grid, px, x, polar, norms, prof, N, B, stream,
-                             plain_top)
+                             plain_top, plib)
 
     cpu = None
     top1 = None
@@ -524,6 +530,7 @@ def main():
             "B": B, "H": cfg.H, "W": cfg.W, "R": cfg.R, "n_theta": cfg.n_theta,
             "templates": cfg.n_templates, "templates_with_mirrors": info["n_templates_total"],
             "template_pixels": n_spots, "top_n": N, "path": "plain fp32",
+            "polar_rows_written": n_out_rows,
             "library_layout": layout,
             "parallelism": "single GPU",
         },

@@ -139,13 +139,16 @@ enum {
  *                     whose certified set is larger is scored in full.
  *   n_rescored        optional device [B] int32 output: templates scored
  *                     exactly per pattern (T' for a full scan), or NULL.
- *   reserved          must be zero. */
+ *   compact_rows      0: polar is [B, R, n_theta]; 1: polar holds only the
+ *                     library's touched rows in increasing order,
+ *                     [B, n_rows, n_theta] (tm_polar_transform_rows with the
+ *                     map of tm_library_rows). */
 typedef struct {
     double prefilter_keep;
     int32_t prefilter_prec;
     int32_t coarse;
     int32_t rescore_policy;
-    int32_t reserved;
+    int32_t compact_rows;
     double rescore_keep;
     int32_t* n_rescored;
 } tm_match_opts;
@@ -218,6 +221,12 @@ int tm_library_info(const tm_library* lib, int32_t* n_templates_total, int64_t* 
 int tm_library_layout(const tm_library* lib, int32_t* group, int32_t* n_bands, int32_t* n_rows,
                       int64_t* n_records, int32_t* row_width);
 
+/* tm_library_rows - the polar rows any template of lib touches: their number
+ * and a library-owned device map [R] (int32: compact index of polar row j in
+ * increasing row order, -1 if no template touches row j), valid until
+ * tm_free_library. Errors: TM_EINVAL (null library). */
+int tm_library_rows(const tm_library* lib, int32_t* n_rows, const int32_t** row_map);
+
 /* tm_polar_transform - intensity transform, polar resampling, norms and
  * azimuthal profiles of a batch of patterns (Section 2.2: gamma correction
  * and constant subtraction of the pattern; polar transform about the
@@ -245,6 +254,24 @@ int tm_polar_transform(const void* patterns, tm_dtype dtype, int32_t B, int32_t 
                        const tm_polar_grid* grid, float gamma, float subtract,
                        float* polar_out, double* norm_out, float* profile_out,
                        void* hip_stream);
+
+/* tm_polar_transform_rows - tm_polar_transform writing only selected polar
+ * rows. Every row is still sampled (||P|| and the profiles cover the whole
+ * polar image, Eq. 1); polar row j goes to output row row_map[j], or is not
+ * stored when row_map[j] < 0 (entries outside [0, n_out_rows) are not
+ * stored either). With a library's map (tm_library_rows) the output holds
+ * exactly the rows its templates touch, which is all the search reads
+ * (Section 2.2: the template is non-zero only at its spots).
+ *
+ * Arguments as in tm_polar_transform, plus
+ *   row_map      device, [R] int32, or NULL (then n_out_rows must be R).
+ *   n_out_rows   1 <= n_out_rows <= R.
+ *   polar_out    device, [B, n_out_rows, n_theta] float32, written.
+ * Errors as tm_polar_transform. */
+int tm_polar_transform_rows(const void* patterns, tm_dtype dtype, int32_t B, int32_t H,
+                            int32_t W, const tm_polar_grid* grid, float gamma, float subtract,
+                            const int32_t* row_map, int32_t n_out_rows, float* polar_out,
+                            double* norm_out, float* profile_out, void* hip_stream);
 
 /* tm_match_batch - score every template of lib against every pattern at every
  * in-plane shift and keep the N best templates per pattern (Eq. 1; Section
@@ -349,6 +376,8 @@ int tm_match_candidates(const tm_library* lib, const float* polar, const double*
  *   lib           library loaded with TM_LIB_FFT.
  *   polar, norms  as in tm_match_batch.
  *   B             >= 0 (0 is a no-op).
+ *   compact_rows  0: polar is [B, R, n_theta]; 1: [B, n_rows, n_theta] holding
+ *                 the library's touched rows (as tm_match_opts.compact_rows).
  *   approx_score  device, [B, T'] float32, written.
  *   approx_angle  device, [B, T'] int16, written, or NULL.
  * Scratch (spectra of a chunk of patterns; up to about 8 GiB) is taken from
@@ -356,7 +385,8 @@ int tm_match_candidates(const tm_library* lib, const float* polar, const double*
  * Errors: TM_EINVAL (null pointer, library without TM_LIB_FFT), TM_ENOMEM,
  *         TM_EHIP, TM_ENODEV. */
 int tm_fft_scores(const tm_library* lib, const float* polar, const double* norms, int32_t B,
-                  float* approx_score, int16_t* approx_angle, void* hip_stream);
+                  int32_t compact_rows, float* approx_score, int16_t* approx_angle,
+                  void* hip_stream);
 
 /* tm_fft_error_bound - a-priori bound eps with |Q~ - Q32| <= eps for every
  * template and shift, where Q~ is tm_fft_scores' arithmetic and Q32 the exact

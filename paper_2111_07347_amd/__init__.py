@@ -36,7 +36,7 @@ TM_RESCORE_CERTIFIED, TM_RESCORE_KEEP = 0, 1
 TM_MAX_N = 64
 
 EXPORTED = ("tm_load_library", "tm_free_library", "tm_library_info", "tm_library_layout",
-            "tm_polar_transform", "tm_match_batch", "tm_prefilter", "tm_match_candidates",
+            "tm_library_rows", "tm_polar_transform", "tm_polar_transform_rows", "tm_match_batch", "tm_prefilter", "tm_match_candidates",
             "tm_fft_scores", "tm_fft_error_bound", "tm_topn", "tm_last_error", "tm_version")
 
 
@@ -55,7 +55,7 @@ class _Grid(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("prefilter_keep", ctypes.c_double), ("prefilter_prec", ctypes.c_int32),
                 ("coarse", ctypes.c_int32), ("rescore_policy", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("rescore_keep", ctypes.c_double),
+                ("compact_rows", ctypes.c_int32), ("rescore_keep", ctypes.c_double),
                 ("n_rescored", ctypes.c_void_p)]
 
 
@@ -72,12 +72,15 @@ def _load():
         "tm_free_library": [P],
         "tm_library_info": [P, P, P, P],
         "tm_library_layout": [P, P, P, P, P, P],
+        "tm_library_rows": [P, P, ctypes.POINTER(P)],
         "tm_polar_transform": [P, ctypes.c_int, I32, I32, I32, ctypes.POINTER(_Grid), F, F, P, P,
                                P, P],
+        "tm_polar_transform_rows": [P, ctypes.c_int, I32, I32, I32, ctypes.POINTER(_Grid), F, F,
+                                    P, I32, P, P, P, P],
         "tm_match_batch": [P, P, P, P, I32, ctypes.POINTER(_Opts), I32, P, P, P, P, P, P],
         "tm_prefilter": [P, P, I32, I32, I32, P, P],
         "tm_match_candidates": [P, P, P, I32, P, I32, I32, P, P, P, P],
-        "tm_fft_scores": [P, P, P, I32, P, P, P],
+        "tm_fft_scores": [P, P, P, I32, I32, P, P, P],
         "tm_fft_error_bound": [P, ctypes.POINTER(D)],
         "tm_topn": [P, P, I32, I32, I32, P, P, P, P],
         "tm_last_error": [],
@@ -206,6 +209,15 @@ class Library:
         return {"group": g.value, "n_bands": nb.value, "n_rows": nr.value, "n_records": rec.value,
                 "row_width": rw.value, "narrow": rw.value == n_theta + 63}
 
+    def rows(self):
+        """tm_library_rows: (number of polar rows the templates touch, device
+        address of the library's [R] int32 row map)."""
+        if getattr(self, "_rows", None) is None:
+            n, m = ctypes.c_int32(), ctypes.c_void_p()
+            _check(_lib.tm_library_rows(self._h, ctypes.byref(n), ctypes.byref(m)), "tm_library_rows")
+            self._rows = (n.value, m.value)
+        return self._rows
+
     def fft_error_bound(self) -> float:
         """tm_fft_error_bound: certified bound on |Q~ - Q32| of the Fourier
         route (library loaded with fft=True)."""
@@ -231,9 +243,12 @@ class Library:
 
 def polar_transform(patterns, grid: PolarGrid, gamma: float = 1.0, subtract: float = 0.0,
                     polar_out=None, norm_out=None, profile_out=None, want_profile: bool = True,
-                    stream=None):
+                    lib: "Library | None" = None, stream=None):
     """tm_polar_transform on a [B, H, W] uint16/float32 device tensor.
-    Returns (polar [B, R, n_theta] f32, norms [B] f64, profiles [R, B] f32 or None)."""
+    Returns (polar [B, R, n_theta] f32, norms [B] f64, profiles [R, B] f32 or None).
+    With lib (tm_polar_transform_rows), polar holds only the rows lib's
+    templates touch: [B, n_rows, n_theta]; norms and profiles still cover
+    all R rows."""
     torch = _torch()
     if patterns.dtype == torch.float32:
         dt = TM_F32
@@ -247,21 +262,41 @@ def polar_transform(patterns, grid: PolarGrid, gamma: float = 1.0, subtract: flo
         raise ValueError("patterns must be a contiguous device tensor")
     B, H, W = patterns.shape
     dev = patterns.device
+    n_out, row_map = grid.R, None
+    if lib is not None and lib.rows()[0] > 0:
+        n_out, row_map = lib.rows()
     if polar_out is None:
-        polar_out = torch.empty((B, grid.R, grid.n_theta), dtype=torch.float32, device=dev)
+        polar_out = torch.empty((B, n_out, grid.n_theta), dtype=torch.float32, device=dev)
     if norm_out is None:
         norm_out = torch.empty((B,), dtype=torch.float64, device=dev)
     if profile_out is None and want_profile:
         profile_out = torch.empty((grid.R, B), dtype=torch.float32, device=dev)
-    _require(polar_out, "polar_out", torch.float32, (B, grid.R, grid.n_theta))
+    _require(polar_out, "polar_out", torch.float32, (B, n_out, grid.n_theta))
     _require(norm_out, "norm_out", torch.float64, (B,))
     if profile_out is not None:
         _require(profile_out, "profile_out", torch.float32, (grid.R, B))
     g = grid._c()
-    _check(_lib.tm_polar_transform(_ptr(patterns), dt, B, H, W, ctypes.byref(g), float(gamma),
-                                   float(subtract), _ptr(polar_out), _ptr(norm_out),
-                                   _ptr(profile_out), _stream_ptr(stream)), "tm_polar_transform")
+    if row_map is None:
+        _check(_lib.tm_polar_transform(_ptr(patterns), dt, B, H, W, ctypes.byref(g), float(gamma),
+                                       float(subtract), _ptr(polar_out), _ptr(norm_out),
+                                       _ptr(profile_out), _stream_ptr(stream)), "tm_polar_transform")
+    else:
+        _check(_lib.tm_polar_transform_rows(_ptr(patterns), dt, B, H, W, ctypes.byref(g),
+                                            float(gamma), float(subtract), row_map, int(n_out),
+                                            _ptr(polar_out), _ptr(norm_out), _ptr(profile_out),
+                                            _stream_ptr(stream)), "tm_polar_transform_rows")
     return polar_out, norm_out, profile_out
+
+
+def _layout(lib: "Library", polar) -> int:
+    """1 if polar holds only lib's touched rows, 0 if all R rows."""
+    rows = polar.shape[1]
+    if rows == lib.grid.R:
+        return 0
+    if rows == lib.rows()[0]:
+        return 1
+    raise ValueError(f"polar has {rows} rows: expected R={lib.grid.R} or the library's "
+                     f"{lib.rows()[0]} touched rows")
 
 
 COARSE = {None: TM_COARSE_NONE, "none": TM_COARSE_NONE, "fft": TM_COARSE_FFT}
@@ -269,10 +304,12 @@ RESCORE = {"certified": TM_RESCORE_CERTIFIED, "keep": TM_RESCORE_KEEP}
 
 
 def _opts(prefilter_keep: float, prefilter_prec: int, coarse: int = TM_COARSE_NONE,
-          rescore: int = TM_RESCORE_CERTIFIED, rescore_keep: float = 0.0, n_rescored=None):
-    if prefilter_keep == 0.0 and coarse == TM_COARSE_NONE and n_rescored is None:
+          rescore: int = TM_RESCORE_CERTIFIED, rescore_keep: float = 0.0, n_rescored=None,
+          compact: int = 0):
+    if prefilter_keep == 0.0 and coarse == TM_COARSE_NONE and n_rescored is None and not compact:
         return None
     o = _Opts()
+    o.compact_rows = int(compact)
     o.prefilter_keep = float(prefilter_keep)
     o.prefilter_prec = int(prefilter_prec)
     o.coarse = int(coarse)
@@ -294,7 +331,8 @@ def match_batch(lib: Library, polar, norms, N: int, profiles=None, prefilter_kee
     given receives the number of templates scored exactly per pattern."""
     torch = _torch()
     B = polar.shape[0]
-    _require(polar, "polar", torch.float32, (B, lib.grid.R, lib.grid.n_theta))
+    compact = _layout(lib, polar)
+    _require(polar, "polar", torch.float32, (B, polar.shape[1], lib.grid.n_theta))
     _require(norms, "norms", torch.float64, (B,))
     if profiles is not None:
         _require(profiles, "profiles", torch.float32, (lib.grid.R, B))
@@ -316,7 +354,7 @@ def match_batch(lib: Library, polar, norms, N: int, profiles=None, prefilter_kee
         _require(n_rescored, "n_rescored", torch.int32, (B,))
     o = _opts(prefilter_keep, _prec(prefilter_prec), COARSE[coarse],
               RESCORE[rescore] if isinstance(rescore, str) else int(rescore), rescore_keep,
-              n_rescored)
+              n_rescored, compact)
     _check(_lib.tm_match_batch(lib._h, _ptr(polar), _ptr(norms), _ptr(profiles), B,
                                ctypes.byref(o) if o is not None else None, int(N), _ptr(tt),
                                _ptr(ts), _ptr(tq), _ptr(bq), _ptr(bs), _stream_ptr(stream)),
@@ -370,12 +408,13 @@ def fft_scores(lib: Library, polar, norms, with_angle: bool = True, stream=None)
     i16 or None)."""
     torch = _torch()
     B = polar.shape[0]
-    _require(polar, "polar", torch.float32, (B, lib.grid.R, lib.grid.n_theta))
+    compact = _layout(lib, polar)
+    _require(polar, "polar", torch.float32, (B, polar.shape[1], lib.grid.n_theta))
     _require(norms, "norms", torch.float64, (B,))
     Tn = lib.n_total
     q = torch.empty((B, Tn), dtype=torch.float32, device=polar.device)
     a = torch.empty((B, Tn), dtype=torch.int16, device=polar.device) if with_angle else None
-    _check(_lib.tm_fft_scores(lib._h, _ptr(polar), _ptr(norms), B, _ptr(q), _ptr(a),
+    _check(_lib.tm_fft_scores(lib._h, _ptr(polar), _ptr(norms), B, compact, _ptr(q), _ptr(a),
                               _stream_ptr(stream)), "tm_fft_scores")
     return q, a
 

@@ -137,7 +137,7 @@ int device_cus() {
     static int n = 0;
     if (!n) {
         int dev = 0, v = 0;
-        hipGetDevice(&dev);
+        (void)hipGetDevice(&dev);
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v < 1) v = 256;
         n = v;
     }
@@ -157,7 +157,7 @@ __device__ __forceinline__ uint32_t pack_half2(float lo, float hi) {
            (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, b)) << 16);
 }
 
-// Pattern spectra of one chunk: workgroup (pattern bl, rows j0..j0+7), in
+// Pattern spectra of one chunk: workgroup (pattern bl, touched rows j0..j0+7), in
 // float64 by one Cooley-Tukey split n = n1 * n2 (theta = n2 a + b,
 // k = k1 + n1 k2, W(m) = e^{-2 pi i m / n}):
 //   Z[k1][b] = W(k1 b) * sum_a x[n2 a + b] W(n2 a k1)      (n2 DFTs of length n1)
@@ -165,9 +165,10 @@ __device__ __forceinline__ uint32_t pack_half2(float lo, float hi) {
 // then scaled by 2^8/||P|| and rounded to float16. Thread item of the second
 // stage: one frequency for all 8 rows (one 16-byte store per half).
 __global__ void __launch_bounds__(256)
-fft_patterns(const float* __restrict__ polar, const double* __restrict__ norms, int R,
-             int n_theta, int n1, int F, int Fp, int Rp, int nb_valid, int ld_cols,
-             const double* __restrict__ dft, _Float16* __restrict__ Ph) {
+fft_patterns(const float* __restrict__ polar, const double* __restrict__ norms,
+             const int* __restrict__ rows, int Rs, int nr, int n_theta, int n1, int F, int Fp,
+             int Rp, int nb_valid, int ld_cols, const double* __restrict__ dft,
+             _Float16* __restrict__ Ph) {
     extern __shared__ double smem[];
     double* cs = smem;                                   // [n_theta][2] cos, sin
     double* zr = cs + 2 * n_theta;                       // [kDftRows][n_theta] re Z
@@ -182,13 +183,15 @@ fft_patterns(const float* __restrict__ polar, const double* __restrict__ norms, 
         const double pn = norms[bl];
         scale = pn > 0.0 ? 256.0 / pn : 0.0;
     }
-    const bool live = scale != 0.0 && j0 < R;
+    const bool live = scale != 0.0 && j0 < nr;
     if (live) {
-        const float* src = polar + static_cast<size_t>(bl) * R * n_theta;
+        // spectrum row j (a touched row) reads polar row rows[j], or row j of
+        // a compact polar image
+        const float* src = polar + static_cast<size_t>(bl) * Rs * n_theta;
         for (int i = threadIdx.x; i < kDftRows * n_theta; i += 256) {
             const int r = i / n_theta, c = i - r * n_theta;
             const int j = j0 + r;
-            xs[i] = j < R ? src[static_cast<size_t>(j) * n_theta + c] : 0.0f;
+            xs[i] = j < nr ? src[static_cast<size_t>(rows ? rows[j] : j) * n_theta + c] : 0.0f;
         }
         for (int i = threadIdx.x; i < 2 * n_theta; i += 256) cs[i] = dft[i];
         __syncthreads();
@@ -541,8 +544,9 @@ int alloc_async(T** p, size_t count, hipStream_t s) {
 // Approximate per-template best scores (and angles) for B patterns, chunked
 // so that the stored C(k) stays within kChatBudget.
 int fft_scores_impl(const tm_library* L, const float* polar, const double* norms, int32_t B,
-                    float* Qt, short* St, hipStream_t s) {
-    const int n = L->n_theta, R = L->R, Tp = L->Tp;
+                    float* Qt, short* St, bool compact, hipStream_t s) {
+    const int n = L->n_theta, Tp = L->Tp;
+    const int Rs = compact ? L->n_rows : L->R;   // rows per pattern in the polar input
     const int F = L->fft_F, Fp = L->fft_Fp, Rp = L->fft_Rp, Tpad = L->fft_Tpad, Sh = L->fft_Sh;
     const double per_pattern = static_cast<double>(Fp) * Tp * 4.0;
     int64_t bc_max = static_cast<int64_t>(kChatBudget / per_pattern) / 64 * 64;
@@ -578,7 +582,8 @@ int fft_scores_impl(const tm_library* L, const float* polar, const double* norms
         const int nb = static_cast<int>(std::min<int64_t>(bc, B - c0));
         const int nbp = (nb + 63) / 64 * 64;
         hipLaunchKernelGGL(fft_patterns, dim3(nbp, Rp / kDftRows), dim3(256),
-                           dft_lds, s, polar + c0 * R * n, norms + c0, R, n, n1, F, Fp, Rp, nb,
+                           dft_lds, s, polar + c0 * Rs * n, norms + c0,
+                           compact ? nullptr : L->d_rows, Rs, L->n_rows, n, n1, F, Fp, Rp, nb,
                            2 * nbp, L->d_fft_dft, Ph);
         hipLaunchKernelGGL(fft_forward, dim3((Fp / 4) * (nbp / 64) * (Tpad / 32)), dim3(kFwdWaves * 64), 0, s,
                            reinterpret_cast<const _Float16*>(L->d_fft_t), Ph, Ch, L->T, Tp, Tpad,
@@ -593,8 +598,8 @@ int fft_scores_impl(const tm_library* L, const float* polar, const double* norms
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) r = tmlib::hip_fail(e, "Fourier-route kernel launch");
     }
-    if (Ph) hipFreeAsync(Ph, s);
-    if (Ch) hipFreeAsync(Ch, s);
+    if (Ph) (void)hipFreeAsync(Ph, s);
+    if (Ch) (void)hipFreeAsync(Ch, s);
     return r;
 }
 
@@ -610,10 +615,11 @@ int check_fft_lib(const tm_library* lib) {
 
 int tmlib::fft_prepare(tm_library* L, const std::vector<std::vector<HostPixel>>& pix,
                        hipStream_t s, size_t& bytes) {
-    const int n = L->n_theta, R = L->R, T = L->T;
+    const int n = L->n_theta, T = L->T;
     const int F = n / 2 + 1;
     const int Fp = (F + 15) / 16 * 16;
-    const int Rp = (R + 15) / 16 * 16;
+    const int nr = std::max(1, L->n_rows);       // spectra cover the touched rows only
+    const int Rp = (nr + 15) / 16 * 16;
     const int Tpad = (T + 31) / 32 * 32;
     const int half = n / 2;
     const int Sh = (half + 31) / 32 * 32;
@@ -660,7 +666,7 @@ int tmlib::fft_prepare(tm_library* L, const std::vector<std::vector<HostPixel>>&
                         if (m >= n) m -= n;
                     }
                 }
-                const int j = px[i].j;
+                const int j = L->row_index[px[i].j];
                 for (int k = 0; k < F; ++k) {
                     const size_t row = (static_cast<size_t>(k) * 2 * Tpad + 2 * t) * Rp + j;
                     th[row] = half_bits(re[k]);
@@ -700,7 +706,7 @@ int tmlib::fft_prepare(tm_library* L, const std::vector<std::vector<HostPixel>>&
     L->fft_Tpad = Tpad;
     L->fft_Sh = Sh;
     L->fft_sc = sc;
-    L->fft_eps = error_bound(R, Fp, sc, n_max);
+    L->fft_eps = error_bound(nr, Fp, sc, n_max);
     int r = upload_vec(&L->d_fft_t, th, s, bytes);
     if (!r) r = upload_vec(&L->d_fft_w, tw, s, bytes);
     if (!r) r = upload_vec(&L->d_fft_dft, cs, s, bytes);
@@ -714,9 +720,9 @@ int tmlib::fft_prepare(tm_library* L, const std::vector<std::vector<HostPixel>>&
 }
 
 void tmlib::fft_release(tm_library* L) {
-    hipFree(L->d_fft_t);
-    hipFree(L->d_fft_w);
-    hipFree(L->d_fft_dft);
+    (void)hipFree(L->d_fft_t);
+    (void)hipFree(L->d_fft_w);
+    (void)hipFree(L->d_fft_dft);
     L->d_fft_t = nullptr;
     L->d_fft_w = nullptr;
     L->d_fft_dft = nullptr;
@@ -733,11 +739,12 @@ int tmlib::fill_i32(int32_t* dst, int64_t n, int32_t value, hipStream_t s) {
 
 int tmlib::fft_match(const tm_library* lib, const float* polar, const double* norms, int32_t B,
                      int32_t N, int32_t policy, double keep, int32_t* n_rescored,
-                     int32_t* top_template, int32_t* top_angle, float* top_score, hipStream_t s) {
+                     int32_t* top_template, int32_t* top_angle, float* top_score, bool compact,
+                     hipStream_t s) {
     const int Tp = lib->Tp;
     float* Qt = nullptr;
     int r = alloc_async(&Qt, static_cast<size_t>(B) * Tp, s);
-    if (!r) r = fft_scores_impl(lib, polar, norms, B, Qt, nullptr, s);
+    if (!r) r = fft_scores_impl(lib, polar, norms, B, Qt, nullptr, compact, s);
     if (policy == TM_RESCORE_KEEP) {
         int32_t n_keep = static_cast<int32_t>(std::ceil(keep * Tp - 1e-9));
         n_keep = std::max(N, std::min(n_keep, Tp));
@@ -745,9 +752,9 @@ int tmlib::fft_match(const tm_library* lib, const float* polar, const double* no
         if (!r) r = alloc_async(&cand, static_cast<size_t>(B) * n_keep, s);
         if (!r) r = tmlib::select_top(Qt, B, Tp, n_keep, cand, s);
         if (!r) r = tmlib::launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score,
-                                        nullptr, nullptr, cand, n_keep, nullptr, nullptr, s);
+                                        nullptr, nullptr, cand, n_keep, nullptr, nullptr, compact, s);
         if (!r && n_rescored) r = tmlib::fill_i32(n_rescored, B, n_keep, s);
-        if (cand) hipFreeAsync(cand, s);
+        if (cand) (void)hipFreeAsync(cand, s);
     } else {
         const double frac = keep > 0.0 ? keep : 0.1;
         int32_t cap = static_cast<int32_t>(std::ceil(frac * Tp - 1e-9));
@@ -768,7 +775,7 @@ int tmlib::fft_match(const tm_library* lib, const float* polar, const double* no
         // 1. approximate top-N, rescored exactly: N-th best exact score
         if (!r) r = tmlib::launch_topn(Qt, nullptr, B, Tp, N, t0, s0, q0, s);
         if (!r) r = tmlib::launch_match(lib, polar, norms, B, N, t1, s1, q1, nullptr, nullptr, t0,
-                                        N, nullptr, nullptr, s);
+                                        N, nullptr, nullptr, compact, s);
         // 2. every template the bound cannot rule out
         if (!r) {
             hipLaunchKernelGGL(certify_select, dim3(B), dim3(kSelThreads), 0, s, Qt, Tp, q1, N,
@@ -778,26 +785,27 @@ int tmlib::fft_match(const tm_library* lib, const float* polar, const double* no
         }
         // 3. exact rescoring of the candidates; full scans where the set was too large
         if (!r) r = tmlib::launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score,
-                                        nullptr, nullptr, cand, cap, cnt, nullptr, s);
+                                        nullptr, nullptr, cand, cap, cnt, nullptr, compact, s);
         if (!r) r = tmlib::launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score,
-                                        nullptr, nullptr, nullptr, 0, nullptr, full, s);
+                                        nullptr, nullptr, nullptr, 0, nullptr, full, compact, s);
         for (void* p : {static_cast<void*>(t0), static_cast<void*>(s0), static_cast<void*>(q0),
                         static_cast<void*>(t1), static_cast<void*>(s1), static_cast<void*>(q1),
                         static_cast<void*>(cand), static_cast<void*>(cnt), static_cast<void*>(full)})
-            if (p) hipFreeAsync(p, s);
+            if (p) (void)hipFreeAsync(p, s);
     }
-    if (Qt) hipFreeAsync(Qt, s);
+    if (Qt) (void)hipFreeAsync(Qt, s);
     return r;
 }
 
 // --------------------------------------------------------------- C ABI
 
 extern "C" int tm_fft_scores(const tm_library* lib, const float* polar, const double* norms,
-                             int32_t B, float* approx_score, int16_t* approx_angle,
-                             void* hip_stream) {
+                             int32_t B, int32_t compact_rows, float* approx_score,
+                             int16_t* approx_angle, void* hip_stream) {
     tmlib::clear_error();
     if (int r = check_fft_lib(lib)) return r;
     if (B < 0) { tmlib::set_error("B=%d < 0", B); return TM_EINVAL; }
+    if (compact_rows != 0 && compact_rows != 1) { tmlib::set_error("compact_rows=%d must be 0 or 1", compact_rows); return TM_EINVAL; }
     if (B == 0) return TM_OK;
     if (!polar || !norms || !approx_score) {
         tmlib::set_error("polar, norms and approx_score must be non-NULL");
@@ -805,7 +813,7 @@ extern "C" int tm_fft_scores(const tm_library* lib, const float* polar, const do
     }
     if (int r = tmlib::require_device()) return r;
     return fft_scores_impl(lib, polar, norms, B, approx_score,
-                           reinterpret_cast<short*>(approx_angle),
+                           reinterpret_cast<short*>(approx_angle), compact_rows == 1,
                            static_cast<hipStream_t>(hip_stream));
 }
 

@@ -41,11 +41,13 @@ int prefilter_kept(const tm_library* lib, const float* profiles, int32_t B, int3
 // Exact rescoring launch of the match kernel (tm_match.hip): all templates
 // (cand == nullptr) or per-pattern candidate lists of up to n_items ids;
 // cand_count (optional, [B]) limits each pattern's list; pat_mask (optional,
-// [B]) skips patterns whose entry is 0. Enqueued on s.
+// [B]) skips patterns whose entry is 0; compact: polar holds only the
+// library's touched rows, in order ([B, n_rows, n_theta]). Enqueued on s.
 int launch_match(const tm_library* lib, const float* polar, const double* norms, int32_t B,
                  int32_t N, int32_t* top_template, int32_t* top_angle, float* top_score,
                  float* best_score, int16_t* best_angle, const int32_t* cand, int32_t n_items,
-                 const int32_t* cand_count, const int32_t* pat_mask, hipStream_t s);
+                 const int32_t* cand_count, const int32_t* pat_mask, bool compact,
+                 hipStream_t s);
 
 // Top-N over per-template scores [B, T] (tm_topn's kernel); best_angle may be
 // null (angles reported as 0). Enqueued on s.
@@ -72,7 +74,7 @@ void fft_release(tm_library* L);
 // Certified or keep-fraction rescoring after the Fourier-route coarse scorer.
 int fft_match(const tm_library* lib, const float* polar, const double* norms, int32_t B,
               int32_t N, int32_t policy, double keep, int32_t* n_rescored, int32_t* top_template,
-              int32_t* top_angle, float* top_score, hipStream_t s);
+              int32_t* top_angle, float* top_score, bool compact, hipStream_t s);
 // Fill a device int32 array with a value. Enqueued on s.
 int fill_i32(int32_t* dst, int64_t n, int32_t value, hipStream_t s);
 
@@ -116,6 +118,7 @@ struct tm_library {
 
     // device arrays
     int32_t* d_rows = nullptr;      // [n_rows] global row of each touched row
+    int32_t* d_row_map = nullptr;   // [R] compact index of polar row j, -1 if untouched
     int32_t* d_band_off = nullptr;  // [n_bands + 1] first touched-row index of each band
     uint32_t* d_recs = nullptr;     // [n_records * (group + 1)]: LDS float offset within the
                                     // band, then one float32 weight per group member
@@ -136,15 +139,17 @@ struct tm_library {
     bool fft = false;
     int32_t fft_F = 0;          // frequencies 0..n_theta/2
     int32_t fft_Fp = 0;         // padded to a multiple of 16 (8 per parity)
-    int32_t fft_Rp = 0;         // polar rows padded to a multiple of 16
+    int32_t fft_Rp = 0;         // touched polar rows padded to a multiple of 16
     int32_t fft_Tpad = 0;       // base templates padded to a multiple of 32
     int32_t fft_Sh = 0;         // shifts of half a turn padded to a multiple of 32
     int32_t fft_sc = 0;         // power of two applied to C(k) before float16 storage
     double fft_eps = 0.0;       // certified bound |Q~ - Q32|
-    uint16_t* d_fft_t = nullptr;    // [Fp][2 Tpad][Rp] float16 template spectra (x 2^8)
+    uint16_t* d_fft_t = nullptr;    // [Fp][2 Tpad][Rp] float16 template spectra (x 2^8),
+                                    // rows = the touched polar rows in order
     uint16_t* d_fft_w = nullptr;    // [2 parities][Sh][Fp + 8] float16 inverse tables (x 2^12)
     double* d_fft_dft = nullptr;    // [n_theta][2] cos, sin of 2 pi m / n_theta
 
     // host copies used for validation and info
     std::vector<double> tnorm;      // [Tp]
+    std::vector<int32_t> row_index; // [R] compact index of polar row j, -1 if untouched
 };

@@ -163,15 +163,16 @@ int upload(T** dst, const std::vector<T>& src, hipStream_t s, size_t& bytes) {
 
 void release(tm_library* L) {
     if (!L) return;
-    hipFree(L->d_rows);
-    hipFree(L->d_band_off);
-    hipFree(L->d_recs);
-    hipFree(L->d_members);
-    hipFree(L->d_recs1);
-    hipFree(L->d_seg1);
-    hipFree(L->d_seg);
-    hipFree(L->d_prof);
-    hipFree(L->d_prof_max);
+    (void)hipFree(L->d_rows);
+    (void)hipFree(L->d_row_map);
+    (void)hipFree(L->d_band_off);
+    (void)hipFree(L->d_recs);
+    (void)hipFree(L->d_members);
+    (void)hipFree(L->d_recs1);
+    (void)hipFree(L->d_seg1);
+    (void)hipFree(L->d_seg);
+    (void)hipFree(L->d_prof);
+    (void)hipFree(L->d_prof_max);
     tmlib::fft_release(L);
     delete L;
 }
@@ -402,7 +403,7 @@ extern "C" int tm_load_library(const double* kx, const double* ky, const double*
     L->dr = g.dr;
     L->px_per = px_per_inv_angstrom;
     L->flags = flags;
-    hipGetDevice(&L->device);
+    (void)hipGetDevice(&L->device);
     L->n_rows = n_rows;
     L->n_bands = n_bands;
     L->band_rows = band_rows;
@@ -414,10 +415,12 @@ extern "C" int tm_load_library(const double* kx, const double* ky, const double*
     L->n_groups = n_groups;
     L->n_records = static_cast<int64_t>(recs.size() / (G + 1));
     L->tnorm = tnorm;
+    L->row_index = row_index;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     int r = TM_OK;
     size_t bytes = 0;
     if (!r) r = upload(&L->d_rows, rows, s, bytes);
+    if (!r) r = upload(&L->d_row_map, row_index, s, bytes);
     if (!r) r = upload(&L->d_band_off, band_off, s, bytes);
     if (!r) r = upload(&L->d_recs, recs, s, bytes);
     if (!r) r = upload(&L->d_seg, seg, s, bytes);
@@ -453,6 +456,15 @@ extern "C" int tm_library_info(const tm_library* lib, int32_t* n_templates_total
     if (n_templates_total) *n_templates_total = lib->Tp;
     if (n_spots) *n_spots = lib->n_spots;
     if (device_bytes) *device_bytes = lib->device_bytes;
+    return TM_OK;
+}
+
+extern "C" int tm_library_rows(const tm_library* lib, int32_t* n_rows,
+                               const int32_t** row_map) {
+    tmlib::clear_error();
+    if (!lib) { tmlib::set_error("library is NULL"); return TM_EINVAL; }
+    if (n_rows) *n_rows = lib->n_rows;
+    if (row_map) *row_map = lib->d_row_map;
     return TM_OK;
 }
 

@@ -176,7 +176,8 @@ match_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
     auto stage = [&](int band) {
         const int r0 = band_off[band], r1 = band_off[band + 1];
         for (int r = r0 + wave; r < r1; r += NW) {
-            const float* row = src + static_cast<size_t>(rows[r]) * n_theta;
+            const int prow = rows ? rows[r] : r;   // compact polar: row r is touched row r
+            const float* row = src + static_cast<size_t>(prow) * n_theta;
             float* dst = lds + (r - r0) * row_width;
             for (int c = lane; c < row_width; c += 64) {
                 int cc = c;
@@ -333,7 +334,7 @@ int tmlib::launch_match(const tm_library* lib, const float* polar, const double*
                         int32_t N, int32_t* top_template, int32_t* top_angle, float* top_score,
                         float* best_score, int16_t* best_angle, const int32_t* cand,
                         int32_t n_items, const int32_t* cand_count, const int32_t* pat_mask,
-                        hipStream_t s) {
+                        bool compact, hipStream_t s) {
     const int K = tmlib::slots_for(lib->n_theta);
     const bool multi = lib->n_bands > 1;
     const int G = cand ? 1 : lib->group;
@@ -349,8 +350,9 @@ int tmlib::launch_match(const tm_library* lib, const float* polar, const double*
     const uint32_t* recs = cand ? lib->recs_single() : lib->d_recs;
     const int32_t* seg = cand ? lib->seg_single() : lib->d_seg;
     const int32_t n_groups = cand ? n_items : lib->n_groups;
-    hipLaunchKernelGGL(fn, dim3(B), dim3(nw * 64), lds_bytes, s, polar, norms, lib->R,
-                       lib->n_theta, lib->d_rows, lib->d_band_off, lib->n_bands, lib->row_width,
+    hipLaunchKernelGGL(fn, dim3(B), dim3(nw * 64), lds_bytes, s, polar, norms,
+                       compact ? lib->n_rows : lib->R, lib->n_theta,
+                       compact ? nullptr : lib->d_rows, lib->d_band_off, lib->n_bands, lib->row_width,
                        recs, seg, lib->d_members, n_groups, lib->Tp, N, top_template, top_angle,
                        top_score, best_score, reinterpret_cast<short*>(best_angle), cand,
                        cand_count, pat_mask);
@@ -377,8 +379,10 @@ extern "C" int tm_match_batch(const tm_library* lib, const float* polar, const d
     double keep = 0.0, rescore_keep = 0.0;
     int32_t prec = TM_PREC_FP32, coarse = TM_COARSE_NONE, policy = TM_RESCORE_CERTIFIED;
     int32_t* n_rescored = nullptr;
+    bool compact = false;
     if (opts) {
-        if (opts->reserved) { tmlib::set_error("tm_match_opts.reserved must be zero"); return TM_EINVAL; }
+        if (opts->compact_rows != 0 && opts->compact_rows != 1) { tmlib::set_error("compact_rows=%d must be 0 or 1", opts->compact_rows); return TM_EINVAL; }
+        compact = opts->compact_rows == 1;
         if (!(opts->prefilter_keep >= 0.0 && opts->prefilter_keep <= 1.0)) {
             tmlib::set_error("prefilter_keep=%g outside [0, 1]", opts->prefilter_keep);
             return TM_EINVAL;
@@ -419,10 +423,11 @@ extern "C" int tm_match_batch(const tm_library* lib, const float* polar, const d
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     if (coarse == TM_COARSE_FFT)
         return tmlib::fft_match(lib, polar, norms, B, N, policy, rescore_keep, n_rescored,
-                                top_template, top_angle, top_score, s);
+                                top_template, top_angle, top_score, compact, s);
     if (n_keep == 0) {
         int r = tmlib::launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score,
-                                    best_score, best_angle, nullptr, 0, nullptr, nullptr, s);
+                                    best_score, best_angle, nullptr, 0, nullptr, nullptr, compact,
+                                    s);
         if (!r && n_rescored) r = tmlib::fill_i32(n_rescored, B, lib->Tp, s);
         return r;
     }
@@ -433,7 +438,8 @@ extern "C" int tm_match_batch(const tm_library* lib, const float* polar, const d
                           static_cast<size_t>(B) * n_items * sizeof(int32_t), s));
     int r = tmlib::prefilter_kept(lib, profiles, B, n_keep, prec, items, n_items, mirror, s);
     if (!r) r = tmlib::launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score,
-                                    nullptr, nullptr, items, n_items, nullptr, nullptr, s);
+                                    nullptr, nullptr, items, n_items, nullptr, nullptr, compact,
+                                    s);
     if (!r && n_rescored) r = tmlib::fill_i32(n_rescored, B, n_items, s);
     hipError_t e = hipFreeAsync(items, s);
     if (!r && e != hipSuccess) r = tmlib::hip_fail(e, "hipFreeAsync");
@@ -458,6 +464,6 @@ extern "C" int tm_match_candidates(const tm_library* lib, const float* polar, co
     }
     if (int r = tmlib::require_device()) return r;
     return tmlib::launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score, nullptr,
-                               nullptr, candidates, n_cand, nullptr, nullptr,
+                               nullptr, candidates, n_cand, nullptr, nullptr, false,
                                static_cast<hipStream_t>(hip_stream));
 }

@@ -166,7 +166,7 @@ int get_lut(const LutKey& key, hipStream_t s, Lut& out) {
     hipError_t err = hipMalloc(&L.blocks, blocks.size() * sizeof(PolarBlock));
     if (err == hipSuccess) err = hipMalloc(&L.cs, nt * sizeof(double2));
     if (err != hipSuccess) {
-        hipFree(L.blocks); hipFree(L.cs);
+        (void)hipFree(L.blocks); (void)hipFree(L.cs);
         tmlib::set_error("polar table allocation failed: %s", hipGetErrorString(err));
         return TM_ENOMEM;
     }
@@ -198,14 +198,17 @@ __device__ __forceinline__ double half_wave_sum(double v) {
 // are resampled. Half-wave h of wave w owns rows g0 + 32 i + 2 w + h (i < 4)
 // and its 32 lanes walk the block's columns, so stores are 128-byte runs and
 // each lane keeps float64 partial row sums in registers across blocks; a row
-// is reduced across its half-wave once.
+// is reduced across its half-wave once. With a row map, polar row j is
+// written to output row row_map[j] (skipped when negative); norms and
+// profiles always cover all R rows.
 template <typename Tin, bool BILINEAR>
 __global__ void __launch_bounds__(kPolarThreads)
 polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
              const PolarBlock* __restrict__ blocks, int n_blocks,
              const double2* __restrict__ cs, double r0, double dr, double cx, double cy,
-             int R, int n_theta, float gamma, float sub, float* __restrict__ polar,
-             double* __restrict__ norm_out, float* __restrict__ prof_out) {
+             int R, int n_theta, float gamma, float sub, const int* __restrict__ row_map,
+             int out_rows, float* __restrict__ polar, double* __restrict__ norm_out,
+             float* __restrict__ prof_out) {
     extern __shared__ double smem[];
     double* partial = smem;                                   // [waves]
     float* box = reinterpret_cast<float*>(smem + kPolarWaves);
@@ -217,12 +220,18 @@ polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
     const int wave = tmlib::uniform(tid >> 6);
     const bool pw = gamma != 1.0f;
     const Tin* img = patterns + static_cast<size_t>(b) * H * W;
-    float* out = polar + static_cast<size_t>(b) * R * n_theta;
+    float* out = polar + static_cast<size_t>(b) * out_rows * n_theta;
     double sq = 0.0;
     for (int g0 = 0; g0 < R; g0 += kRowGroup) {
         double rs[kRowSteps];
+        int orow[kRowSteps];   // output row of this lane's polar rows (-1: not written)
 #pragma unroll
-        for (int i = 0; i < kRowSteps; ++i) rs[i] = 0.0;
+        for (int i = 0; i < kRowSteps; ++i) {
+            rs[i] = 0.0;
+            const int j = g0 + i * kRowsPerStep + 2 * wave + half;
+            const int m = j < R ? (row_map ? row_map[j] : j) : -1;
+            orow[i] = (m >= 0 && m < out_rows) ? m : -1;   // entries out of range: skipped
+        }
         for (int bi = 0; bi < n_blocks; ++bi) {
             const PolarBlock blk = blocks[bi];
             if (blk.j1 <= g0 || blk.j0 >= g0 + kRowGroup) continue;   // uniform
@@ -303,7 +312,7 @@ polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
                     } else {
                         v = box[o];
                     }
-                    out[j * n_theta + blk.k0 + kk] = v;
+                    if (orow[i] >= 0) out[orow[i] * n_theta + blk.k0 + kk] = v;
                     const double vd = static_cast<double>(v);
                     rs[i] += vd;
                     sq += vd * vd;
@@ -330,11 +339,12 @@ polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
 
 }  // namespace
 
-extern "C" int tm_polar_transform(const void* patterns, tm_dtype dtype, int32_t B, int32_t H,
-                                  int32_t W, const tm_polar_grid* grid, float gamma,
-                                  float subtract, float* polar_out, double* norm_out,
-                                  float* profile_out, void* hip_stream) {
-    tmlib::clear_error();
+namespace {
+
+int polar_impl(const void* patterns, tm_dtype dtype, int32_t B, int32_t H, int32_t W,
+               const tm_polar_grid* grid, float gamma, float subtract, const int32_t* row_map,
+               int32_t out_rows, float* polar_out, double* norm_out, float* profile_out,
+               void* hip_stream) {
     if (int r = tmlib::validate_grid(grid)) return r;
     if (B < 0) { tmlib::set_error("B=%d < 0", B); return TM_EINVAL; }
     if (H < 1 || W < 1 || H > 32767 || W > 32767) { tmlib::set_error("H=%d, W=%d outside [1, 32767]", H, W); return TM_EINVAL; }
@@ -361,7 +371,8 @@ extern "C" int tm_polar_transform(const void* patterns, tm_dtype dtype, int32_t 
                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
         hipLaunchKernelGGL(fn, dim3(B), dim3(kPolarThreads), lds, s, ptr, B, H, W, lut.blocks,
                            lut.n_blocks, lut.cs, grid->r0, grid->dr, grid->cx, grid->cy, grid->R,
-                           grid->n_theta, gamma, subtract, polar_out, norm_out, profile_out);
+                           grid->n_theta, gamma, subtract, row_map, out_rows, polar_out, norm_out,
+                           profile_out);
         return TM_OK;
     };
     int r = TM_OK;
@@ -375,4 +386,33 @@ extern "C" int tm_polar_transform(const void* patterns, tm_dtype dtype, int32_t 
     if (r) return r;
     TM_HIP(hipGetLastError());
     return TM_OK;
+}
+
+}  // namespace
+
+extern "C" int tm_polar_transform(const void* patterns, tm_dtype dtype, int32_t B, int32_t H,
+                                  int32_t W, const tm_polar_grid* grid, float gamma,
+                                  float subtract, float* polar_out, double* norm_out,
+                                  float* profile_out, void* hip_stream) {
+    tmlib::clear_error();
+    return polar_impl(patterns, dtype, B, H, W, grid, gamma, subtract, nullptr,
+                      grid ? grid->R : 0, polar_out, norm_out, profile_out, hip_stream);
+}
+
+extern "C" int tm_polar_transform_rows(const void* patterns, tm_dtype dtype, int32_t B,
+                                       int32_t H, int32_t W, const tm_polar_grid* grid,
+                                       float gamma, float subtract, const int32_t* row_map,
+                                       int32_t n_out_rows, float* polar_out, double* norm_out,
+                                       float* profile_out, void* hip_stream) {
+    tmlib::clear_error();
+    if (grid && (n_out_rows < 1 || n_out_rows > grid->R)) {
+        tmlib::set_error("n_out_rows=%d outside [1, R=%d]", n_out_rows, grid->R);
+        return TM_EINVAL;
+    }
+    if (!row_map && grid && n_out_rows != grid->R) {
+        tmlib::set_error("without a row map, n_out_rows must equal R");
+        return TM_EINVAL;
+    }
+    return polar_impl(patterns, dtype, B, H, W, grid, gamma, subtract, row_map, n_out_rows,
+                      polar_out, norm_out, profile_out, hip_stream);
 }

@@ -50,7 +50,7 @@ int require_device() {
             hipMemPool_t pool;
             if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
                 uint64_t keep = UINT64_MAX;
-                hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+                (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
             }
         }
     }

@@ -170,7 +170,8 @@ class GpuExecutor:
     def footprint(self, n_patterns: int, H: int, W: int, itemsize: int, lib_id: int) -> int:
         """Device bytes one request of n_patterns holds while in flight."""
         R, nt = self.grid.R, self.grid.n_theta
-        b = n_patterns * (H * W * itemsize + R * nt * 4 + 8 + R * 4 + self.N * 12)
+        rows = self.libraries[lib_id].rows()[0] or R       # compact polar: touched rows
+        b = n_patterns * (H * W * itemsize + rows * nt * 4 + 8 + R * 4 + self.N * 12)
         if self.keep > 0.0:
             T = self.libraries[lib_id].T
             n_keep = int(np.ceil(self.keep * T))
@@ -190,7 +191,7 @@ class GpuExecutor:
                 x[o:o + h.shape[0]].copy_(h, non_blocking=True)
                 o += h.shape[0]
             polar, norms, prof = tm.polar_transform(x, self.grid, self.gamma, self.subtract,
-                                                    want_profile=self.keep > 0.0)
+                                                    want_profile=self.keep > 0.0, lib=lib)
             if self.keep > 0.0:
                 tt, ts, tq = tm.match_batch(lib, polar, norms, self.N, profiles=prof,
                                             prefilter_keep=self.keep, prefilter_prec=self.precision)

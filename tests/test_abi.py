@@ -108,7 +108,15 @@ def test_polar_and_topn_argument_errors(tm):
                             None) == tm.TM_EINVAL
     e = ctypes.c_double()
     assert L.tm_fft_error_bound(None, ctypes.byref(e)) == tm.TM_EINVAL
-    assert L.tm_fft_scores(None, buf, buf, 1, buf, None, None) == tm.TM_EINVAL
+    assert L.tm_fft_scores(None, buf, buf, 1, 0, buf, None, None) == tm.TM_EINVAL
+    assert L.tm_library_rows(None, None, None) == tm.TM_EINVAL
+    # compact polar rows: n_out_rows within [1, R]; without a map it must be R
+    assert L.tm_polar_transform_rows(buf, 1, 1, 16, 16, ctypes.byref(g), 1.0, 0.0, buf, 0, buf,
+                                     buf, None, None) == tm.TM_EINVAL
+    assert L.tm_polar_transform_rows(buf, 1, 1, 16, 16, ctypes.byref(g), 1.0, 0.0, buf, 17, buf,
+                                     buf, None, None) == tm.TM_EINVAL
+    assert L.tm_polar_transform_rows(buf, 1, 1, 16, 16, ctypes.byref(g), 1.0, 0.0, None, 8, buf,
+                                     buf, None, None) == tm.TM_EINVAL
     assert L.tm_free_library(None) == tm.TM_OK
     assert L.tm_library_info(None, None, None, None) == tm.TM_EINVAL
 

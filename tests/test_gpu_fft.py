@@ -38,9 +38,11 @@ def _say(*a):
 
 
 def _row_and_max(olib):
+    """(touched polar rows, most pixels of one template in one row, most
+    pixels of one template)."""
     key = olib.tid * olib.R + olib.J
     row_max = int(np.bincount(key).max()) if len(key) else 1
-    return row_max, int(np.diff(olib.starts).max())
+    return max(1, len(np.unique(olib.J))), row_max, int(np.diff(olib.starts).max())
 
 
 def _lib(tm, lib_np, cfg_or_grid, px_per, **kw):
@@ -85,8 +87,9 @@ def _check_scores(q, a, imgs, olib, R, n_theta, eps, cx=None, cy=None):
 def test_bound_value_matches_derivation(tm, c1, c1_lib, c1_olib):
     _say("fft bound c1")
     lib, _ = _lib(tm, c1_lib, c1, synth.px_per_inv_A(c1))
-    row_max, n_max = _row_and_max(c1_olib)
-    ref = fft16_error_bound(c1.R, c1.n_theta, row_max, n_max)
+    n_rows, row_max, n_max = _row_and_max(c1_olib)
+    assert n_rows == lib.rows()[0]
+    ref = fft16_error_bound(n_rows, c1.n_theta, row_max, n_max)
     assert abs(lib.fft_error_bound() - ref) <= 1e-12 * ref
     assert lib.fft_error_bound() < 2.5e-3
 
@@ -177,9 +180,9 @@ def test_theta_widths(tm, n_theta):
     grid = tm.PolarGrid(R=R, n_theta=n_theta, cx=cx, cy=cy)
     lib, _ = _lib(tm, lib_np, grid, px_per)
     olib = oracle.OracleLibrary.build(lib_np, px_per, R, n_theta)
-    row_max, n_max = _row_and_max(olib)
+    n_rows, row_max, n_max = _row_and_max(olib)
     eps = lib.fft_error_bound()
-    assert abs(eps - fft16_error_bound(R, n_theta, row_max, n_max)) <= 1e-12 * eps
+    assert abs(eps - fft16_error_bound(n_rows, n_theta, row_max, n_max)) <= 1e-12 * eps
     polar, norms, _ = _polar(tm, imgs, grid)
     q, a = tm.fft_scores(lib, polar, norms)
     tt, ts, tq = tm.match_batch(lib, polar, norms, 4, coarse="fft")
@@ -233,3 +236,23 @@ def test_zero_pattern_and_errors(tm, c1, c1_lib):
         tm.match_batch(plain, polar, norms, 5, coarse="fft")
     with pytest.raises(tm.TMError):
         tm.match_batch(lib, polar, norms, 5, coarse="fft", rescore="keep")   # keep fraction 0
+
+
+def test_compact_rows_equal_full(tm, c1, c1_lib):
+    """The Fourier route on a polar image holding only the library's touched
+    rows gives bit-identical scores and top-N to the full image."""
+    _say("fft compact rows c1")
+    import torch
+    lib, grid = _lib(tm, c1_lib, c1, synth.px_per_inv_A(c1))
+    imgs = synth.make_patterns(c1, c1_lib, range(40))
+    x = torch.from_numpy(imgs).cuda()
+    polar, norms, _ = tm.polar_transform(x, grid)
+    cpolar, cnorms, _ = tm.polar_transform(x, grid, lib=lib)
+    assert cpolar.shape[1] == lib.rows()[0] < c1.R
+    q, a = tm.fft_scores(lib, polar, norms)
+    cq, ca = tm.fft_scores(lib, cpolar, cnorms)
+    assert torch.equal(q, cq) and torch.equal(a, ca)
+    full = tm.match_batch(lib, polar, norms, 5, coarse="fft")
+    comp = tm.match_batch(lib, cpolar, cnorms, 5, coarse="fft")
+    for u, v in zip(full, comp):
+        assert torch.equal(u, v)

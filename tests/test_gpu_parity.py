@@ -290,3 +290,53 @@ def test_library_info(tm, c1, c1_lib, c1_olib):
     assert info["n_templates_total"] == c1_olib.n_total
     assert info["n_spots"] == len(c1_olib.J)
     assert info["device_bytes"] > 0
+
+
+@pytest.mark.parametrize("case", ["c1", "c3", "multiband"])
+def test_compact_rows_equal_full(tm, case):
+    """tm_polar_transform_rows with the library's row map writes exactly the
+    touched rows of the full polar image (bit for bit), the same norms and
+    profiles; the match on the compact image (plain, with per-template best
+    arrays, and pre-filtered) equals the match on the full image bit for
+    bit."""
+    import torch
+    if case == "multiband":
+        R, nt = 128, 360
+        lib_np = small_library(300, seed=99, max_spots=40, g_max=1.2, g_min=0.05)
+        px = (R - 4) / 1.2
+        imgs = np.random.default_rng(100).random((6, 256, 256)).astype(np.float32)
+        grid = tm.PolarGrid(R=R, n_theta=nt, cx=128.0, cy=128.0)
+    else:
+        cfg = synth.CONFIGS[1 if case == "c1" else 3]
+        lib_np = synth.make_library(cfg)
+        px = synth.px_per_inv_A(cfg)
+        imgs = synth.make_patterns(cfg, lib_np, range(8))
+        grid = _grid_for(tm, cfg)
+    _say("compact rows", case, imgs.shape)
+    lib = tm.Library(lib_np["kx"], lib_np["ky"], lib_np["intensity"], lib_np["offsets"], px, grid)
+    n_rows, row_map = lib.rows()
+    x = torch.from_numpy(np.ascontiguousarray(imgs)).cuda()
+    polar, norms, prof = tm.polar_transform(x, grid)
+    cpolar, cnorms, cprof = tm.polar_transform(x, grid, lib=lib)
+    torch.cuda.synchronize()
+    assert cpolar.shape == (len(imgs), n_rows, grid.n_theta)
+    touched = sorted({int(j) for j in _olib_rows(lib_np, px, grid)})
+    assert len(touched) == n_rows
+    assert torch.equal(cpolar, polar[:, touched, :])
+    assert torch.equal(cnorms, norms) and torch.equal(cprof, prof)
+    N = 5
+    full = tm.match_batch(lib, polar, norms, N, with_best=True)
+    comp = tm.match_batch(lib, cpolar, cnorms, N, with_best=True)
+    for u, v in zip(full, comp):
+        assert torch.equal(u, v)
+    full = tm.match_batch(lib, polar, norms, N, profiles=prof, prefilter_keep=0.2,
+                          prefilter_prec="bf16")
+    comp = tm.match_batch(lib, cpolar, cnorms, N, profiles=cprof, prefilter_keep=0.2,
+                          prefilter_prec="bf16")
+    for u, v in zip(full, comp):
+        assert torch.equal(u, v)
+
+
+def _olib_rows(lib_np, px, grid):
+    olib = oracle.OracleLibrary.build(lib_np, px, grid.R, grid.n_theta)
+    return np.unique(olib.J)
