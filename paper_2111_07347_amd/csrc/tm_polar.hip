@@ -9,7 +9,8 @@
 // split into the base pixel and float32 fractions; the float32 path never
 // evaluates trigonometry.
 //
-// Kernel layout: one workgroup per pattern, 16 waves. The polar grid is cut
+// Kernel layout: one workgroup per pattern, 16 waves (two per CU: at most 64
+// registers per lane). The polar grid is cut
 // into blocks (angular sectors, and radial bands if needed) whose bilinear
 // tap footprint, clipped to the image plus a one-pixel zero ring, fits the
 // LDS budget; for a centred grid these are the four quadrants. Per block the
@@ -183,7 +184,8 @@ constexpr int kPolarWaves = kPolarThreads / 64;
 constexpr int kRowsPerStep = 2 * kPolarWaves;   // each half-wave owns one row per step
 constexpr int kRowSteps = 4;                    // rows held per half-wave: a group of 128
 constexpr int kRowGroup = kRowsPerStep * kRowSteps;
-constexpr int kStageUnroll = 8;                 // independent loads in flight per thread
+constexpr int kStageUnroll = 4;                 // independent loads in flight per thread
+constexpr int kVecUnroll = 2;                   // 4-pixel groups in flight per thread
 
 // Sum over the 32 lanes of a half-wave (fixed tree, identical in every lane
 // of the half).
@@ -202,7 +204,7 @@ __device__ __forceinline__ double half_wave_sum(double v) {
 // written to output row row_map[j] (skipped when negative); norms and
 // profiles always cover all R rows.
 template <typename Tin, bool BILINEAR>
-__global__ void __launch_bounds__(kPolarThreads)
+__global__ void __launch_bounds__(kPolarThreads, 8)   // two workgroups per CU
 polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
              const PolarBlock* __restrict__ blocks, int n_blocks,
              const double2* __restrict__ cs, double r0, double dr, double cx, double cy,
@@ -238,9 +240,54 @@ polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
             const int bw = blk.bw, pitch = blk.pitch, total = blk.bw * blk.bh;
             __syncthreads();
             // stage the footprint (transform once per pixel, zero outside the
-            // image); element i = tid + 1024 m walks the box row-major, eight
-            // loads in flight per thread before the stores
-            {
+            // image). Image widths divisible by 4: aligned groups of 4 pixels
+            // (one 16- or 8-byte load each, several in flight per thread);
+            // otherwise element i = tid + 1024 m walks the box row-major.
+            if ((W & 3) == 0) {
+                const int gx0 = (blk.x_lo + 4) / 4 - 1;             // floor(x_lo / 4), x_lo >= -4
+                const int ng = (blk.x_lo + bw - 1 + 4) / 4 - 1 - gx0 + 1;
+                const int ntot = ng * blk.bh;
+                for (int g0 = tid; g0 < ntot; g0 += kPolarThreads * kVecUnroll) {
+                    float v[kVecUnroll][4];
+                    int gy[kVecUnroll], gxs[kVecUnroll];
+#pragma unroll
+                    for (int u = 0; u < kVecUnroll; ++u) {
+                        const int g = g0 + u * kPolarThreads;
+                        const int yy = g / ng, cg = g - yy * ng;
+                        const int y = blk.y_lo + yy, xs = 4 * (gx0 + cg);
+                        gy[u] = g < ntot ? yy : -1;
+                        gxs[u] = xs;
+                        const bool in = g < ntot && y >= 0 && y < H && xs >= 0 && xs < W;
+                        if (in) {
+                            const Tin* q = img + static_cast<size_t>(y) * W + xs;
+                            if constexpr (sizeof(Tin) == 4) {
+                                const float4 t = *reinterpret_cast<const float4*>(q);
+                                v[u][0] = t.x; v[u][1] = t.y; v[u][2] = t.z; v[u][3] = t.w;
+                            } else {
+                                const ushort4 t = *reinterpret_cast<const ushort4*>(q);
+                                v[u][0] = t.x; v[u][1] = t.y; v[u][2] = t.z; v[u][3] = t.w;
+                            }
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                if (pw) v[u][e] = powf(fmaxf(v[u][e], 0.0f), gamma);
+                                v[u][e] -= sub;
+                            }
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) v[u][e] = 0.0f;
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < kVecUnroll; ++u) {
+                        if (gy[u] < 0) continue;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int px = gxs[u] + e - blk.x_lo;
+                            if (px >= 0 && px < bw) box[gy[u] * pitch + px] = v[u][e];
+                        }
+                    }
+                }
+            } else {
                 const int step_y = kPolarThreads / bw, step_x = kPolarThreads - step_y * bw;
                 int yy = tid / bw, xx = tid - yy * bw;
                 for (int base = tid; base < total; base += kPolarThreads * kStageUnroll) {
@@ -294,17 +341,22 @@ polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
                     }
                     const double xf = BILINEAR ? floor(x) : rint(x);
                     const double yf = BILINEAR ? floor(y) : rint(y);
-                    const int x0 = static_cast<int>(fmin(fmax(xf, -4.0), 40000.0));
-                    const int y0 = static_cast<int>(fmin(fmax(yf, -4.0), 40000.0));
-                    const bool in = x0 >= -1 && x0 <= W - 1 && y0 >= -1 && y0 <= H - 1;
-                    // the clamp keeps every read inside the staged box
-                    const int o = in ? min(max(y0 - blk.y_lo, 0), bhm) * pitch +
-                                           min(max(x0 - blk.x_lo, 0), bwm)
-                                     : zero_slot;
+                    // |x|, |y| < 2^21 (checked on the host), so the conversions are exact
+                    const int ix = static_cast<int>(xf) - blk.x_lo;
+                    const int iy = static_cast<int>(yf) - blk.y_lo;
+                    // the box holds exactly the 2x2 footprints of this block's samples
+                    // that touch the image (a one-pixel zero ring outside it): a sample
+                    // is in the image's support iff its base pixel lies in the box
+                    // minus its last row and column; every read stays in the box
+                    const bool in = static_cast<unsigned>(ix) <= static_cast<unsigned>(bwm) &&
+                                    static_cast<unsigned>(iy) <= static_cast<unsigned>(bhm);
+                    const int o = in ? __mul24(iy, pitch) + ix : zero_slot;
                     float v;
                     if (BILINEAR) {
-                        const float fx = in ? static_cast<float>(x - xf) : 0.0f;
-                        const float fy = in ? static_cast<float>(y - yf) : 0.0f;
+                        // outside the support all four taps read zeros, so the
+                        // (finite) fractions need no masking
+                        const float fx = static_cast<float>(x - xf);
+                        const float fy = static_cast<float>(y - yf);
                         const float p00 = box[o], p01 = box[o + 1];
                         const float p10 = box[o + pitch], p11 = box[o + pitch + 1];
                         const float gx = 1.0f - fx, gy = 1.0f - fy;
@@ -312,7 +364,8 @@ polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
                     } else {
                         v = box[o];
                     }
-                    if (orow[i] >= 0) out[orow[i] * n_theta + blk.k0 + kk] = v;
+                    if (orow[i] >= 0)
+                        out[static_cast<unsigned>(orow[i] * n_theta + blk.k0 + kk)] = v;
                     const double vd = static_cast<double>(v);
                     rs[i] += vd;
                     sq += vd * vd;
@@ -355,6 +408,13 @@ int polar_impl(const void* patterns, tm_dtype dtype, int32_t B, int32_t H, int32
     }
     if (grid->interp != 0 && grid->interp != 1) { tmlib::set_error("interp=%d must be 0 or 1", grid->interp); return TM_EINVAL; }
     if (!std::isfinite(grid->cx) || !std::isfinite(grid->cy)) { tmlib::set_error("centre must be finite"); return TM_EINVAL; }
+    // sample coordinates must stay far inside the int range (|x|, |y| < 2^21)
+    const double lim = 1048576.0;
+    if (std::fabs(grid->cx) > lim || std::fabs(grid->cy) > lim ||
+        std::fabs(grid->r0) + grid->dr * grid->R > lim) {
+        tmlib::set_error("centre and radii must lie within +-2^20 pixels");
+        return TM_EINVAL;
+    }
     if (B == 0) return TM_OK;
     if (!patterns || !polar_out || !norm_out) { tmlib::set_error("patterns, polar_out and norm_out must be non-NULL"); return TM_EINVAL; }
     if (int r = tmlib::require_device()) return r;
