@@ -255,8 +255,16 @@ int tm_polar_transform(const void* patterns, tm_dtype dtype, int32_t B, int32_t 
                        float* polar_out, double* norm_out, float* profile_out,
                        void* hip_stream);
 
-/* tm_polar_transform_rows - tm_polar_transform writing only selected polar
- * rows. Every row is still sampled (||P|| and the profiles cover the whole
+/* tm_polar_transform_rows - tm_polar_transform with an optional pattern mask,
+ * writing only selected polar rows.
+ *
+ * Mask (Section 4, custom indexation procedures: the dominant phase's
+ * reflections are masked before the second phase is indexed): the
+ * transformed pattern is multiplied pixel by pixel by mask[y*W + x] before
+ * resampling, P~ = mask * (max(x, 0)^gamma - c), so a masked pixel is 0 and
+ * contributes neither to Q nor to ||P|| (see tm_mask_from_mean).
+ *
+ * Rows: every row is still sampled (||P|| and the profiles cover the whole
  * polar image, Eq. 1); polar row j goes to output row row_map[j], or is not
  * stored when row_map[j] < 0 (entries outside [0, n_out_rows) are not
  * stored either). With a library's map (tm_library_rows) the output holds
@@ -264,14 +272,38 @@ int tm_polar_transform(const void* patterns, tm_dtype dtype, int32_t B, int32_t 
  * (Section 2.2: the template is non-zero only at its spots).
  *
  * Arguments as in tm_polar_transform, plus
+ *   mask         device, [H, W] float32, 16-byte aligned, or NULL (no mask).
  *   row_map      device, [R] int32, or NULL (then n_out_rows must be R).
  *   n_out_rows   1 <= n_out_rows <= R.
  *   polar_out    device, [B, n_out_rows, n_theta] float32, written.
  * Errors as tm_polar_transform. */
 int tm_polar_transform_rows(const void* patterns, tm_dtype dtype, int32_t B, int32_t H,
                             int32_t W, const tm_polar_grid* grid, float gamma, float subtract,
-                            const int32_t* row_map, int32_t n_out_rows, float* polar_out,
-                            double* norm_out, float* profile_out, void* hip_stream);
+                            const float* mask, const int32_t* row_map, int32_t n_out_rows,
+                            float* polar_out, double* norm_out, float* profile_out,
+                            void* hip_stream);
+
+/* tm_mask_from_mean - the mask of the dominant phase for two-stage indexing
+ * (Section 4, custom indexation procedures): average all patterns, threshold
+ * the average, then erode and dilate to remove small noise-like features and
+ * the tails of intense peaks.
+ *
+ *   bright[y, x] = (1/B) sum_b pattern_b[y, x] > threshold   (float64)
+ *   bright       = dilate^n_open(erode^n_open(bright))          (opening)
+ *   bright       = dilate^n_grow(bright)
+ *   mask_out     = 0 where bright, 1 elsewhere
+ * Erosion / dilation: 3x3 square neighbourhood, pixels outside the image
+ * count as not bright.
+ *
+ * Arguments
+ *   patterns   device, [B, H, W] uint16 or float32 (dtype), B >= 1.
+ *   threshold  finite; n_open, n_grow in [0, 64].
+ *   mask_out   device, [H, W] float32, written.
+ * Scratch (chunk sums, two byte images) from the stream-ordered allocator.
+ * Errors: TM_EINVAL, TM_ENOMEM, TM_EHIP, TM_ENODEV. */
+int tm_mask_from_mean(const void* patterns, tm_dtype dtype, int32_t B, int32_t H, int32_t W,
+                      double threshold, int32_t n_open, int32_t n_grow, float* mask_out,
+                      void* hip_stream);
 
 /* tm_match_batch - score every template of lib against every pattern at every
  * in-plane shift and keep the N best templates per pattern (Eq. 1; Section

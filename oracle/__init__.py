@@ -22,7 +22,9 @@ out plainly, in float64, one function per step:
 * ``prefilter64`` - azimuthally integrated pre-filter of the library
   (Section 2.2, Fig. 3);
 * ``fft_match64`` - the same in-plane search through Fourier transforms
-  along the azimuth (Section 3, computational cost).
+  along the azimuth (Section 3, computational cost);
+* ``matrix_mask64`` - the mask of the dominant phase's reflections for
+  two-stage indexing (Section 4, custom indexation procedures).
 
 Readings where the paper is silent are stated in each function.
 """
@@ -32,10 +34,12 @@ from .library import template_pixels64, OracleLibrary
 from .match import scores64, match_exact64, topn64, index_pattern64, index_batch64
 from .fft import template_images64, fft_numerators64, fft_match64
 from .prefilter import radial_profiles64, prefilter64, index_pattern_prefiltered64
+from .mask import mean_pattern64, binary_erode64, binary_dilate64, matrix_mask64
 
 __all__ = [
     "polar_coords64", "bilinear64", "intensity_transform64", "polar64", "norm64",
     "profile64", "template_pixels64", "OracleLibrary", "scores64", "match_exact64",
     "topn64", "index_pattern64", "index_batch64", "radial_profiles64", "prefilter64",
     "index_pattern_prefiltered64", "template_images64", "fft_numerators64", "fft_match64",
+    "mean_pattern64", "binary_erode64", "binary_dilate64", "matrix_mask64",
 ]

@@ -74,12 +74,16 @@ def nearest64(img: np.ndarray, x: np.ndarray, y: np.ndarray) -> np.ndarray:
 
 def polar64(img: np.ndarray, R: int, n_theta: int, r0: float = 0.0, dr: float = 1.0,
             cx: float | None = None, cy: float | None = None, gamma: float = 1.0,
-            subtract: float = 0.0, interp: str = "bilinear") -> np.ndarray:
-    """Polar image P[j, k] of one pattern, float64 [R, n_theta]."""
+            subtract: float = 0.0, interp: str = "bilinear", mask=None) -> np.ndarray:
+    """Polar image P[j, k] of one pattern, float64 [R, n_theta]. An optional
+    [H, W] mask multiplies the transformed pattern before resampling (the
+    masking step of two-stage indexing, Section 4; see oracle.mask)."""
     H, W = img.shape
     cx = W / 2.0 if cx is None else cx
     cy = H / 2.0 if cy is None else cy
     t = intensity_transform64(img, gamma, subtract)
+    if mask is not None:
+        t = t * np.asarray(mask, dtype=np.float64)
     x, y = polar_coords64(R, n_theta, r0, dr, cx, cy)
     if interp == "bilinear":
         return bilinear64(t, x, y)

@@ -36,7 +36,8 @@ TM_RESCORE_CERTIFIED, TM_RESCORE_KEEP = 0, 1
 TM_MAX_N = 64
 
 EXPORTED = ("tm_load_library", "tm_free_library", "tm_library_info", "tm_library_layout",
-            "tm_library_rows", "tm_polar_transform", "tm_polar_transform_rows", "tm_match_batch", "tm_prefilter", "tm_match_candidates",
+            "tm_library_rows", "tm_polar_transform", "tm_polar_transform_rows",
+            "tm_mask_from_mean", "tm_match_batch", "tm_prefilter", "tm_match_candidates",
             "tm_fft_scores", "tm_fft_error_bound", "tm_topn", "tm_last_error", "tm_version")
 
 
@@ -76,7 +77,8 @@ def _load():
         "tm_polar_transform": [P, ctypes.c_int, I32, I32, I32, ctypes.POINTER(_Grid), F, F, P, P,
                                P, P],
         "tm_polar_transform_rows": [P, ctypes.c_int, I32, I32, I32, ctypes.POINTER(_Grid), F, F,
-                                    P, I32, P, P, P, P],
+                                    P, P, I32, P, P, P, P],
+        "tm_mask_from_mean": [P, ctypes.c_int, I32, I32, I32, D, I32, I32, P, P],
         "tm_match_batch": [P, P, P, P, I32, ctypes.POINTER(_Opts), I32, P, P, P, P, P, P],
         "tm_prefilter": [P, P, I32, I32, I32, P, P],
         "tm_match_candidates": [P, P, P, I32, P, I32, I32, P, P, P, P],
@@ -243,12 +245,13 @@ class Library:
 
 def polar_transform(patterns, grid: PolarGrid, gamma: float = 1.0, subtract: float = 0.0,
                     polar_out=None, norm_out=None, profile_out=None, want_profile: bool = True,
-                    lib: "Library | None" = None, stream=None):
+                    lib: "Library | None" = None, mask=None, stream=None):
     """tm_polar_transform on a [B, H, W] uint16/float32 device tensor.
     Returns (polar [B, R, n_theta] f32, norms [B] f64, profiles [R, B] f32 or None).
     With lib (tm_polar_transform_rows), polar holds only the rows lib's
     templates touch: [B, n_rows, n_theta]; norms and profiles still cover
-    all R rows."""
+    all R rows. mask, an [H, W] float32 device tensor, multiplies every
+    transformed pattern before resampling (two-stage indexing)."""
     torch = _torch()
     if patterns.dtype == torch.float32:
         dt = TM_F32
@@ -276,16 +279,39 @@ def polar_transform(patterns, grid: PolarGrid, gamma: float = 1.0, subtract: flo
     if profile_out is not None:
         _require(profile_out, "profile_out", torch.float32, (grid.R, B))
     g = grid._c()
-    if row_map is None:
+    if mask is not None:
+        _require(mask, "mask", torch.float32, (H, W))
+    if row_map is None and mask is None:
         _check(_lib.tm_polar_transform(_ptr(patterns), dt, B, H, W, ctypes.byref(g), float(gamma),
                                        float(subtract), _ptr(polar_out), _ptr(norm_out),
                                        _ptr(profile_out), _stream_ptr(stream)), "tm_polar_transform")
     else:
         _check(_lib.tm_polar_transform_rows(_ptr(patterns), dt, B, H, W, ctypes.byref(g),
-                                            float(gamma), float(subtract), row_map, int(n_out),
-                                            _ptr(polar_out), _ptr(norm_out), _ptr(profile_out),
-                                            _stream_ptr(stream)), "tm_polar_transform_rows")
+                                            float(gamma), float(subtract), _ptr(mask), row_map,
+                                            int(n_out), _ptr(polar_out), _ptr(norm_out),
+                                            _ptr(profile_out), _stream_ptr(stream)),
+               "tm_polar_transform_rows")
     return polar_out, norm_out, profile_out
+
+
+def mask_from_mean(patterns, threshold: float, n_open: int = 1, n_grow: int = 2, stream=None):
+    """tm_mask_from_mean: [H, W] float32 mask (1 keep, 0 masked) of the
+    pixels that are bright in the average of the [B, H, W] patterns, after an
+    opening and n_grow dilations."""
+    torch = _torch()
+    if patterns.dtype == torch.float32:
+        dt = TM_F32
+    elif patterns.dtype in (torch.uint16, torch.int16):
+        dt = TM_U16
+    else:
+        raise TypeError("patterns must be float32 or uint16")
+    _require(patterns, "patterns", patterns.dtype)
+    B, H, W = patterns.shape
+    out = torch.empty((H, W), dtype=torch.float32, device=patterns.device)
+    _check(_lib.tm_mask_from_mean(_ptr(patterns), dt, B, H, W, float(threshold), int(n_open),
+                                  int(n_grow), _ptr(out), _stream_ptr(stream)),
+           "tm_mask_from_mean")
+    return out
 
 
 def _layout(lib: "Library", polar) -> int:

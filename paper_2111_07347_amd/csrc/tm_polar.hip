@@ -208,9 +208,9 @@ __global__ void __launch_bounds__(kPolarThreads, 8)   // two workgroups per CU
 polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
              const PolarBlock* __restrict__ blocks, int n_blocks,
              const double2* __restrict__ cs, double r0, double dr, double cx, double cy,
-             int R, int n_theta, float gamma, float sub, const int* __restrict__ row_map,
-             int out_rows, float* __restrict__ polar, double* __restrict__ norm_out,
-             float* __restrict__ prof_out) {
+             int R, int n_theta, float gamma, float sub, const float* __restrict__ mask,
+             const int* __restrict__ row_map, int out_rows, float* __restrict__ polar,
+             double* __restrict__ norm_out, float* __restrict__ prof_out) {
     extern __shared__ double smem[];
     double* partial = smem;                                   // [waves]
     float* box = reinterpret_cast<float*>(smem + kPolarWaves);
@@ -272,6 +272,11 @@ polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
                                 if (pw) v[u][e] = powf(fmaxf(v[u][e], 0.0f), gamma);
                                 v[u][e] -= sub;
                             }
+                            if (mask) {
+                                const float4 m = *reinterpret_cast<const float4*>(
+                                    mask + static_cast<size_t>(y) * W + xs);
+                                v[u][0] *= m.x; v[u][1] *= m.y; v[u][2] *= m.z; v[u][3] *= m.w;
+                            }
                         } else {
 #pragma unroll
                             for (int e = 0; e < 4; ++e) v[u][e] = 0.0f;
@@ -292,7 +297,7 @@ polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
                 int yy = tid / bw, xx = tid - yy * bw;
                 for (int base = tid; base < total; base += kPolarThreads * kStageUnroll) {
                     float v[kStageUnroll];
-                    int dst[kStageUnroll];
+                    int dst[kStageUnroll], midx[kStageUnroll];
                     bool in[kStageUnroll];
 #pragma unroll
                     for (int u = 0; u < kStageUnroll; ++u) {
@@ -300,6 +305,7 @@ polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
                         const bool live = base + u * kPolarThreads < total;
                         in[u] = live && y >= 0 && y < H && x >= 0 && x < W;
                         dst[u] = live ? yy * pitch + xx : -1;
+                        midx[u] = y * W + x;
                         v[u] = in[u] ? static_cast<float>(img[y * W + x]) : 0.0f;
                         xx += step_x;
                         yy += step_y;
@@ -311,6 +317,7 @@ polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
                         if (in[u]) {
                             if (pw) t = powf(fmaxf(t, 0.0f), gamma);
                             t -= sub;
+                            if (mask) t *= mask[midx[u]];
                         }
                         if (dst[u] >= 0) box[dst[u]] = t;
                     }
@@ -395,9 +402,9 @@ polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
 namespace {
 
 int polar_impl(const void* patterns, tm_dtype dtype, int32_t B, int32_t H, int32_t W,
-               const tm_polar_grid* grid, float gamma, float subtract, const int32_t* row_map,
-               int32_t out_rows, float* polar_out, double* norm_out, float* profile_out,
-               void* hip_stream) {
+               const tm_polar_grid* grid, float gamma, float subtract, const float* mask,
+               const int32_t* row_map, int32_t out_rows, float* polar_out, double* norm_out,
+               float* profile_out, void* hip_stream) {
     if (int r = tmlib::validate_grid(grid)) return r;
     if (B < 0) { tmlib::set_error("B=%d < 0", B); return TM_EINVAL; }
     if (H < 1 || W < 1 || H > 32767 || W > 32767) { tmlib::set_error("H=%d, W=%d outside [1, 32767]", H, W); return TM_EINVAL; }
@@ -431,8 +438,8 @@ int polar_impl(const void* patterns, tm_dtype dtype, int32_t B, int32_t H, int32
                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
         hipLaunchKernelGGL(fn, dim3(B), dim3(kPolarThreads), lds, s, ptr, B, H, W, lut.blocks,
                            lut.n_blocks, lut.cs, grid->r0, grid->dr, grid->cx, grid->cy, grid->R,
-                           grid->n_theta, gamma, subtract, row_map, out_rows, polar_out, norm_out,
-                           profile_out);
+                           grid->n_theta, gamma, subtract, mask, row_map, out_rows, polar_out,
+                           norm_out, profile_out);
         return TM_OK;
     };
     int r = TM_OK;
@@ -455,15 +462,16 @@ extern "C" int tm_polar_transform(const void* patterns, tm_dtype dtype, int32_t 
                                   float subtract, float* polar_out, double* norm_out,
                                   float* profile_out, void* hip_stream) {
     tmlib::clear_error();
-    return polar_impl(patterns, dtype, B, H, W, grid, gamma, subtract, nullptr,
+    return polar_impl(patterns, dtype, B, H, W, grid, gamma, subtract, nullptr, nullptr,
                       grid ? grid->R : 0, polar_out, norm_out, profile_out, hip_stream);
 }
 
 extern "C" int tm_polar_transform_rows(const void* patterns, tm_dtype dtype, int32_t B,
                                        int32_t H, int32_t W, const tm_polar_grid* grid,
-                                       float gamma, float subtract, const int32_t* row_map,
-                                       int32_t n_out_rows, float* polar_out, double* norm_out,
-                                       float* profile_out, void* hip_stream) {
+                                       float gamma, float subtract, const float* mask,
+                                       const int32_t* row_map, int32_t n_out_rows,
+                                       float* polar_out, double* norm_out, float* profile_out,
+                                       void* hip_stream) {
     tmlib::clear_error();
     if (grid && (n_out_rows < 1 || n_out_rows > grid->R)) {
         tmlib::set_error("n_out_rows=%d outside [1, R=%d]", n_out_rows, grid->R);
@@ -473,6 +481,6 @@ extern "C" int tm_polar_transform_rows(const void* patterns, tm_dtype dtype, int
         tmlib::set_error("without a row map, n_out_rows must equal R");
         return TM_EINVAL;
     }
-    return polar_impl(patterns, dtype, B, H, W, grid, gamma, subtract, row_map, n_out_rows,
-                      polar_out, norm_out, profile_out, hip_stream);
+    return polar_impl(patterns, dtype, B, H, W, grid, gamma, subtract, mask, row_map,
+                      n_out_rows, polar_out, norm_out, profile_out, hip_stream);
 }

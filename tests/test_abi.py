@@ -111,12 +111,17 @@ def test_polar_and_topn_argument_errors(tm):
     assert L.tm_fft_scores(None, buf, buf, 1, 0, buf, None, None) == tm.TM_EINVAL
     assert L.tm_library_rows(None, None, None) == tm.TM_EINVAL
     # compact polar rows: n_out_rows within [1, R]; without a map it must be R
-    assert L.tm_polar_transform_rows(buf, 1, 1, 16, 16, ctypes.byref(g), 1.0, 0.0, buf, 0, buf,
-                                     buf, None, None) == tm.TM_EINVAL
-    assert L.tm_polar_transform_rows(buf, 1, 1, 16, 16, ctypes.byref(g), 1.0, 0.0, buf, 17, buf,
-                                     buf, None, None) == tm.TM_EINVAL
-    assert L.tm_polar_transform_rows(buf, 1, 1, 16, 16, ctypes.byref(g), 1.0, 0.0, None, 8, buf,
-                                     buf, None, None) == tm.TM_EINVAL
+    assert L.tm_polar_transform_rows(buf, 1, 1, 16, 16, ctypes.byref(g), 1.0, 0.0, None, buf, 0,
+                                     buf, buf, None, None) == tm.TM_EINVAL
+    assert L.tm_polar_transform_rows(buf, 1, 1, 16, 16, ctypes.byref(g), 1.0, 0.0, None, buf, 17,
+                                     buf, buf, None, None) == tm.TM_EINVAL
+    assert L.tm_polar_transform_rows(buf, 1, 1, 16, 16, ctypes.byref(g), 1.0, 0.0, None, None, 8,
+                                     buf, buf, None, None) == tm.TM_EINVAL
+    # mask builder argument checks
+    assert L.tm_mask_from_mean(buf, 1, 0, 16, 16, 1.0, 1, 1, buf, None) == tm.TM_EINVAL
+    assert L.tm_mask_from_mean(buf, 1, 4, 16, 16, 1.0, -1, 1, buf, None) == tm.TM_EINVAL
+    assert L.tm_mask_from_mean(buf, 1, 4, 16, 16, float("nan"), 1, 1, buf, None) == tm.TM_EINVAL
+    assert L.tm_mask_from_mean(None, 1, 4, 16, 16, 1.0, 1, 1, buf, None) == tm.TM_EINVAL
     assert L.tm_free_library(None) == tm.TM_OK
     assert L.tm_library_info(None, None, None, None) == tm.TM_EINVAL
 

@@ -456,3 +456,54 @@ def test_fft_route_matches_direct_search():
             q = np.sort(Q[t])[::-1]
             if q[0] - q[1] > 1e-9:
                 assert arg_f[t] == arg_d[t]
+
+
+# ------------------------------------------------- two-stage indexing mask
+def test_mask_morphology_equals_scipy():
+    """Erosion / dilation with the 3x3 square element and an unset border
+    equal scipy.ndimage's binary morphology (library-routine cross-check)."""
+    from scipy import ndimage
+    rng = np.random.default_rng(21)
+    b = rng.random((37, 41)) > 0.45
+    st = np.ones((3, 3), dtype=bool)
+    for n in (1, 2, 3):
+        assert np.array_equal(oracle.binary_erode64(b, n),
+                              ndimage.binary_erosion(b, st, iterations=n, border_value=0))
+        assert np.array_equal(oracle.binary_dilate64(b, n),
+                              ndimage.binary_dilation(b, st, iterations=n, border_value=0))
+
+
+def test_mask_removes_matrix_reflections_keeps_precipitate_spot():
+    """A reflection present in every pattern (matrix) is masked with its
+    tails; a spot present in one pattern only (precipitate) survives; a
+    single bright noise pixel in the average is removed by the opening."""
+    H = W = 48
+    yy, xx = np.mgrid[0:H, 0:W]
+    matrix = 10.0 * np.exp(-((xx - 12) ** 2 + (yy - 30) ** 2) / (2 * 1.5 ** 2))
+    imgs = np.repeat(matrix[None], 8, axis=0)
+    imgs[3] += 10.0 * np.exp(-((xx - 36) ** 2 + (yy - 10) ** 2) / (2 * 1.5 ** 2))
+    imgs[:, 5, 40] = 50.0                       # one-pixel noise feature in every pattern
+    m = oracle.matrix_mask64(imgs, threshold=2.0, n_open=1, n_grow=2)
+    assert m[30, 12] == 0.0 and m[30, 15] == 0.0 and m[33, 12] == 0.0   # core and tails
+    assert m[10, 36] == 1.0                    # precipitate spot: mean 1.25 < 2
+    assert m[5, 40] == 1.0                     # opened away
+    assert set(np.unique(m)) <= {0.0, 1.0}
+
+
+def test_masked_polar_special_cases():
+    """Mask of ones = no mask; mask of zeros = zero polar image; a mask
+    multiplies the transformed pattern (gamma, then subtraction) before
+    resampling."""
+    rng = np.random.default_rng(22)
+    img = rng.random((40, 44)) * 3.0
+    R, nt = 18, 72
+    P = oracle.polar64(img, R, nt, gamma=0.5, subtract=0.2)
+    assert np.array_equal(oracle.polar64(img, R, nt, gamma=0.5, subtract=0.2,
+                                         mask=np.ones_like(img)), P)
+    assert not oracle.polar64(img, R, nt, gamma=0.5, subtract=0.2,
+                              mask=np.zeros_like(img)).any()
+    m = (rng.random(img.shape) > 0.5).astype(float)
+    ref = oracle.bilinear64((np.sqrt(img) - 0.2) * m, *oracle.polar_coords64(R, nt, 0.0, 1.0,
+                                                                            22.0, 20.0))
+    assert np.allclose(oracle.polar64(img, R, nt, gamma=0.5, subtract=0.2, mask=m), ref,
+                       rtol=0, atol=1e-14)
