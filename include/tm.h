@@ -387,6 +387,28 @@ int tm_match_candidates(const tm_library* lib, const float* polar, const double*
                         int32_t* top_template, int32_t* top_angle, float* top_score,
                         void* hip_stream);
 
+/* tm_refine_angles - sub-bin in-plane angles of reported matches (Section 4,
+ * discussion: improving the optimisation of the in-plane angle phi1).
+ *
+ * For row i of pattern b with template t = top_template[b, i] and shift
+ * s = top_angle[b, i]: q-, q0, q+ = Q(b, t, s-1), Q(b, t, s), Q(b, t, s+1)
+ * (Eq. 1, shifts mod n_theta, float32 as in tm_match_batch); when the
+ * parabola through them is a maximum (q- - 2 q0 + q+ < 0) its vertex offset
+ * d = (q- - q+) / (2 (q- - 2 q0 + q+)) clipped to [-1/2, 1/2], else d = 0;
+ *   refined_deg[b, i] = ((s + d) * 360 / n_theta) mod 360.
+ * Templates outside [0, T') give s * 360 / n_theta.
+ *
+ * Arguments
+ *   lib, polar, norms, B    as in tm_match_batch (B >= 0; 0 is a no-op).
+ *   compact_rows            layout of polar (tm_match_opts.compact_rows).
+ *   N                       >= 1, columns of the top arrays.
+ *   top_template, top_angle device, [B, N] int32 (tm_match_batch output).
+ *   refined_deg             device, [B, N] float32, written.
+ * Errors: TM_EINVAL, TM_EHIP, TM_ENODEV. */
+int tm_refine_angles(const tm_library* lib, const float* polar, const double* norms, int32_t B,
+                     int32_t compact_rows, int32_t N, const int32_t* top_template,
+                     const int32_t* top_angle, float* refined_deg, void* hip_stream);
+
 /* tm_fft_scores - approximate best score and angle of every template for every
  * pattern through the Fourier route (Section 3: the azimuthal sliding is a
  * circular cross-correlation along theta, evaluated with Fourier transforms).

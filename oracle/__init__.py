@@ -19,6 +19,8 @@ out plainly, in float64, one function per step:
   every in-plane shift with wraparound, and its maximum per template
   (Section 2.2, Fig. 2 e);
 * ``topn64`` - sort and keep the N best templates (Section 2.2, end);
+* ``refine_angle64`` - sub-bin in-plane angle by a parabola through the
+  scores at the best shift and its neighbours (Section 4, discussion);
 * ``prefilter64`` - azimuthally integrated pre-filter of the library
   (Section 2.2, Fig. 3);
 * ``fft_match64`` - the same in-plane search through Fourier transforms
@@ -31,7 +33,8 @@ Readings where the paper is silent are stated in each function.
 from .polar import (polar_coords64, bilinear64, intensity_transform64,
                     polar64, norm64, profile64)
 from .library import template_pixels64, OracleLibrary
-from .match import scores64, match_exact64, topn64, index_pattern64, index_batch64
+from .match import (scores64, match_exact64, topn64, index_pattern64, index_batch64,
+                    refine_angle64)
 from .fft import template_images64, fft_numerators64, fft_match64
 from .prefilter import radial_profiles64, prefilter64, index_pattern_prefiltered64
 from .mask import mean_pattern64, binary_erode64, binary_dilate64, matrix_mask64
@@ -41,5 +44,5 @@ __all__ = [
     "profile64", "template_pixels64", "OracleLibrary", "scores64", "match_exact64",
     "topn64", "index_pattern64", "index_batch64", "radial_profiles64", "prefilter64",
     "index_pattern_prefiltered64", "template_images64", "fft_numerators64", "fft_match64",
-    "mean_pattern64", "binary_erode64", "binary_dilate64", "matrix_mask64",
+    "mean_pattern64", "binary_erode64", "binary_dilate64", "matrix_mask64", "refine_angle64",
 ]

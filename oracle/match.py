@@ -117,3 +117,23 @@ def index_batch64(imgs: np.ndarray, lib: OracleLibrary, N: int, processes: int =
     q = np.stack([r[2] for r in res])
     pn = np.array([r[3] for r in res])
     return t, s, q, pn
+
+
+def refine_angle64(P: np.ndarray, lib: OracleLibrary, t: int, s: int,
+                   pnorm: float | None = None) -> float:
+    """Sub-bin in-plane angle of template t around its best shift s
+    (Section 4, discussion: improving the optimisation of the in-plane angle).
+
+    Reading: the parabola through Q(t, s-1), Q(t, s), Q(t, s+1) (shifts mod
+    n_theta); its vertex offset d = (q- - q+) / (2 (q- - 2 q0 + q+)) is used
+    when the curvature q- - 2 q0 + q+ is negative (a maximum), clipped to
+    [-1/2, 1/2], else d = 0. Returns (s + d) * 360 / n_theta in degrees,
+    taken modulo 360."""
+    n_theta = lib.n_theta
+    Q = scores64(P, lib.subset([int(t)]), pnorm)[0]
+    qm, q0, qp = Q[(s - 1) % n_theta], Q[s % n_theta], Q[(s + 1) % n_theta]
+    den = qm - 2.0 * q0 + qp
+    d = 0.0
+    if den < 0.0:
+        d = min(0.5, max(-0.5, 0.5 * (qm - qp) / den))
+    return float(((s + d) * 360.0 / n_theta) % 360.0)

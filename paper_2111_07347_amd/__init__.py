@@ -37,7 +37,7 @@ TM_MAX_N = 64
 
 EXPORTED = ("tm_load_library", "tm_free_library", "tm_library_info", "tm_library_layout",
             "tm_library_rows", "tm_polar_transform", "tm_polar_transform_rows",
-            "tm_mask_from_mean", "tm_match_batch", "tm_prefilter", "tm_match_candidates",
+            "tm_mask_from_mean", "tm_match_batch", "tm_refine_angles", "tm_prefilter", "tm_match_candidates",
             "tm_fft_scores", "tm_fft_error_bound", "tm_topn", "tm_last_error", "tm_version")
 
 
@@ -83,6 +83,7 @@ def _load():
         "tm_prefilter": [P, P, I32, I32, I32, P, P],
         "tm_match_candidates": [P, P, P, I32, P, I32, I32, P, P, P, P],
         "tm_fft_scores": [P, P, P, I32, I32, P, P, P],
+        "tm_refine_angles": [P, P, P, I32, I32, I32, P, P, P, P],
         "tm_fft_error_bound": [P, ctypes.POINTER(D)],
         "tm_topn": [P, P, I32, I32, I32, P, P, P, P],
         "tm_last_error": [],
@@ -426,6 +427,24 @@ def match_candidates(lib: Library, polar, norms, candidates, N: int, stream=None
                                     candidates.shape[1], int(N), _ptr(tt), _ptr(ts), _ptr(tq),
                                     _stream_ptr(stream)), "tm_match_candidates")
     return tt, ts, tq
+
+
+def refine_angles(lib: Library, polar, norms, top_template, top_angle, stream=None):
+    """tm_refine_angles: sub-bin in-plane angles (degrees, [B, N] float32) of
+    the matches (top_template, top_angle) from match_batch."""
+    torch = _torch()
+    B = polar.shape[0]
+    compact = _layout(lib, polar)
+    _require(norms, "norms", torch.float64, (B,))
+    _require(top_template, "top_template", torch.int32)
+    N = top_template.shape[1]
+    _require(top_template, "top_template", torch.int32, (B, N))
+    _require(top_angle, "top_angle", torch.int32, (B, N))
+    out = torch.empty((B, N), dtype=torch.float32, device=polar.device)
+    _check(_lib.tm_refine_angles(lib._h, _ptr(polar), _ptr(norms), B, compact, int(N),
+                                 _ptr(top_template), _ptr(top_angle), _ptr(out),
+                                 _stream_ptr(stream)), "tm_refine_angles")
+    return out
 
 
 def fft_scores(lib: Library, polar, norms, with_angle: bool = True, stream=None):

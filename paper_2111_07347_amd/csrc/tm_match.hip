@@ -467,3 +467,103 @@ extern "C" int tm_match_candidates(const tm_library* lib, const float* polar, co
                                nullptr, candidates, n_cand, nullptr, nullptr, false,
                                static_cast<hipStream_t>(hip_stream));
 }
+
+// ----------------------------------------------------- sub-bin in-plane angle
+
+namespace {
+
+// One wave per (pattern, rank): the exact float32 scores of the reported
+// template at shifts s-1, s, s+1 (lanes stride its per-template records, a
+// fixed butterfly reduces them), then the vertex of the parabola through the
+// three when it is a maximum (Section 4, discussion: improving the
+// optimisation of the in-plane angle).
+__global__ void __launch_bounds__(256)
+refine_kernel(const float* __restrict__ polar, const double* __restrict__ norms, int Rs,
+              int n_theta, const int* __restrict__ rows, const int* __restrict__ band_off,
+              int n_bands, int n_cls, int row_width, const uint32_t* __restrict__ recs,
+              const int* __restrict__ seg, int Tp, int n_items, int N,
+              const int* __restrict__ top_t, const int* __restrict__ top_s,
+              float* __restrict__ out_deg) {
+    const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (item >= n_items) return;                      // uniform per wave
+    const int b = item / N;
+    const int t = top_t[item];
+    int s = top_s[item] % n_theta;
+    if (s < 0) s += n_theta;
+    const float step = 360.0f / static_cast<float>(n_theta);
+    if (t < 0 || t >= Tp) {
+        if (lane == 0) out_deg[item] = static_cast<float>(s) * step;
+        return;
+    }
+    const float* src = polar + static_cast<size_t>(b) * Rs * n_theta;
+    const double pn = norms[b];
+    const float invP = pn > 0.0 ? static_cast<float>(1.0 / pn) : 0.0f;
+    const int sm = s == 0 ? n_theta - 1 : s - 1;
+    const int sp = s + 1 == n_theta ? 0 : s + 1;
+    float am = 0.0f, a0 = 0.0f, ap = 0.0f;
+    for (int band = 0; band < n_bands; ++band) {
+        const int lo = seg[(static_cast<size_t>(t) * n_bands + band) * n_cls];
+        const int hi = seg[(static_cast<size_t>(t) * n_bands + band + 1) * n_cls];
+        for (int r = lo + lane; r < hi; r += 64) {
+            const uint32_t off = recs[2 * static_cast<size_t>(r)];
+            const float w = __uint_as_float(recs[2 * static_cast<size_t>(r) + 1]);
+            const int lr = static_cast<int>(off / static_cast<uint32_t>(row_width));
+            const int k = static_cast<int>(off) - lr * row_width;
+            const int row = band_off[band] + lr;
+            const float* p = src + static_cast<size_t>(rows ? rows[row] : row) * n_theta;
+            int km = k + sm, k0 = k + s, kp = k + sp;
+            if (km >= n_theta) km -= n_theta;
+            if (k0 >= n_theta) k0 -= n_theta;
+            if (kp >= n_theta) kp -= n_theta;
+            am += w * p[km];
+            a0 += w * p[k0];
+            ap += w * p[kp];
+        }
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        am += __shfl_xor(am, m, 64);
+        a0 += __shfl_xor(a0, m, 64);
+        ap += __shfl_xor(ap, m, 64);
+    }
+    if (lane == 0) {
+        const float qm = am * invP, q0 = a0 * invP, qp = ap * invP;
+        const float den = qm - 2.0f * q0 + qp;
+        float d = 0.0f;
+        if (den < 0.0f) d = fminf(0.5f, fmaxf(-0.5f, 0.5f * (qm - qp) / den));
+        float deg = (static_cast<float>(s) + d) * step;
+        if (deg < 0.0f) deg += 360.0f;
+        if (deg >= 360.0f) deg -= 360.0f;
+        out_deg[item] = deg;
+    }
+}
+
+}  // namespace
+
+extern "C" int tm_refine_angles(const tm_library* lib, const float* polar, const double* norms,
+                                int32_t B, int32_t compact_rows, int32_t N,
+                                const int32_t* top_template, const int32_t* top_angle,
+                                float* refined_deg, void* hip_stream) {
+    tmlib::clear_error();
+    if (!lib) { tmlib::set_error("library is NULL"); return TM_EINVAL; }
+    if (B < 0 || N < 1) { tmlib::set_error("B=%d, N=%d: need B >= 0, N >= 1", B, N); return TM_EINVAL; }
+    if (compact_rows != 0 && compact_rows != 1) { tmlib::set_error("compact_rows=%d must be 0 or 1", compact_rows); return TM_EINVAL; }
+    if (B == 0) return TM_OK;
+    if (!polar || !norms || !top_template || !top_angle || !refined_deg) {
+        tmlib::set_error("polar, norms, top_template, top_angle and refined_deg must be non-NULL");
+        return TM_EINVAL;
+    }
+    if (int r = tmlib::require_device()) return r;
+    const long long items = static_cast<long long>(B) * N;
+    if (items > (1LL << 31) - 1) { tmlib::set_error("B*N too large"); return TM_EINVAL; }
+    const bool compact = compact_rows == 1;
+    hipLaunchKernelGGL(refine_kernel, dim3(static_cast<unsigned>((items + 3) / 4)), dim3(256), 0,
+                       static_cast<hipStream_t>(hip_stream), polar, norms,
+                       compact ? lib->n_rows : lib->R, lib->n_theta,
+                       compact ? nullptr : lib->d_rows, lib->d_band_off, lib->n_bands, lib->n_cls,
+                       lib->row_width, lib->recs_single(), lib->seg_single(), lib->Tp,
+                       static_cast<int>(items), N, top_template, top_angle, refined_deg);
+    TM_HIP(hipGetLastError());
+    return TM_OK;
+}

@@ -507,3 +507,47 @@ def test_masked_polar_special_cases():
                                                                             22.0, 20.0))
     assert np.allclose(oracle.polar64(img, R, nt, gamma=0.5, subtract=0.2, mask=m), ref,
                        rtol=0, atol=1e-14)
+
+
+# ------------------------------------------------- sub-bin in-plane angle
+def _render_polar_spots(olib, t, phi_bins, sigma=1.2):
+    """Polar image of template t's pixels as Gaussians along theta at a
+    fractional rotation (in bins): an exactly known sub-bin angle."""
+    P = np.zeros((olib.R, olib.n_theta))
+    a, b = olib.starts[t], olib.starts[t + 1]
+    k = np.arange(olib.n_theta)
+    for j, kk, w in zip(olib.J[a:b], olib.K[a:b], olib.Wt[a:b]):
+        d = (k - (kk + phi_bins) + olib.n_theta / 2) % olib.n_theta - olib.n_theta / 2
+        P[j] += w * np.exp(-d ** 2 / (2 * sigma ** 2))
+    return P
+
+
+def test_refined_angle_recovers_fractional_rotation():
+    """A template's own (Gaussian-broadened) image rotated by s0 + f bins:
+    the best shift is within a bin of s0 + f and the parabola recovers f to
+    a few hundredths of a bin (the peak is nearly parabolic)."""
+    lib, olib = _lib(R=24, n_theta=180, n=6, seed=31, px_per=10.0)
+    for t in range(olib.T_base):
+        if olib.starts[t + 1] - olib.starts[t] < 2:
+            continue
+        for s0, f in ((17, 0.0), (40, 0.3), (111, -0.45)):
+            P = _render_polar_spots(olib, t, s0 + f)
+            Q = oracle.scores64(P, olib.subset([t]))[0]
+            s = int(np.argmax(Q))
+            ang = oracle.refine_angle64(P, olib, t, s)
+            want = ((s0 + f) * 2.0) % 360.0              # 2 degrees per bin
+            assert abs((ang - want + 180) % 360 - 180) < 0.06 * 2.0, (t, s0, f, ang, want)
+
+
+def test_refined_angle_moves_one_bin_with_a_rolled_image():
+    """Rolling the polar image by one column moves the refined angle by
+    exactly one bin (the three scores are the same numbers, relabelled)."""
+    lib, olib = _lib(n=8, seed=32)
+    rng = np.random.default_rng(33)
+    P = rng.random((olib.R, olib.n_theta)) ** 4
+    best, arg = oracle.match_exact64(P, olib)
+    step = 360.0 / olib.n_theta
+    for t in range(olib.n_total):
+        a0 = oracle.refine_angle64(P, olib, t, int(arg[t]))
+        a1 = oracle.refine_angle64(np.roll(P, 1, axis=1), olib, t, (int(arg[t]) + 1) % olib.n_theta)
+        assert abs((a1 - a0 - step + 180) % 360 - 180) < 1e-9
