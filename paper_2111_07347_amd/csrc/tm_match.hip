@@ -57,60 +57,70 @@ struct Rec {
     float w[G];
 };
 
-// Accumulate records [i0, i1): every lane adds w * P[col + lane + 64 k] for
-// its K shift slots. Slots k < CLS read from the pixel's column, the others
+// NB records [i, i + NB): every lane adds w * P[col + lane + 64 k] for its
+// K shift slots. Slots k < CLS read from the pixel's column, the others
 // (narrow rows only) one period back, where the row's wraparound continues.
-template <int K, int G, int CLS>
+// The records' scalar loads and all their LDS reads are in flight before
+// the first FMA.
+template <int K, int G, int CLS, int NB>
+__device__ __forceinline__ void accumulate_batch(const Rec<G>* __restrict__ rec, int i,
+                                                 const float* lds, int lane, int n_theta,
+                                                 float (&acc)[G][K]) {
+    Rec<G> r[NB];
+    float v[NB][K];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) r[u] = rec[i + u];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const float* pa = lds + r[u].off + lane;
+        const float* pb = pa - n_theta;
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[u][k] = (k < CLS) ? pa[64 * k] : pb[64 * k];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[g][k] = fmaf(r[u].w[g], v[u][k], acc[g][k]);
+}
+
+// Accumulate records [i0, i1) in batches of NB (8 when a wave may hold the
+// registers, i.e. when a workgroup fills the CU), then 4, then singly. The
+// summation order per accumulator is the record order in every case.
+template <int K, int G, int CLS, int NB>
 __device__ __forceinline__ void accumulate(const Rec<G>* __restrict__ rec, int i0, int i1,
                                            const float* lds, int lane, int n_theta,
                                            float (&acc)[G][K]) {
     int i = i0;
-    // four records per step: their scalar loads and LDS reads are all in
-    // flight before the first FMA
-    for (; i + 4 <= i1; i += 4) {
-        Rec<G> r[4];
-        float v[4][K];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) r[u] = rec[i + u];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const float* pa = lds + r[u].off + lane;
-            const float* pb = pa - n_theta;
-#pragma unroll
-            for (int k = 0; k < K; ++k) v[u][k] = (k < CLS) ? pa[64 * k] : pb[64 * k];
+    for (; i + NB <= i1; i += NB) accumulate_batch<K, G, CLS, NB>(rec, i, lds, lane, n_theta, acc);
+    if constexpr (NB > 4) {
+        if (i + 4 <= i1) {
+            accumulate_batch<K, G, CLS, 4>(rec, i, lds, lane, n_theta, acc);
+            i += 4;
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int g = 0; g < G; ++g)
-#pragma unroll
-                for (int k = 0; k < K; ++k) acc[g][k] = fmaf(r[u].w[g], v[u][k], acc[g][k]);
     }
-    for (; i < i1; ++i) {
-        const Rec<G> r = rec[i];
-        const float* pa = lds + r.off + lane;
-        const float* pb = pa - n_theta;
-        float v[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = (k < CLS) ? pa[64 * k] : pb[64 * k];
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-            for (int k = 0; k < K; ++k) acc[g][k] = fmaf(r.w[g], v[k], acc[g][k]);
-    }
+    for (; i < i1; ++i) accumulate_batch<K, G, CLS, 1>(rec, i, lds, lane, n_theta, acc);
 }
+
+// Records per batch: 8 when a workgroup fills the CU (at most 4 waves per
+// SIMD, so up to 128 VGPRs cost no occupancy) and the accumulators and
+// values fit, else 4.
+template <int K, int G, int M, int NW>
+constexpr int batch_size() { return (NW >= 16 && M * G * K + 8 * K <= 96) ? 8 : 4; }
 
 // Records of one (group, band): one segment on wide rows, K class segments
 // (CLS = 1..K) on narrow rows.
-template <int K, int G, bool NARROW, int CLS = 1>
+template <int K, int G, bool NARROW, int NB, int CLS = 1>
 __device__ __forceinline__ void accumulate_segments(const Rec<G>* __restrict__ rec,
                                                     const int* __restrict__ sg, const float* lds,
                                                     int lane, int n_theta, float (&acc)[G][K]) {
     if constexpr (!NARROW) {
-        accumulate<K, G, K>(rec, sg[0], sg[1], lds, lane, n_theta, acc);
+        accumulate<K, G, K, NB>(rec, sg[0], sg[1], lds, lane, n_theta, acc);
     } else {
-        accumulate<K, G, CLS>(rec, sg[CLS - 1], sg[CLS], lds, lane, n_theta, acc);
-        if constexpr (CLS < K) accumulate_segments<K, G, true, CLS + 1>(rec, sg, lds, lane, n_theta, acc);
+        accumulate<K, G, CLS, NB>(rec, sg[CLS - 1], sg[CLS], lds, lane, n_theta, acc);
+        if constexpr (CLS < K)
+            accumulate_segments<K, G, true, NB, CLS + 1>(rec, sg, lds, lane, n_theta, acc);
     }
 }
 
@@ -237,26 +247,27 @@ match_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
                 const int grp = (G == 1 && items) ? mem[m][0] : (gb + m < n_groups ? gb + m : -1);
                 if (grp >= 0) {
                     const int* sg = seg + (static_cast<size_t>(grp) * n_bands + band) * NCLS;
-                    accumulate_segments<K, G, NARROW>(rec, sg, lds, lane, n_theta, acc[m]);
+                    accumulate_segments<K, G, NARROW, batch_size<K, G, M, NW>()>(rec, sg, lds, lane,
+                                                                               n_theta, acc[m]);
                 }
             }
         }
         // a template needs the full reduction only if some lane's maximum
-        // can enter the wave's list; test all members before branching
+        // can enter the wave's list. One test per group against the largest
+        // lane maximum of its members (absent members hold zeros, which
+        // cannot exceed a real member's maximum unless every score is <= 0)
+        // is a superset of the exact test; ties and members that fail are
+        // sorted out below.
         float mx[M][G];
-        unsigned long long any = 0;
+        float gmx = -INFINITY;
 #pragma unroll
         for (int m = 0; m < M; ++m)
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 mx[m][g] = lane_max<K>(acc[m][g]);
-                const int t = mem[m][g];
-                const float q = mx[m][g] * invP;
-                const bool tie_wins = t < st.thr_t;
-                const bool hit = tie_wins ? (q >= st.thr) : (q > st.thr);
-                any |= (t >= 0) ? tmlib::ballot(hit) : 0ull;
+                gmx = fmaxf(gmx, mx[m][g]);
             }
-        if (!any && !write_all) continue;
+        if (!tmlib::ballot(gmx * invP >= st.thr) && !write_all) continue;
 #pragma unroll
         for (int m = 0; m < M; ++m)
 #pragma unroll
