@@ -242,6 +242,52 @@ def fft_bench(tm, a, lib_np, cfg, grid, px, x, polar, norms, prof, N, B, stream,
     return res
 
 
+def orientation_accuracy(tm, cfg, lib, polar, norms, top, B):
+    """Orientation output and Eq. (2) deviation against the generator's ground
+    truth (template, mirror, in-plane angle) for every pattern of the batch:
+    Bunge angles of the best match from its angle bin and from the sub-bin
+    angle, IPF-x/y/z deviations, and the share of patterns deviating by more
+    than 3 degrees (misindexed)."""
+    import torch
+    import synth
+    dev = polar.device
+    T = lib.n_total // 2
+    le = torch.from_numpy(synth.template_euler(cfg)).to(dev)
+    truth = [synth.ground_truth(cfg, i, T) for i in range(B)]
+    t_true = torch.tensor([[t + (T if m else 0)] for t, m, _ in truth], dtype=torch.int32,
+                          device=dev)
+    a_true = torch.tensor([[np.degrees(p)] for _, _, p in truth], dtype=torch.float32, device=dev)
+    laue = cfg.phases[0].sector
+    tt, ts = top[0][:, :1].contiguous(), top[1][:, :1].contiguous()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    deg = tm.refine_angles(lib, polar, norms, top[0], top[1])[:, :1].contiguous()
+    ev[1].record()
+    e_true = tm.orientations(le, t_true, angle_deg=a_true, n_theta=cfg.n_theta)
+    e_bin = tm.orientations(le, tt, top_angle=ts, n_theta=cfg.n_theta)
+    ev[2].record()
+    e_ref = tm.orientations(le, tt, angle_deg=deg, n_theta=cfg.n_theta)
+    d_bin = tm.ipf_deviation(e_bin, e_true, laue)
+    d_ref = tm.ipf_deviation(e_ref, e_true, laue)
+    ev[3].record()
+    torch.cuda.synchronize()
+    d_bin = np.degrees(d_bin.cpu().numpy())
+    d_ref = np.degrees(d_ref.cpu().numpy())
+    hit = (tt.cpu().numpy()[:, 0] == t_true.cpu().numpy()[:, 0])
+
+    def stats(d):
+        return {"median_deg": [round(float(np.median(d[:, k])), 4) for k in range(3)],
+                "p90_deg": [round(float(np.percentile(d[:, k], 90)), 4) for k in range(3)],
+                "misindexed_over_3deg": round(float(np.mean(d.max(axis=1) > 3.0)), 5)}
+    return {
+        "laue": laue, "patterns": B, "axes": ["ipf_x", "ipf_y", "ipf_z"],
+        "generating_template_found": round(float(hit.mean()), 5),
+        "angle_bins": stats(d_bin), "sub_bin_angles": stats(d_ref),
+        "refine_ms": round(ev[0].elapsed_time(ev[1]), 4),
+        "orientation_and_eq2_ms": round(ev[1].elapsed_time(ev[2]) + ev[2].elapsed_time(ev[3]), 4),
+    }
+
+
 def c5_bench(a):
     """Large multi-phase workload: 262 144 uint16 patterns (1024 scan rows of
     256) against 50 000 templates (5000 FCC, 15 000 HCP, 30 000
@@ -445,6 +491,8 @@ def main():
     ms_per_step = wall / a.steps * 1e3
     value = B * a.steps / wall
     plain_top = [o.clone() for o in out]
+    accuracy = orientation_accuracy(tm, cfg, lib, polar, norms, plain_top, B)
+    print(f"[bench] orientation accuracy: {accuracy}", file=sys.stderr, flush=True)
 
     # the precision form: pre-filter in reduced precision, exact rescoring
     prec_path = None
@@ -537,6 +585,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "top1_agreement_vs_oracle_on_sample": top1,
+        "orientation_accuracy": accuracy,
         "precision_path": prec_path,
         "fft_path": fft_path,
         "serving": serving,

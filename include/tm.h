@@ -409,6 +409,65 @@ int tm_refine_angles(const tm_library* lib, const float* polar, const double* no
                      int32_t compact_rows, int32_t N, const int32_t* top_template,
                      const int32_t* top_angle, float* refined_deg, void* hip_stream);
 
+/* Laue groups for the inverse-pole-figure reduction of tm_ipf_deviation
+ * (Cartesian crystal frame; hexagonal with a along x). */
+enum {
+    TM_LAUE_M3M = 0,    /* cubic m-3m: sector z >= x >= y >= 0 */
+    TM_LAUE_MMM = 1,    /* orthorhombic mmm: x, y, z >= 0 */
+    TM_LAUE_6MMM = 2    /* hexagonal 6/mmm: z >= 0, azimuth in [0, 30 degrees] */
+};
+
+/* tm_orientations - Bunge Euler angles (phi1, Phi, phi2) of reported matches
+ * (Section 2.1: the library samples (Phi, phi2) with phi1 = 0 and phi1 is
+ * found by the in-plane search; Section 2.2: mirrored templates stand for
+ * further orientations).
+ *
+ * Frames: sample x along image columns, y along image rows, z = x cross y;
+ * g = Z(phi2) X(Phi) Z(phi1) (frame rotations) maps sample to crystal
+ * coordinates. A match of base template t at in-plane angle phi (the
+ * counter-clockwise rotation of the matching convention) is
+ * (phi, Phi_t, phi2_t). A mirrored match is read as the template's
+ * orientation rotated by pi about the sample x axis, then by phi about z,
+ * i.e. (phi + pi, pi - Phi_t, phi2_t + pi). Output ranges: phi1, phi2 in
+ * [0, 2 pi), Phi in [0, pi]; where sin(Phi) = 0 the pair is returned as
+ * (phi1 +- phi2, Phi, 0). Entries whose template is outside [0, T') are NaN.
+ *
+ * Arguments
+ *   lib_euler      device, [T, 2] float64: (Phi, phi2) of each base template,
+ *                  radians.
+ *   T              >= 1, base templates.
+ *   mirrors        1 if template ids T..2T-1 are mirrors (TM_LIB_MIRROR), else 0.
+ *   n_theta        polar columns (angle bin s is s * 2 pi / n_theta).
+ *   top_template   device, [B, N] int32 (tm_match_batch output).
+ *   top_angle      device, [B, N] int32 angle bins, or NULL;
+ *   angle_deg      device, [B, N] float32 degrees (tm_refine_angles), or NULL;
+ *                  exactly one of the two is given.
+ *   B, N           B >= 0 (0 is a no-op), N >= 1.
+ *   euler_out      device, [B, N, 3] float64 radians, written.
+ * Errors: TM_EINVAL, TM_EHIP, TM_ENODEV. */
+int tm_orientations(const double* lib_euler, int32_t T, int32_t mirrors, int32_t n_theta,
+                    const int32_t* top_template, const int32_t* top_angle,
+                    const float* angle_deg, int32_t B, int32_t N, double* euler_out,
+                    void* hip_stream);
+
+/* tm_ipf_deviation - angular deviation between two orientation maps, Eq. (2)
+ * (Section 4.2): for each sample direction d in (x, y, z), v = g d is the
+ * crystal direction an IPF-d map shows, reduced to the fundamental sector of
+ * the Laue group; theta = |arccos(v_A . v_P / (|v_A| |v_P|))|.
+ *
+ * Arguments
+ *   euler_a, euler_b  device float64 Bunge triples (radians); pattern b's
+ *                     triple starts at element b * stride (stride >= 3, e.g.
+ *                     3 * N to take the best match of a [B, N, 3] array).
+ *   B                 >= 0 (0 is a no-op).
+ *   laue              TM_LAUE_*.
+ *   deviation_out     device, [B, 3] float64 radians (IPF-x, IPF-y, IPF-z),
+ *                     written.
+ * Errors: TM_EINVAL, TM_EHIP, TM_ENODEV. */
+int tm_ipf_deviation(const double* euler_a, int32_t stride_a, const double* euler_b,
+                     int32_t stride_b, int32_t B, int32_t laue, double* deviation_out,
+                     void* hip_stream);
+
 /* tm_fft_scores - approximate best score and angle of every template for every
  * pattern through the Fourier route (Section 3: the azimuthal sliding is a
  * circular cross-correlation along theta, evaluated with Fourier transforms).

@@ -26,7 +26,10 @@ out plainly, in float64, one function per step:
 * ``fft_match64`` - the same in-plane search through Fourier transforms
   along the azimuth (Section 3, computational cost);
 * ``matrix_mask64`` - the mask of the dominant phase's reflections for
-  two-stage indexing (Section 4, custom indexation procedures).
+  two-stage indexing (Section 4, custom indexation procedures);
+* ``match_orientation64`` / ``ipf_deviation64`` - Bunge Euler angles of a
+  match (Section 2.1, Section 2.2 for mirrors) and the angular deviation
+  between two orientation maps, Eq. (2) (Section 4.2).
 
 Readings where the paper is silent are stated in each function.
 """
@@ -38,6 +41,9 @@ from .match import (scores64, match_exact64, topn64, index_pattern64, index_batc
 from .fft import template_images64, fft_numerators64, fft_match64
 from .prefilter import radial_profiles64, prefilter64, index_pattern_prefiltered64
 from .mask import mean_pattern64, binary_erode64, binary_dilate64, matrix_mask64
+from .orient import (bunge_matrix64, euler_from_matrix64, match_orientation64,
+                     symmetry_operators64, in_sector64, sector_direction64,
+                     ipf_deviation64)
 
 __all__ = [
     "polar_coords64", "bilinear64", "intensity_transform64", "polar64", "norm64",
@@ -45,4 +51,6 @@ __all__ = [
     "topn64", "index_pattern64", "index_batch64", "radial_profiles64", "prefilter64",
     "index_pattern_prefiltered64", "template_images64", "fft_numerators64", "fft_match64",
     "mean_pattern64", "binary_erode64", "binary_dilate64", "matrix_mask64", "refine_angle64",
+    "bunge_matrix64", "euler_from_matrix64", "match_orientation64", "symmetry_operators64",
+    "sector_direction64", "ipf_deviation64", "in_sector64",
 ]

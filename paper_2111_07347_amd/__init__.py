@@ -34,11 +34,14 @@ TM_LIB_FFT = 16
 TM_COARSE_NONE, TM_COARSE_FFT = 0, 1
 TM_RESCORE_CERTIFIED, TM_RESCORE_KEEP = 0, 1
 TM_MAX_N = 64
+TM_LAUE_M3M, TM_LAUE_MMM, TM_LAUE_6MMM = 0, 1, 2
+LAUE_GROUPS = {"m-3m": TM_LAUE_M3M, "mmm": TM_LAUE_MMM, "6/mmm": TM_LAUE_6MMM}
 
 EXPORTED = ("tm_load_library", "tm_free_library", "tm_library_info", "tm_library_layout",
             "tm_library_rows", "tm_polar_transform", "tm_polar_transform_rows",
             "tm_mask_from_mean", "tm_match_batch", "tm_refine_angles", "tm_prefilter", "tm_match_candidates",
-            "tm_fft_scores", "tm_fft_error_bound", "tm_topn", "tm_last_error", "tm_version")
+            "tm_fft_scores", "tm_fft_error_bound", "tm_orientations", "tm_ipf_deviation",
+            "tm_topn", "tm_last_error", "tm_version")
 
 
 class TMError(RuntimeError):
@@ -85,6 +88,8 @@ def _load():
         "tm_fft_scores": [P, P, P, I32, I32, P, P, P],
         "tm_refine_angles": [P, P, P, I32, I32, I32, P, P, P, P],
         "tm_fft_error_bound": [P, ctypes.POINTER(D)],
+        "tm_orientations": [P, I32, I32, I32, P, P, P, I32, I32, P, P],
+        "tm_ipf_deviation": [P, I32, P, I32, I32, I32, P, P],
         "tm_topn": [P, P, I32, I32, I32, P, P, P, P],
         "tm_last_error": [],
         "tm_version": [],
@@ -444,6 +449,54 @@ def refine_angles(lib: Library, polar, norms, top_template, top_angle, stream=No
     _check(_lib.tm_refine_angles(lib._h, _ptr(polar), _ptr(norms), B, compact, int(N),
                                  _ptr(top_template), _ptr(top_angle), _ptr(out),
                                  _stream_ptr(stream)), "tm_refine_angles")
+    return out
+
+
+def orientations(lib_euler, top_template, top_angle=None, angle_deg=None, n_theta: int = 360,
+                 mirrors: bool = True, stream=None):
+    """tm_orientations: Bunge angles (phi1, Phi, phi2) in radians, [B, N, 3]
+    float64, of matches (top_template with either angle bins top_angle or
+    refined angles angle_deg in degrees). lib_euler: [T, 2] float64 device
+    tensor of the base templates' (Phi, phi2)."""
+    torch = _torch()
+    _require(lib_euler, "lib_euler", torch.float64)
+    T = lib_euler.shape[0]
+    _require(lib_euler, "lib_euler", torch.float64, (T, 2))
+    _require(top_template, "top_template", torch.int32)
+    B, N = top_template.shape
+    if (top_angle is None) == (angle_deg is None):
+        raise ValueError("give exactly one of top_angle and angle_deg")
+    if top_angle is not None:
+        _require(top_angle, "top_angle", torch.int32, (B, N))
+    else:
+        _require(angle_deg, "angle_deg", torch.float32, (B, N))
+    out = torch.empty((B, N, 3), dtype=torch.float64, device=top_template.device)
+    _check(_lib.tm_orientations(_ptr(lib_euler), int(T), 1 if mirrors else 0, int(n_theta),
+                                _ptr(top_template), _ptr(top_angle), _ptr(angle_deg), int(B),
+                                int(N), _ptr(out), _stream_ptr(stream)), "tm_orientations")
+    return out
+
+
+def ipf_deviation(euler_a, euler_b, laue: str, stream=None):
+    """tm_ipf_deviation, Eq. (2): [B, 3] float64 radians (IPF-x, -y, -z) between
+    two orientation maps. euler_a / euler_b: [B, 3] or [B, N, 3] float64
+    (the first triple of each pattern is used)."""
+    torch = _torch()
+    if laue not in LAUE_GROUPS:
+        raise ValueError(f"laue must be one of {sorted(LAUE_GROUPS)}")
+    strides = []
+    for name, e in (("euler_a", euler_a), ("euler_b", euler_b)):
+        _require(e, name, torch.float64)
+        if e.dim() not in (2, 3) or e.shape[-1] != 3:
+            raise ValueError(f"{name} must be [B, 3] or [B, N, 3]")
+        strides.append(3 if e.dim() == 2 else 3 * e.shape[1])
+    B = euler_a.shape[0]
+    if euler_b.shape[0] != B:
+        raise ValueError("euler_a and euler_b must have the same number of patterns")
+    out = torch.empty((B, 3), dtype=torch.float64, device=euler_a.device)
+    _check(_lib.tm_ipf_deviation(_ptr(euler_a), strides[0], _ptr(euler_b), strides[1], int(B),
+                                 LAUE_GROUPS[laue], _ptr(out), _stream_ptr(stream)),
+           "tm_ipf_deviation")
     return out
 
 

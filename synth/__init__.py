@@ -26,7 +26,7 @@ import numpy as np
 
 __all__ = [
     "Config", "CONFIGS", "wavelength_A", "make_library", "make_patterns",
-    "ground_truth", "rng_for", "px_per_inv_A",
+    "ground_truth", "rng_for", "px_per_inv_A", "template_euler", "laue_of",
 ]
 
 # --------------------------------------------------------------------------
@@ -314,6 +314,26 @@ def _simulate_phase(phase: Phase, cfg: Config, phase_idx: int):
 
 
 _LIB_CACHE: dict = {}
+
+
+def template_euler(cfg: Config | int, phases: tuple | None = None) -> np.ndarray:
+    """(Phi, phi2) in radians of every template of make_library(cfg, phases),
+    the Bunge angles of its beam direction with phi1 = 0 (the orientation the
+    template was simulated for), [T, 2] float64."""
+    if isinstance(cfg, int):
+        cfg = CONFIGS[cfg]
+    phases = cfg.phases if phases is None else phases
+    out = []
+    for pi, phase in enumerate(phases):
+        v = _directions(phase, cfg.cid, pi)
+        out.append(np.stack([np.arccos(np.clip(v[:, 2], -1.0, 1.0)),
+                             np.arctan2(v[:, 0], v[:, 1])], axis=1))
+    return np.concatenate(out).astype(np.float64)
+
+
+def laue_of(phase: Phase) -> str:
+    """Laue group of a phase (the symmetry of its sampled sector)."""
+    return phase.sector
 
 
 def make_library(cfg: Config | int, phases: tuple | None = None):

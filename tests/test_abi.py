@@ -124,6 +124,17 @@ def test_polar_and_topn_argument_errors(tm):
     assert L.tm_mask_from_mean(None, 1, 4, 16, 16, 1.0, 1, 1, buf, None) == tm.TM_EINVAL
     assert L.tm_free_library(None) == tm.TM_OK
     assert L.tm_library_info(None, None, None, None) == tm.TM_EINVAL
+    # orientations: exactly one angle source, valid sizes and flags
+    assert L.tm_orientations(buf, 4, 1, 360, buf, buf, buf, 1, 1, buf, None) == tm.TM_EINVAL
+    assert L.tm_orientations(buf, 4, 1, 360, buf, None, None, 1, 1, buf, None) == tm.TM_EINVAL
+    assert L.tm_orientations(buf, 0, 1, 360, buf, buf, None, 1, 1, buf, None) == tm.TM_EINVAL
+    assert L.tm_orientations(buf, 4, 2, 360, buf, buf, None, 1, 1, buf, None) == tm.TM_EINVAL
+    assert L.tm_orientations(buf, 4, 1, 360, buf, buf, None, 1, 0, buf, None) == tm.TM_EINVAL
+    assert L.tm_orientations(None, 4, 1, 360, buf, buf, None, 1, 1, buf, None) == tm.TM_EINVAL
+    assert L.tm_ipf_deviation(buf, 3, buf, 3, 1, 3, buf, None) == tm.TM_EINVAL
+    assert L.tm_ipf_deviation(buf, 2, buf, 3, 1, 0, buf, None) == tm.TM_EINVAL
+    assert L.tm_ipf_deviation(buf, 3, None, 3, 1, 0, buf, None) == tm.TM_EINVAL
+    assert L.tm_ipf_deviation(buf, 3, buf, 3, -1, 0, buf, None) == tm.TM_EINVAL
 
 
 def _has_gpu():

@@ -9,6 +9,7 @@ import pytest
 import oracle
 import oracle.library as olibmod
 import oracle.match as omatch
+import oracle.orient as oorient
 import oracle.polar as opolar
 import test_oracle_pins as pins
 
@@ -94,6 +95,34 @@ def _topn_ties_high_index(best, arg, N, templates=None):
     return tids[order], np.asarray(arg)[order], np.asarray(best)[order]
 
 
+_orig_bunge = oorient.bunge_matrix64
+
+
+def _bunge_transposed(phi1, Phi, phi2):
+    return _orig_bunge(phi1, Phi, phi2).T        # active and passive confused
+
+
+def _mirror_about_y(Phi, phi2, phi, mirrored):
+    M = oorient.bunge_matrix64(0.0, Phi, phi2).T
+    if mirrored:
+        M = np.diag([-1.0, 1.0, -1.0]) @ M       # pi about sample y: spots (-kx, ky)
+    M = oorient.rot_z_active64(phi) @ M
+    return oorient.euler_from_matrix64(M.T)
+
+
+def _sector_xy_swapped(v, laue):
+    w = _orig_sector(v, laue)
+    return np.array([w[1], w[0], w[2]]) if laue == "m-3m" else w
+
+
+_orig_sector = oorient.sector_direction64
+
+
+def _ipf_unreduced(euler_a, euler_b, laue):
+    ga, gb = oorient.bunge_matrix64(*euler_a), oorient.bunge_matrix64(*euler_b)
+    return np.abs(np.arccos(np.clip(np.sum(ga * gb, axis=0), -1.0, 1.0)))
+
+
 CASES = [
     ("x/y swapped in polar coordinates", opolar, "polar_coords64", _swapped_coords,
      [pins.test_p9_polar_reproduces_bilinear_functions]),
@@ -113,6 +142,14 @@ CASES = [
      [pins.test_p7_topn_brute_force]),
     ("ties ranked by higher index", omatch, "topn64", _topn_ties_high_index,
      [pins.test_p7_topn_brute_force]),
+    ("Bunge matrix transposed", oorient, "bunge_matrix64", _bunge_transposed,
+     [pins.test_bunge_matrix_equals_scipy_intrinsic_zxz]),
+    ("mirror read as a rotation about y", oorient, "match_orientation64", _mirror_about_y,
+     [pins.test_match_orientation_reproduces_rotated_and_mirrored_spots]),
+    ("cubic sector with x and y swapped", oorient, "sector_direction64", _sector_xy_swapped,
+     [lambda: pins.test_laue_group_is_a_group_and_sector_is_fundamental("m-3m", 48)]),
+    ("Eq. (2) without the symmetry reduction", oorient, "ipf_deviation64", _ipf_unreduced,
+     [pins.test_eq2_closed_forms]),
 ]
 
 

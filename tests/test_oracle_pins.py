@@ -551,3 +551,106 @@ def test_refined_angle_moves_one_bin_with_a_rolled_image():
         a0 = oracle.refine_angle64(P, olib, t, int(arg[t]))
         a1 = oracle.refine_angle64(np.roll(P, 1, axis=1), olib, t, (int(arg[t]) + 1) % olib.n_theta)
         assert abs((a1 - a0 - step + 180) % 360 - 180) < 1e-9
+
+
+# ------------------------------------------------- orientations and Eq. (2)
+def _random_euler(rng, n):
+    return np.stack([rng.uniform(0, 2 * np.pi, n), np.arccos(rng.uniform(-1, 1, n)),
+                     rng.uniform(0, 2 * np.pi, n)], axis=1)
+
+
+def test_bunge_matrix_equals_scipy_intrinsic_zxz():
+    """Bunge g (sample -> crystal) is the transpose of scipy's intrinsic
+    z-x'-z'' rotation with the same three angles."""
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(40)
+    for e in _random_euler(rng, 50):
+        want = Rotation.from_euler("ZXZ", e).as_matrix().T
+        assert np.allclose(oracle.bunge_matrix64(*e), want, atol=1e-13)
+
+
+def test_euler_round_trip_and_degenerate_axes():
+    rng = np.random.default_rng(41)
+    for e in _random_euler(rng, 50):
+        back = oracle.euler_from_matrix64(oracle.bunge_matrix64(*e))
+        d = (back - e + np.pi) % (2 * np.pi) - np.pi
+        assert np.allclose(d, 0.0, atol=1e-9), (e, back)
+    for Phi in (0.0, np.pi):
+        for a, c in ((0.3, 1.1), (5.9, 4.0)):
+            g = oracle.bunge_matrix64(a, Phi, c)
+            back = oracle.euler_from_matrix64(g)
+            assert back[2] == 0.0 and back[1] == Phi
+            assert np.allclose(oracle.bunge_matrix64(*back), g, atol=1e-12)
+
+
+def test_match_orientation_reproduces_rotated_and_mirrored_spots():
+    """Section 2.1/2.2: the orientation of a match at in-plane angle phi maps
+    the crystal's reciprocal vectors onto the template's spots rotated by phi
+    (counter-clockwise, +x toward +y), or onto the mirrored spots (kx, -ky)
+    rotated by phi for a mirrored template."""
+    rng = np.random.default_rng(42)
+    gc = rng.standard_normal((20, 3))                    # crystal-frame g vectors
+    for _ in range(20):
+        Phi, phi2 = np.arccos(rng.uniform(-1, 1)), rng.uniform(0, 2 * np.pi)
+        phi = rng.uniform(0, 2 * np.pi)
+        tmpl = (oracle.bunge_matrix64(0.0, Phi, phi2).T @ gc.T).T[:, :2]   # template spots
+        c, s = np.cos(phi), np.sin(phi)
+        for mirrored in (False, True):
+            sp = tmpl * np.array([1.0, -1.0]) if mirrored else tmpl
+            want = np.stack([c * sp[:, 0] - s * sp[:, 1], s * sp[:, 0] + c * sp[:, 1]], axis=1)
+            e = oracle.match_orientation64(Phi, phi2, phi, mirrored)
+            got = (oracle.bunge_matrix64(*e).T @ gc.T).T[:, :2]
+            assert np.allclose(got, want, atol=1e-12), (mirrored, e)
+            assert 0 <= e[0] < 2 * np.pi and 0 <= e[1] <= np.pi and 0 <= e[2] < 2 * np.pi
+
+
+@pytest.mark.parametrize("laue, order", [("m-3m", 48), ("mmm", 8), ("6/mmm", 24)])
+def test_laue_group_is_a_group_and_sector_is_fundamental(laue, order):
+    ops = oracle.symmetry_operators64(laue)
+    assert len(ops) == order
+    keys = {tuple(np.round(o, 9).ravel()) for o in ops}
+    assert len(keys) == order
+    for a in ops[:8]:
+        for b in ops:
+            assert tuple(np.round(a @ b, 9).ravel()) in keys       # closed under products
+    rng = np.random.default_rng(43)
+    for v in rng.standard_normal((200, 3)):
+        w = oracle.sector_direction64(v, laue)
+        assert oracle.in_sector64(w, laue)
+        assert np.isclose(np.linalg.norm(w), np.linalg.norm(v))
+        assert any(np.allclose(w, o @ v, atol=1e-12) for o in ops)
+        # exactly one image lies strictly inside the sector for a generic v
+        inside = sum(all(np.isclose(o @ v, w, atol=1e-12)) for o in ops)
+        assert inside == 1
+    if laue == "m-3m":
+        for v in rng.standard_normal((50, 3)):
+            a = np.sort(np.abs(v))
+            assert np.allclose(oracle.sector_direction64(v, laue), [a[1], a[0], a[2]])
+
+
+def test_eq2_closed_forms():
+    """Eq. (2): identical and symmetry-equivalent orientations deviate by 0;
+    a rotation about the beam leaves IPF-z unchanged; beam along [001] vs
+    [101] and [111] (cubic) gives 45 degrees and arccos(1/sqrt(3))."""
+    rng = np.random.default_rng(44)
+    for laue in ("m-3m", "mmm", "6/mmm"):
+        ops = oracle.symmetry_operators64(laue)
+        proper = [o for o in ops if np.linalg.det(o) > 0]
+        for e in _random_euler(rng, 10):
+            assert np.allclose(oracle.ipf_deviation64(e, e, laue), 0.0, atol=1e-7)
+            S = proper[rng.integers(len(proper))]
+            e2 = oracle.euler_from_matrix64(S @ oracle.bunge_matrix64(*e))
+            assert np.allclose(oracle.ipf_deviation64(e, e2, laue), 0.0, atol=1e-6)
+            e3 = e.copy()
+            e3[0] = (e3[0] + 0.3) % (2 * np.pi)      # phi1 rotates about the sample z axis
+            assert oracle.ipf_deviation64(e, e3, laue)[2] < 1e-7
+    # beam (sample z) along crystal [001]: Phi = 0; along [101]: Phi = 45 deg,
+    # phi2 = 90 deg (v = (sin phi2 sin Phi, cos phi2 sin Phi, cos Phi))
+    z001 = np.array([0.0, 0.0, 0.0])
+    z101 = np.array([0.0, np.pi / 4, np.pi / 2])
+    z111 = np.array([0.0, np.arccos(1 / np.sqrt(3)), np.pi / 4])
+    assert np.isclose(oracle.ipf_deviation64(z001, z101, "m-3m")[2], np.pi / 4, atol=1e-12)
+    assert np.isclose(oracle.ipf_deviation64(z001, z111, "m-3m")[2],
+                      np.arccos(1 / np.sqrt(3)), atol=1e-12)
+    assert np.isclose(oracle.ipf_deviation64(z101, z111, "m-3m")[2],
+                      np.arccos(2 / np.sqrt(6)), atol=1e-12)
