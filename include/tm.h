@@ -468,6 +468,52 @@ int tm_ipf_deviation(const double* euler_a, int32_t stride_a, const double* eule
                      int32_t stride_b, int32_t B, int32_t laue, double* deviation_out,
                      void* hip_stream);
 
+/* tm_simulate_library - kinematical template library on the device
+ * (Section 2.1): a reciprocal-space grid within a limiting radius is rotated
+ * by each orientation (phi1 = 0, Phi, phi2); each point's excitation error
+ * (distance to the Ewald sphere) sets a shape factor; spot intensity is
+ * F F* times the shape factor; the excited spots are projected onto kx-ky.
+ *
+ *   grid       all hkl != 000 with |g| <= g_lim, g = h b1 + k b2 + l b3,
+ *              lexicographic in (h, k, l); F = sum_a f_a exp(2 pi i h.x_a),
+ *              reflections with F F* <= 1e-6 dropped;
+ *   rotation   g_sample = g0^T g_crystal, g0 the Bunge matrix of
+ *              (0, Phi, phi2) (tm_orientations' frames);
+ *   Ewald      beam along -z: s = k - |g_sample - (0, 0, k)|;
+ *   shape      max(0, 1 - |s| / s_max) (linear relrod);
+ *   kept       shape > 0 and sqrt(gx^2 + gy^2) <= g_max, then intensity
+ *              >= rel_min * the template's brightest; ordered by intensity
+ *              (descending, ties in grid order), at most max_spots;
+ *              intensities divided by the brightest.
+ *
+ * Arguments
+ *   recip_basis   host, [3][3] float64, rows b1, b2, b3 in 1/Angstrom
+ *                 (Cartesian crystal frame, no factor 2 pi).
+ *   atoms_frac    host, [n_atoms][3] float64 fractional positions.
+ *   f_atoms       host, [n_atoms] float64 scattering factor per atom (1 for
+ *                 unit scattering factors).
+ *   n_atoms       1..32.
+ *   g_lim         > 0, grid radius (1/Angstrom); the (h, k, l) box it spans
+ *                 may hold at most 2^20 points.
+ *   orientations  device, [T, 2] float64 (Phi, phi2) radians.
+ *   T             >= 0 (0 is a no-op).
+ *   k             > 0, 1 / wavelength (1/Angstrom).
+ *   s_max, g_max  > 0 (1/Angstrom). rel_min >= 0. max_spots 1..4096.
+ *   kx_out, ky_out, intensity_out  device, [T, max_spots] float64, written
+ *                 up to count_out[t] entries per row (the rest untouched).
+ *   count_out     device, [T] int32, written.
+ * Scratch (the reflection list, and spill space for orientations that excite
+ * more than 256 reflections: about 12 bytes x reflections x 8 x 4 x CUs)
+ * comes from the stream-ordered allocator.
+ * Errors: TM_EINVAL, TM_EUNSUPPORTED (box too large), TM_ENOMEM, TM_EHIP,
+ *         TM_ENODEV. */
+int tm_simulate_library(const double* recip_basis, const double* atoms_frac,
+                        const double* f_atoms, int32_t n_atoms, double g_lim,
+                        const double* orientations, int32_t T, double k, double s_max,
+                        double g_max, double rel_min, int32_t max_spots, double* kx_out,
+                        double* ky_out, double* intensity_out, int32_t* count_out,
+                        void* hip_stream);
+
 /* tm_fft_scores - approximate best score and angle of every template for every
  * pattern through the Fourier route (Section 3: the azimuthal sliding is a
  * circular cross-correlation along theta, evaluated with Fourier transforms).

@@ -29,7 +29,10 @@ out plainly, in float64, one function per step:
   two-stage indexing (Section 4, custom indexation procedures);
 * ``match_orientation64`` / ``ipf_deviation64`` - Bunge Euler angles of a
   match (Section 2.1, Section 2.2 for mirrors) and the angular deviation
-  between two orientation maps, Eq. (2) (Section 4.2).
+  between two orientation maps, Eq. (2) (Section 4.2);
+* ``simulate_library64`` - kinematical template library: reciprocal grid,
+  rotation, excitation error, shape and structure factors, projection
+  (Section 2.1).
 
 Readings where the paper is silent are stated in each function.
 """
@@ -41,6 +44,9 @@ from .match import (scores64, match_exact64, topn64, index_pattern64, index_batc
 from .fft import template_images64, fft_numerators64, fft_match64
 from .prefilter import radial_profiles64, prefilter64, index_pattern_prefiltered64
 from .mask import mean_pattern64, binary_erode64, binary_dilate64, matrix_mask64
+from .simulate import (reciprocal_grid64, structure_factor_sq64, reflections64,
+                       excitation_error64, shape_factor64, simulate_template64,
+                       simulate_library64)
 from .orient import (bunge_matrix64, euler_from_matrix64, match_orientation64,
                      symmetry_operators64, in_sector64, sector_direction64,
                      ipf_deviation64)
@@ -52,5 +58,7 @@ __all__ = [
     "index_pattern_prefiltered64", "template_images64", "fft_numerators64", "fft_match64",
     "mean_pattern64", "binary_erode64", "binary_dilate64", "matrix_mask64", "refine_angle64",
     "bunge_matrix64", "euler_from_matrix64", "match_orientation64", "symmetry_operators64",
-    "sector_direction64", "ipf_deviation64", "in_sector64",
+    "sector_direction64", "ipf_deviation64", "in_sector64", "reciprocal_grid64",
+    "structure_factor_sq64", "reflections64", "excitation_error64", "shape_factor64",
+    "simulate_template64", "simulate_library64",
 ]

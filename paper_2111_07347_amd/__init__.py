@@ -41,6 +41,7 @@ EXPORTED = ("tm_load_library", "tm_free_library", "tm_library_info", "tm_library
             "tm_library_rows", "tm_polar_transform", "tm_polar_transform_rows",
             "tm_mask_from_mean", "tm_match_batch", "tm_refine_angles", "tm_prefilter", "tm_match_candidates",
             "tm_fft_scores", "tm_fft_error_bound", "tm_orientations", "tm_ipf_deviation",
+            "tm_simulate_library",
             "tm_topn", "tm_last_error", "tm_version")
 
 
@@ -90,6 +91,7 @@ def _load():
         "tm_fft_error_bound": [P, ctypes.POINTER(D)],
         "tm_orientations": [P, I32, I32, I32, P, P, P, I32, I32, P, P],
         "tm_ipf_deviation": [P, I32, P, I32, I32, I32, P, P],
+        "tm_simulate_library": [P, P, P, I32, D, P, I32, D, D, D, D, I32, P, P, P, P, P],
         "tm_topn": [P, P, I32, I32, I32, P, P, P, P],
         "tm_last_error": [],
         "tm_version": [],
@@ -498,6 +500,45 @@ def ipf_deviation(euler_a, euler_b, laue: str, stream=None):
                                  LAUE_GROUPS[laue], _ptr(out), _stream_ptr(stream)),
            "tm_ipf_deviation")
     return out
+
+
+def simulate_library(recip_basis, atoms_frac, f_atoms, g_lim: float, orientations, k: float,
+                     s_max: float, g_max: float, rel_min: float = 1e-3, max_spots: int = 100,
+                     stream=None, csr: bool = True):
+    """tm_simulate_library: kinematical templates for orientations [T, 2]
+    (Phi, phi2) radians (float64 device tensor). recip_basis [3, 3] (rows b1,
+    b2, b3, 1/Angstrom), atoms_frac [n, 3] and f_atoms [n] are host arrays.
+    Returns the device arrays (kx, ky, intensity [T, max_spots], count [T]),
+    or with csr=True a host CSR dict (kx, ky, intensity, offsets) ready for
+    Library()."""
+    torch = _torch()
+    Bm = np.ascontiguousarray(recip_basis, dtype=np.float64).reshape(3, 3)
+    X = np.ascontiguousarray(atoms_frac, dtype=np.float64).reshape(-1, 3)
+    f = np.ascontiguousarray(f_atoms, dtype=np.float64).reshape(-1)
+    if len(f) != len(X):
+        raise ValueError("atoms_frac and f_atoms must describe the same atoms")
+    _require(orientations, "orientations", torch.float64)
+    T = orientations.shape[0]
+    _require(orientations, "orientations", torch.float64, (T, 2))
+    dev = orientations.device
+    kx = torch.empty((T, max_spots), dtype=torch.float64, device=dev)
+    ky = torch.empty_like(kx)
+    inten = torch.empty_like(kx)
+    cnt = torch.empty((T,), dtype=torch.int32, device=dev)
+    _check(_lib.tm_simulate_library(Bm.ctypes.data, X.ctypes.data, f.ctypes.data, len(f),
+                                    float(g_lim), _ptr(orientations), int(T), float(k),
+                                    float(s_max), float(g_max), float(rel_min), int(max_spots),
+                                    _ptr(kx), _ptr(ky), _ptr(inten), _ptr(cnt),
+                                    _stream_ptr(stream)), "tm_simulate_library")
+    if not csr:
+        return kx, ky, inten, cnt
+    # host CSR for the library loader (tm_load_library reads host arrays)
+    c = cnt.cpu().numpy().astype(np.int64)
+    off = np.zeros(T + 1, dtype=np.int64)
+    off[1:] = np.cumsum(c)
+    sel = np.arange(max_spots)[None, :] < c[:, None]
+    return dict(kx=kx.cpu().numpy()[sel], ky=ky.cpu().numpy()[sel],
+                intensity=inten.cpu().numpy()[sel], offsets=off)
 
 
 def fft_scores(lib: Library, polar, norms, with_angle: bool = True, stream=None):

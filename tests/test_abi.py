@@ -135,6 +135,25 @@ def test_polar_and_topn_argument_errors(tm):
     assert L.tm_ipf_deviation(buf, 2, buf, 3, 1, 0, buf, None) == tm.TM_EINVAL
     assert L.tm_ipf_deviation(buf, 3, None, 3, 1, 0, buf, None) == tm.TM_EINVAL
     assert L.tm_ipf_deviation(buf, 3, buf, 3, -1, 0, buf, None) == tm.TM_EINVAL
+    # library simulation: host crystal arrays are read during validation
+    B = np.eye(3) / 4.05
+    X = np.zeros((1, 3))
+    f = np.ones(1)
+    sim = lambda Bm=B, n=1, g_lim=1.4, T=1, k=40.0, smax=0.05, gmax=1.2, rel=1e-3, S=10, o=buf: \
+        L.tm_simulate_library(Bm.ctypes.data if Bm is not None else None, X.ctypes.data,
+                              f.ctypes.data, n, g_lim, o, T, k, smax, gmax, rel, S, buf, buf,
+                              buf, buf, None)
+    assert sim(n=0) == tm.TM_EINVAL
+    assert sim(n=33) == tm.TM_EINVAL
+    assert sim(S=0) == tm.TM_EINVAL
+    assert sim(T=-1) == tm.TM_EINVAL
+    assert sim(g_lim=0.0) == tm.TM_EINVAL
+    assert sim(smax=float("nan")) == tm.TM_EINVAL
+    assert sim(rel=-1.0) == tm.TM_EINVAL
+    assert sim(o=None) == tm.TM_EINVAL
+    assert sim(Bm=np.zeros((3, 3))) == tm.TM_EINVAL                  # singular basis
+    assert sim(Bm=np.eye(3) / 40.0) == tm.TM_EUNSUPPORTED            # box too large
+    assert sim(Bm=None) == tm.TM_EINVAL
 
 
 def _has_gpu():

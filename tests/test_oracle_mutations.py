@@ -11,6 +11,7 @@ import oracle.library as olibmod
 import oracle.match as omatch
 import oracle.orient as oorient
 import oracle.polar as opolar
+import oracle.simulate as osim
 import test_oracle_pins as pins
 
 
@@ -123,6 +124,27 @@ def _ipf_unreduced(euler_a, euler_b, laue):
     return np.abs(np.arccos(np.clip(np.sum(ga * gb, axis=0), -1.0, 1.0)))
 
 
+def _ewald_wrong_side(g_sample, k):
+    d = g_sample + np.array([0.0, 0.0, k])     # sphere centred at (0, 0, -k)
+    return k - np.sqrt(np.sum(d * d, axis=-1))
+
+
+def _make_sim(transpose=True, ties_reversed=False):
+    def sim(g_c, F2, Phi, phi2, k, s_max, g_max, rel_min, max_spots):
+        M = oorient.bunge_matrix64(0.0, Phi, phi2)
+        M = M.T if transpose else M
+        gs = np.asarray(g_c) @ M.T
+        shape = osim.shape_factor64(osim.excitation_error64(gs, k), s_max)
+        I = np.asarray(F2) * shape
+        idx = np.nonzero((shape > 0) & (np.hypot(gs[:, 0], gs[:, 1]) <= g_max))[0]
+        top = I[idx].max()
+        idx = idx[I[idx] >= rel_min * top]
+        key = (lambda i: (-I[i], -i)) if ties_reversed else (lambda i: (-I[i], i))
+        order = np.array(sorted(idx.tolist(), key=key)[:max_spots], dtype=np.int64)
+        return gs[order, 0], gs[order, 1], I[order] / top
+    return sim
+
+
 CASES = [
     ("x/y swapped in polar coordinates", opolar, "polar_coords64", _swapped_coords,
      [pins.test_p9_polar_reproduces_bilinear_functions]),
@@ -150,6 +172,12 @@ CASES = [
      [lambda: pins.test_laue_group_is_a_group_and_sector_is_fundamental("m-3m", 48)]),
     ("Eq. (2) without the symmetry reduction", oorient, "ipf_deviation64", _ipf_unreduced,
      [pins.test_eq2_closed_forms]),
+    ("Ewald sphere on the wrong side", osim, "excitation_error64", _ewald_wrong_side,
+     [pins.test_excitation_error_ewald_geometry]),
+    ("orientation applied untransposed", osim, "simulate_template64", _make_sim(False),
+     [pins.test_phi2_rotates_a_zone_pattern_in_plane]),
+    ("equal intensities in reverse grid order", osim, "simulate_template64",
+     _make_sim(True, True), [pins.test_fcc_001_zone_axis_pattern]),
 ]
 
 

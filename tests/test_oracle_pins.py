@@ -654,3 +654,103 @@ def test_eq2_closed_forms():
                       np.arccos(1 / np.sqrt(3)), atol=1e-12)
     assert np.isclose(oracle.ipf_deviation64(z101, z111, "m-3m")[2],
                       np.arccos(2 / np.sqrt(6)), atol=1e-12)
+
+
+# ------------------------------------------------ library simulation (2.1)
+FCC_A = 4.05
+K_200KV = 1.0 / synth.wavelength_A(200.0)
+FCC_ATOMS = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]], dtype=float)
+
+
+def test_reciprocal_grid_equals_brute_force():
+    from oracle import simulate as osim
+    Bm = np.diag([1 / 5.1, 1 / 7.3, 1 / 4.6])
+    hkl, g = osim.reciprocal_grid64(Bm, 1.0)
+    want = [(h, k, l) for h in range(-12, 13) for k in range(-12, 13) for l in range(-12, 13)
+            if (h, k, l) != (0, 0, 0) and (h / 5.1) ** 2 + (k / 7.3) ** 2 + (l / 4.6) ** 2 <= 1.0]
+    assert [tuple(r) for r in hkl] == sorted(want)
+    assert np.allclose(g, hkl * np.array([1 / 5.1, 1 / 7.3, 1 / 4.6]))
+
+
+def test_structure_factors_textbook():
+    """FCC: F F* = 16 for unmixed hkl, 0 for mixed. HCP (atoms at 0 and
+    (1/3, 2/3, 1/2)): 4, 0, 1, 3 by (h + 2k mod 3, l parity)."""
+    from oracle import simulate as osim
+    rng = np.random.default_rng(60)
+    hkl = rng.integers(-6, 7, (300, 3))
+    F2 = osim.structure_factor_sq64(hkl, FCC_ATOMS, np.ones(4))
+    unmixed = np.all(hkl % 2 == 0, axis=1) | np.all(hkl % 2 == 1, axis=1)
+    assert np.allclose(F2, np.where(unmixed, 16.0, 0.0), atol=1e-9)
+    F2 = osim.structure_factor_sq64(hkl, [[0, 0, 0], [1 / 3, 2 / 3, 0.5]], np.ones(2))
+    r3 = (hkl[:, 0] + 2 * hkl[:, 1]) % 3
+    lo = hkl[:, 2] % 2 == 1
+    want = np.where(r3 == 0, np.where(lo, 0.0, 4.0), np.where(lo, 3.0, 1.0))
+    assert np.allclose(F2, want, atol=1e-9)
+
+
+def test_excitation_error_ewald_geometry():
+    """Points on the sphere through the origin with centre (0, 0, k) have
+    s = 0, points inside s > 0; near the origin s = gz - gxy^2 / (2k) to
+    second order."""
+    from oracle import simulate as osim
+    rng = np.random.default_rng(61)
+    u = rng.standard_normal((50, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    on = np.array([0, 0, K_200KV]) + K_200KV * u
+    assert np.allclose(osim.excitation_error64(on, K_200KV), 0.0, atol=1e-10)
+    assert np.all(osim.excitation_error64(np.array([0, 0, K_200KV]) + 0.5 * K_200KV * u, K_200KV) > 0)
+    g = rng.uniform(-1.0, 1.0, (50, 3)) * np.array([1, 1, 0.05])
+    approx = g[:, 2] - (g[:, 0] ** 2 + g[:, 1] ** 2) / (2 * K_200KV)
+    err = np.abs(osim.excitation_error64(g, K_200KV) - approx)
+    assert np.all(err < 5 * np.linalg.norm(g, axis=1) ** 3 / K_200KV ** 2 + 1e-12)
+
+
+def _fcc_zone(Phi, phi2, max_spots=200):
+    from oracle import simulate as osim
+    _, g, F2 = osim.reflections64(np.eye(3) / FCC_A, FCC_ATOMS, np.ones(4), 1.4)
+    return osim.simulate_template64(g, F2, Phi, phi2, K_200KV, 0.05, 1.2, 1e-3, max_spots)
+
+
+def test_fcc_001_zone_axis_pattern():
+    """Beam along [001]: the zero-order Laue zone only (l = 0), h and k both
+    even, on a square grid of spacing 2/a within g_max; brightest nearest
+    the centre (the Ewald sphere leaves the plane as g^2 / 2k); equal
+    intensities in lexicographic (h, k) order."""
+    kx, ky, I = _fcc_zone(0.0, 0.0)
+    want = sorted([(h, k) for h in range(-8, 9, 2) for k in range(-8, 9, 2)
+                   if (h, k) != (0, 0) and np.hypot(h, k) / FCC_A <= 1.2],
+                  key=lambda hk: (hk[0] ** 2 + hk[1] ** 2, hk))
+    got = np.stack([kx, ky], axis=1) * FCC_A
+    assert np.allclose(got, np.array(want, dtype=float), atol=1e-9)
+    # zero layer: |s| = k - sqrt(k^2 + g^2) exactly = g^2 / (k + sqrt(k^2 + g^2))
+    g2 = kx ** 2 + ky ** 2
+    s = g2 / (K_200KV + np.sqrt(K_200KV ** 2 + g2))
+    assert np.all(np.diff(I) <= 1e-15) and np.isclose(I[0], 1.0)
+    assert np.allclose(I, (1 - s / 0.05) / (1 - s[0] / 0.05), atol=1e-12)
+
+
+def test_phi2_rotates_a_zone_pattern_in_plane():
+    """With Phi = 0 the orientation is a rotation about the beam: phi2
+    rotates the projected spots counter-clockwise by phi2."""
+    kx0, ky0, I0 = _fcc_zone(0.0, 0.0)
+    a = 0.7
+    kx, ky, I = _fcc_zone(0.0, a)
+    rot = np.stack([np.cos(a) * kx0 - np.sin(a) * ky0, np.sin(a) * kx0 + np.cos(a) * ky0], 1)
+    got = np.stack([kx, ky], axis=1)
+    key = lambda p: tuple(np.round(p, 9))
+    assert sorted(map(key, got)) == sorted(map(key, rot))
+    assert np.allclose(np.sort(I), np.sort(I0))
+
+
+def test_simulation_equals_workload_generator_library():
+    """The oracle's simulation reproduces the workload generator's own
+    kinematical library (an independent implementation) for the tiny case."""
+    from oracle import simulate as osim
+    cfg = synth.CONFIGS[1]
+    lib = synth.make_library(cfg)
+    o = osim.simulate_library64(np.eye(3) / FCC_A, FCC_ATOMS, np.ones(4), cfg.g_max + 0.2,
+                                synth.template_euler(cfg), 1 / synth.wavelength_A(cfg.kv),
+                                cfg.s_max, cfg.g_max, 1e-3, cfg.phases[0].max_spots)
+    assert np.array_equal(o["offsets"], lib["offsets"])
+    for key in ("kx", "ky", "intensity"):
+        assert np.allclose(o[key], lib[key], atol=1e-12)
