@@ -71,6 +71,10 @@ def parse():
                     help="orientations of the on-device library simulation leg (0 = skip)")
     ap.add_argument("--sim-cpu-sample", type=int, default=2000,
                     help="orientations the oracle simulates for that leg's CPU baseline")
+    ap.add_argument("--no-preprocess", action="store_true",
+                    help="skip the on-device preprocessing leg")
+    ap.add_argument("--pre-cpu-sample", type=int, default=16,
+                    help="patterns the oracle preprocesses for that leg's CPU baseline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy three times (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -347,6 +351,47 @@ def simulation_bench(tm, a):
     return res
 
 
+def preprocess_bench(tm, x, a):
+    """Preprocessing of the whole batch on the device (Section 4.2: direct
+    beam centred, difference of Gaussians, blur, threshold), against the
+    HBM roofline of reading the patterns and writing the result once, and
+    the oracle on a few patterns as its CPU baseline."""
+    import torch
+    o = dict(r_box=8, frac=0.5, sigma_min=1.0, sigma_max=6.0, sigma_blur=1.0, threshold=0.0)
+    B, H, W = x.shape
+    out = torch.empty((B, H, W), dtype=torch.float32, device=x.device)
+    cen = torch.empty((B, 2), dtype=torch.float64, device=x.device)
+    tm.preprocess(x, out=out, centre_out=cen, **o)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ms = []
+    for _ in range(3):
+        ev[0].record()
+        tm.preprocess(x, out=out, centre_out=cen, **o)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms.append(ev[0].elapsed_time(ev[1]))
+    ms = float(np.median(ms))
+    alg = float(B) * H * W * (x.element_size() + 4)
+    import oracle as _oracle                      # the oracle is timed as the baseline only
+    n_cpu = min(B, a.pre_cpu_sample)
+    sample = x[:n_cpu].cpu().numpy().astype(np.float64)
+    t0 = time.perf_counter()
+    for i in range(n_cpu):
+        _oracle.preprocess64(sample[i], **o)
+    cpu_s = time.perf_counter() - t0
+    res = {"patterns": B, "options": o, "ms": round(ms, 4),
+           "patterns_per_s": round(B / (ms * 1e-3), 1),
+           "roofline": {"bound": "hbm", "achieved": round(alg / (ms * 1e-3) / 1e9, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "algorithmic_bytes": alg},
+           "cpu_baseline": {"value": round(n_cpu / cpu_s, 2), "unit": "patterns/s", "cores": 1,
+                            "kind": "oracle", "sample": f"first {n_cpu} patterns, FP64 NumPy"}}
+    print(f"[bench] preprocessing: {res}", file=sys.stderr, flush=True)
+    return res
+
+
 def c5_bench(a):
     """Large multi-phase workload: 262 144 uint16 patterns (1024 scan rows of
     256) against 50 000 templates (5000 FCC, 15 000 HCP, 30 000
@@ -616,6 +661,7 @@ def main():
         fft_path.pop("_top")
 
     simulation = simulation_bench(tm, a) if a.sim_templates > 0 else None
+    preprocessing = None if a.no_preprocess else preprocess_bench(tm, x, a)
 
     serving = None
     if a.serving_rows > 0:
@@ -648,6 +694,7 @@ def main():
         "top1_agreement_vs_oracle_on_sample": top1,
         "orientation_accuracy": accuracy,
         "library_simulation": simulation,
+        "preprocessing": preprocessing,
         "precision_path": prec_path,
         "fft_path": fft_path,
         "serving": serving,

@@ -514,6 +514,49 @@ int tm_simulate_library(const double* recip_basis, const double* atoms_frac,
                         double* ky_out, double* intensity_out, int32_t* count_out,
                         void* hip_stream);
 
+/* Options of tm_preprocess (Section 4.2: direct beam centred, diffuse
+ * background removed by a difference of Gaussians, Gaussian blur, low
+ * intensities set to zero). */
+typedef struct {
+    int32_t r_box;       /* centre search half-width in px around (W/2, H/2); < 0: no centring */
+    double frac;         /* box pixels >= frac * box maximum enter the centroid */
+    double sigma_min;    /* difference of Gaussians G(sigma_min) - G(sigma_max), px; */
+    double sigma_max;    /*   sigma_max = 0 skips it; else 0 <= sigma_min < sigma_max */
+    double sigma_blur;   /* Gaussian blur of the result, px; 0 skips it */
+    double threshold;    /* values below it become 0; -inf skips it */
+} tm_preprocess_opts;
+
+/* tm_preprocess - the preprocessing the paper applies before indexing, in
+ * its order, on the device (Section 4.2; the discussion lists moving these
+ * steps off the CPU as an open optimisation).
+ *
+ *   centre    (cx, cy) = intensity-weighted centroid (float64) of the pixels
+ *             of the box |x - W/2| <= r_box, |y - H/2| <= r_box whose value
+ *             is >= frac * the box maximum (the direct beam); a box whose
+ *             maximum is <= 0 gives (W/2, H/2). The pattern is resampled
+ *             as c(x, y) = p(x + cx - W/2, y + cy - H/2), bilinear, zero
+ *             outside, which puts the beam on (W/2, H/2);
+ *   DoG       d = G(sigma_min) c - G(sigma_max) c;
+ *   blur      e = G(sigma_blur) d;  threshold: e < threshold -> 0.
+ * G(sigma): separable correlation with exp(-t^2 / 2 sigma^2) on
+ * |t| <= floor(4 sigma + 0.5) (at most 64), normalised to sum 1, mirror
+ * boundary (... c b a | a b c ...); G(0) is the identity. Arithmetic in
+ * float32 (centroid in float64). The output feeds tm_polar_transform as a
+ * TM_F32 pattern stack (its gamma step follows, as in the paper).
+ *
+ * Arguments
+ *   patterns     device, [B, H, W] uint16 or float32 (dtype).
+ *   B, H, W      B >= 0 (0 is a no-op), 1 <= H, W <= 8192.
+ *   opts         host, read during the call.
+ *   out          device, [B, H, W] float32, written (may not alias patterns).
+ *   centre_out   device, [B, 2] float64 (cx, cy), written, or NULL.
+ * Scratch (two float32 images per pattern of a chunk, at most 1 GiB) comes
+ * from the stream-ordered allocator.
+ * Errors: TM_EINVAL, TM_ENOMEM, TM_EHIP, TM_ENODEV. */
+int tm_preprocess(const void* patterns, tm_dtype dtype, int32_t B, int32_t H, int32_t W,
+                  const tm_preprocess_opts* opts, float* out, double* centre_out,
+                  void* hip_stream);
+
 /* tm_fft_scores - approximate best score and angle of every template for every
  * pattern through the Fourier route (Section 3: the azimuthal sliding is a
  * circular cross-correlation along theta, evaluated with Fourier transforms).

@@ -32,7 +32,9 @@ out plainly, in float64, one function per step:
   between two orientation maps, Eq. (2) (Section 4.2);
 * ``simulate_library64`` - kinematical template library: reciprocal grid,
   rotation, excitation error, shape and structure factors, projection
-  (Section 2.1).
+  (Section 2.1);
+* ``preprocess64`` - direct-beam centring, difference-of-Gaussians
+  background removal, Gaussian blur and thresholding (Section 4.2).
 
 Readings where the paper is silent are stated in each function.
 """
@@ -47,6 +49,8 @@ from .mask import mean_pattern64, binary_erode64, binary_dilate64, matrix_mask64
 from .simulate import (reciprocal_grid64, structure_factor_sq64, reflections64,
                        excitation_error64, shape_factor64, simulate_template64,
                        simulate_library64)
+from .preprocess import (gaussian_weights64, convolve_axis64, gaussian64, beam_centre64,
+                         shift_image64, preprocess64)
 from .orient import (bunge_matrix64, euler_from_matrix64, match_orientation64,
                      symmetry_operators64, in_sector64, sector_direction64,
                      ipf_deviation64)
@@ -60,5 +64,6 @@ __all__ = [
     "bunge_matrix64", "euler_from_matrix64", "match_orientation64", "symmetry_operators64",
     "sector_direction64", "ipf_deviation64", "in_sector64", "reciprocal_grid64",
     "structure_factor_sq64", "reflections64", "excitation_error64", "shape_factor64",
-    "simulate_template64", "simulate_library64",
+    "simulate_template64", "simulate_library64", "gaussian_weights64", "convolve_axis64",
+    "gaussian64", "beam_centre64", "shift_image64", "preprocess64",
 ]

@@ -41,7 +41,7 @@ EXPORTED = ("tm_load_library", "tm_free_library", "tm_library_info", "tm_library
             "tm_library_rows", "tm_polar_transform", "tm_polar_transform_rows",
             "tm_mask_from_mean", "tm_match_batch", "tm_refine_angles", "tm_prefilter", "tm_match_candidates",
             "tm_fft_scores", "tm_fft_error_bound", "tm_orientations", "tm_ipf_deviation",
-            "tm_simulate_library",
+            "tm_simulate_library", "tm_preprocess",
             "tm_topn", "tm_last_error", "tm_version")
 
 
@@ -55,6 +55,12 @@ class _Grid(ctypes.Structure):
     _fields_ = [("R", ctypes.c_int32), ("n_theta", ctypes.c_int32), ("r0", ctypes.c_double),
                 ("dr", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double),
                 ("interp", ctypes.c_int32)]
+
+
+class _PreOpts(ctypes.Structure):
+    _fields_ = [("r_box", ctypes.c_int32), ("frac", ctypes.c_double),
+                ("sigma_min", ctypes.c_double), ("sigma_max", ctypes.c_double),
+                ("sigma_blur", ctypes.c_double), ("threshold", ctypes.c_double)]
 
 
 class _Opts(ctypes.Structure):
@@ -92,6 +98,7 @@ def _load():
         "tm_orientations": [P, I32, I32, I32, P, P, P, I32, I32, P, P],
         "tm_ipf_deviation": [P, I32, P, I32, I32, I32, P, P],
         "tm_simulate_library": [P, P, P, I32, D, P, I32, D, D, D, D, I32, P, P, P, P, P],
+        "tm_preprocess": [P, ctypes.c_int, I32, I32, I32, ctypes.POINTER(_PreOpts), P, P, P],
         "tm_topn": [P, P, I32, I32, I32, P, P, P, P],
         "tm_last_error": [],
         "tm_version": [],
@@ -539,6 +546,36 @@ def simulate_library(recip_basis, atoms_frac, f_atoms, g_lim: float, orientation
     sel = np.arange(max_spots)[None, :] < c[:, None]
     return dict(kx=kx.cpu().numpy()[sel], ky=ky.cpu().numpy()[sel],
                 intensity=inten.cpu().numpy()[sel], offsets=off)
+
+
+def preprocess(patterns, r_box: int = 8, frac: float = 0.5, sigma_min: float = 1.0,
+               sigma_max: float = 6.0, sigma_blur: float = 1.0, threshold: float = 0.0,
+               out=None, centre_out=None, stream=None):
+    """tm_preprocess: direct-beam centring, difference of Gaussians, blur and
+    threshold of a [B, H, W] uint16/float32 stack. Returns (float32 [B, H, W],
+    float64 [B, 2] beam centres). r_box < 0, sigma_max = 0, sigma_blur = 0 and
+    threshold = -inf switch the steps off."""
+    torch = _torch()
+    if patterns.dtype == torch.float32:
+        dt = TM_F32
+    elif patterns.dtype in (torch.uint16, torch.int16):
+        dt = TM_U16
+    else:
+        raise TypeError("patterns must be float32 or uint16")
+    B, H, W = patterns.shape
+    _require(patterns, "patterns", patterns.dtype, (B, H, W))
+    if out is None:
+        out = torch.empty((B, H, W), dtype=torch.float32, device=patterns.device)
+    _require(out, "out", torch.float32, (B, H, W))
+    if centre_out is None:
+        centre_out = torch.empty((B, 2), dtype=torch.float64, device=patterns.device)
+    _require(centre_out, "centre_out", torch.float64, (B, 2))
+    o = _PreOpts(int(r_box), float(frac), float(sigma_min), float(sigma_max), float(sigma_blur),
+                 float(threshold))
+    _check(_lib.tm_preprocess(_ptr(patterns), dt, int(B), int(H), int(W), ctypes.byref(o),
+                              _ptr(out), _ptr(centre_out), _stream_ptr(stream)),
+           "tm_preprocess")
+    return out, centre_out
 
 
 def fft_scores(lib: Library, polar, norms, with_angle: bool = True, stream=None):

@@ -154,6 +154,21 @@ def test_polar_and_topn_argument_errors(tm):
     assert sim(Bm=np.zeros((3, 3))) == tm.TM_EINVAL                  # singular basis
     assert sim(Bm=np.eye(3) / 40.0) == tm.TM_EUNSUPPORTED            # box too large
     assert sim(Bm=None) == tm.TM_EINVAL
+    # preprocessing options
+    po = lambda **k: tm._PreOpts(**{**dict(r_box=8, frac=0.5, sigma_min=1.0, sigma_max=6.0,
+                                          sigma_blur=1.0, threshold=0.0), **k})
+    pre = lambda o, B=1, H=16, W=16, dt=1, p=buf: L.tm_preprocess(p, dt, B, H, W,
+                                                                   ctypes.byref(o), buf, None, None)
+    assert L.tm_preprocess(buf, 1, 1, 16, 16, None, buf, None, None) == tm.TM_EINVAL
+    assert pre(po(), B=-1) == tm.TM_EINVAL
+    assert pre(po(), H=0) == tm.TM_EINVAL
+    assert pre(po(), dt=5) == tm.TM_EINVAL
+    assert pre(po(sigma_min=6.0, sigma_max=1.0)) == tm.TM_EINVAL
+    assert pre(po(sigma_blur=-1.0)) == tm.TM_EINVAL
+    assert pre(po(sigma_blur=100.0)) == tm.TM_EINVAL
+    assert pre(po(threshold=float("nan"))) == tm.TM_EINVAL
+    assert pre(po(), p=None) == tm.TM_EINVAL
+    assert pre(po(), B=0, p=None) in (tm.TM_OK, tm.TM_ENODEV)
 
 
 def _has_gpu():

@@ -11,6 +11,7 @@ import oracle.library as olibmod
 import oracle.match as omatch
 import oracle.orient as oorient
 import oracle.polar as opolar
+import oracle.preprocess as oprep
 import oracle.simulate as osim
 import test_oracle_pins as pins
 
@@ -145,6 +146,25 @@ def _make_sim(transpose=True, ties_reversed=False):
     return sim
 
 
+_orig_convolve = oprep.convolve_axis64
+
+
+def _convolve_zero_border(img, w, axis):
+    r = (len(w) - 1) // 2
+    pad = [(0, 0), (0, 0)]
+    pad[axis] = (r, r)
+    p = np.pad(np.asarray(img, dtype=np.float64), pad)
+    n = np.asarray(img).shape[axis]
+    return sum(w[t] * np.take(p, np.arange(n) + t, axis=axis) for t in range(2 * r + 1))
+
+
+def _shift_wrong_way(img, dx, dy):
+    return _orig_shift(img, -dx, -dy)
+
+
+_orig_shift = oprep.shift_image64
+
+
 CASES = [
     ("x/y swapped in polar coordinates", opolar, "polar_coords64", _swapped_coords,
      [pins.test_p9_polar_reproduces_bilinear_functions]),
@@ -178,6 +198,10 @@ CASES = [
      [pins.test_phi2_rotates_a_zone_pattern_in_plane]),
     ("equal intensities in reverse grid order", osim, "simulate_template64",
      _make_sim(True, True), [pins.test_fcc_001_zone_axis_pattern]),
+    ("Gaussian with a zero border", oprep, "convolve_axis64", _convolve_zero_border,
+     [lambda: pins.test_gaussian_equals_scipy_reflect(2.5)]),
+    ("centring shift the wrong way", oprep, "shift_image64", _shift_wrong_way,
+     [pins.test_shift_integer_fraction_and_round_trip, pins.test_preprocess_centres_an_offset_beam]),
 ]
 
 

@@ -754,3 +754,80 @@ def test_simulation_equals_workload_generator_library():
     assert np.array_equal(o["offsets"], lib["offsets"])
     for key in ("kx", "ky", "intensity"):
         assert np.allclose(o[key], lib[key], atol=1e-12)
+
+
+# ------------------------------------------------ preprocessing (Section 4.2)
+@pytest.mark.parametrize("sigma", [0.7, 1.0, 2.5, 6.0])
+def test_gaussian_equals_scipy_reflect(sigma):
+    rng = np.random.default_rng(80)
+    img = rng.random((37, 50))
+    want = ndimage.gaussian_filter(img, sigma, mode="reflect", truncate=4.0)
+    assert np.allclose(oracle.gaussian64(img, sigma), want, atol=1e-12)
+    # an image narrower than the kernel folds the mirror more than once
+    small = rng.random((5, 7))
+    assert np.allclose(oracle.gaussian64(small, sigma),
+                       ndimage.gaussian_filter(small, sigma, mode="reflect", truncate=4.0),
+                       atol=1e-12)
+
+
+def test_dog_of_constant_is_zero_and_linear():
+    rng = np.random.default_rng(81)
+    img = rng.random((40, 40))
+    d = lambda a: oracle.gaussian64(a, 1.0) - oracle.gaussian64(a, 6.0)
+    assert np.allclose(d(np.full((40, 40), 3.5)), 0.0, atol=1e-12)
+    assert np.allclose(d(img + 7.0), d(img), atol=1e-12)
+
+
+def test_beam_centre_brute_force_and_symmetric_spots():
+    img = np.zeros((32, 32))
+    img[16, 16] = img[16, 17] = 5.0                 # two equal pixels: the midpoint
+    assert oracle.beam_centre64(img, 4, 0.5) == (16.5, 16.0)
+    yy, xx = np.mgrid[0:64, 0:64].astype(float)
+    for x0, y0 in ((31.0, 33.0), (34.5, 29.5)):     # pixel- and half-pixel-centred spots
+        spot = np.exp(-((xx - x0) ** 2 + (yy - y0) ** 2) / (2 * 1.7 ** 2))
+        cx, cy = oracle.beam_centre64(spot, 8, 0.3)
+        assert abs(cx - x0) < 1e-12 and abs(cy - y0) < 1e-12
+    # brute force on a random box: centroid of the kept pixels
+    rng = np.random.default_rng(82)
+    img = rng.random((20, 24))
+    H, W = img.shape
+    pts = [(x, y, img[y, x]) for y in range(H) for x in range(W)
+           if abs(x - W / 2) <= 3 and abs(y - H / 2) <= 3]
+    m = max(v for _, _, v in pts)
+    keep = [(x, y, v) for x, y, v in pts if v >= 0.6 * m]
+    s = sum(v for _, _, v in keep)
+    want = (sum(x * v for x, _, v in keep) / s, sum(y * v for _, y, v in keep) / s)
+    assert np.allclose(oracle.beam_centre64(img, 3, 0.6), want, atol=1e-13)
+    assert oracle.beam_centre64(np.zeros((8, 8)), 2, 0.5) == (4.0, 4.0)
+
+
+def test_shift_integer_fraction_and_round_trip():
+    rng = np.random.default_rng(83)
+    img = rng.random((16, 20))
+    s = oracle.shift_image64(img, 3.0, -2.0)        # out(x, y) = in(x + 3, y - 2)
+    want = np.zeros_like(img)
+    want[2:, :-3] = img[:-2, 3:]
+    assert np.allclose(s, want, atol=1e-14)
+    s = oracle.shift_image64(img, 0.25, 0.0)
+    assert np.allclose(s[:, :-1], 0.75 * img[:, :-1] + 0.25 * img[:, 1:], atol=1e-14)
+    # a bilinear function is reproduced exactly away from the border
+    yy, xx = np.mgrid[0:16, 0:20].astype(float)
+    f = 1.0 + 0.3 * xx - 0.2 * yy + 0.01 * xx * yy
+    s = oracle.shift_image64(f, 1.3, -0.6)
+    g = 1.0 + 0.3 * (xx + 1.3) - 0.2 * (yy - 0.6) + 0.01 * (xx + 1.3) * (yy - 0.6)
+    assert np.allclose(s[2:-2, 1:-3], g[2:-2, 1:-3], atol=1e-12)
+
+
+def test_preprocess_centres_an_offset_beam():
+    """A pattern whose direct beam sits 3.4 px right and 2.25 px down of the
+    centre: after preprocessing the beam's centroid is back at (W/2, H/2)."""
+    H = W = 64
+    yy, xx = np.mgrid[0:H, 0:W].astype(float)
+    img = 10 * np.exp(-((xx - 35.4) ** 2 + (yy - 34.25) ** 2) / (2 * 1.5 ** 2)) + 0.2
+    out, (cx, cy) = oracle.preprocess64(img, r_box=8, frac=0.05, sigma_min=0.0,
+                                        sigma_max=0.0, sigma_blur=0.0)
+    # a thresholded centroid of an off-grid spot is biased by a small part of
+    # a pixel (less the lower the threshold)
+    assert abs(cx - 35.4) < 0.03 and abs(cy - 34.25) < 0.03
+    c2 = oracle.beam_centre64(out, 8, 0.05)
+    assert abs(c2[0] - 32.0) < 0.03 and abs(c2[1] - 32.0) < 0.03
