@@ -31,6 +31,14 @@ namespace {
 
 constexpr int kMaxRadius = 64;            // sigma <= 15.9
 constexpr int kRowThreads = 256;
+constexpr int kRowWaves = kRowThreads / 64;
+constexpr size_t kLdsLimit = 156 * 1024;
+constexpr int kTileRows = 256;            // column-strip kernel: images up to this high
+constexpr int kTapBlock = 8;              // taps per weight block of the column-strip kernel
+
+// Floats of one wave's row strip: the row rounded up to 256 columns (the
+// last chunk's lanes read past W) plus the two halos.
+__host__ __device__ inline int row_strip(int W, int rh) { return (W + 255) / 256 * 256 + 2 * rh; }
 constexpr int kCentreThreads = 256;
 constexpr size_t kScratchBudget = size_t(1) << 30;
 
@@ -40,6 +48,10 @@ struct Taps {
 };
 
 __device__ __forceinline__ int mirror(int i, int n) {
+    if (static_cast<unsigned>(i) < static_cast<unsigned>(n)) return i;
+    if (i < 0 && i >= -n) return -i - 1;
+    if (i >= n && i < 2 * n) return 2 * n - 1 - i;
+    // images narrower than the halo: fold modulo the period 2n
     const int p = 2 * n;
     int j = i % p;
     if (j < 0) j += p;
@@ -110,53 +122,140 @@ centre_kernel(const Tin* __restrict__ patterns, int H, int W, int r_box, double 
     }
 }
 
-// One row of the source correlated along x with taps a (-> out_a) and, when
-// out_b is given, taps b (-> out_b). The source is the input pattern (`in`),
-// centred when `centre` is given, else the float image `src`.
+// One image row per wave (4 rows per workgroup): the row of the source is
+// staged in the wave's LDS strip with a mirrored halo of rh columns on each
+// side, then correlated along x with taps a (-> out_a) and, when out_b is
+// given, taps b (-> out_b). The source is the input pattern (`in`), centred
+// when `centre` is given, else the float image `src`. Lanes own columns
+// lane + 64 m (m < 4) of each 256-column chunk; the tap loop is the outer
+// one, so each weight is loaded once per chunk.
 template <typename Tin>
 __global__ void __launch_bounds__(kRowThreads)
 row_kernel(const Tin* __restrict__ in, const float* __restrict__ src,
-           const double* __restrict__ centre, int H, int W, Taps a, Taps bt,
+           const double* __restrict__ centre, int H, int W, Taps a, Taps bt, int rh,
            float* __restrict__ out_a, float* __restrict__ out_b) {
-    extern __shared__ float row[];
-    const int y = blockIdx.x, b = blockIdx.y;
+    extern __shared__ float lds[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int y = blockIdx.x * kRowWaves + wave, b = blockIdx.y;
+    if (y >= H) return;    // the wave leaves; no workgroup barrier follows
+    const int span = W + 2 * rh;
+    float* row = lds + static_cast<size_t>(wave) * row_strip(W, rh);
     const size_t base = (static_cast<size_t>(b) * H + y) * W;
-    if (in && !centre) {
-        for (int x = threadIdx.x; x < W; x += kRowThreads) row[x] = static_cast<float>(in[base + x]);
-    } else if (in) {
+    if (in && centre) {
         const Tin* img = in + static_cast<size_t>(b) * H * W;
         const double dx = centre[2 * b] - 0.5 * W, dy = centre[2 * b + 1] - 0.5 * H;
         const double ys = y + dy;
         const double yf = floor(ys);
         const float fy = static_cast<float>(ys - yf);
         const int yi = static_cast<int>(fmax(fmin(yf, 1e9), -1e9));
-        for (int x = threadIdx.x; x < W; x += kRowThreads) {
-            const double xs = x + dx;
+        for (int i = lane; i < span; i += 64) {
+            const double xs = mirror(i - rh, W) + dx;
             const double xf = floor(xs);
             const float fx = static_cast<float>(xs - xf);
             const int xi = static_cast<int>(fmax(fmin(xf, 1e9), -1e9));
             const float p00 = load_px(img, H, W, yi, xi), p01 = load_px(img, H, W, yi, xi + 1);
             const float p10 = load_px(img, H, W, yi + 1, xi), p11 = load_px(img, H, W, yi + 1, xi + 1);
-            row[x] = (1.0f - fx) * (1.0f - fy) * p00 + fx * (1.0f - fy) * p01 +
+            row[i] = (1.0f - fx) * (1.0f - fy) * p00 + fx * (1.0f - fy) * p01 +
                      (1.0f - fx) * fy * p10 + fx * fy * p11;
         }
+    } else if (in) {
+        for (int i = lane; i < span; i += 64) row[i] = static_cast<float>(in[base + mirror(i - rh, W)]);
     } else {
-        for (int x = threadIdx.x; x < W; x += kRowThreads) row[x] = src[base + x];
+        for (int i = lane; i < span; i += 64) row[i] = src[base + mirror(i - rh, W)];
     }
-    __syncthreads();
-    for (int x = threadIdx.x; x < W; x += kRowThreads) {
-        float va = 0.0f;
-        for (int t = -a.r; t <= a.r; ++t) va += a.w[t + a.r] * row[mirror(x + t, W)];
-        out_a[base + x] = va;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    for (int x0 = 0; x0 < W; x0 += 4 * 64) {
+        const float* c = row + x0 + lane + rh;    // strip padded: reads past W stay inside
+        float va[4] = {0.0f, 0.0f, 0.0f, 0.0f}, vb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int t = -a.r; t <= a.r; ++t) {
+            const float w = a.w[t + a.r];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) va[m] += w * c[64 * m + t];
+        }
         if (out_b) {
-            float vb = 0.0f;
-            for (int t = -bt.r; t <= bt.r; ++t) vb += bt.w[t + bt.r] * row[mirror(x + t, W)];
-            out_b[base + x] = vb;
+            for (int t = -bt.r; t <= bt.r; ++t) {
+                const float w = bt.w[t + bt.r];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) vb[m] += w * c[64 * m + t];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int x = x0 + lane + 64 * m;
+            if (x < W) {
+                out_a[base + x] = va[m];
+                if (out_b) out_b[base + x] = vb[m];
+            }
         }
     }
 }
 
-// Correlation along y: out = G_a(ia) [- G_b(ib)], then the threshold.
+// acc[i] += sum_t w[t] * L[(y + i + t) * 32 + c] for kTileRows / 8 rows i,
+// taps in blocks of kTapBlock: per block the weights are loaded once and a
+// window of rows + kTapBlock - 1 LDS values serves kTapBlock * rows FMAs
+// (weights past the radius are zero; the tile carries kTapBlock spare rows).
+template <int kRows>
+__device__ __forceinline__ void tap_block_col(const float* L, const Taps& tp, int y, int c,
+                                              float (&acc)[kRows]) {
+    for (int t0 = -tp.r; t0 <= tp.r; t0 += kTapBlock) {
+        float w[kTapBlock];
+#pragma unroll
+        for (int j = 0; j < kTapBlock; ++j) w[j] = t0 + j <= tp.r ? tp.w[t0 + j + tp.r] : 0.0f;
+        const float* p = L + (y + t0) * 32 + c;
+        float win[kRows + kTapBlock - 1];
+#pragma unroll
+        for (int i = 0; i < kRows + kTapBlock - 1; ++i) win[i] = p[i * 32];
+#pragma unroll
+        for (int j = 0; j < kTapBlock; ++j)
+#pragma unroll
+            for (int i = 0; i < kRows; ++i) acc[i] += w[j] * win[i + j];
+    }
+}
+
+// Correlation along y for a strip of 32 columns of an image at most
+// kTileRows high, held whole in LDS with a mirrored halo of rh rows:
+// out = G_a(ia) [- G_b(ib)], then the threshold. Threads: 32 columns x 8
+// row groups of kTileRows / 8 consecutive rows (rows of 128 bytes load
+// coalesced); the tap loop is the outer one, so each weight is loaded once
+// per thread and feeds 32 FMAs.
+__global__ void __launch_bounds__(kRowThreads)
+col_tile_kernel(const float* __restrict__ ia, const float* __restrict__ ib, int H, int W, Taps a,
+                Taps bt, int rh, bool thresh, float threshold, float* __restrict__ out) {
+    extern __shared__ float lds[];
+    constexpr int kRows = kTileRows / (kRowThreads / 32);
+    const int c = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int x = blockIdx.x * 32 + c, b = blockIdx.y;
+    const bool col_ok = x < W;
+    const int hp = kTileRows + 2 * rh + kTapBlock;
+    float* la = lds;
+    float* lb = lds + static_cast<size_t>(hp) * 32;
+    const size_t img = static_cast<size_t>(b) * H * W;
+    for (int i = g; i < hp; i += kRowThreads / 32) {
+        const size_t src = img + static_cast<size_t>(mirror(i - rh, H)) * W + x;
+        la[i * 32 + c] = col_ok ? ia[src] : 0.0f;
+        if (ib) lb[i * 32 + c] = col_ok ? ib[src] : 0.0f;
+    }
+    __syncthreads();
+    const int y0 = g * kRows;
+    if (!col_ok || y0 >= H) return;
+    float va[kRows], vb[kRows];
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) va[i] = vb[i] = 0.0f;
+    tap_block_col(la, a, y0 + rh, c, va);
+    if (ib) tap_block_col(lb, bt, y0 + rh, c, vb);
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+        if (y0 + i >= H) break;
+        float v = ib ? va[i] - vb[i] : va[i];
+        if (thresh && v < threshold) v = 0.0f;
+        out[img + static_cast<size_t>(y0 + i) * W + x] = v;
+    }
+}
+
+// Correlation along y for any height (one thread per column, coalesced rows):
+// out = G_a(ia) [- G_b(ib)], then the threshold.
 __global__ void __launch_bounds__(kRowThreads)
 col_kernel(const float* __restrict__ ia, const float* __restrict__ ib, int H, int W, Taps a,
            Taps bt, bool thresh, float threshold, float* __restrict__ out) {
@@ -220,7 +319,33 @@ int run(const Tin* in, int B, int H, int W, const tm_preprocess_opts& o, float* 
     int r = TM_OK;
     if (e != hipSuccess) r = tmlib::hip_fail(e, "hipMallocAsync");
     double* cptr = centre_out ? centre_out : cen;
-    const size_t row_lds = static_cast<size_t>(W) * sizeof(float);
+    // LDS: rows with a mirrored halo (any W up to 8192 fits), column strips
+    // of the full height when they fit, else the per-column kernel
+    const int rh1 = dog ? std::max(ta.r, tb.r) : 0, rhb = tblur.r;
+    const size_t row_lds1 = static_cast<size_t>(kRowWaves) * row_strip(W, rh1) * sizeof(float);
+    const size_t row_ldsb = static_cast<size_t>(kRowWaves) * row_strip(W, rhb) * sizeof(float);
+    const size_t col_lds1 =
+        static_cast<size_t>(kTileRows + 2 * rh1 + kTapBlock) * 32 * sizeof(float) * (dog ? 2 : 1);
+    const size_t col_ldsb = static_cast<size_t>(kTileRows + 2 * rhb + kTapBlock) * 32 * sizeof(float);
+    const bool tile1 = H <= kTileRows && col_lds1 <= kLdsLimit;
+    const bool tileb = H <= kTileRows && col_ldsb <= kLdsLimit;
+    if (r == TM_OK) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(row_kernel<Tin>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(row_lds1));
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(row_kernel<float>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    static_cast<int>(std::max(row_ldsb, row_lds1)));
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(col_tile_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    static_cast<int>(std::min(kLdsLimit, std::max(col_lds1, col_ldsb))));
+        if (e != hipSuccess) r = tmlib::hip_fail(e, "hipFuncSetAttribute");
+    }
+    const dim3 rgrid((H + kRowWaves - 1) / kRowWaves, 1);
+    const dim3 tgrid((W + 31) / 32, 1);
+    const dim3 cgrid((W + kRowThreads - 1) / kRowThreads, 1);
+    const bool blur = o.sigma_blur > 0.0;
     for (int b0 = 0; r == TM_OK && b0 < B; b0 += chunk) {
         const int nb = std::min(chunk, B - b0);
         const Tin* cin = in + static_cast<size_t>(b0) * img;
@@ -232,24 +357,32 @@ int run(const Tin* in, int B, int H, int W, const tm_preprocess_opts& o, float* 
                                o.r_box, o.frac, cc);
         }
         // centred rows, correlated along x with G(sigma_min) and G(sigma_max)
-        hipLaunchKernelGGL(row_kernel<Tin>, dim3(H, nb), dim3(kRowThreads), row_lds, s, cin,
+        hipLaunchKernelGGL(row_kernel<Tin>, dim3(rgrid.x, nb), dim3(kRowThreads), row_lds1, s, cin,
                            static_cast<const float*>(nullptr), o.r_box >= 0 ? cc : nullptr, H, W,
-                           dog ? ta : tid, tb, s1, dog ? s2 : nullptr);
-        // along y: difference of Gaussians (or the plain centred image)
-        const dim3 cgrid((W + kRowThreads - 1) / kRowThreads, nb);
-        const bool blur = o.sigma_blur > 0.0;
-        hipLaunchKernelGGL(col_kernel, cgrid, dim3(kRowThreads), 0, s, s1, dog ? s2 : nullptr, H, W,
-                           dog ? ta : tid, tb, !blur && thresh, static_cast<float>(o.threshold),
-                           cout);
+                           dog ? ta : tid, tb, rh1, s1, dog ? s2 : nullptr);
+        // along y: difference of Gaussians (or the plain centred image) -> out
+        if (tile1)
+            hipLaunchKernelGGL(col_tile_kernel, dim3(tgrid.x, nb), dim3(kRowThreads), col_lds1, s,
+                               s1, dog ? s2 : nullptr, H, W, dog ? ta : tid, tb, rh1,
+                               !blur && thresh, static_cast<float>(o.threshold), cout);
+        else
+            hipLaunchKernelGGL(col_kernel, dim3(cgrid.x, nb), dim3(kRowThreads), 0, s, s1,
+                               dog ? s2 : nullptr, H, W, dog ? ta : tid, tb, !blur && thresh,
+                               static_cast<float>(o.threshold), cout);
         if (blur) {
             // rows of the difference image (now in out) -> s1, then columns -> out
-            hipLaunchKernelGGL(row_kernel<float>, dim3(H, nb), dim3(kRowThreads), row_lds, s,
+            hipLaunchKernelGGL(row_kernel<float>, dim3(rgrid.x, nb), dim3(kRowThreads), row_ldsb, s,
                                static_cast<const float*>(nullptr), static_cast<const float*>(cout),
-                               static_cast<const double*>(nullptr), H, W, tblur, tid, s1,
+                               static_cast<const double*>(nullptr), H, W, tblur, tid, rhb, s1,
                                static_cast<float*>(nullptr));
-            hipLaunchKernelGGL(col_kernel, cgrid, dim3(kRowThreads), 0, s, s1,
-                               static_cast<const float*>(nullptr), H, W, tblur, tid, thresh,
-                               static_cast<float>(o.threshold), cout);
+            if (tileb)
+                hipLaunchKernelGGL(col_tile_kernel, dim3(tgrid.x, nb), dim3(kRowThreads), col_ldsb,
+                                   s, s1, static_cast<const float*>(nullptr), H, W, tblur, tid,
+                                   rhb, thresh, static_cast<float>(o.threshold), cout);
+            else
+                hipLaunchKernelGGL(col_kernel, dim3(cgrid.x, nb), dim3(kRowThreads), 0, s, s1,
+                                   static_cast<const float*>(nullptr), H, W, tblur, tid, thresh,
+                                   static_cast<float>(o.threshold), cout);
         }
         e = hipGetLastError();
         if (e != hipSuccess) r = tmlib::hip_fail(e, "preprocess kernel launch");
