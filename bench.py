@@ -631,6 +631,28 @@ def main():
         }
         print(f"[bench] precision path {a.precision}: {pwall / a.steps * 1e3:.2f} ms/step, "
               f"top-1 agreement with the plain path {same_t1:.4f}", file=sys.stderr, flush=True)
+        # below 99 % same top-1, show what larger kept fractions cost
+        if same_t1 < 0.99:
+            sweep = []
+            for keep in (0.25, 0.5):
+                def step_k(keep=keep):
+                    tm.polar_transform(x, grid, polar_out=polar, norm_out=norms, profile_out=prof,
+                                       lib=plib)
+                    tm.match_batch(lib, polar, norms, N, profiles=prof, prefilter_keep=keep,
+                                   prefilter_prec=a.precision, out=out)
+                step_k()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(a.steps):
+                    step_k()
+                torch.cuda.synchronize()
+                kwall = time.perf_counter() - t0
+                agree = float((out[0][:, 0] == plain_top[0][:, 0]).float().mean().item())
+                sweep.append({"keep_fraction": keep, "value": round(B * a.steps / kwall, 1),
+                              "ms_per_step": round(kwall / a.steps * 1e3, 4),
+                              "top1_agreement_vs_fp32_path": agree})
+            prec_path["keep_sweep"] = sweep
+            print(f"[bench] precision path keep sweep: {sweep}", file=sys.stderr, flush=True)
 
     # the precision form, Fourier route: approximate scores of every template
     # through the theta spectra (float16 on the matrix cores), then exact
