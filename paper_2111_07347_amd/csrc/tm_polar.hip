@@ -18,8 +18,8 @@
 // transform applied once per pixel and out-of-image pixels set to zero, so
 // the tap reads need no bounds checks. Half-waves own polar rows and their
 // lanes consecutive columns, so the polar writes are coalesced along theta.
-// Each lane accumulates float64 partial row sums (profile) and squares
-// (norm) in registers across blocks; rows are reduced once per half-wave and
+// Each lane accumulates float32 partial row sums (profile; a dozen samples
+// per lane and row) and float64 squares (norm) in registers across blocks; rows are reduced once per half-wave and
 // the squares per wave and then across waves in a fixed order, so norms and
 // profiles are bit-reproducible.
 #include <cmath>
@@ -199,8 +199,8 @@ __device__ __forceinline__ double half_wave_sum(double v) {
 // group every block's footprint is staged and its samples of the group's rows
 // are resampled. Half-wave h of wave w owns rows g0 + 32 i + 2 w + h (i < 4)
 // and its 32 lanes walk the block's columns, so stores are 128-byte runs and
-// each lane keeps float64 partial row sums in registers across blocks; a row
-// is reduced across its half-wave once. With a row map, polar row j is
+// each lane keeps float32 partial row sums in registers across blocks; a row
+// is reduced across its half-wave once, in float64. With a row map, polar row j is
 // written to output row row_map[j] (skipped when negative); norms and
 // profiles always cover all R rows.
 template <typename Tin, bool BILINEAR>
@@ -225,11 +225,11 @@ polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
     float* out = polar + static_cast<size_t>(b) * out_rows * n_theta;
     double sq = 0.0;
     for (int g0 = 0; g0 < R; g0 += kRowGroup) {
-        double rs[kRowSteps];
+        float rs[kRowSteps];   // per-lane partial row sums (a dozen samples each)
         int orow[kRowSteps];   // output row of this lane's polar rows (-1: not written)
 #pragma unroll
         for (int i = 0; i < kRowSteps; ++i) {
-            rs[i] = 0.0;
+            rs[i] = 0.0f;
             const int j = g0 + i * kRowsPerStep + 2 * wave + half;
             const int m = j < R ? (row_map ? row_map[j] : j) : -1;
             orow[i] = (m >= 0 && m < out_rows) ? m : -1;   // entries out of range: skipped
@@ -374,7 +374,7 @@ polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
                     if (orow[i] >= 0)
                         out[static_cast<unsigned>(orow[i] * n_theta + blk.k0 + kk)] = v;
                     const double vd = static_cast<double>(v);
-                    rs[i] += vd;
+                    rs[i] += v;
                     sq += vd * vd;
                 }
             }
@@ -382,7 +382,7 @@ polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
         // one reduction per row of the group
 #pragma unroll
         for (int i = 0; i < kRowSteps; ++i) {
-            const double t = half_wave_sum(rs[i]);
+            const double t = half_wave_sum(static_cast<double>(rs[i]));
             const int j = g0 + i * kRowsPerStep + 2 * wave + half;
             if (prof_out && col == 0 && j < R) prof_out[static_cast<size_t>(j) * B + b] = static_cast<float>(t);
         }
