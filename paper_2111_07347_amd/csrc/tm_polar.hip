@@ -19,9 +19,10 @@
 // the tap reads need no bounds checks. Half-waves own polar rows and their
 // lanes consecutive columns, so the polar writes are coalesced along theta.
 // Each lane accumulates float32 partial row sums (profile; a dozen samples
-// per lane and row) and float64 squares (norm) in registers across blocks; rows are reduced once per half-wave and
-// the squares per wave and then across waves in a fixed order, so norms and
-// profiles are bit-reproducible.
+// per lane and row) and float64 squares (norm) in registers across blocks;
+// rows are reduced once per half-wave (in float64) and the squares per wave
+// and then across waves in a fixed order, so norms and profiles are
+// bit-reproducible.
 #include <cmath>
 #include <map>
 #include <mutex>
