@@ -582,7 +582,7 @@ int tm_preprocess(const void* patterns, tm_dtype dtype, int32_t B, int32_t H, in
  *                 the library's touched rows (as tm_match_opts.compact_rows).
  *   approx_score  device, [B, T'] float32, written.
  *   approx_angle  device, [B, T'] int16, written, or NULL.
- * Scratch (spectra of a chunk of patterns; up to about 8 GiB) is taken from
+ * Scratch (spectra of a chunk of patterns; about 2 GiB) is taken from
  * the stream-ordered allocator.
  * Errors: TM_EINVAL (null pointer, library without TM_LIB_FFT), TM_ENOMEM,
  *         TM_EHIP, TM_ENODEV. */

@@ -51,7 +51,10 @@ constexpr int kInvWaves = 12;  // fft_inverse: 6 pair tiles x 2 halves of the sh
 constexpr int kInvTiles = kInvWaves / 2;
 constexpr int kInvMaxBlocks = 3;                // 32-shift blocks per wave per part
 constexpr size_t kInvLdsBudget = 160 * 1024 - 2048;
-constexpr double kChatBudget = 16.0 * 1024 * 1024 * 1024;  // bytes of stored C(k)
+// Bytes of stored C(k) per chunk of patterns. Larger chunks bring nothing
+// (64 patterns already fill the chip) and multi-GiB stream-ordered
+// allocations made on several streams stalled the host for seconds.
+constexpr double kChatBudget = 2.0 * 1024 * 1024 * 1024;
 constexpr int kSelThreads = 256;
 
 // ---------------------------------------------------------------- host side

@@ -145,12 +145,14 @@ class Scheduler:
 
 class GpuExecutor:
     """Device work of a batch on the slot's stream: host-to-device copy of the
-    rows, polar transform, match (plain, or pre-filtered in reduced precision
-    with exact rescoring), device-to-host copy of the top-N, completion
-    event."""
+    rows, polar transform, match (plain; or the Fourier route with certified
+    rescoring for the libraries listed in `fourier`, which gives the plain
+    path's top-N; or pre-filtered in reduced precision with exact
+    rescoring), device-to-host copy of the top-N, completion event."""
 
     def __init__(self, libraries: dict, grid, N: int, slots: int, gamma: float = 1.0,
-                 subtract: float = 0.0, prefilter_keep: float = 0.0, precision: str = "bf16"):
+                 subtract: float = 0.0, prefilter_keep: float = 0.0, precision: str = "bf16",
+                 fourier=()):
         import torch
 
         import paper_2111_07347_amd as tm
@@ -163,6 +165,7 @@ class GpuExecutor:
         self.subtract = subtract
         self.keep = prefilter_keep
         self.precision = precision
+        self.fourier = set(fourier)     # library ids loaded with spectra (Library(fft=True))
         self.streams = [torch.cuda.Stream() for _ in range(slots)]   # default priority
         self.events = [None] * slots
         self.outputs = [None] * slots
@@ -172,7 +175,13 @@ class GpuExecutor:
         R, nt = self.grid.R, self.grid.n_theta
         rows = self.libraries[lib_id].rows()[0] or R       # compact polar: touched rows
         b = n_patterns * (H * W * itemsize + rows * nt * 4 + 8 + R * 4 + self.N * 12)
-        if self.keep > 0.0:
+        if lib_id in self.fourier:
+            # stored C(k) (float16 re/im per frequency and template, chunked
+            # to 2 GiB), approximate scores and the certified candidate lists
+            lib = self.libraries[lib_id]
+            Tp, Fp = lib.n_total, nt // 2 + 1
+            b += min(n_patterns * Fp * Tp * 4, 2 << 30) + n_patterns * Tp * 8
+        elif self.keep > 0.0:
             T = self.libraries[lib_id].T
             n_keep = int(np.ceil(self.keep * T))
             b += n_patterns * (T * 4 + 2 * n_keep * 4)
@@ -192,7 +201,9 @@ class GpuExecutor:
                 o += h.shape[0]
             polar, norms, prof = tm.polar_transform(x, self.grid, self.gamma, self.subtract,
                                                     want_profile=self.keep > 0.0, lib=lib)
-            if self.keep > 0.0:
+            if batch.lib_id in self.fourier:
+                tt, ts, tq = tm.match_batch(lib, polar, norms, self.N, coarse="fft")
+            elif self.keep > 0.0:
                 tt, ts, tq = tm.match_batch(lib, polar, norms, self.N, profiles=prof,
                                             prefilter_keep=self.keep, prefilter_prec=self.precision)
             else:

@@ -80,3 +80,25 @@ def test_serving_matches_oracle(setup):
             r = res[i]
             check_topn(ref, r.top_template[b], r.top_angle[b], r.top_score[b], margin=1e-4,
                        tight=True)
+
+
+def test_fourier_route_library_serves_the_plain_results(setup):
+    """A library served through the Fourier route with certified rescoring
+    returns exactly the plain path's top-N, alone and in the mix."""
+    tm, GpuExecutor, Server, grid, px, libs_np, libs, lib_ids, rows_np, rows = setup
+    from paper_2111_07347_amd.serve import run_stream
+    l2 = libs_np[2]
+    libs_f = dict(libs)
+    libs_f[2] = tm.Library(l2["kx"], l2["ky"], l2["intensity"], l2["offsets"], px, grid, fft=True)
+    n = len(lib_ids)
+    _say("serving: library 2 through the Fourier route, mixed, 3 slots")
+    ex = GpuExecutor(libs_f, grid, N=5, slots=3, fourier={2})
+    srv = Server(ex, budget_bytes=16 << 30, slots=3, max_batch_rows=3)
+    res = run_stream(srv, rows, list(lib_ids), np.zeros(n))
+    assert all(r.error is None for r in res)
+    plain = _serve(setup, list(range(n)), slots=3, max_rows=3)
+    for r in res:
+        p = plain[r.req_id]
+        assert np.array_equal(r.top_template, p.top_template), (r.req_id, lib_ids[r.req_id])
+        assert np.array_equal(r.top_angle, p.top_angle), (r.req_id, lib_ids[r.req_id])
+        assert np.array_equal(r.top_score, p.top_score), (r.req_id, lib_ids[r.req_id])
