@@ -67,16 +67,16 @@ std::map<LutKey, Lut> g_luts;
 // Base pixel of a sample, computed exactly as the kernel does.
 struct Sample { int x0, y0; };
 
-// LDS row pitch for a block: among bw .. bw + 31 the one that minimises the
+// LDS row pitch for a block: among bw .. bw + 31 (multiples of step) the one that minimises the
 // mean worst-bank load of the four taps over each half-wave of consecutive
 // columns (32 banks of 4 bytes; equal addresses broadcast), within the LDS
 // budget.
 template <typename BaseFn, typename InFn>
-int choose_pitch(const PolarBlock& B, BaseFn base_pixel, InFn inside, size_t max_floats) {
+int choose_pitch(const PolarBlock& B, BaseFn base_pixel, InFn inside, size_t max_floats, int step) {
     int best_p = B.bw;
     double best_c = 1e30;
     std::vector<int> addr;
-    for (int p = B.bw; p < B.bw + 32; ++p) {
+    for (int p = B.bw; p < B.bw + 32; p += step) {
         if (static_cast<size_t>(p) * B.bh + p + 2 > max_floats) break;
         double cost = 0.0;
         for (int j = B.j0; j < B.j1; ++j) {
@@ -130,6 +130,9 @@ int get_lut(const LutKey& key, hipStream_t s, Lut& out) {
     // smallest sector / band split whose every footprint box fits the budget
     std::vector<PolarBlock> blocks;
     const size_t max_floats = kBoxBytes / sizeof(float);
+    // widths divisible by 4: boxes start and end on aligned 4-pixel groups and
+    // row pitches are multiples of 4 floats (16-byte aligned LDS rows)
+    const bool aligned = (key.W & 3) == 0;
     int lds_floats = 0;
     for (int sk = 4, sj = 1;;) {
         blocks.clear();
@@ -150,8 +153,14 @@ int get_lut(const LutKey& key, hipStream_t s, Lut& out) {
                         yl = std::min(yl, q.y0); yh = std::max(yh, q.y0 + 1);
                     }
                 if (xl > xh) { xl = xh = yl = yh = 0; }   // block entirely outside
+                if (aligned) {
+                    // widen to whole aligned 4-pixel groups (xl >= -4): staged
+                    // with one 16-byte LDS store per group
+                    xl = (xl + 4) / 4 * 4 - 4;
+                    xh = (xh + 4) / 4 * 4 - 1;
+                }
                 B.x_lo = xl; B.y_lo = yl; B.bw = xh - xl + 1; B.bh = yh - yl + 1;
-                B.pitch = choose_pitch(B, base_pixel, inside, max_floats);
+                B.pitch = choose_pitch(B, base_pixel, inside, max_floats, aligned ? 4 : 1);
                 const size_t need = static_cast<size_t>(B.pitch) * B.bh + B.pitch + 2;
                 if (need > max_floats) fits = false;
                 lds_floats = std::max(lds_floats, static_cast<int>(need));
@@ -245,53 +254,54 @@ polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
             // (one 16- or 8-byte load each, several in flight per thread);
             // otherwise element i = tid + 1024 m walks the box row-major.
             if ((W & 3) == 0) {
-                const int gx0 = (blk.x_lo + 4) / 4 - 1;             // floor(x_lo / 4), x_lo >= -4
-                const int ng = (blk.x_lo + bw - 1 + 4) / 4 - 1 - gx0 + 1;
+                // the box starts and ends on aligned 4-pixel groups (the
+                // table is built that way for these widths) and its pitch is
+                // a multiple of 4: group g = row g / ng, column g % ng is one
+                // 16- or 8-byte load and one 16-byte LDS store
+                const int ng = bw >> 2;
                 const int ntot = ng * blk.bh;
+                // row of g as trunc((g + 0.5) * fl(1 / ng)): the relative error
+                // of the product is below 2^-23, so the quotient is exact
+                // while g + 0.5 < 2^22 (the box holds under 2^15 groups)
+                const float inv_ng = 1.0f / static_cast<float>(ng);
                 for (int g0 = tid; g0 < ntot; g0 += kPolarThreads * kVecUnroll) {
-                    float v[kVecUnroll][4];
-                    int gy[kVecUnroll], gxs[kVecUnroll];
+                    float4 v[kVecUnroll];
+                    int dst[kVecUnroll];
 #pragma unroll
                     for (int u = 0; u < kVecUnroll; ++u) {
                         const int g = g0 + u * kPolarThreads;
-                        const int yy = g / ng, cg = g - yy * ng;
-                        const int y = blk.y_lo + yy, xs = 4 * (gx0 + cg);
-                        gy[u] = g < ntot ? yy : -1;
-                        gxs[u] = xs;
+                        const int yy = static_cast<int>((static_cast<float>(g) + 0.5f) * inv_ng);
+                        const int cg = g - yy * ng;
+                        const int y = blk.y_lo + yy, xs = blk.x_lo + 4 * cg;
+                        dst[u] = g < ntot ? yy * pitch + 4 * cg : -1;
                         const bool in = g < ntot && y >= 0 && y < H && xs >= 0 && xs < W;
+                        v[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                         if (in) {
                             const Tin* q = img + static_cast<size_t>(y) * W + xs;
+                            float t[4];
                             if constexpr (sizeof(Tin) == 4) {
-                                const float4 t = *reinterpret_cast<const float4*>(q);
-                                v[u][0] = t.x; v[u][1] = t.y; v[u][2] = t.z; v[u][3] = t.w;
+                                const float4 r = *reinterpret_cast<const float4*>(q);
+                                t[0] = r.x; t[1] = r.y; t[2] = r.z; t[3] = r.w;
                             } else {
-                                const ushort4 t = *reinterpret_cast<const ushort4*>(q);
-                                v[u][0] = t.x; v[u][1] = t.y; v[u][2] = t.z; v[u][3] = t.w;
+                                const ushort4 r = *reinterpret_cast<const ushort4*>(q);
+                                t[0] = r.x; t[1] = r.y; t[2] = r.z; t[3] = r.w;
                             }
 #pragma unroll
                             for (int e = 0; e < 4; ++e) {
-                                if (pw) v[u][e] = powf(fmaxf(v[u][e], 0.0f), gamma);
-                                v[u][e] -= sub;
+                                if (pw) t[e] = powf(fmaxf(t[e], 0.0f), gamma);
+                                t[e] -= sub;
                             }
                             if (mask) {
                                 const float4 m = *reinterpret_cast<const float4*>(
                                     mask + static_cast<size_t>(y) * W + xs);
-                                v[u][0] *= m.x; v[u][1] *= m.y; v[u][2] *= m.z; v[u][3] *= m.w;
+                                t[0] *= m.x; t[1] *= m.y; t[2] *= m.z; t[3] *= m.w;
                             }
-                        } else {
-#pragma unroll
-                            for (int e = 0; e < 4; ++e) v[u][e] = 0.0f;
+                            v[u] = make_float4(t[0], t[1], t[2], t[3]);
                         }
                     }
 #pragma unroll
-                    for (int u = 0; u < kVecUnroll; ++u) {
-                        if (gy[u] < 0) continue;
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const int px = gxs[u] + e - blk.x_lo;
-                            if (px >= 0 && px < bw) box[gy[u] * pitch + px] = v[u][e];
-                        }
-                    }
+                    for (int u = 0; u < kVecUnroll; ++u)
+                        if (dst[u] >= 0) *reinterpret_cast<float4*>(box + dst[u]) = v[u];
                 }
             } else {
                 const int step_y = kPolarThreads / bw, step_x = kPolarThreads - step_y * bw;
@@ -367,8 +377,10 @@ polar_kernel(const Tin* __restrict__ patterns, int B, int H, int W,
                         const float fy = static_cast<float>(y - yf);
                         const float p00 = box[o], p01 = box[o + 1];
                         const float p10 = box[o + pitch], p11 = box[o + pitch + 1];
-                        const float gx = 1.0f - fx, gy = 1.0f - fy;
-                        v = gx * gy * p00 + fx * gy * p01 + gx * fy * p10 + fx * fy * p11;
+                        // two interpolations along x, then one along y
+                        const float a = fmaf(fx, p01 - p00, p00);
+                        const float e = fmaf(fx, p11 - p10, p10);
+                        v = fmaf(fy, e - a, a);
                     } else {
                         v = box[o];
                     }

@@ -105,6 +105,48 @@ def test_polar_options(tm, case):
         assert abs(norms[b] - oracle.norm64(P)) <= 1e-6 * oracle.norm64(P) + 1e-9
 
 
+@pytest.mark.parametrize("case", ["f32", "u16_gamma", "nearest_offcentre", "mask"])
+def test_polar_aligned_boxes_many_patterns(tm, case):
+    """Widths divisible by 4 stage the LDS boxes as aligned 4-pixel groups
+    (one 16-byte store each). B = 700 patterns (more than one workgroup per
+    CU over the launch); sampled patterns equal the oracle, and every pattern
+    equals the same pattern transformed alone."""
+    import torch
+    rng = np.random.default_rng(sum(map(ord, case)) + 7)
+    B, H, W, R, nt = 700, 72, 96, 40, 180
+    gk = dict(R=R, n_theta=nt, cx=47.5, cy=36.0)
+    kw = dict(gamma=1.0, subtract=0.0)
+    imgs = (rng.random((B, H, W)) * 5.0).astype(np.float32)
+    mask = None
+    if case == "u16_gamma":
+        imgs = rng.integers(0, 60000, (B, H, W)).astype(np.uint16)
+        kw = dict(gamma=0.5, subtract=3.0)
+    elif case == "nearest_offcentre":
+        gk.update(interp="nearest", cx=20.3, cy=61.7, R=60)
+    elif case == "mask":
+        mask = (rng.random((H, W)) > 0.3).astype(np.float32)
+    _say("polar aligned boxes", case, imgs.shape, gk, kw)
+    grid = tm.PolarGrid(**gk)
+    x = torch.from_numpy(imgs).cuda()
+    m = torch.from_numpy(mask).cuda() if mask is not None else None
+    polar, norms, prof = tm.polar_transform(x, grid, mask=m, **kw)
+    polar, norms, prof = polar.cpu().numpy(), norms.cpu().numpy(), prof.cpu().numpy()
+    interp = gk.get("interp", "bilinear")
+    for b in list(range(0, B, 97)) + [B - 1]:
+        img = imgs[b].astype(np.float64)
+        P = oracle.polar64(img, gk["R"], nt, 0.0, 1.0, gk["cx"], gk["cy"], kw["gamma"],
+                           kw["subtract"], interp, mask=mask)
+        ref_img = oracle.intensity_transform64(img, kw["gamma"], kw["subtract"])
+        _polar_close(polar[b], P, ref_img)
+        assert abs(norms[b] - oracle.norm64(P)) <= 1e-6 * oracle.norm64(P) + 1e-9
+        pr = oracle.profile64(P)
+        assert np.allclose(prof[:, b], pr, rtol=1e-5, atol=1e-5 * max(np.abs(pr).max(), 1e-30))
+    for b in (0, 255, 256, 511, 699):
+        p1, n1, f1 = tm.polar_transform(x[b:b + 1].contiguous(), grid, mask=m, **kw)
+        assert np.array_equal(p1.cpu().numpy()[0], polar[b])
+        assert n1.cpu().numpy()[0] == norms[b] and np.array_equal(f1.cpu().numpy()[:, 0], prof[:, b])
+
+
 # --------------------------------------------------------------------------- match
 @pytest.mark.parametrize("grouping", [True, False])
 def test_match_c1_full(tm, c1, c1_lib, c1_olib, grouping):
