@@ -35,17 +35,53 @@ constexpr int kRowWaves = kRowThreads / 64;
 constexpr size_t kLdsLimit = 156 * 1024;
 constexpr int kTileRows = 256;            // column-strip kernel: images up to this high
 constexpr int kTapBlock = 8;              // taps per weight block of the column-strip kernel
+constexpr int kStageBatch = 8;            // loads in flight per thread while staging
+constexpr int kRowBatch = 4;              // columns per lane in flight while staging a row
 
 // Floats of one wave's row strip: the row rounded up to 256 columns (the
-// last chunk's lanes read past W) plus the two halos.
-__host__ __device__ inline int row_strip(int W, int rh) { return (W + 255) / 256 * 256 + 2 * rh; }
+// last chunk's lanes read past W) plus the two halos of rh (a multiple of 4)
+// and 16 more, which the last tap block's window may reach.
+__host__ __device__ inline int row_strip(int W, int rh) { return (W + 255) / 256 * 256 + 2 * rh + 16; }
+
 constexpr int kCentreThreads = 256;
 constexpr size_t kScratchBudget = size_t(1) << 30;
+
+// Zero-padded copy of a tap table for the row kernel: wp[t + r4] = w(t) for
+// t in [-r4, r4 + 7], r4 = the radius rounded up to a multiple of 4, zero
+// past the radius.
+constexpr int kWLen = 2 * kMaxRadius + 16;
 
 struct Taps {
     int r;
     float w[2 * kMaxRadius + 1];
+    alignas(32) float wp[kWLen];
 };
+
+
+// acc[m] += sum_t w(t) * row[c + m + t], m < 4, over the padded table of
+// tp, in blocks of 8 taps: per block one 32-byte scalar load of weights and
+// a 12-float window (aligned 16-byte LDS reads) feed 32 FMAs. c and the
+// block starts are multiples of 4.
+__device__ __forceinline__ void conv4(const float* row, int c, const Taps& tp, float (&acc)[4]) {
+    const int r4 = (tp.r + 3) & ~3;
+    for (int t0 = -r4; t0 <= r4; t0 += 8) {
+        float w[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) w[j] = tp.wp[t0 + r4 + j];
+        const float4* p = static_cast<const float4*>(__builtin_assume_aligned(row + c + t0, 16));
+        float win[12];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const float4 v = p[q];
+            win[4 * q] = v.x; win[4 * q + 1] = v.y; win[4 * q + 2] = v.z; win[4 * q + 3] = v.w;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) acc[m] += w[j] * win[m + j];
+    }
+}
+
 
 __device__ __forceinline__ int mirror(int i, int n) {
     if (static_cast<unsigned>(i) < static_cast<unsigned>(n)) return i;
@@ -124,11 +160,11 @@ centre_kernel(const Tin* __restrict__ patterns, int H, int W, int r_box, double 
 
 // One image row per wave (4 rows per workgroup): the row of the source is
 // staged in the wave's LDS strip with a mirrored halo of rh columns on each
-// side, then correlated along x with taps a (-> out_a) and, when out_b is
-// given, taps b (-> out_b). The source is the input pattern (`in`), centred
-// when `centre` is given, else the float image `src`. Lanes own columns
-// lane + 64 m (m < 4) of each 256-column chunk; the tap loop is the outer
-// one, so each weight is loaded once per chunk.
+// side (rh a multiple of 4, at least the largest radius), then correlated
+// along x with taps a (-> out_a) and, when out_b is given, taps b
+// (-> out_b). The source is the input pattern (`in`), centred when `centre`
+// is given, else the float image `src`. Lanes own 4 consecutive columns of
+// each 256-column chunk and share one tap window among them (conv4).
 template <typename Tin>
 __global__ void __launch_bounds__(kRowThreads)
 row_kernel(const Tin* __restrict__ in, const float* __restrict__ src,
@@ -148,45 +184,64 @@ row_kernel(const Tin* __restrict__ in, const float* __restrict__ src,
         const double yf = floor(ys);
         const float fy = static_cast<float>(ys - yf);
         const int yi = static_cast<int>(fmax(fmin(yf, 1e9), -1e9));
-        for (int i = lane; i < span; i += 64) {
-            const double xs = mirror(i - rh, W) + dx;
-            const double xf = floor(xs);
-            const float fx = static_cast<float>(xs - xf);
-            const int xi = static_cast<int>(fmax(fmin(xf, 1e9), -1e9));
-            const float p00 = load_px(img, H, W, yi, xi), p01 = load_px(img, H, W, yi, xi + 1);
-            const float p10 = load_px(img, H, W, yi + 1, xi), p11 = load_px(img, H, W, yi + 1, xi + 1);
-            row[i] = (1.0f - fx) * (1.0f - fy) * p00 + fx * (1.0f - fy) * p01 +
-                     (1.0f - fx) * fy * p10 + fx * fy * p11;
+        // kRowBatch columns per lane in flight: all taps are loaded first
+        for (int i0 = lane; i0 < span; i0 += 64 * kRowBatch) {
+            float p[kRowBatch][4], fx[kRowBatch];
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) {
+                const int i = min(i0 + 64 * u, span - 1);
+                const double xs = mirror(i - rh, W) + dx;
+                const double xf = floor(xs);
+                fx[u] = static_cast<float>(xs - xf);
+                const int xi = static_cast<int>(fmax(fmin(xf, 1e9), -1e9));
+                p[u][0] = load_px(img, H, W, yi, xi);
+                p[u][1] = load_px(img, H, W, yi, xi + 1);
+                p[u][2] = load_px(img, H, W, yi + 1, xi);
+                p[u][3] = load_px(img, H, W, yi + 1, xi + 1);
+            }
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) {
+                const int i = i0 + 64 * u;
+                if (i < span)
+                    row[i] = (1.0f - fx[u]) * (1.0f - fy) * p[u][0] + fx[u] * (1.0f - fy) * p[u][1] +
+                             (1.0f - fx[u]) * fy * p[u][2] + fx[u] * fy * p[u][3];
+            }
         }
-    } else if (in) {
-        for (int i = lane; i < span; i += 64) row[i] = static_cast<float>(in[base + mirror(i - rh, W)]);
     } else {
-        for (int i = lane; i < span; i += 64) row[i] = src[base + mirror(i - rh, W)];
+        for (int i0 = lane; i0 < span; i0 += 64 * kRowBatch) {
+            float v[kRowBatch];
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u) {
+                const size_t q = base + mirror(min(i0 + 64 * u, span - 1) - rh, W);
+                v[u] = in ? static_cast<float>(in[q]) : src[q];
+            }
+#pragma unroll
+            for (int u = 0; u < kRowBatch; ++u)
+                if (i0 + 64 * u < span) row[i0 + 64 * u] = v[u];
+        }
     }
+    // the tail of the strip (past the right halo) holds zeros: the zero
+    // weights of the last tap blocks read it
+    for (int i = span + lane; i < row_strip(W, rh); i += 64) row[i] = 0.0f;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    // each lane owns 4 consecutive columns of every 256-column chunk
     for (int x0 = 0; x0 < W; x0 += 4 * 64) {
-        const float* c = row + x0 + lane + rh;    // strip padded: reads past W stay inside
+        const int x = x0 + 4 * lane;
         float va[4] = {0.0f, 0.0f, 0.0f, 0.0f}, vb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int t = -a.r; t <= a.r; ++t) {
-            const float w = a.w[t + a.r];
+        conv4(row, x + rh, a, va);
+        if (out_b) conv4(row, x + rh, bt, vb);
+        if ((W & 3) == 0 && x + 3 < W) {
+            *reinterpret_cast<float4*>(out_a + base + x) = make_float4(va[0], va[1], va[2], va[3]);
+            if (out_b) *reinterpret_cast<float4*>(out_b + base + x) = make_float4(vb[0], vb[1], vb[2], vb[3]);
+        } else {
 #pragma unroll
-            for (int m = 0; m < 4; ++m) va[m] += w * c[64 * m + t];
-        }
-        if (out_b) {
-            for (int t = -bt.r; t <= bt.r; ++t) {
-                const float w = bt.w[t + bt.r];
-#pragma unroll
-                for (int m = 0; m < 4; ++m) vb[m] += w * c[64 * m + t];
-            }
-        }
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int x = x0 + lane + 64 * m;
-            if (x < W) {
-                out_a[base + x] = va[m];
-                if (out_b) out_b[base + x] = vb[m];
+            for (int m = 0; m < 4; ++m) {
+                if (x + m < W) {
+                    out_a[base + x + m] = va[m];
+                    if (out_b) out_b[base + x + m] = vb[m];
+                }
             }
         }
     }
@@ -232,10 +287,27 @@ col_tile_kernel(const float* __restrict__ ia, const float* __restrict__ ib, int 
     float* la = lds;
     float* lb = lds + static_cast<size_t>(hp) * 32;
     const size_t img = static_cast<size_t>(b) * H * W;
-    for (int i = g; i < hp; i += kRowThreads / 32) {
-        const size_t src = img + static_cast<size_t>(mirror(i - rh, H)) * W + x;
-        la[i * 32 + c] = col_ok ? ia[src] : 0.0f;
-        if (ib) lb[i * 32 + c] = col_ok ? ib[src] : 0.0f;
+    // staging: kStageBatch rows per thread loaded before any is stored, so
+    // their latencies overlap (every lane loads; columns past W read column
+    // 0 and store zeros)
+    constexpr int kGroups = kRowThreads / 32;
+    for (int i0 = g; i0 < hp; i0 += kGroups * kStageBatch) {
+        float va[kStageBatch], vb[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int i = min(i0 + kGroups * u, hp - 1);
+            const size_t src = img + static_cast<size_t>(mirror(i - rh, H)) * W + (col_ok ? x : 0);
+            va[u] = ia[src];
+            vb[u] = ib ? ib[src] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int i = i0 + kGroups * u;
+            if (i < hp) {
+                la[i * 32 + c] = col_ok ? va[u] : 0.0f;
+                if (ib) lb[i * 32 + c] = col_ok ? vb[u] : 0.0f;
+            }
+        }
     }
     __syncthreads();
     const int y0 = g * kRows;
@@ -276,11 +348,20 @@ col_kernel(const float* __restrict__ ia, const float* __restrict__ ib, int H, in
     }
 }
 
+void pad_taps(Taps& t) {
+    const int r4 = (t.r + 3) & ~3;
+    for (int i = 0; i < kWLen; ++i) {
+        const int k = i - r4;
+        t.wp[i] = (k >= -t.r && k <= t.r) ? t.w[k + t.r] : 0.0f;
+    }
+}
+
 bool make_taps(double sigma, Taps& t) {
     t = Taps{};
     if (!(sigma > 0.0)) {
         t.r = 0;
         t.w[0] = 1.0f;
+        pad_taps(t);
         return true;
     }
     const int r = static_cast<int>(4.0 * sigma + 0.5);
@@ -292,6 +373,7 @@ bool make_taps(double sigma, Taps& t) {
     }
     t.r = r;
     for (int i = 0; i <= 2 * r; ++i) t.w[i] = static_cast<float>(w[i] / s);
+    pad_taps(t);
     return true;
 }
 
@@ -322,8 +404,10 @@ int run(const Tin* in, int B, int H, int W, const tm_preprocess_opts& o, float* 
     // LDS: rows with a mirrored halo (any W up to 8192 fits), column strips
     // of the full height when they fit, else the per-column kernel
     const int rh1 = dog ? std::max(ta.r, tb.r) : 0, rhb = tblur.r;
-    const size_t row_lds1 = static_cast<size_t>(kRowWaves) * row_strip(W, rh1) * sizeof(float);
-    const size_t row_ldsb = static_cast<size_t>(kRowWaves) * row_strip(W, rhb) * sizeof(float);
+    // row halos rounded up to multiples of 4 (aligned tap windows)
+    const int rr1 = (rh1 + 3) & ~3, rrb = (rhb + 3) & ~3;
+    const size_t row_lds1 = static_cast<size_t>(kRowWaves) * row_strip(W, rr1) * sizeof(float);
+    const size_t row_ldsb = static_cast<size_t>(kRowWaves) * row_strip(W, rrb) * sizeof(float);
     const size_t col_lds1 =
         static_cast<size_t>(kTileRows + 2 * rh1 + kTapBlock) * 32 * sizeof(float) * (dog ? 2 : 1);
     const size_t col_ldsb = static_cast<size_t>(kTileRows + 2 * rhb + kTapBlock) * 32 * sizeof(float);
@@ -359,7 +443,7 @@ int run(const Tin* in, int B, int H, int W, const tm_preprocess_opts& o, float* 
         // centred rows, correlated along x with G(sigma_min) and G(sigma_max)
         hipLaunchKernelGGL(row_kernel<Tin>, dim3(rgrid.x, nb), dim3(kRowThreads), row_lds1, s, cin,
                            static_cast<const float*>(nullptr), o.r_box >= 0 ? cc : nullptr, H, W,
-                           dog ? ta : tid, tb, rh1, s1, dog ? s2 : nullptr);
+                           dog ? ta : tid, tb, rr1, s1, dog ? s2 : nullptr);
         // along y: difference of Gaussians (or the plain centred image) -> out
         if (tile1)
             hipLaunchKernelGGL(col_tile_kernel, dim3(tgrid.x, nb), dim3(kRowThreads), col_lds1, s,
@@ -373,7 +457,7 @@ int run(const Tin* in, int B, int H, int W, const tm_preprocess_opts& o, float* 
             // rows of the difference image (now in out) -> s1, then columns -> out
             hipLaunchKernelGGL(row_kernel<float>, dim3(rgrid.x, nb), dim3(kRowThreads), row_ldsb, s,
                                static_cast<const float*>(nullptr), static_cast<const float*>(cout),
-                               static_cast<const double*>(nullptr), H, W, tblur, tid, rhb, s1,
+                               static_cast<const double*>(nullptr), H, W, tblur, tid, rrb, s1,
                                static_cast<float*>(nullptr));
             if (tileb)
                 hipLaunchKernelGGL(col_tile_kernel, dim3(tgrid.x, nb), dim3(kRowThreads), col_ldsb,
