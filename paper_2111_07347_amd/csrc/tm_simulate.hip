@@ -15,15 +15,18 @@
 //                    g0 of (0, Phi, phi2)) and keep those near the Ewald
 //                    sphere (beam along -z, centre (0, 0, k)). A square-root
 //                    free test |g - (0, 0, k)|^2 in ((k - s_max)^2,
-//                    (k + s_max)^2) (slightly widened) admits a superset;
-//                    survivors get the exact s = k - |g - (0, 0, k)|, shape
-//                    max(0, 1 - |s| / s_max) and projected radius tests and
-//                    are appended in grid order (ballot compaction) to a
-//                    wave list: the first entries in LDS, the rest in a
-//                    per-wave global area. The wave then drops spots below
-//                    rel_min times the brightest, ranks the rest by
-//                    (intensity desc, grid order) by counting, and writes the
-//                    first max_spots, intensities divided by the brightest.
+//                    (k + s_max)^2) and |g_xy|^2 <= g_max^2 (slightly
+//                    widened) admits a superset, appended in grid order
+//                    (ballot compaction) to a wave list: the first entries in
+//                    LDS, the rest in a per-wave global area. The exact
+//                    s = k - |g - (0, 0, k)|, shape max(0, 1 - |s| / s_max)
+//                    and projected radius tests then run on the dense list
+//                    (so the square roots and the division run once per
+//                    survivor, not once per 64 reflections). The wave drops
+//                    spots below rel_min times the brightest, ranks the rest
+//                    by (intensity desc, grid order) by counting, and writes
+//                    the first max_spots, intensities divided by the
+//                    brightest.
 //
 // float64 throughout. The work is a few dozen float64 operations per
 // (orientation, reflection) pair plus the ranking of the excited spots; the
@@ -114,14 +117,13 @@ struct CandList {
     int* lj;
     double* gi;
     int* gj;
-    __device__ __forceinline__ void put(int o, double I, int j) const {
-        if (o < kLdsCand) {
-            li[o] = I;
-            lj[o] = j;
-        } else {
-            gi[o - kLdsCand] = I;
-            gj[o - kLdsCand] = j;
-        }
+    __device__ __forceinline__ void put_j(int o, int j) const {
+        if (o < kLdsCand) lj[o] = j;
+        else gj[o - kLdsCand] = j;
+    }
+    __device__ __forceinline__ void put_i(int o, double I) const {
+        if (o < kLdsCand) li[o] = I;
+        else gi[o - kLdsCand] = I;
     }
     __device__ __forceinline__ double I(int o) const { return o < kLdsCand ? li[o] : gi[o - kLdsCand]; }
     __device__ __forceinline__ int J(int o) const { return o < kLdsCand ? lj[o] : gj[o - kLdsCand]; }
@@ -150,17 +152,19 @@ template_kernel(const double* __restrict__ orient, int T, const double4* __restr
         const int t = static_cast<int>(tl);
         const double Phi = orient[2 * static_cast<size_t>(t)];
         const double phi2 = orient[2 * static_cast<size_t>(t) + 1];
-        const double c = cos(Phi), s = sin(Phi), c2 = cos(phi2), s2 = sin(phi2);
+        double c, s, c2, s2;
+        sincos(Phi, &s, &c);
+        sincos(phi2, &s2, &c2);
         // crystal -> sample: transpose of Bunge g(0, Phi, phi2)
         const double m00 = c2, m01 = -s2, m02 = 0.0;
         const double m10 = s2 * c, m11 = c2 * c, m12 = -s;
         const double m20 = s2 * s, m21 = c2 * s, m22 = c;
-        int n_cand = 0;
-        double top = 0.0;
+        // 1. the cheap superset test over all reflections; survivors'
+        // indices are appended in grid order
+        int n_sup = 0;
         for (int j0 = 0; j0 < n_refl; j0 += 64) {
             const int j = j0 + lane;
             bool ok = false;
-            double I = 0.0;
             if (j < n_refl) {
                 const double4 r = refl[j];
                 const double sx = m00 * r.x + m01 * r.y + m02 * r.z;
@@ -168,36 +172,62 @@ template_kernel(const double* __restrict__ orient, int T, const double4* __restr
                 const double sz = m20 * r.x + m21 * r.y + m22 * r.z - k;
                 const double rxy = sx * sx + sy * sy;
                 const double q = rxy + sz * sz;
-                if (q > lo && q < hi && rxy <= r2) {
-                    const double err = k - sqrt(q);
-                    const double shape = fmax(0.0, 1.0 - fabs(err) / s_max);
-                    ok = shape > 0.0 && sqrt(rxy) <= g_max;
-                    I = r.w * shape;
-                }
+                ok = q > lo && q < hi && rxy <= r2;
             }
             const unsigned long long m = __ballot(ok);
-            if (ok) {
-                cl.put(n_cand + __popcll(m & ((1ull << lane) - 1ull)), I, j);
+            if (ok) cl.put_j(n_sup + __popcll(m & ((1ull << lane) - 1ull)), j);
+            n_sup += __popcll(m);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        // 2. the exact tests on the dense survivor list: intensity, or -1
+        // for a survivor outside the relrod or the projection radius
+        double top = 0.0;
+        for (int i0 = 0; i0 < n_sup; i0 += 64) {
+            const int i = i0 + lane;
+            if (i < n_sup) {
+                const double4 r = refl[cl.J(i)];
+                const double sx = m00 * r.x + m01 * r.y + m02 * r.z;
+                const double sy = m10 * r.x + m11 * r.y + m12 * r.z;
+                const double sz = m20 * r.x + m21 * r.y + m22 * r.z - k;
+                const double rxy = sx * sx + sy * sy;
+                const double q = rxy + sz * sz;
+                const double err = k - sqrt(q);
+                const double shape = fmax(0.0, 1.0 - fabs(err) / s_max);
+                const bool ok = shape > 0.0 && sqrt(rxy) <= g_max;
+                const double I = ok ? r.w * shape : -1.0;
+                cl.put_i(i, I);
                 top = fmax(top, I);
             }
-            n_cand += __popcll(m);
         }
         top = wave_max_d(top);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        // 3. spots at or above rel_min times the brightest, ranked by
+        // (intensity desc, grid order) by counting; a counted entry has
+        // I >= the lane's I >= thr >= 0, so rejected survivors (-1) never count
         const double thr = rel_min * top;
         int n_keep = 0;
-        for (int i0 = 0; i0 < n_cand; i0 += 64) {
+        for (int i0 = 0; i0 < n_sup; i0 += 64) {
             const int i = i0 + lane;
-            const bool keep = i < n_cand && cl.I(i) >= thr;
+            const bool keep = i < n_sup && cl.I(i) >= thr;
             n_keep += __popcll(__ballot(keep));
             if (!keep) continue;
             const double Ii = cl.I(i);
             int rank = 0;
-            for (int q = 0; q < n_cand; ++q) {
-                const double Iq = cl.I(q);
-                rank += (Iq >= thr && (Iq > Ii || (Iq == Ii && q < i))) ? 1 : 0;
+            if (n_sup <= kLdsCand) {
+#pragma unroll 4
+                for (int q = 0; q < n_sup; ++q) {
+                    const double Iq = cl.li[q];
+                    rank += (Iq > Ii || (Iq == Ii && q < i)) ? 1 : 0;
+                }
+            } else {
+                for (int q = 0; q < n_sup; ++q) {
+                    const double Iq = cl.I(q);
+                    rank += (Iq > Ii || (Iq == Ii && q < i)) ? 1 : 0;
+                }
             }
             if (rank < max_spots) {
                 const double4 r = refl[cl.J(i)];

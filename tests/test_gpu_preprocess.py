@@ -93,6 +93,26 @@ def test_preprocess_ragged_and_tiny_images(tm, shape):
         _compare(out[b], want, pre, 0.0, (shape, b))
 
 
+@pytest.mark.parametrize("shape,sigmas", [((300, 260), (2.0, 15.9, 3.3)), ((64, 516), (1.0, 6.0, 1.0))])
+def test_preprocess_wide_tall_images_and_largest_radius(tm, shape, sigmas):
+    """Rows wider than one 256-column chunk (the row pass walks several),
+    images taller than the column-strip tile (the per-column pass), and the
+    largest supported radius (sigma 15.9: 64 taps each side)."""
+    import torch
+    rng = np.random.default_rng(93)
+    imgs = (rng.random((2,) + shape) * 3.0).astype(np.float32)
+    o = dict(r_box=5, frac=0.4, sigma_min=sigmas[0], sigma_max=sigmas[1], sigma_blur=sigmas[2],
+             threshold=0.05)
+    _say("preprocess wide/tall", shape, sigmas)
+    out, cen = tm.preprocess(torch.from_numpy(imgs).cuda(), **o)
+    out, cen = out.cpu().numpy(), cen.cpu().numpy()
+    for b in range(2):
+        want, (cx, cy) = oracle.preprocess64(imgs[b].astype(np.float64), **o)
+        pre, _ = oracle.preprocess64(imgs[b].astype(np.float64), **{**o, "threshold": float("-inf")})
+        assert abs(cen[b, 0] - cx) < 1e-9 and abs(cen[b, 1] - cy) < 1e-9
+        _compare(out[b], want, pre, 0.05, (shape, b))
+
+
 def test_preprocess_degenerate_inputs(tm):
     import torch
     _say("preprocess degenerate")
