@@ -81,16 +81,28 @@ def parse():
     return ap.parse_args()
 
 
+# Sources that define each kernel whose traffic the benchmark reports.
+KERNEL_SOURCES = {
+    "match_kernel": ("tm_match.hip", "tm_library.hip", "tm_topn.h"),
+    "polar_kernel": ("tm_polar.hip",),
+    "fft_": ("tm_fft.hip",),
+}
+
+
 def recorded_traffic(cid, kernel_prefix):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
     record (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings), or
-    None if the record is missing or any kernel source changed since."""
+    None if the record is missing or a source defining the kernel changed
+    since (all recorded sources for kernels not listed in KERNEL_SOURCES)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_config{cid}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
+    files = next((v for k, v in KERNEL_SOURCES.items() if kernel_prefix.startswith(k)), None)
     for f, h in rec["sources"].items():
+        if files is not None and f not in files:
+            continue
         src = os.path.join(ROOT, "paper_2111_07347_amd", "csrc", f)
         if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != h:
             return None
