@@ -7,21 +7,25 @@
 //                  |x - W/2| <= r_box, |y - H/2| <= r_box, then the
 //                  intensity-weighted centroid (float64) of the box pixels
 //                  >= frac times that maximum.
-//   row_kernel     one workgroup per image row: the row of the centred
-//                  pattern, out(x, y) = in(x + cx - W/2, y + cy - H/2)
+//   row_kernel     one wave per image row (4 per workgroup): the row of the
+//                  centred pattern, out(x, y) = in(x + cx - W/2, y + cy - H/2)
 //                  (bilinear, zero outside), or of an intermediate image, is
 //                  built in LDS, then correlated along x with one or two
 //                  sampled Gaussians (mirror boundary).
-//   col_kernel     one thread per column (coalesced rows): correlation along
-//                  y with one or two Gaussians; two give the difference of
-//                  Gaussians; an optional threshold sets values below it to 0.
+//   col_tile_kernel  32-column strips of images up to 256 rows, staged whole
+//                  in LDS: correlation along y with one or two Gaussians; two
+//                  give the difference of Gaussians; an optional threshold
+//                  sets values below it to 0. col_kernel does the same for
+//                  taller images, one thread per column (coalesced rows).
 //
 // Gaussians: exp(-t^2 / (2 sigma^2)) on |t| <= floor(4 sigma + 0.5),
 // normalised in float64 on the host, applied in float32; mirror boundary
 // (... c b a | a b c ...) by folding indices modulo 2n. The passes run over
 // chunks of patterns so that the two float32 scratch images stay within
-// 1 GiB. Every pass streams images through HBM: the work is bound by memory
-// traffic (about ten image sizes per pattern with all steps on).
+// 1 GiB. The filters cost 2 (2 r + 1) FMAs per pixel and Gaussian, more
+// than the machine balance for the default radii, but each pass also
+// streams images through HBM (about ten image sizes per pattern with all
+// steps on) and waits on its staging loads.
 #include <algorithm>
 #include <cmath>
 
