@@ -495,6 +495,7 @@ def c5_bench(a):
     agree = float(np.mean(tops["plain"][:, 0] == tops["fp8_prefilter"][:, 0]))
     cpu = None
     top1 = None
+    oracle_check = None
     if not a.no_cpu:
         import oracle
         procs = a.cpu_procs or min(16, os.cpu_count() or 1)
@@ -720,6 +721,18 @@ def main():
                          f"the same workload, FP64 NumPy, {procs} processes"}
         gt = plain_top[0].cpu().numpy()
         top1 = float(np.mean(gt[idx, 0] == ot[:, 0]))
+        # the parity criterion: best (template, angle) identical wherever the
+        # oracle's margin between its first and second template exceeds 1e-4,
+        # and the best score within 1e-5 relative
+        gs = plain_top[1].cpu().numpy()[idx, 0]
+        gq = plain_top[2].cpu().numpy()[idx, 0].astype(np.float64)
+        clear = (oq[:, 0] - oq[:, 1]) > 1e-4
+        same = (gt[idx, 0] == ot[:, 0]) & (gs == os_[:, 0])
+        oracle_check = {
+            "patterns": len(idx), "margin_above_1e-4": int(clear.sum()),
+            "best_template_and_angle_identical_where_margin_above_1e-4":
+                float(np.mean(same[clear])) if clear.any() else None,
+            "max_best_score_rel_err": float(np.max(np.abs(gq - oq[:, 0]) / np.abs(oq[:, 0])))}
         if prec_path is not None:
             pt = pre_top[0].cpu().numpy()
             prec_path["top1_agreement_vs_oracle_on_sample"] = float(np.mean(pt[idx, 0] == ot[:, 0]))
@@ -761,6 +774,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "top1_agreement_vs_oracle_on_sample": top1,
+        "oracle_check_on_sample": oracle_check,
         "orientation_accuracy": accuracy,
         "library_simulation": simulation,
         "preprocessing": preprocessing,
