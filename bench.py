@@ -495,7 +495,6 @@ def c5_bench(a):
     agree = float(np.mean(tops["plain"][:, 0] == tops["fp8_prefilter"][:, 0]))
     cpu = None
     top1 = None
-    oracle_check = None
     if not a.no_cpu:
         import oracle
         procs = a.cpu_procs or min(16, os.cpu_count() or 1)
@@ -712,6 +711,7 @@ def main():
 
     cpu = None
     top1 = None
+    oracle_check = None
     if not a.no_cpu:
         procs = a.cpu_procs or min(16, os.cpu_count() or 1)
         idx, (ot, os_, oq), dt = oracle_baseline(cfg, lib_np, min(a.cpu_sample, B), procs, B)
