@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import synth
-from parity import PatternRef, check_topn
+from parity import PatternRef, check_topn, scores_close
 
 pytestmark = pytest.mark.gpu
 
@@ -29,24 +29,70 @@ def _properties(tt, ts, tq, Tp, n_theta):
     assert (np.diff(np.sort(tt, axis=1), axis=1) > 0).all()
 
 
-# the oracle's exact search over 40 000 templates takes about half a minute
-# per pattern on one core: one sampled pattern (the scan's last) for C3
-@pytest.mark.parametrize("cid,n_sample", [(2, 10), (3, 1)])
-def test_full_scan_sampled_against_oracle(cid, n_sample):
+_SCANS = {}
+
+
+def _scan(cid):
+    """The whole scan of workload cid generated, uploaded, polar-transformed
+    (compact rows, as the benchmark times it) and matched once; kept for the
+    module's tests."""
+    if cid in _SCANS:
+        return _SCANS[cid]
     import torch
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     import paper_2111_07347_amd as tm
+    _SCANS.clear()                       # one scan resident at a time
     cfg = synth.CONFIGS[cid]
-    B = cfg.B
-    _say("full scan", cid, B, "patterns", cfg.H, "x", cfg.W)
+    _say("full scan", cid, cfg.B, "patterns", cfg.H, "x", cfg.W)
     lib_np = synth.make_library(cfg)
-    imgs = synth.make_patterns_parallel(cfg, lib_np, B, workers=16)
+    imgs = synth.make_patterns_parallel(cfg, lib_np, cfg.B, workers=16)
     grid = tm.PolarGrid(R=cfg.R, n_theta=cfg.n_theta, cx=cfg.cx, cy=cfg.cy)
     px = synth.px_per_inv_A(cfg)
     lib = tm.Library(lib_np["kx"], lib_np["ky"], lib_np["intensity"], lib_np["offsets"], px, grid)
     x = torch.from_numpy(imgs).cuda()
-    polar, norms, _ = tm.polar_transform(x, grid, lib=lib)
-    tt, ts, tq = (o.cpu().numpy() for o in tm.match_batch(lib, polar, norms, cfg.N))
+    polar, norms, prof = tm.polar_transform(x, grid, lib=lib)
+    top = [o.cpu().numpy() for o in tm.match_batch(lib, polar, norms, cfg.N)]
+    _SCANS[cid] = dict(tm=tm, cfg=cfg, lib_np=lib_np, imgs=imgs, grid=grid, px=px, lib=lib, x=x,
+                       polar=polar, norms=norms, prof=prof, top=top)
+    return _SCANS[cid]
+
+
+def test_full_scan_precision_forms():
+    """FCC scan, precision form: the BF16 pre-filter path (keep 10 %) returns
+    exact FP32 scores (sampled patterns against the oracle), and the Fourier
+    route with certified rescoring returns exactly the plain path's top-N on
+    every pattern."""
+    sc = _scan(2)
+    tm, cfg, lib_np, imgs, grid, px = (sc[k] for k in ("tm", "cfg", "lib_np", "imgs", "grid", "px"))
+    lib, polar, norms, prof = sc["lib"], sc["polar"], sc["norms"], sc["prof"]
+    tt, ts, tq = sc["top"]
+    _say("BF16 pre-filter, keep 0.1, full scan")
+    pt, ps, pq = (o.cpu().numpy() for o in tm.match_batch(lib, polar, norms, cfg.N, profiles=prof,
+                                                           prefilter_keep=0.1,
+                                                           prefilter_prec="bf16"))
+    _properties(pt, ps, pq, lib.info()["n_templates_total"], cfg.n_theta)
+    olib = oracle.OracleLibrary.build(lib_np, px, cfg.R, cfg.n_theta)
+    for b in (0, cfg.B - 1):
+        ref = PatternRef(oracle.polar64(imgs[b].astype(np.float64), cfg.R, cfg.n_theta), olib)
+        for t, s_, q in zip(pt[b], ps[b], pq[b]):
+            assert scores_close(q, ref.best[int(t)]) and scores_close(q, ref.q_at(t, s_))
+    _say("Fourier route, certified, full scan")
+    flib = tm.Library(lib_np["kx"], lib_np["ky"], lib_np["intensity"], lib_np["offsets"], px, grid,
+                      fft=True)
+    ft, fs, fq = (o.cpu().numpy() for o in tm.match_batch(flib, polar, norms, cfg.N, coarse="fft"))
+    assert np.array_equal(ft, tt) and np.array_equal(fs, ts)
+    assert scores_close(fq, tq).all()
+
+
+# the oracle's exact search over 40 000 templates takes about half a minute
+# per pattern on one core: one sampled pattern (the scan's last) for C3
+@pytest.mark.parametrize("cid,n_sample", [(2, 10), (3, 1)])
+def test_full_scan_sampled_against_oracle(cid, n_sample):
+    sc = _scan(cid)
+    tm, cfg, lib_np, imgs, grid, px, lib, x = (sc[k] for k in
+                                              ("tm", "cfg", "lib_np", "imgs", "grid", "px", "lib", "x"))
+    B = cfg.B
+    tt, ts, tq = sc["top"]
     Tp = lib.info()["n_templates_total"]
     _say("layout", lib.layout(), "Tp", Tp)
     _properties(tt, ts, tq, Tp, cfg.n_theta)
@@ -66,3 +112,4 @@ def test_full_scan_sampled_against_oracle(cid, n_sample):
         p1, n1, _ = tm.polar_transform(x[b:b + 1].contiguous(), grid, lib=lib)
         t1, s1, q1 = (o.cpu().numpy()[0] for o in tm.match_batch(lib, p1, n1, cfg.N))
         assert np.array_equal(t1, tt[b]) and np.array_equal(s1, ts[b]) and np.array_equal(q1, tq[b])
+
