@@ -32,6 +32,15 @@ def _properties(tt, ts, tq, Tp, n_theta):
 _SCANS = {}
 
 
+@pytest.fixture(scope="module", autouse=True)
+def _release_scans():
+    """Drop the cached scan (several GiB of device memory) after the module."""
+    yield
+    _SCANS.clear()
+    import torch
+    torch.cuda.empty_cache()
+
+
 def _scan(cid):
     """The whole scan of workload cid generated, uploaded, polar-transformed
     (compact rows, as the benchmark times it) and matched once; kept for the
