@@ -453,7 +453,7 @@ def c5_bench(a):
     import paper_2111_07347_amd as tm
     import synth
     from paper_2111_07347_amd.serve import GpuExecutor, Server, latency_report, run_stream
-    cfg = synth.CONFIGS[5]
+    cfg = synth.WORKLOADS[5]
     n_rows = a.c5_rows
     distinct = min(a.c5_distinct, n_rows)
     row = synth.SERVING_ROW
@@ -536,7 +536,7 @@ def c5_bench(a):
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(patterns are independent; sharding scan rows across GPUs needs no exchange)",
               file=sys.stderr)
         return 2
@@ -554,7 +554,7 @@ def main():
     import paper_2111_07347_amd as tm
     import synth
 
-    cfg = synth.CONFIGS[a.config]
+    cfg = synth.WORKLOADS[a.config]
     B = a.batch or cfg.B
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)

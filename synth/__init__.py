@@ -25,7 +25,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = [
-    "Config", "CONFIGS", "wavelength_A", "make_library", "make_patterns",
+    "Config", "WORKLOADS", "wavelength_A", "make_library", "make_patterns",
     "ground_truth", "rng_for", "px_per_inv_A", "template_euler", "laue_of",
 ]
 
@@ -95,7 +95,7 @@ FCC_AL = ("fcc", (4.05,))
 ORTHO = ("ortho", (5.1, 7.3, 4.6))
 HCP = ("hcp", (2.95, 2.95 * 1.59))
 
-CONFIGS = {
+WORKLOADS = {
     1: Config(1, "tiny: 64 f32 patterns 128x128, 300 FCC templates <=30 spots",
               B=64, H=128, W=128, R=64, n_theta=360,
               phases=(Phase(*FCC_AL, 300, 30, "m-3m", "random"),), N=5,
@@ -321,7 +321,7 @@ def template_euler(cfg: Config | int, phases: tuple | None = None) -> np.ndarray
     the Bunge angles of its beam direction with phi1 = 0 (the orientation the
     template was simulated for), [T, 2] float64."""
     if isinstance(cfg, int):
-        cfg = CONFIGS[cfg]
+        cfg = WORKLOADS[cfg]
     phases = cfg.phases if phases is None else phases
     out = []
     for pi, phase in enumerate(phases):
@@ -343,7 +343,7 @@ def make_library(cfg: Config | int, phases: tuple | None = None):
     phase_of [int32, T]). Templates of all phases are concatenated in phase
     order."""
     if isinstance(cfg, int):
-        cfg = CONFIGS[cfg]
+        cfg = WORKLOADS[cfg]
     phases = cfg.phases if phases is None else phases
     key = (cfg.cid, phases, cfg.kv, cfg.g_max, cfg.s_max)
     if key in _LIB_CACHE:
@@ -449,7 +449,7 @@ def make_pattern(cfg: Config, lib: dict, index: int, truth=None) -> np.ndarray:
 def make_patterns(cfg: Config | int, lib: dict, indices) -> np.ndarray:
     """Stack [n, H, W] of patterns (float32 or uint16) for scan indices."""
     if isinstance(cfg, int):
-        cfg = CONFIGS[cfg]
+        cfg = WORKLOADS[cfg]
     indices = list(indices)
     dt = np.float32 if cfg.dtype == "f32" else np.uint16
     out = np.empty((len(indices), cfg.H, cfg.W), dtype=dt)
@@ -460,7 +460,7 @@ def make_patterns(cfg: Config | int, lib: dict, indices) -> np.ndarray:
 
 def _worker(args):
     cid, lib, lo, hi = args
-    return lo, make_patterns(CONFIGS[cid], lib, range(lo, hi))
+    return lo, make_patterns(WORKLOADS[cid], lib, range(lo, hi))
 
 
 def make_patterns_parallel(cfg: Config | int, lib: dict, n: int, workers: int = 8,
@@ -469,7 +469,7 @@ def make_patterns_parallel(cfg: Config | int, lib: dict, n: int, workers: int = 
     make_patterns(cfg, lib, range(n))."""
     import multiprocessing as mp
     if isinstance(cfg, int):
-        cfg = CONFIGS[cfg]
+        cfg = WORKLOADS[cfg]
     dt = np.float32 if cfg.dtype == "f32" else np.uint16
     if out is None:
         out = np.empty((n, cfg.H, cfg.W), dtype=dt)
@@ -493,7 +493,7 @@ SERVING_INTERVAL_S = SERVING_ROW / 4000.0      # 4000 patterns/s
 
 
 def serving_config(lib_id: int) -> Config:
-    base = CONFIGS[4]
+    base = WORKLOADS[4]
     return Config(4, f"serving row, library {lib_id}", B=SERVING_ROW, H=base.H, W=base.W,
                   R=base.R, n_theta=base.n_theta, phases=SERVING_LIBRARIES[lib_id], N=base.N,
                   dtype="u16", lognormal=True)

@@ -17,7 +17,7 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def c1():
     import synth
-    return synth.CONFIGS[1]
+    return synth.WORKLOADS[1]
 
 
 @pytest.fixture(scope="session")

@@ -21,7 +21,7 @@ def c5():
     import torch
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     import paper_2111_07347_amd as tm
-    cfg = synth.CONFIGS[5]
+    cfg = synth.WORKLOADS[5]
     lib_np = synth.make_library(cfg)
     grid = tm.PolarGrid(R=cfg.R, n_theta=cfg.n_theta, cx=cfg.cx, cy=cfg.cy)
     px = synth.px_per_inv_A(cfg)

@@ -51,7 +51,7 @@ def _scan(cid):
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     import paper_2111_07347_amd as tm
     _SCANS.clear()                       # one scan resident at a time
-    cfg = synth.CONFIGS[cid]
+    cfg = synth.WORKLOADS[cid]
     _say("full scan", cid, cfg.B, "patterns", cfg.H, "x", cfg.W)
     lib_np = synth.make_library(cfg)
     imgs = synth.make_patterns_parallel(cfg, lib_np, cfg.B, workers=16)

@@ -249,7 +249,7 @@ def test_match_multiband_synthetic(tm, n_theta, grouping):
 def test_match_c3_library(tm, grouping):
     """The 20 000-template orthorhombic library (93 touched rows, one band of
     narrow rows) on three patterns of the precision-form scan."""
-    cfg = synth.CONFIGS[3]
+    cfg = synth.WORKLOADS[3]
     lib = synth.make_library(3)
     imgs = synth.make_patterns(cfg, lib, [0, 4096, 16383])
     _say("c3 library, 3 patterns, T'=40000, grouping", grouping)
@@ -349,7 +349,7 @@ def test_compact_rows_equal_full(tm, case):
         imgs = np.random.default_rng(100).random((6, 256, 256)).astype(np.float32)
         grid = tm.PolarGrid(R=R, n_theta=nt, cx=128.0, cy=128.0)
     else:
-        cfg = synth.CONFIGS[1 if case == "c1" else 3]
+        cfg = synth.WORKLOADS[1 if case == "c1" else 3]
         lib_np = synth.make_library(cfg)
         px = synth.px_per_inv_A(cfg)
         imgs = synth.make_patterns(cfg, lib_np, range(8))

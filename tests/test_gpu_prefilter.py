@@ -27,7 +27,7 @@ def _say(*a):
 
 def _setup(tm, cid, idx, grouping=True):
     import torch
-    cfg = synth.CONFIGS[cid]
+    cfg = synth.WORKLOADS[cid]
     lib = synth.make_library(cid)
     imgs = synth.make_patterns(cfg, lib, idx)
     grid = tm.PolarGrid(R=cfg.R, n_theta=cfg.n_theta, cx=cfg.cx, cy=cfg.cy)

@@ -746,7 +746,7 @@ def test_simulation_equals_workload_generator_library():
     """The oracle's simulation reproduces the workload generator's own
     kinematical library (an independent implementation) for the tiny case."""
     from oracle import simulate as osim
-    cfg = synth.CONFIGS[1]
+    cfg = synth.WORKLOADS[1]
     lib = synth.make_library(cfg)
     o = osim.simulate_library64(np.eye(3) / FCC_A, FCC_ATOMS, np.ones(4), cfg.g_max + 0.2,
                                 synth.template_euler(cfg), 1 / synth.wavelength_A(cfg.kv),
