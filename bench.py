@@ -388,7 +388,7 @@ def simulation_bench(tm, a):
 
 
 def preprocess_bench(tm, x, a):
-    """Preprocessing of the whole batch on the device (Section 4.2: direct
+    """Preprocessing of the whole batch on the device (Section 4.1: direct
     beam centred, difference of Gaussians, blur, threshold), and the oracle
     on a few patterns as its CPU baseline. The separable filters cost
     (sum over the three Gaussians of 2 r + 1 taps) x 2 passes + 4 (bilinear

@@ -126,7 +126,7 @@ enum {
  *                     (FP32, BF16, FP16 or FP8 on the matrix cores with
  *                     float32 accumulation).
  *   coarse            TM_COARSE_NONE, or TM_COARSE_FFT: score every template
- *                     approximately through the Fourier route (Section 3;
+ *                     approximately through the Fourier route (Section 2.2;
  *                     tm_fft_scores; the library needs TM_LIB_FFT), then
  *                     rescore candidates exactly in float32. Exclusive with
  *                     the pre-filter.
@@ -258,7 +258,7 @@ int tm_polar_transform(const void* patterns, tm_dtype dtype, int32_t B, int32_t 
 /* tm_polar_transform_rows - tm_polar_transform with an optional pattern mask,
  * writing only selected polar rows.
  *
- * Mask (Section 4, custom indexation procedures: the dominant phase's
+ * Mask (Section 4.3, custom indexation procedures: the dominant phase's
  * reflections are masked before the second phase is indexed): the
  * transformed pattern is multiplied pixel by pixel by mask[y*W + x] before
  * resampling, P~ = mask * (max(x, 0)^gamma - c), so a masked pixel is 0 and
@@ -284,7 +284,7 @@ int tm_polar_transform_rows(const void* patterns, tm_dtype dtype, int32_t B, int
                             void* hip_stream);
 
 /* tm_mask_from_mean - the mask of the dominant phase for two-stage indexing
- * (Section 4, custom indexation procedures): average all patterns, threshold
+ * (Section 4.3, custom indexation procedures): average all patterns, threshold
  * the average, then erode and dilate to remove small noise-like features and
  * the tails of intense peaks.
  *
@@ -315,6 +315,9 @@ int tm_mask_from_mean(const void* patterns, tm_dtype dtype, int32_t B, int32_t H
  *   top rows: N distinct templates by best descending, ties to the lower
  *   template index, each with its best angle. Accumulation is float32 in a
  *   fixed order per (pattern, template), independent of the batch.
+ *   A pattern whose norm is not finite (its polar image holds a NaN or an
+ *   infinity) is not ranked: its N rows are template -1, angle -1, score NaN
+ *   (per-template outputs: NaN and -1). This holds on every path below.
  *
  * Arguments
  *   lib          loaded library; its grid defines R and n_theta.
@@ -380,14 +383,15 @@ int tm_prefilter(const tm_library* lib, const float* profiles, int32_t B, int32_
  *              are T..T'-1); entries outside that range are ignored; a row
  *              must not list a template twice.
  *   n_cand     >= 1; 1 <= N <= min(TM_MAX_N, n_cand).
- *   other arguments as in tm_match_batch.
+ *   other arguments as in tm_match_batch (a pattern with a non-finite norm
+ *   gets template -1, angle -1, score NaN).
  * Errors: TM_EINVAL, TM_EHIP, TM_ENODEV. */
 int tm_match_candidates(const tm_library* lib, const float* polar, const double* norms,
                         int32_t B, const int32_t* candidates, int32_t n_cand, int32_t N,
                         int32_t* top_template, int32_t* top_angle, float* top_score,
                         void* hip_stream);
 
-/* tm_refine_angles - sub-bin in-plane angles of reported matches (Section 4,
+/* tm_refine_angles - sub-bin in-plane angles of reported matches (Section 5,
  * discussion: improving the optimisation of the in-plane angle phi1).
  *
  * For row i of pattern b with template t = top_template[b, i] and shift
@@ -451,7 +455,7 @@ int tm_orientations(const double* lib_euler, int32_t T, int32_t mirrors, int32_t
                     void* hip_stream);
 
 /* tm_ipf_deviation - angular deviation between two orientation maps, Eq. (2)
- * (Section 4.2): for each sample direction d in (x, y, z), v = g d is the
+ * (Section 4.1): for each sample direction d in (x, y, z), v = g d is the
  * crystal direction an IPF-d map shows, reduced to the fundamental sector of
  * the Laue group; theta = |arccos(v_A . v_P / (|v_A| |v_P|))|.
  *
@@ -514,7 +518,7 @@ int tm_simulate_library(const double* recip_basis, const double* atoms_frac,
                         double* ky_out, double* intensity_out, int32_t* count_out,
                         void* hip_stream);
 
-/* Options of tm_preprocess (Section 4.2: direct beam centred, diffuse
+/* Options of tm_preprocess (Section 4.1: direct beam centred, diffuse
  * background removed by a difference of Gaussians, Gaussian blur, low
  * intensities set to zero). */
 typedef struct {
@@ -527,7 +531,7 @@ typedef struct {
 } tm_preprocess_opts;
 
 /* tm_preprocess - the preprocessing the paper applies before indexing, in
- * its order, on the device (Section 4.2; the discussion lists moving these
+ * its order, on the device (Section 4.1; the discussion lists moving these
  * steps off the CPU as an open optimisation).
  *
  *   centre    (cx, cy) = intensity-weighted centroid (float64) of the pixels
@@ -558,7 +562,7 @@ int tm_preprocess(const void* patterns, tm_dtype dtype, int32_t B, int32_t H, in
                   void* hip_stream);
 
 /* tm_fft_scores - approximate best score and angle of every template for every
- * pattern through the Fourier route (Section 3: the azimuthal sliding is a
+ * pattern through the Fourier route (Section 2.2: the azimuthal sliding is a
  * circular cross-correlation along theta, evaluated with Fourier transforms).
  *
  *   spectra  P^[b, j, k] = sum_theta P[b, j, theta] e^{-2 pi i k theta / n}

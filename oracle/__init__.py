@@ -20,21 +20,21 @@ out plainly, in float64, one function per step:
   (Section 2.2, Fig. 2 e);
 * ``topn64`` - sort and keep the N best templates (Section 2.2, end);
 * ``refine_angle64`` - sub-bin in-plane angle by a parabola through the
-  scores at the best shift and its neighbours (Section 4, discussion);
+  scores at the best shift and its neighbours (Section 5, discussion);
 * ``prefilter64`` - azimuthally integrated pre-filter of the library
   (Section 2.2, Fig. 3);
 * ``fft_match64`` - the same in-plane search through Fourier transforms
-  along the azimuth (Section 3, computational cost);
+  along the azimuth (Section 2.2, computational cost);
 * ``matrix_mask64`` - the mask of the dominant phase's reflections for
-  two-stage indexing (Section 4, custom indexation procedures);
+  two-stage indexing (Section 4.3, custom indexation procedures);
 * ``match_orientation64`` / ``ipf_deviation64`` - Bunge Euler angles of a
   match (Section 2.1, Section 2.2 for mirrors) and the angular deviation
-  between two orientation maps, Eq. (2) (Section 4.2);
+  between two orientation maps, Eq. (2) (Section 4.1);
 * ``simulate_library64`` - kinematical template library: reciprocal grid,
   rotation, excitation error, shape and structure factors, projection
   (Section 2.1);
 * ``preprocess64`` - direct-beam centring, difference-of-Gaussians
-  background removal, Gaussian blur and thresholding (Section 4.2).
+  background removal, Gaussian blur and thresholding (Section 4.1).
 
 Readings where the paper is silent are stated in each function.
 """

@@ -3,7 +3,7 @@
 
 Test infrastructure only (see the package docstring).
 
-Section 3 (computational cost): sliding a template along the azimuthal axis
+Section 2.2 (computational cost): sliding a template along the azimuthal axis
 of the polar image with wraparound is a circular cross-correlation along
 theta, so it can be evaluated with fast Fourier transforms at a cost that
 grows as r * phi * log(phi) instead of with the number of spots; the paper

@@ -2,7 +2,7 @@
 
 Test infrastructure only (see the package docstring).
 
-Section 4 (custom indexation procedures): to index nano-precipitates in a
+Section 4.3 (custom indexation procedures): to index nano-precipitates in a
 crystalline matrix, the matrix is indexed first, then its intense
 reflections are masked in every pattern, and the masked patterns are indexed
 with the precipitate library. The mask is made by averaging all diffraction

@@ -122,7 +122,7 @@ def index_batch64(imgs: np.ndarray, lib: OracleLibrary, N: int, processes: int =
 def refine_angle64(P: np.ndarray, lib: OracleLibrary, t: int, s: int,
                    pnorm: float | None = None) -> float:
     """Sub-bin in-plane angle of template t around its best shift s
-    (Section 4, discussion: improving the optimisation of the in-plane angle).
+    (Section 5, discussion: improving the optimisation of the in-plane angle).
 
     Reading: the parabola through Q(t, s-1), Q(t, s), Q(t, s+1) (shifts mod
     n_theta); its vertex offset d = (q- - q+) / (2 (q- - 2 q0 + q+)) is used

@@ -7,7 +7,7 @@ Section 2.1: orientations are Bunge Euler angles (phi1, Phi, phi2); all
 templates that share Phi and phi2 are related by an in-plane rotation, so the
 library samples only (Phi, phi2) with phi1 = 0 and phi1 is found by the
 in-plane search. Section 2.2: mirrored templates are the templates reflected
-across y = 0 and stand for further orientations. Section 4.2, Eq. (2): the
+across y = 0 and stand for further orientations. Section 4.1, Eq. (2): the
 angular deviation between two orientation maps is the angle between the
 vectors shown in each pixel of their inverse-pole-figure maps.
 

@@ -2,7 +2,7 @@
 
 Test infrastructure only (see the package docstring).
 
-Section 4.2 lists the preprocessing applied before template matching: the
+Section 4.1 lists the preprocessing applied before template matching: the
 direct beam of every pattern is centred, the diffuse background is removed
 by a difference of Gaussians, the result is smoothed by a Gaussian blur, and
 low-intensity pixels are set to zero (the gamma correction that follows is

@@ -41,7 +41,7 @@ def hipcc() -> str:
 
 # Per-source extra flags. The match kernel never produces NaNs (finite
 # patterns and weights), so NaN-quieting around fmaxf is dropped there.
-EXTRA = {"tm_match.hip": ["-fno-honor-nans"]}
+EXTRA = {"tm_match.hip": ["-Xarch_device", "-fno-honor-nans"]}
 
 
 def _compile(src: str, verbose: bool) -> str:

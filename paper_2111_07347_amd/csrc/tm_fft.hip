@@ -1,4 +1,4 @@
-// Fourier route of the in-plane search (Section 3, computational cost): the
+// Fourier route of the in-plane search (Section 2.2, computational cost): the
 // azimuthal sliding of a template over the polar image is a circular
 // cross-correlation along theta, so per pattern and template
 //
@@ -486,13 +486,18 @@ fft_inverse(const _Float16* __restrict__ Ch, const _Float16* __restrict__ Wg, in
 // compact with ballots (two passes: count, then write).
 __global__ void __launch_bounds__(kSelThreads)
 certify_select(const float* __restrict__ Qt, int Tp, const float* __restrict__ q_exact, int N,
-               float margin, int cap, int32_t* __restrict__ cand, int32_t* __restrict__ cnt,
+               double margin, int cap, int32_t* __restrict__ cand, int32_t* __restrict__ cnt,
                int32_t* __restrict__ full, int32_t* __restrict__ n_rescored) {
     constexpr int W = kSelThreads / 64;
     __shared__ int wcount[W];
     const int b = blockIdx.x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const float thr = q_exact[static_cast<size_t>(b) * N + N - 1] - margin;
+    // threshold rounded toward -inf: a template whose approximate score could
+    // reach the N-th best exact score within the bound is never dropped by
+    // the rounding of the subtraction
+    const double thr_d = static_cast<double>(q_exact[static_cast<size_t>(b) * N + N - 1]) - margin;
+    float thr = static_cast<float>(thr_d);
+    if (static_cast<double>(thr) > thr_d) thr = nextafterf(thr, -INFINITY);
     const float* row = Qt + static_cast<size_t>(b) * Tp;
     const int lo = static_cast<int>((static_cast<long long>(Tp) * wave) / W);
     const int hi = static_cast<int>((static_cast<long long>(Tp) * (wave + 1)) / W);
@@ -782,7 +787,7 @@ int tmlib::fft_match(const tm_library* lib, const float* polar, const double* no
         // 2. every template the bound cannot rule out
         if (!r) {
             hipLaunchKernelGGL(certify_select, dim3(B), dim3(kSelThreads), 0, s, Qt, Tp, q1, N,
-                               static_cast<float>(lib->fft_eps), cap, cand, cnt, full, n_rescored);
+                               lib->fft_eps, cap, cand, cnt, full, n_rescored);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) r = tmlib::hip_fail(e, "certify_select launch");
         }

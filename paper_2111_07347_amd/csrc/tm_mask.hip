@@ -1,4 +1,4 @@
-// Mask of the dominant phase's reflections for two-stage indexing (Section 4,
+// Mask of the dominant phase's reflections for two-stage indexing (Section 4.3,
 // custom indexation procedures: average all patterns, threshold the average,
 // erode and dilate to drop small features and cover the peak tails; the mask
 // then multiplies every pattern before the precipitate library is matched).

@@ -198,6 +198,23 @@ match_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
     };
 
     const double pn = norms[b];
+    // a polar image holding a non-finite value has a non-finite norm: its
+    // rows are reported as template -1, angle -1, score NaN (and NaN / -1
+    // per template). Tested on the bits, which the device build's
+    // no-NaN assumption cannot fold away.
+    if ((__double_as_longlong(pn) & 0x7ff0000000000000LL) == 0x7ff0000000000000LL) {
+        if (best_q)
+            for (int t = threadIdx.x; t < Tp; t += NW * 64) {
+                best_q[static_cast<size_t>(b) * Tp + t] = __int_as_float(0x7fc00000);
+                best_s[static_cast<size_t>(b) * Tp + t] = -1;
+            }
+        for (int i = threadIdx.x; i < N; i += NW * 64) {
+            top_t[static_cast<size_t>(b) * N + i] = -1;
+            top_s[static_cast<size_t>(b) * N + i] = -1;
+            top_q[static_cast<size_t>(b) * N + i] = __int_as_float(0x7fc00000);
+        }
+        return;
+    }
     const float invP = pn > 0.0 ? static_cast<float>(1.0 / pn) : 0.0f;
     // the last slot of lanes past n_theta holds no shift: start it at -inf
     const float lastinit = (64 * (K - 1) + lane < n_theta) ? 0.0f : -INFINITY;
@@ -486,7 +503,7 @@ namespace {
 // One wave per (pattern, rank): the exact float32 scores of the reported
 // template at shifts s-1, s, s+1 (lanes stride its per-template records, a
 // fixed butterfly reduces them), then the vertex of the parabola through the
-// three when it is a maximum (Section 4, discussion: improving the
+// three when it is a maximum (Section 5, discussion: improving the
 // optimisation of the in-plane angle).
 __global__ void __launch_bounds__(256)
 refine_kernel(const float* __restrict__ polar, const double* __restrict__ norms, int Rs,

@@ -3,7 +3,7 @@
 //
 // Section 2.1: the library samples (Phi, phi2) with phi1 = 0; the in-plane
 // search finds phi1. Section 2.2: a mirrored template (spots reflected
-// across y = 0) stands for a further orientation. Section 4.2, Eq. (2): the
+// across y = 0) stands for a further orientation. Section 4.1, Eq. (2): the
 // deviation between two maps is the angle between the crystal directions
 // their inverse-pole-figure (IPF) maps show in each pixel.
 //

@@ -1,4 +1,4 @@
-// Pattern preprocessing before indexing (Section 4.2: the direct beam is
+// Pattern preprocessing before indexing (Section 4.1: the direct beam is
 // centred, the diffuse background removed by a difference of Gaussians, the
 // result smoothed by a Gaussian blur and low intensities set to zero; the
 // discussion names parallelising these steps as an open optimisation).

@@ -10,7 +10,7 @@ correlation, no ranking. It only produces inputs:
   stored as CSR arrays (kx, ky, intensity, offsets);
 * stacks of diffraction patterns rendered from randomly chosen templates at
   random in-plane angles, with a bright direct beam, background and noise
-  (Section 3 and Section 4.2 give the pattern sizes and detector depth).
+  (Section 3, Section 4.1 and Section 4.2 give the pattern sizes and detector depth).
 
 Every random draw comes from ``numpy.random.default_rng(SeedSequence([2111,
 7347, config_id, stream, index]))`` so any single pattern can be regenerated

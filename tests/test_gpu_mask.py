@@ -1,4 +1,4 @@
-"""GPU parity of the two-stage indexing tools (Section 4, custom indexation
+"""GPU parity of the two-stage indexing tools (Section 4.3, custom indexation
 procedures): the mask built from the average pattern equals the oracle's
 bit for bit, masked polar images match the oracle, and indexing masked
 patterns with a second library (unit intensities, a subtracted constant)

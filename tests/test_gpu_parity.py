@@ -382,3 +382,62 @@ def test_compact_rows_equal_full(tm, case):
 def _olib_rows(lib_np, px, grid):
     olib = oracle.OracleLibrary.build(lib_np, px, grid.R, grid.n_theta)
     return np.unique(olib.J)
+
+
+# --------------------------------------------------------------------------- non-finite input
+def test_nonfinite_pattern_is_flagged_and_nan_options_rejected(tm, c1, c1_lib):
+    """A pattern holding a NaN or an infinity inside the polar footprint gets
+    template -1, angle -1, score NaN on every path (plain, per-template,
+    pre-filtered, Fourier route); the other patterns of the batch are
+    unaffected. NaN option fractions are rejected before any launch."""
+    import ctypes
+
+    import torch
+    _say("non-finite patterns c1 B=6")
+    imgs = synth.make_patterns(c1, c1_lib, range(6))
+    imgs[1, 64, 70] = np.nan
+    imgs[4, 60, 64] = np.inf
+    grid = _grid_for(tm, c1)
+    lib = tm.Library(c1_lib["kx"], c1_lib["ky"], c1_lib["intensity"], c1_lib["offsets"],
+                     synth.px_per_inv_A(c1), grid, fft=True)
+    x = torch.from_numpy(imgs).cuda()
+    polar, norms, prof = tm.polar_transform(x, grid)
+    bad = [1, 4]
+    good = [0, 2, 3, 5]
+    ref = tm.match_batch(lib, polar[good].contiguous(), norms[good].contiguous(), 5)
+    ref = [r.cpu().numpy() for r in ref]
+    runs = {
+        "plain": dict(),
+        "best": dict(with_best=True),
+        "prefilter": dict(profiles=prof, prefilter_keep=1.0, prefilter_prec="bf16"),
+        "fourier": dict(coarse="fft"),
+    }
+    for name, kw in runs.items():
+        _say("non-finite path", name)
+        out = tm.match_batch(lib, polar, norms, 5, **kw)
+        torch.cuda.synchronize()
+        tt, ts, tq = (o.cpu().numpy() for o in out[:3])
+        assert np.all(tt[bad] == -1) and np.all(ts[bad] == -1) and np.all(np.isnan(tq[bad])), name
+        # the other patterns: same best score; same best template and angle
+        # where the runner-up is clearly behind (other paths may sum in
+        # another order)
+        assert np.allclose(tq[good, 0], ref[2][:, 0], rtol=1e-5, atol=1e-7), name
+        clear = (ref[2][:, 0] - ref[2][:, 1]) > 1e-4
+        assert np.array_equal(tt[good, 0][clear], ref[0][clear, 0]), name
+        assert np.array_equal(ts[good, 0][clear], ref[1][clear, 0]), name
+        if name == "best":
+            bq, bs = out[3].cpu().numpy(), out[4].cpu().numpy()
+            assert np.all(np.isnan(bq[bad])) and np.all(bs[bad] == -1)
+            assert np.all(np.isfinite(bq[good]))
+    # NaN fractions never reach a kernel
+    for field in ("prefilter_keep", "rescore_keep"):
+        o = tm._Opts()
+        setattr(o, field, float("nan"))
+        if field == "rescore_keep":
+            o.coarse = tm.TM_COARSE_FFT
+        r = tm._lib.tm_match_batch(lib._h, polar.data_ptr(), norms.data_ptr(), prof.data_ptr(), 6,
+                                   ctypes.byref(o), 5, ref[0].ctypes.data, ref[0].ctypes.data,
+                                   ref[0].ctypes.data, None, None, None)
+        assert r == tm.TM_EINVAL, field
+        assert "outside [0, 1]" in tm.last_error()
+    lib.free()

@@ -1,5 +1,5 @@
 """GPU parity of the preprocessing steps (tm_preprocess: direct-beam
-centring, difference of Gaussians, blur, threshold; Section 4.2) against the
+centring, difference of Gaussians, blur, threshold; Section 4.1) against the
 oracle, and indexing of off-centre patterns after centring. Runs only on an
 MI355X (marked gpu)."""
 import numpy as np

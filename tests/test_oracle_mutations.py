@@ -11,6 +11,7 @@ import oracle.library as olibmod
 import oracle.match as omatch
 import oracle.orient as oorient
 import oracle.polar as opolar
+import oracle.prefilter as opre
 import oracle.preprocess as oprep
 import oracle.simulate as osim
 import test_oracle_pins as pins
@@ -165,6 +166,47 @@ def _shift_wrong_way(img, dx, dy):
 _orig_shift = oprep.shift_image64
 
 
+
+def _nearest_floor(img, x, y):
+    return opolar._pixel(img, np.floor(y).astype(np.int64), np.floor(x).astype(np.int64))
+
+
+def _nearest_swapped(img, x, y):
+    return opolar._pixel(img, np.rint(x).astype(np.int64), np.rint(y).astype(np.int64))
+
+
+def _nearest_half_up(img, x, y):
+    return opolar._pixel(img, np.floor(y + 0.5).astype(np.int64),
+                         np.floor(x + 0.5).astype(np.int64))
+
+
+def _prefilter_unnormalised(prof_P, prof_T, keep):
+    import math
+    dots = prof_T @ np.asarray(prof_P, dtype=np.float64)
+    n_keep = min(len(prof_T), int(math.ceil(keep * len(prof_T))))
+    return np.lexsort((np.arange(len(prof_T)), -dots))[:n_keep].astype(np.int64), dots
+
+
+def _profile_wrong_axis(P):
+    return np.asarray(P, dtype=np.float64).sum(axis=0)
+
+
+_orig_prefilter = opre.prefilter64
+
+
+def _prefilter_ties_high(prof_P, prof_T, keep):
+    kept, cos = _orig_prefilter(prof_P, prof_T, keep)
+    import math
+    n_keep = len(kept)
+    order = np.lexsort((-np.arange(len(prof_T)), -cos))[:n_keep]
+    return order.astype(np.int64), cos
+
+
+def _prefilter_floor_count(prof_P, prof_T, keep):
+    kept, cos = _orig_prefilter(prof_P, prof_T, 1.0)
+    return kept[:max(1, int(keep * len(prof_T)))], cos
+
+
 CASES = [
     ("x/y swapped in polar coordinates", opolar, "polar_coords64", _swapped_coords,
      [pins.test_p9_polar_reproduces_bilinear_functions]),
@@ -202,6 +244,21 @@ CASES = [
      [lambda: pins.test_gaussian_equals_scipy_reflect(2.5)]),
     ("centring shift the wrong way", oprep, "shift_image64", _shift_wrong_way,
      [pins.test_shift_integer_fraction_and_round_trip, pins.test_preprocess_centres_an_offset_beam]),
+    ("nearest sample by floor instead of rint", opolar, "nearest64", _nearest_floor,
+     [pins.test_nearest_on_pixel_centres_fixes_axes, pins.test_nearest_equals_brute_force_closest_centre]),
+    ("nearest sample with x and y swapped", opolar, "nearest64", _nearest_swapped,
+     [pins.test_nearest_on_pixel_centres_fixes_axes]),
+    ("nearest half-pixel ties rounded up", opolar, "nearest64", _nearest_half_up,
+     [pins.test_nearest_half_pixel_ties_round_half_to_even]),
+    ("pre-filter by unnormalised dot product", opre, "prefilter64", _prefilter_unnormalised,
+     [pins.test_prefilter_own_image_has_cosine_one_and_ranks_first,
+      pins.test_prefilter_cosine_equals_half_squared_distance_of_unit_profiles]),
+    ("image profile summed over radii", opolar, "profile64", _profile_wrong_axis,
+     [pins.test_prefilter_own_image_has_cosine_one_and_ranks_first]),
+    ("pre-filter ties to the higher index", opre, "prefilter64", _prefilter_ties_high,
+     [pins.test_prefilter_own_image_has_cosine_one_and_ranks_first]),
+    ("pre-filter keeps floor(f T)", opre, "prefilter64", _prefilter_floor_count,
+     [pins.test_prefilter_invariances_and_count]),
 ]
 
 

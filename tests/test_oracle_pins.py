@@ -410,7 +410,7 @@ def test_oracle_does_not_import_product():
 
 # ------------------------------------------------ Fourier route along theta
 def test_fft_route_numerator_equals_shift_sum_brute_force():
-    """Section 3: the in-plane search is a circular cross-correlation along
+    """Section 2.2: the in-plane search is a circular cross-correlation along
     theta. On a tiny case the Fourier-route numerator must equal the plain
     double sum over (row, column) of T[j, c] * P[j, (c + s) mod n_theta]."""
     lib, olib = _lib(R=12, n_theta=20, n=5, seed=11, px_per=9.0)
@@ -756,7 +756,7 @@ def test_simulation_equals_workload_generator_library():
         assert np.allclose(o[key], lib[key], atol=1e-12)
 
 
-# ------------------------------------------------ preprocessing (Section 4.2)
+# ------------------------------------------------ preprocessing (Section 4.1)
 @pytest.mark.parametrize("sigma", [0.7, 1.0, 2.5, 6.0])
 def test_gaussian_equals_scipy_reflect(sigma):
     rng = np.random.default_rng(80)
@@ -831,3 +831,148 @@ def test_preprocess_centres_an_offset_beam():
     assert abs(cx - 35.4) < 0.03 and abs(cy - 34.25) < 0.03
     c2 = oracle.beam_centre64(out, 8, 0.05)
     assert abs(c2[0] - 32.0) < 0.03 and abs(c2[1] - 32.0) < 0.03
+
+
+# ---------------------------------------------------------------- nearest-pixel sampling
+def _asymmetric_image(H=31, W=37, seed=71):
+    """Distinct values everywhere (no symmetry can hide a swapped axis)."""
+    rng = np.random.default_rng(seed)
+    return rng.permutation(H * W).reshape(H, W).astype(np.float64) + 1.0
+
+
+def test_nearest_on_pixel_centres_fixes_axes():
+    """Integer radii along the four axes put the sample points on pixel
+    centres: polar column 0 walks along +x (image columns), column n/4 along
+    +y (image rows), and each sample returns exactly that pixel."""
+    img = _asymmetric_image()
+    cx, cy, R, n = 17.0, 14.0, 12, 360
+    P = oracle.polar64(img, R, n, 0.0, 1.0, cx, cy, interp="nearest")
+    j = np.arange(R)
+    assert np.array_equal(P[:, 0], img[14, 17 + j])
+    assert np.array_equal(P[:, 90], img[14 + j, 17])
+    assert np.array_equal(P[:, 180], img[14, 17 - j])
+    assert np.array_equal(P[:, 270], img[14 - j, 17])
+
+
+def test_nearest_equals_brute_force_closest_centre():
+    """Away from ties, the nearest sample is the pixel whose centre is
+    closest in Euclidean distance, searched over a lattice extended past the
+    border (a closest centre outside the image gives 0)."""
+    img = _asymmetric_image(23, 29, seed=72)
+    H, W = img.shape
+    R, n, cx, cy = 18, 97, 13.3, 10.6
+    P = oracle.polar64(img, R, n, 0.35, 0.93, cx, cy, interp="nearest")
+    x, y = oracle.polar_coords64(R, n, 0.35, 0.93, cx, cy)
+    ys, xs = np.mgrid[-3:H + 3, -3:W + 3]
+    for jj in range(R):
+        for kk in range(n):
+            d2 = (xs - x[jj, kk]) ** 2 + (ys - y[jj, kk]) ** 2
+            flat = np.sort(d2.ravel())
+            assert flat[1] - flat[0] > 1e-9          # no tie at this sample
+            i = np.argmin(d2)
+            yi, xi = ys.ravel()[i], xs.ravel()[i]
+            inside = 0 <= yi < H and 0 <= xi < W
+            want = img[yi, xi] if inside else 0.0
+            assert P[jj, kk] == want, (jj, kk)
+
+
+def test_nearest_half_pixel_ties_round_half_to_even():
+    """Reading: exact half-pixel coordinates round half to even (IEEE
+    default), so x = 10.5 -> 10, 11.5 -> 12, 12.5 -> 12, 13.5 -> 14."""
+    img = _asymmetric_image()
+    P = oracle.polar64(img, 4, 360, 0.5, 1.0, 10.0, 6.0, interp="nearest")
+    assert list(P[:, 0]) == [img[6, c] for c in (10, 12, 12, 14)]
+    # along +y: y = 6.5, 7.5, 8.5, 9.5 -> rows 6, 8, 8, 10
+    assert list(P[:, 90]) == [img[r, 10] for r in (6, 8, 8, 10)]
+
+
+def test_nearest_outside_image_is_zero():
+    img = _asymmetric_image(20, 20, seed=73)
+    P = oracle.polar64(img, 40, 360, 0.0, 1.0, 10.0, 10.0, interp="nearest")
+    x, y = oracle.polar_coords64(40, 360, 0.0, 1.0, 10.0, 10.0)
+    out = (np.rint(x) < 0) | (np.rint(x) > 19) | (np.rint(y) < 0) | (np.rint(y) > 19)
+    assert out.any() and np.all(P[out] == 0.0)
+    assert np.all(P[~out] != 0.0)
+
+
+# ---------------------------------------------------------------- pre-filter ranking
+def _distinct_profile_library(T=18, seed=81, dup=(3, 11)):
+    """Base templates of 3-6 spots on distinct rows with random weights
+    (pairwise non-proportional radial profiles), except that template dup[1]
+    repeats the spots of dup[0] exactly."""
+    rng = np.random.default_rng(seed)
+    kx, ky, w, off = [], [], [], [0]
+    spots = []
+    for t in range(T):
+        n = int(rng.integers(3, 7))
+        rad = rng.choice(np.arange(6, 28), size=n, replace=False) / 30.0 + 1e-3
+        ang = rng.uniform(0, 2 * np.pi, n)
+        spots.append((rad * np.cos(ang), rad * np.sin(ang), rng.uniform(0.2, 1.0, n)))
+    spots[dup[1]] = spots[dup[0]]
+    for x, y, i in spots:
+        kx += list(x)
+        ky += list(y)
+        w += list(i)
+        off.append(off[-1] + len(x))
+    lib = dict(kx=np.array(kx), ky=np.array(ky), intensity=np.array(w),
+               offsets=np.array(off, dtype=np.int64))
+    return oracle.OracleLibrary.build(lib, 30.0, 32, 72)
+
+
+def test_prefilter_own_image_has_cosine_one_and_ranks_first():
+    """A polar image equal to template t's pixel image, at any roll, has the
+    same radial profile as t, so the cosine is 1 (Cauchy-Schwarz equality)
+    and t is kept first; an exact duplicate of t ties and the lower index
+    comes first."""
+    olib = _distinct_profile_library()
+    profT = oracle.radial_profiles64(olib)
+    u = profT / np.linalg.norm(profT, axis=1, keepdims=True)
+    C = u @ u.T
+    np.fill_diagonal(C, 0.0)
+    C[3, 11] = C[11, 3] = 0.0
+    assert C.max() < 1 - 1e-6                      # no other proportional pair
+    for t in range(olib.T_base):
+        for roll in (0, 5, 41):
+            P = np.roll(_dense_template(olib, t), roll, axis=1)
+            prof = oracle.profile64(P)
+            assert prof.shape == (olib.R,)
+            kept, cos = oracle.prefilter64(prof, profT, 0.2)
+            assert abs(cos[t] - 1.0) < 1e-12
+            first = 3 if t in (3, 11) else t
+            assert kept[0] == first
+            if t in (3, 11):
+                assert kept[1] == 11 and cos[3] == cos[11]
+            assert np.all(cos <= 1.0 + 1e-12)
+
+
+def test_prefilter_cosine_equals_half_squared_distance_of_unit_profiles():
+    """For unit vectors u, v: u . v = 1 - |u - v|^2 / 2, a formula that
+    involves no dot product; checks that both profiles are normalised."""
+    olib = _distinct_profile_library(seed=82)
+    profT = oracle.radial_profiles64(olib)
+    rng = np.random.default_rng(83)
+    pP = rng.random(olib.R) * 3.0
+    _, cos = oracle.prefilter64(pP, profT, 0.5)
+    u = profT / np.sqrt((profT ** 2).sum(axis=1, keepdims=True))
+    v = pP / np.sqrt((pP ** 2).sum())
+    assert np.allclose(cos, 1.0 - ((u - v) ** 2).sum(axis=1) / 2.0, rtol=0, atol=1e-12)
+
+
+def test_prefilter_invariances_and_count():
+    """The ranking does not change when the polar image is rolled along
+    theta or scaled, or when every weight of one template is scaled; the
+    kept count is ceil(f T) (reading: 'a tenth' of 25 keeps 3)."""
+    olib = _distinct_profile_library(T=25, seed=84, dup=(0, 0))
+    profT = oracle.radial_profiles64(olib)
+    rng = np.random.default_rng(85)
+    P = rng.random((olib.R, olib.n_theta))
+    k0, c0 = oracle.prefilter64(oracle.profile64(P), profT, 0.1)
+    assert len(k0) == 3
+    k1, c1 = oracle.prefilter64(oracle.profile64(np.roll(P, 13, axis=1)), profT, 0.1)
+    k2, c2 = oracle.prefilter64(oracle.profile64(7.5 * P), profT, 0.1)
+    pT = profT.copy()
+    pT[int(k0[1])] *= 40.0
+    k3, c3 = oracle.prefilter64(oracle.profile64(P), pT, 0.1)
+    for k, c in ((k1, c1), (k2, c2), (k3, c3)):
+        assert list(k) == list(k0)
+        assert np.allclose(c, c0, rtol=0, atol=1e-13)
