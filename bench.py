@@ -1,18 +1,25 @@
 """Benchmark of the template-matching hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 3] [--batch B]
 
-One step = one pass of the whole plain FP32 path over one batch: polar
-transform (intensity transform, resampling, norms, profiles) and the match
-kernel (Eq. 1 at every shift for every template and mirror, per-template
-maximum, top-N), with the batch already resident in HBM. The workload is the
-paper-scale scan: 16384 float32 patterns of 256 x 256 px, 2000 FCC templates
-(4000 with mirrors), polar grid 128 x 360, top-5. Inputs are seeded synthetic
+One step = one pass of the whole hot path over one batch already resident in
+HBM: polar transform (intensity transform, resampling, norms, profiles) and
+the match (Eq. 1 at every shift for every template and mirror, per-template
+maximum, top-N). The default workload is the precision-form scan: 16384
+float32 patterns of 256 x 256 px against 20000 orthorhombic templates (40000
+with mirrors), polar grid 128 x 360, top-5. Inputs are seeded synthetic
 patterns and templates (the paper's datasets are not available).
 
-Prints one JSON line with patterns/s, the dominant kernel's roofline
-fraction (timed live with HIP events on the launch stream) and the FP64
-oracle's patterns/s on this host's cores on a bounded sample.
+The JSON line's value is the plain float32 path's patterns/s; beside it:
+the reduced-precision pre-filter paths (BF16, FP16, FP8 on the matrix cores,
+exact float32 rescoring) at the smallest kept fraction whose top-1 equals the
+float32 path's, the certified Fourier route (FP16 on the matrix cores, same
+top-N as the float32 path by construction), end-to-end rates from pinned host
+memory to results on the host, the match kernel's roofline fraction (timed
+live with HIP events on the launch stream), the FP64 oracle's patterns/s on
+this host's cores on a bounded sample with the parity check on that sample,
+and the paper-scale FCC scan, orientation accuracy, library simulation,
+preprocessing and serving legs.
 """
 from __future__ import annotations
 
@@ -29,14 +36,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = "patterns indexed/sec (FP32 vs BF16 path, same top-1) + p99 scan-row latency"
 
-# MI355X published peaks; the LDS rate is derived from the chip's unit counts
-# and clock for the kernel's 4-byte lane reads (128 bytes per clock per CU)
+# MI355X published peaks; the LDS figure is derived from the chip's unit
+# counts and clock for 4-byte lane reads (128 bytes per clock per CU)
 HBM_PEAK_GBS = 8000.0
 CU, CLK_GHZ = 256, 2.4
 LDS_BYTES_PER_CLK_CU = 128.0
 LDS_PEAK_GBS = CU * LDS_BYTES_PER_CLK_CU * CLK_GHZ          # 78 643 GB/s
 FP32_PEAK_TFLOPS = 157.3                                    # vector FP32, published
+FP32_NONPACKED_TFLOPS = FP32_PEAK_TFLOPS / 2                # one FMA per lane per clock
 FP64_PEAK_TFLOPS = 78.6                                     # vector FP64, published
+BF16_MFMA_TFLOPS = 2500.0                                   # dense, published
+CLEAR_MARGIN = 1e-4                                         # parity contract's score margin
 
 
 def parse():
@@ -44,17 +54,24 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--batch", type=int, default=0, help="override B (0 = config's)")
-    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="patterns the oracle indexes for the CPU baseline and parity check "
+                         "(0 = 16 for the 20000-template library, 256 otherwise)")
     ap.add_argument("--cpu-procs", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-grouping", action="store_true",
                     help="score every template on its own (no shared-pixel groups)")
-    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp16", "fp8", "none"],
-                    help="arithmetic of the pre-filtered path timed beside the plain path")
-    ap.add_argument("--keep", type=float, default=0.1,
-                    help="fraction of base templates the pre-filter keeps")
+    ap.add_argument("--precisions", default="bf16,fp16,fp8",
+                    help="pre-filter arithmetics timed beside the plain path ('' = none)")
+    ap.add_argument("--keeps", default="0.05,0.1,0.2,0.3,0.5",
+                    help="kept fractions tried, smallest first, per pre-filter arithmetic")
+    ap.add_argument("--prec-steps", type=int, default=10,
+                    help="timed steps of each reduced-precision and Fourier leg")
+    ap.add_argument("--e2e-reps", type=int, default=3,
+                    help="end-to-end (pinned host -> results on host) repetitions per path")
+    ap.add_argument("--e2e-chunk", type=int, default=1024)
     ap.add_argument("--c5-rows", type=int, default=1024,
                     help="config 5: scan rows of 256 patterns streamed (burst)")
     ap.add_argument("--c5-distinct", type=int, default=128,
@@ -63,6 +80,8 @@ def parse():
                     help="write all R polar rows (default: only the rows the library touches)")
     ap.add_argument("--no-fft", action="store_true",
                     help="skip the Fourier-route (coarse + certified rescoring) leg")
+    ap.add_argument("--no-c2", action="store_true",
+                    help="skip the paper-scale FCC leg (run beside the default workload)")
     ap.add_argument("--serving-rows", type=int, default=1024,
                     help="scan rows replayed through the serving loop (0 = skip)")
     ap.add_argument("--serving-distinct", type=int, default=128,
@@ -73,12 +92,65 @@ def parse():
                     help="orientations the oracle simulates for that leg's CPU baseline")
     ap.add_argument("--no-preprocess", action="store_true",
                     help="skip the on-device preprocessing leg")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the orientation accuracy leg")
     ap.add_argument("--pre-cpu-sample", type=int, default=16,
                     help="patterns the oracle preprocesses for that leg's CPU baseline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy three times (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
+
+
+def say(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def host_info():
+    """CPU model and counts of this host (the GPU machine's, when run there)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count()
+    return {"cpu_model": model, "cpu_count": os.cpu_count(), "cpus_allowed": allowed}
+
+
+def pool_size(a):
+    """Oracle worker processes: the CPUs this process may use, at most 16
+    (one GPU's share of the machine's cores)."""
+    return a.cpu_procs or max(1, min(16, host_info()["cpus_allowed"] or 1))
+
+
+def step_stats(ms):
+    ms = np.asarray(ms, dtype=np.float64)
+    return {"median_ms": round(float(np.median(ms)), 4), "mean_ms": round(float(ms.mean()), 4),
+            "sd_ms": round(float(ms.std(ddof=1)) if len(ms) > 1 else 0.0, 4), "n": int(len(ms))}
+
+
+def time_steps(step, steps, warmup, n_marks=3):
+    """Run warmup untimed steps, then `steps` timed ones; step(ev) records
+    its events (or ev is None). Returns (wall seconds, events per step,
+    per-step device ms from the first to the last event)."""
+    import torch
+    for _ in range(warmup):
+        step(None)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(n_marks)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, evs, [e[0].elapsed_time(e[-1]) for e in evs]
 
 
 # Sources that define each kernel whose traffic the benchmark reports.
@@ -112,19 +184,332 @@ def recorded_traffic(cid, kernel_prefix):
     return None
 
 
-def oracle_baseline(cfg, lib_np, n_sample, procs, B):
-    """FP64 oracle patterns/s on a bounded sample (every (B // n_sample)-th
-    pattern of the batch)."""
+def _angle_margins(args):
+    """Oracle angle margins (best Q minus the best Q at any other shift) of
+    a pattern's top-N templates."""
+    import oracle
+    img, olib, tids = args
+    P = oracle.polar64(img, olib.R, olib.n_theta)
+    Q = oracle.scores64(P, olib.subset([int(t) for t in tids]), oracle.norm64(P))
+    srt = np.sort(Q, axis=1)
+    return srt[:, -1] - srt[:, -2]
+
+
+def oracle_sample(cfg, lib_np, n_sample, procs, B):
+    """FP64 oracle on every (B // n_sample)-th pattern of the batch: the
+    timed index (top N+1, the CPU baseline), then the angle margins of its
+    top-N templates (untimed, for the parity rule)."""
     os.environ.setdefault("OMP_NUM_THREADS", "1")
+    import multiprocessing as mp
+
     import oracle
     import synth
     idx = list(range(0, B, max(1, B // n_sample)))[:n_sample]
     imgs = synth.make_patterns(cfg, lib_np, idx)
     olib = oracle.OracleLibrary.build(lib_np, synth.px_per_inv_A(cfg), cfg.R, cfg.n_theta)
     t0 = time.perf_counter()
-    t, s, q, _ = oracle.index_batch64(imgs, olib, cfg.N, processes=procs)
+    t, s, q, _ = oracle.index_batch64(imgs, olib, cfg.N + 1, processes=procs)
     dt = time.perf_counter() - t0
-    return idx, (t, s, q), dt
+    jobs = [(imgs[i], olib, t[i, :cfg.N]) for i in range(len(idx))]
+    if procs > 1:
+        with mp.get_context("fork").Pool(procs) as pool:
+            am = np.stack(pool.map(_angle_margins, jobs, chunksize=1))
+    else:
+        am = np.stack([_angle_margins(j) for j in jobs])
+    return idx, (t, s, q, am), dt
+
+
+def parity_on_sample(top, idx, ref, N):
+    """The parity contract on the oracle's sample: on every rank r, the
+    template must equal the oracle's where the oracle's score gap to both
+    neighbouring ranks exceeds 1e-4, and the angle too where that template's
+    angle margin exceeds 1e-4; every score within max(1e-5 |Q|, 1e-7) of the
+    oracle's ranked score."""
+    ot, os_, oq, am = ref
+    gt = top[0].cpu().numpy()[idx]
+    gs = top[1].cpu().numpy()[idx]
+    gq = top[2].cpu().numpy()[idx].astype(np.float64)
+    n_t = same_t = n_a = same_a = 0
+    for i in range(len(idx)):
+        for r in range(N):
+            lo = oq[i, r] - oq[i, r + 1]
+            hi = oq[i, r - 1] - oq[i, r] if r > 0 else np.inf
+            if min(lo, hi) > CLEAR_MARGIN:
+                n_t += 1
+                same_t += int(gt[i, r] == ot[i, r])
+                if am[i, r] > CLEAR_MARGIN:
+                    n_a += 1
+                    same_a += int(gs[i, r] == os_[i, r])
+    err = np.abs(gq - oq[:, :N])
+    ok = err <= np.maximum(1e-5 * np.abs(oq[:, :N]), 1e-7)
+    return {
+        "patterns": len(idx), "ranks": len(idx) * N,
+        "ranks_with_template_margin_above_1e-4": n_t,
+        "template_identical_there": (same_t / n_t) if n_t else None,
+        "ranks_with_angle_margin_above_1e-4": n_a,
+        "angle_identical_there": (same_a / n_a) if n_a else None,
+        "scores_within_tolerance": float(ok.mean()),
+        "max_score_rel_err": float(np.max(err / np.maximum(np.abs(oq[:, :N]), 1e-7))),
+        "top1_agreement": float(np.mean(gt[:, 0] == ot[:, 0])),
+        "passed": bool(n_t == same_t and n_a == same_a and ok.all()),
+    }
+
+
+def match_roofline(cid, B, n_spots, n_theta, match_ms, layout, label):
+    """Roofline of the direct-correlation kernel: algorithmic flops (2 per
+    template pixel per shift per pattern) against the published float32
+    vector peak; beside it the same against the non-packed rate (the build
+    does not emit packed float32 instructions) and the LDS bytes the kernel
+    physically reads (one 64-lane, 4-byte read per record and 64-shift slot)
+    against the LDS figure."""
+    flops = 2.0 * B * n_spots * n_theta
+    tf = flops / (match_ms * 1e-3) / 1e12
+    slots = -(-n_theta // 64)
+    lds_bytes = float(B) * layout["n_records"] * slots * 64 * 4
+    lds_gbs = lds_bytes / (match_ms * 1e-3) / 1e9
+    return {
+        "bound": "alu", "kernel": label, "achieved": round(tf, 3), "peak": FP32_PEAK_TFLOPS,
+        "unit": "TFLOP/s", "frac": round(tf / FP32_PEAK_TFLOPS, 4),
+        "traffic": recorded_traffic(cid, "match_kernel"),
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+        "kernel_ms": round(match_ms, 4),
+        "work_per_launch": {"flops": flops, "fma": flops / 2, "patterns": B,
+                            "template_pixels": n_spots, "shifts": n_theta},
+        "nonpacked_fp32": {"peak": FP32_NONPACKED_TFLOPS,
+                           "frac": round(tf / FP32_NONPACKED_TFLOPS, 4)},
+        "lds_physical": {"bytes_per_launch": lds_bytes, "achieved_gbs": round(lds_gbs, 1),
+                         "peak_gbs": LDS_PEAK_GBS, "frac": round(lds_gbs / LDS_PEAK_GBS, 4),
+                         "records_per_pattern": layout["n_records"]},
+    }
+
+
+class Scan:
+    """One workload resident on the device: library, patterns, buffers."""
+
+    def __init__(self, tm, cfg, B, a, dev, want_host=False):
+        import torch
+        import synth
+        self.cfg, self.B, self.N = cfg, B, cfg.N
+        t0 = time.perf_counter()
+        self.lib_np = synth.make_library(cfg)
+        workers = pool_size(a)
+        dt = torch.float32 if cfg.dtype == "f32" else torch.int16
+        # patterns are generated straight into pinned host memory (the
+        # end-to-end leg streams them from there), then copied to HBM
+        self.host = torch.empty((B, cfg.H, cfg.W), dtype=dt, pin_memory=want_host)
+        hv = self.host.numpy() if cfg.dtype == "f32" else self.host.numpy().view(np.uint16)
+        synth.make_patterns_parallel(cfg, self.lib_np, B, workers=workers, out=hv)
+        say(f"generated {B} patterns + library ({cfg.n_templates} templates) in "
+            f"{time.perf_counter() - t0:.1f}s")
+        self.grid = tm.PolarGrid(R=cfg.R, n_theta=cfg.n_theta, cx=cfg.cx, cy=cfg.cy)
+        self.px = synth.px_per_inv_A(cfg)
+        t0 = time.perf_counter()
+        self.lib = tm.Library(self.lib_np["kx"], self.lib_np["ky"], self.lib_np["intensity"],
+                              self.lib_np["offsets"], self.px, self.grid,
+                              grouping=not a.no_grouping)
+        self.load_s = time.perf_counter() - t0
+        self.info = self.lib.info()
+        self.layout = self.lib.layout()
+        self.x = self.host.to(dev)
+        if not want_host:
+            self.host = None
+        self.plib = None if a.full_polar else self.lib
+        self.n_out_rows = cfg.R if self.plib is None else self.lib.rows()[0]
+        self.polar = torch.empty((B, self.n_out_rows, cfg.n_theta), dtype=torch.float32,
+                                 device=dev)
+        self.norms = torch.empty((B,), dtype=torch.float64, device=dev)
+        self.prof = torch.empty((cfg.R, B), dtype=torch.float32, device=dev)
+        self.out = (torch.empty((B, self.N), dtype=torch.int32, device=dev),
+                    torch.empty((B, self.N), dtype=torch.int32, device=dev),
+                    torch.empty((B, self.N), dtype=torch.float32, device=dev))
+        self.stream = torch.cuda.current_stream()
+
+    def polar_step(self, tm):
+        tm.polar_transform(self.x, self.grid, polar_out=self.polar, norm_out=self.norms,
+                           profile_out=self.prof, lib=self.plib)
+
+    def step_fn(self, tm, **match_kw):
+        lib = match_kw.pop("lib", self.lib)
+
+        def step(ev):
+            if ev is not None:
+                ev[0].record(self.stream)
+            self.polar_step(tm)
+            if ev is not None:
+                ev[1].record(self.stream)
+            tm.match_batch(lib, self.polar, self.norms, self.N, out=self.out, **match_kw)
+            if ev is not None:
+                ev[2].record(self.stream)
+        return step
+
+    def tops(self):
+        return [o.clone() for o in self.out]
+
+
+def plain_leg(tm, sc, steps, warmup, cid):
+    wall, evs, per_step = time_steps(sc.step_fn(tm), steps, warmup)
+    polar_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    match_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    cfg, B = sc.cfg, sc.B
+    in_bytes = B * cfg.H * cfg.W * sc.x.element_size()
+    polar_bytes = in_bytes + B * sc.n_out_rows * cfg.n_theta * 4 + B * 8 + B * cfg.R * 4
+    roof = match_roofline(cid, B, sc.info["n_spots"], cfg.n_theta, match_ms, sc.layout,
+                          "match_kernel")
+    roof["polar"] = {"bound": "hbm", "ms": round(polar_ms, 4),
+                     "achieved": round(polar_bytes / (polar_ms * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(polar_bytes / (polar_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "algorithmic_bytes": polar_bytes,
+                     "traffic": recorded_traffic(cid, "polar_kernel")}
+    say(f"plain fp32: {wall / steps * 1e3:.2f} ms/step (polar {polar_ms:.2f}, match "
+        f"{match_ms:.2f}), match {roof['achieved']} TFLOP/s = {roof['frac']} of the fp32 peak")
+    return {"value": round(B * steps / wall, 1), "ms_per_step": round(wall / steps * 1e3, 4),
+            "step_device_ms": step_stats(per_step), "polar_ms": round(polar_ms, 4),
+            "match_ms": round(match_ms, 4), "roofline": roof, "top": sc.tops()}
+
+
+def precision_sweep(tm, sc, plain_top, precs, keeps, steps, warmup):
+    """Per pre-filter arithmetic: the smallest kept fraction whose top-1
+    equals the float32 path's on every pattern where the float32 path's
+    top-1 leads its runner-up by more than 1e-4 (elsewhere two templates
+    score within the parity tolerance and either answer is correct), timed
+    over `steps` steps; beside it the fraction of all patterns with the same
+    top-1 template."""
+    import torch
+    ref_t = plain_top[0][:, 0]
+    clear = (plain_top[2][:, 0] - plain_top[2][:, 1]) > CLEAR_MARGIN
+    n_clear = int(clear.sum().item())
+    T = sc.lib.T
+    res = {}
+    for prec in precs:
+        tried, chosen = [], None
+        for keep in keeps:
+            step = sc.step_fn(tm, profiles=sc.prof, prefilter_keep=keep, prefilter_prec=prec)
+            step(None)
+            torch.cuda.synchronize()
+            t1 = sc.out[0][:, 0]
+            same = (t1 == ref_t)
+            ok = bool(same[clear].all().item())
+            tried.append({"keep_fraction": keep, "kept_base_templates": int(np.ceil(keep * T)),
+                          "top1_agreement_vs_fp32_path": round(float(same.float().mean().item()), 6),
+                          "clear_patterns_differing": int((~same & clear).sum().item())})
+            if ok:
+                chosen = keep
+                break
+        keep = chosen if chosen is not None else keeps[-1]
+        step = sc.step_fn(tm, profiles=sc.prof, prefilter_keep=keep, prefilter_prec=prec)
+        wall, evs, per_step = time_steps(step, steps, warmup)
+        top = sc.tops()
+        # the pre-filter alone (scores + selection), timed with events on the stream
+        n_keep = int(np.ceil(keep * T))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(sc.stream)
+        for _ in range(3):
+            kept = tm.prefilter(sc.lib, sc.prof, n_keep, prec)
+        e1.record(sc.stream)
+        torch.cuda.synchronize()
+        pre_ms = e0.elapsed_time(e1) / 3
+        del kept
+        match_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+        flops_pre = 2.0 * sc.B * T * sc.cfg.R
+        res[prec] = {
+            "value": round(sc.B * steps / wall, 1), "unit": "patterns/s",
+            "ms_per_step": round(wall / steps * 1e3, 4), "step_device_ms": step_stats(per_step),
+            "keep_fraction": keep, "same_top1_as_fp32_path": chosen is not None,
+            "clear_patterns": n_clear,
+            "top1_agreement_vs_fp32_path": round(float((top[0][:, 0] == ref_t).float().mean().item()), 6),
+            "prefilter_and_rescore_ms": round(match_ms, 4), "prefilter_ms": round(pre_ms, 4),
+            "rescore_ms": round(match_ms - pre_ms, 4),
+            "prefilter_mfma": {"flops": flops_pre,
+                               "achieved_tflops": round(flops_pre / (pre_ms * 1e-3) / 1e12, 2)},
+            "tried": tried, "_top": top,
+        }
+        say(f"precision {prec}: keep {keep} ({'same top-1' if chosen is not None else 'top-1 differs'}), "
+            f"{res[prec]['ms_per_step']:.2f} ms/step, pre-filter {pre_ms:.3f} ms")
+    return res
+
+
+def fourier_leg(tm, sc, plain_top, steps, warmup, cid):
+    """Certified Fourier route: approximate scores of every template through
+    the theta spectra (float16 on the matrix cores), exact float32 rescoring
+    of every template the error bound cannot rule out: same top-N as the
+    plain path."""
+    import torch
+    cfg, B = sc.cfg, sc.B
+    t0 = time.perf_counter()
+    flib = tm.Library(sc.lib_np["kx"], sc.lib_np["ky"], sc.lib_np["intensity"],
+                      sc.lib_np["offsets"], sc.px, sc.grid, fft=True)
+    load_s = time.perf_counter() - t0
+    Tp = flib.n_total
+    nr = torch.empty((B,), dtype=torch.int32, device=sc.x.device)
+    wall, evs, per_step = time_steps(sc.step_fn(tm, lib=flib, coarse="fft", n_rescored=nr),
+                                     steps, warmup)
+    top = sc.tops()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 2
+    e0.record(sc.stream)
+    for _ in range(reps):
+        q, _ = tm.fft_scores(flib, sc.polar, sc.norms, with_angle=False)
+    e1.record(sc.stream)
+    torch.cuda.synchronize()
+    coarse_ms = e0.elapsed_time(e1) / reps
+    del q
+    nrn = nr.cpu().numpy()
+    same = bool(torch.equal(top[0], plain_top[0]) and torch.equal(top[1], plain_top[1]))
+    F = cfg.n_theta // 2 + 1
+    chat_bytes = 2.0 * B * Tp * F * 4
+    hbm_bytes = chat_bytes + B * sc.polar.shape[1] * cfg.n_theta * 4
+    n_rows = flib.rows()[0]
+    flops = 2.0 * (4.0 * B * (Tp // 2 if Tp == 2 * cfg.n_templates else Tp) * n_rows * F
+                   + B * Tp * F * cfg.n_theta)
+    achieved = hbm_bytes / (coarse_ms * 1e-3) / 1e9
+    res = {
+        "value": round(B * steps / wall, 1), "unit": "patterns/s",
+        "ms_per_step": round(wall / steps * 1e3, 4), "step_device_ms": step_stats(per_step),
+        "arithmetic": "float16 spectra, float32 accumulation (MFMA), exact float32 rescoring",
+        "rescore_policy": "certified", "error_bound": flib.fft_error_bound(),
+        "coarse_ms": round(coarse_ms, 4),
+        "rescored_per_pattern_mean": round(float(nrn.mean()), 2),
+        "full_scan_fraction": round(float(np.mean(nrn == Tp)), 5),
+        "top_n_identical_to_fp32_path": same,
+        "top1_agreement_vs_fp32_path": float((top[0][:, 0] == plain_top[0][:, 0]).float().mean().item()),
+        "library_load_s": round(load_s, 2),
+        "roofline": {"bound": "hbm", "kernels": "fft_patterns + fft_forward + fft_inverse",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "work_per_call": {"hbm_bytes": hbm_bytes, "mfma_flops": flops},
+                     "mfma_tflops": round(flops / (coarse_ms * 1e-3) / 1e12, 1),
+                     "mfma_frac_fp16": round(flops / (coarse_ms * 1e-3) / 1e12 / 2500.0, 4)},
+        "_top": top, "_lib": flib,
+    }
+    say(f"fourier route: {res['ms_per_step']:.2f} ms/step, coarse {coarse_ms:.2f} ms, rescored "
+        f"{res['rescored_per_pattern_mean']}/pattern, identical top-N {same}")
+    return res
+
+
+def end_to_end(tm, sc, reps, chunk, paths):
+    """Patterns from pinned host memory to top-N rows in pinned host memory,
+    copies overlapped with compute (serve.PinnedIndexer); wall clock from the
+    first copy to the last result on the host."""
+    import torch
+    from paper_2111_07347_amd.serve import PinnedIndexer
+    res = {}
+    for name, lib, kw in paths:
+        ix = PinnedIndexer(lib, sc.grid, sc.N, chunk, sc.cfg.H, sc.cfg.W, sc.host.dtype, **kw)
+        out = ix(sc.host)                       # warm-up
+        walls = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = ix(sc.host, out)
+            walls.append(time.perf_counter() - t0)
+        w = float(np.median(walls))
+        res[name] = {"value": round(sc.B / w, 1), "unit": "patterns/s",
+                     "wall_ms": step_stats(np.array(walls) * 1e3), "chunk": chunk,
+                     "h2d_bytes": sc.B * sc.cfg.H * sc.cfg.W * sc.host.element_size()}
+        say(f"end-to-end {name}: {res[name]['value']:.0f} patterns/s")
+        del ix
+    return res
 
 
 def serving_bench(tm, n_rows, n_distinct, workers):
@@ -192,100 +577,6 @@ def serving_bench(tm, n_rows, n_distinct, workers):
         out[mode] = latency_report(res)
         print(f"[bench] serving {mode}: {out[mode]}", file=sys.stderr, flush=True)
     return out
-
-
-def fft_bench(tm, a, lib_np, cfg, grid, px, x, polar, norms, prof, N, B, stream, plain_top,
-              plib):
-    import torch
-    t0 = time.perf_counter()
-    flib = tm.Library(lib_np["kx"], lib_np["ky"], lib_np["intensity"], lib_np["offsets"], px,
-                      grid, fft=True)
-    load_s = time.perf_counter() - t0
-    Tp = flib.n_total
-    dev = x.device
-    out = (torch.empty((B, N), dtype=torch.int32, device=dev),
-           torch.empty((B, N), dtype=torch.int32, device=dev),
-           torch.empty((B, N), dtype=torch.float32, device=dev))
-    nr = torch.empty((B,), dtype=torch.int32, device=dev)
-    qt = torch.empty((B, Tp), dtype=torch.float32, device=dev)
-
-    def step_f(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
-        tm.polar_transform(x, grid, polar_out=polar, norm_out=norms, profile_out=prof, lib=plib)
-        if ev is not None:
-            ev[1].record(stream)
-        tm.match_batch(flib, polar, norms, N, coarse="fft", n_rescored=nr, out=out)
-        if ev is not None:
-            ev[2].record(stream)
-    for _ in range(a.warmup):
-        step_f()
-    fevs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(a.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(a.steps):
-        step_f(fevs[i])
-    torch.cuda.synchronize()
-    fwall = time.perf_counter() - t0
-    # the coarse scorer alone (three kernels), timed with events on the stream
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = max(1, min(a.steps, 5))
-    e0.record(stream)
-    for _ in range(reps):
-        q, _ = tm.fft_scores(flib, polar, norms, with_angle=False)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    coarse_ms = e0.elapsed_time(e1) / reps
-    del q
-    top = [o.cpu().numpy() for o in out]
-    nrn = nr.cpu().numpy()
-    same = bool(np.array_equal(top[0], plain_top[0].cpu().numpy())
-                and np.array_equal(top[1], plain_top[1].cpu().numpy()))
-    F = cfg.n_theta // 2 + 1
-    # algorithmic work of the coarse scorer: C(k) written once and read once
-    # (4 bytes per frequency and template-pattern pair), the polar image read;
-    # MACs of the row contraction (4 real products per base pair, row and
-    # frequency) and of the inverse (per pair, F complex terms x n_theta shifts)
-    chat_bytes = 2.0 * B * Tp * F * 4
-    hbm_bytes = chat_bytes + B * polar.shape[1] * cfg.n_theta * 4
-    n_rows = flib.rows()[0]          # the contraction runs over the touched rows
-    flops = 2.0 * (4.0 * B * (Tp // 2 if Tp == 2 * cfg.n_templates else Tp) * n_rows * F
-                   + B * Tp * F * cfg.n_theta)
-    achieved = hbm_bytes / (coarse_ms * 1e-3) / 1e9
-    # measured HBM traffic of one call: per-launch counter record of the three
-    # kernels times the pattern chunks of a call (C(k) kept within 16 GiB)
-    Fp = (F + 15) // 16 * 16
-    bc = max(64, int(16 * 2 ** 30 / (Fp * Tp * 4.0)) // 64 * 64)
-    n_chunks = -(-B // bc)
-    per_launch = [recorded_traffic(a.config, k) for k in ("fft_patterns", "fft_forward", "fft_inverse")]
-    traffic = sum(per_launch) * n_chunks if all(v is not None for v in per_launch) else None
-    res = {
-        "value": round(B * a.steps / fwall, 1), "unit": "patterns/s",
-        "ms_per_step": round(fwall / a.steps * 1e3, 4),
-        "arithmetic": "float16 spectra, float32 accumulation (MFMA), exact float32 rescoring",
-        "rescore_policy": "certified",
-        "error_bound": flib.fft_error_bound(),
-        "coarse_ms": round(coarse_ms, 4),
-        "coarse_and_rescore_ms": round(float(np.mean([e[1].elapsed_time(e[2]) for e in fevs])), 4),
-        "rescored_per_pattern_mean": round(float(nrn.mean()), 2),
-        "full_scan_fraction": round(float(np.mean(nrn == Tp)), 5),
-        "top_n_identical_to_fp32_path": same,
-        "top1_agreement_vs_fp32_path": float(np.mean(top[0][:, 0] == plain_top[0][:, 0].cpu().numpy())),
-        "library_load_s": round(load_s, 2),
-        "roofline": {"bound": "hbm", "kernels": "fft_patterns + fft_forward + fft_inverse",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "pattern_chunks": n_chunks,
-                     "work_per_launch": {"hbm_bytes": hbm_bytes, "mfma_flops": flops},
-                     "mfma_tflops": round(flops / (coarse_ms * 1e-3) / 1e12, 1),
-                     "mfma_frac_fp16": round(flops / (coarse_ms * 1e-3) / 1e12 / 2500.0, 4)},
-        "_top": top[0],
-    }
-    print(f"[bench] fft path: {res['ms_per_step']:.2f} ms/step, coarse {coarse_ms:.2f} ms, "
-          f"rescored {res['rescored_per_pattern_mean']}/pattern, identical top-N {same}",
-          file=sys.stderr, flush=True)
-    flib.free()
-    return res
 
 
 def orientation_accuracy(tm, cfg, lib, polar, norms, top, B):
@@ -459,7 +750,7 @@ def c5_bench(a):
     row = synth.SERVING_ROW
     t0 = time.perf_counter()
     lib_np = synth.make_library(cfg)
-    workers = min(16, os.cpu_count() or 1)
+    workers = pool_size(a)
     imgs = synth.make_patterns_parallel(cfg, lib_np, distinct * row, workers=workers)
     print(f"[bench] C5: library + {distinct * row} patterns generated in "
           f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
@@ -497,7 +788,7 @@ def c5_bench(a):
     top1 = None
     if not a.no_cpu:
         import oracle
-        procs = a.cpu_procs or min(16, os.cpu_count() or 1)
+        procs = pool_size(a)
         n_s = min(a.cpu_sample, 16)
         idx = list(range(0, distinct * row, max(1, distinct * row // n_s)))[:n_s]
         olib = oracle.OracleLibrary.build(lib_np, px, cfg.R, cfg.n_theta)
@@ -533,6 +824,41 @@ def c5_bench(a):
     return 0
 
 
+def workload_label(cfg, B):
+    lat = {"fcc": "FCC", "ortho": "orthorhombic", "hcp": "HCP"}
+    libs = " + ".join(f"{p.n_templates} {lat[p.lattice]} templates <={p.max_spots} spots"
+                      for p in cfg.phases)
+    return (f"template matching: {B} {cfg.dtype} patterns {cfg.H}x{cfg.W}, {libs}, "
+            f"polar {cfg.R}x{cfg.n_theta}, top-{cfg.N}")
+
+
+def c2_leg(tm, a, dev):
+    """The paper-scale FCC scan (16384 float32 patterns, 2000 templates):
+    plain path timed, parity against the oracle on 256 patterns."""
+    import torch
+    import synth
+    cfg = synth.WORKLOADS[2]
+    sc = Scan(tm, cfg, cfg.B, a, dev)
+    leg = plain_leg(tm, sc, max(5, min(a.steps, 20)), a.warmup, 2)
+    top = leg.pop("top")
+    out = {"workload": workload_label(cfg, cfg.B), "value": leg["value"], "unit": "patterns/s",
+           "ms_per_step": leg["ms_per_step"], "step_device_ms": leg["step_device_ms"],
+           "polar_ms": leg["polar_ms"], "match_ms": leg["match_ms"],
+           "library_layout": sc.layout, "template_pixels": sc.info["n_spots"],
+           "roofline": leg["roofline"]}
+    if not a.no_cpu:
+        procs = pool_size(a)
+        idx, ref, dt = oracle_sample(cfg, sc.lib_np, 256, procs, cfg.B)
+        out["cpu_baseline"] = {"value": round(len(idx) / dt, 2), "unit": "patterns/s",
+                               "cores": procs, "kind": "oracle",
+                               "sample": f"{len(idx)} patterns (index = 0 mod {cfg.B // len(idx)})"}
+        out["parity_on_sample"] = parity_on_sample(top, idx, ref, cfg.N)
+    say(f"paper-scale FCC: {leg['value']:.0f} patterns/s")
+    del sc
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -556,233 +882,123 @@ def main():
 
     cfg = synth.WORKLOADS[a.config]
     B = a.batch or cfg.B
+    N = cfg.N
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    sc = Scan(tm, cfg, B, a, dev, want_host=a.e2e_reps > 0)
+    plain = plain_leg(tm, sc, a.steps, a.warmup, a.config)
+    plain_top = plain.pop("top")
+    value = plain["value"]
+    info, layout, n_out_rows, load_s = sc.info, sc.layout, sc.n_out_rows, sc.load_s
 
-    t0 = time.perf_counter()
-    lib_np = synth.make_library(cfg)
-    workers = min(16, os.cpu_count() or 1)
-    imgs = synth.make_patterns_parallel(cfg, lib_np, B, workers=workers)
-    gen_s = time.perf_counter() - t0
-    print(f"[bench] generated {B} patterns + library in {gen_s:.1f}s", file=sys.stderr, flush=True)
+    accuracy = None
+    if not a.no_accuracy:
+        accuracy = orientation_accuracy(tm, cfg, sc.lib, sc.polar, sc.norms, plain_top, B)
+        say(f"orientation accuracy: {accuracy}")
 
-    grid = tm.PolarGrid(R=cfg.R, n_theta=cfg.n_theta, cx=cfg.cx, cy=cfg.cy)
-    px = synth.px_per_inv_A(cfg)
-    lib = tm.Library(lib_np["kx"], lib_np["ky"], lib_np["intensity"], lib_np["offsets"], px, grid,
-                     grouping=not a.no_grouping)
-    info = lib.info()
-    layout = lib.layout()
-    x = torch.from_numpy(imgs).to(dev)
-    del imgs
-    plib = None if a.full_polar else lib            # compact polar: the touched rows only
-    n_out_rows = cfg.R if plib is None else lib.rows()[0]
-    polar = torch.empty((B, n_out_rows, cfg.n_theta), dtype=torch.float32, device=dev)
-    norms = torch.empty((B,), dtype=torch.float64, device=dev)
-    prof = torch.empty((cfg.R, B), dtype=torch.float32, device=dev)
-    N = cfg.N
-    out = (torch.empty((B, N), dtype=torch.int32, device=dev),
-           torch.empty((B, N), dtype=torch.int32, device=dev),
-           torch.empty((B, N), dtype=torch.float32, device=dev))
-    stream = torch.cuda.current_stream()
+    precs = [p for p in a.precisions.split(",") if p]
+    keeps = [float(k) for k in a.keeps.split(",") if k]
+    prec = precision_sweep(tm, sc, plain_top, precs, keeps, a.prec_steps, 1) if precs else {}
+    fourier = None if a.no_fft else fourier_leg(tm, sc, plain_top, a.prec_steps, 1, a.config)
 
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
-        tm.polar_transform(x, grid, polar_out=polar, norm_out=norms, profile_out=prof, lib=plib)
-        if ev is not None:
-            ev[1].record(stream)
-        tm.match_batch(lib, polar, norms, N, out=out)
-        if ev is not None:
-            ev[2].record(stream)
+    e2e = None
+    if a.e2e_reps > 0:
+        paths = [("plain_fp32", sc.lib, {})]
+        if "bf16" in prec:
+            paths.append(("bf16_prefilter", sc.lib,
+                          dict(prefilter_keep=prec["bf16"]["keep_fraction"], prefilter_prec="bf16")))
+        if fourier is not None:
+            paths.append(("fourier_certified", fourier["_lib"], dict(coarse="fft")))
+        e2e = end_to_end(tm, sc, a.e2e_reps, a.e2e_chunk, paths)
+        sc.host = None
+    if fourier is not None:
+        fourier.pop("_lib").free()
+    torch.cuda.empty_cache()
 
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    print(f"[bench] warmup {a.warmup} done", file=sys.stderr, flush=True)
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(a.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(a.steps):
-        step(evs[i])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    print(f"[bench] timed {a.steps} steps in {wall:.3f}s", file=sys.stderr, flush=True)
-    polar_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    match_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-
-    # algorithmic work: one FMA (and one 4-byte LDS operand) per template
-    # pixel per shift; polar: read the pattern, write the polar image
-    n_spots = info["n_spots"]
-    macs = float(B) * n_spots * cfg.n_theta
-    lds_bytes = 4.0 * macs
-    in_bytes = B * cfg.H * cfg.W * x.element_size()
-    polar_bytes = in_bytes + B * n_out_rows * cfg.n_theta * 4 + B * 8 + B * cfg.R * 4
-    match_gbs = lds_bytes / (match_ms * 1e-3) / 1e9
-    roofline = {
-        "bound": "lds",
-        "kernel": "match_kernel",
-        "achieved": round(match_gbs, 1),
-        "peak": LDS_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(match_gbs / LDS_PEAK_GBS, 4),
-        "traffic": recorded_traffic(a.config, "match_kernel"),
-        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-        "work_per_launch": {"fma": macs, "lds_operand_bytes": lds_bytes,
-                            "lds_records": float(B) * layout["n_records"]},
-        "alu": {"achieved_tflops": round(2 * macs / (match_ms * 1e-3) / 1e12, 3),
-                "peak_tflops": FP32_PEAK_TFLOPS,
-                "frac": round(2 * macs / (match_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4)},
-        "polar": {"bound": "hbm", "ms": round(polar_ms, 4),
-                  "achieved": round(polar_bytes / (polar_ms * 1e-3) / 1e9, 1),
-                  "peak": HBM_PEAK_GBS,
-                  "frac": round(polar_bytes / (polar_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                  "traffic": recorded_traffic(a.config, "polar_kernel")},
-    }
-
-    ms_per_step = wall / a.steps * 1e3
-    value = B * a.steps / wall
-    plain_top = [o.clone() for o in out]
-    accuracy = orientation_accuracy(tm, cfg, lib, polar, norms, plain_top, B)
-    print(f"[bench] orientation accuracy: {accuracy}", file=sys.stderr, flush=True)
-
-    # the precision form: pre-filter in reduced precision, exact rescoring
-    prec_path = None
-    if a.precision != "none":
-        def step_p(ev=None):
-            if ev is not None:
-                ev[0].record(stream)
-            tm.polar_transform(x, grid, polar_out=polar, norm_out=norms, profile_out=prof, lib=plib)
-            if ev is not None:
-                ev[1].record(stream)
-            tm.match_batch(lib, polar, norms, N, profiles=prof, prefilter_keep=a.keep,
-                           prefilter_prec=a.precision, out=out)
-            if ev is not None:
-                ev[2].record(stream)
-        for _ in range(a.warmup):
-            step_p()
-        pevs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(a.steps)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(a.steps):
-            step_p(pevs[i])
-        torch.cuda.synchronize()
-        pwall = time.perf_counter() - t0
-        pre_top = [o.clone() for o in out]
-        same_t1 = float((pre_top[0][:, 0] == plain_top[0][:, 0]).float().mean().item())
-        prec_path = {
-            "value": round(B * a.steps / pwall, 1), "unit": "patterns/s",
-            "ms_per_step": round(pwall / a.steps * 1e3, 4),
-            "precision": a.precision, "keep_fraction": a.keep,
-            "prefilter_and_rescore_ms": round(float(np.mean([e[1].elapsed_time(e[2]) for e in pevs])), 4),
-            "top1_agreement_vs_fp32_path": same_t1,
-        }
-        print(f"[bench] precision path {a.precision}: {pwall / a.steps * 1e3:.2f} ms/step, "
-              f"top-1 agreement with the plain path {same_t1:.4f}", file=sys.stderr, flush=True)
-        # below 99 % same top-1, show what larger kept fractions cost
-        if same_t1 < 0.99:
-            sweep = []
-            for keep in (0.25, 0.5):
-                def step_k(keep=keep):
-                    tm.polar_transform(x, grid, polar_out=polar, norm_out=norms, profile_out=prof,
-                                       lib=plib)
-                    tm.match_batch(lib, polar, norms, N, profiles=prof, prefilter_keep=keep,
-                                   prefilter_prec=a.precision, out=out)
-                step_k()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for _ in range(a.steps):
-                    step_k()
-                torch.cuda.synchronize()
-                kwall = time.perf_counter() - t0
-                agree = float((out[0][:, 0] == plain_top[0][:, 0]).float().mean().item())
-                sweep.append({"keep_fraction": keep, "value": round(B * a.steps / kwall, 1),
-                              "ms_per_step": round(kwall / a.steps * 1e3, 4),
-                              "top1_agreement_vs_fp32_path": agree})
-            prec_path["keep_sweep"] = sweep
-            print(f"[bench] precision path keep sweep: {sweep}", file=sys.stderr, flush=True)
-
-    # the precision form, Fourier route: approximate scores of every template
-    # through the theta spectra (float16 on the matrix cores), then exact
-    # rescoring of the certified candidate set: same top-N as the plain path
-    fft_path = None
-    if not a.no_fft:
-        fft_path = fft_bench(tm, a, lib_np, cfg, grid, px, x, polar, norms, prof, N, B, stream,
-                             plain_top, plib)
-
-    cpu = None
-    top1 = None
-    oracle_check = None
+    cpu = parity = None
     if not a.no_cpu:
-        procs = a.cpu_procs or min(16, os.cpu_count() or 1)
-        idx, (ot, os_, oq), dt = oracle_baseline(cfg, lib_np, min(a.cpu_sample, B), procs, B)
-        cpu = {"value": round(len(idx) / dt, 2), "unit": "patterns/s", "cores": procs,
+        procs = pool_size(a)
+        n_sample = a.cpu_sample or (16 if cfg.n_templates >= 10000 else 256)
+        idx, ref, dt = oracle_sample(cfg, sc.lib_np, min(n_sample, B), procs, B)
+        hi = host_info()
+        cpu = {"value": round(len(idx) / dt, 3), "unit": "patterns/s", "cores": procs,
                "kind": "oracle",
-               "sample": f"{len(idx)} patterns (index = 0 mod {max(1, B // len(idx))}) of "
-                         f"the same workload, FP64 NumPy, {procs} processes"}
-        gt = plain_top[0].cpu().numpy()
-        top1 = float(np.mean(gt[idx, 0] == ot[:, 0]))
-        # the parity criterion: best (template, angle) identical wherever the
-        # oracle's margin between its first and second template exceeds 1e-4,
-        # and the best score within 1e-5 relative
-        gs = plain_top[1].cpu().numpy()[idx, 0]
-        gq = plain_top[2].cpu().numpy()[idx, 0].astype(np.float64)
-        clear = (oq[:, 0] - oq[:, 1]) > 1e-4
-        same = (gt[idx, 0] == ot[:, 0]) & (gs == os_[:, 0])
-        oracle_check = {
-            "patterns": len(idx), "margin_above_1e-4": int(clear.sum()),
-            "best_template_and_angle_identical_where_margin_above_1e-4":
-                float(np.mean(same[clear])) if clear.any() else None,
-            "max_best_score_rel_err": float(np.max(np.abs(gq - oq[:, 0]) / np.abs(oq[:, 0])))}
-        if prec_path is not None:
-            pt = pre_top[0].cpu().numpy()
-            prec_path["top1_agreement_vs_oracle_on_sample"] = float(np.mean(pt[idx, 0] == ot[:, 0]))
-        if fft_path is not None:
-            ft = fft_path.pop("_top")
-            fft_path["top1_agreement_vs_oracle_on_sample"] = float(np.mean(ft[idx, 0] == ot[:, 0]))
-    elif fft_path is not None:
-        fft_path.pop("_top")
+               "sample": f"{len(idx)} patterns (index = 0 mod {max(1, B // len(idx))}) of the "
+                         f"same workload, FP64 NumPy, {procs} processes",
+               "cpu_model": hi["cpu_model"], "host_cpu_count": hi["cpu_count"],
+               "host_cpus_allowed": hi["cpus_allowed"], "seconds": round(dt, 2)}
+        parity = parity_on_sample(plain_top, idx, ref, N)
+        say(f"oracle: {cpu['value']} patterns/s on {procs} processes; parity {parity}")
+        ot = ref[0]
+        for p in prec.values():
+            pt = p.pop("_top")[0].cpu().numpy()
+            p["top1_agreement_vs_oracle_on_sample"] = float(np.mean(pt[idx, 0] == ot[:, 0]))
+        if fourier is not None:
+            ft = fourier.pop("_top")
+            fourier["parity_on_sample"] = parity_on_sample(ft, idx, ref, N)
+    for p in prec.values():
+        p.pop("_top", None)
+    if fourier is not None:
+        fourier.pop("_top", None)
 
+    # the metric's comparison: the float32 path against the BF16 path at
+    # the same top-1 (and the other reduced-precision paths beside it)
+    comparison = {"fp32_patterns_per_s": value}
+    for name, p in prec.items():
+        comparison[f"{name}_prefilter_patterns_per_s"] = p["value"]
+        comparison[f"{name}_keep_fraction"] = p["keep_fraction"]
+        comparison[f"{name}_same_top1"] = p["same_top1_as_fp32_path"]
+        comparison[f"{name}_speedup"] = round(p["value"] / value, 3)
+    if fourier is not None:
+        comparison["fourier_certified_patterns_per_s"] = fourier["value"]
+        comparison["fourier_certified_same_top_n"] = fourier["top_n_identical_to_fp32_path"]
+        comparison["fourier_certified_speedup"] = round(fourier["value"] / value, 3)
+
+    c2 = None if (a.no_c2 or a.config != 3) else c2_leg(tm, a, dev)
     simulation = simulation_bench(tm, a) if a.sim_templates > 0 else None
-    preprocessing = None if a.no_preprocess else preprocess_bench(tm, x, a)
-
+    preprocessing = None if a.no_preprocess else preprocess_bench(tm, sc.x, a)
     serving = None
     if a.serving_rows > 0:
-        serving = serving_bench(tm, a.serving_rows, a.serving_distinct, workers)
+        del sc
+        torch.cuda.empty_cache()
+        serving = serving_bench(tm, a.serving_rows, a.serving_distinct, pool_size(a))
 
     line = {
         "metric": METRIC,
-        "value": round(value, 1),
+        "value": value,
         "unit": "patterns/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": plain["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"template matching, {cfg.name}",
+            "workload": workload_label(cfg, B),
             "B": B, "H": cfg.H, "W": cfg.W, "R": cfg.R, "n_theta": cfg.n_theta,
             "templates": cfg.n_templates, "templates_with_mirrors": info["n_templates_total"],
-            "template_pixels": n_spots, "top_n": N, "path": "plain fp32",
-            "polar_rows_written": n_out_rows,
-            "library_layout": layout,
-            "parallelism": "single GPU",
+            "template_pixels": info["n_spots"], "top_n": N, "path": "plain fp32",
+            "polar_rows_written": n_out_rows, "library_layout": layout,
+            "library_load_s": round(load_s, 2), "parallelism": "single GPU",
         },
-        "roofline": roofline,
+        "roofline": plain["roofline"],
         "cpu_baseline": cpu,
-        "top1_agreement_vs_oracle_on_sample": top1,
-        "oracle_check_on_sample": oracle_check,
+        "step_device_ms": plain["step_device_ms"],
+        "kernel_ms": {"polar_transform": plain["polar_ms"], "match_kernel": plain["match_ms"]},
+        "parity_on_sample": parity,
+        "fp32_vs_reduced_precision": comparison,
+        "precision_paths": prec,
+        "fourier_path": fourier,
+        "end_to_end": e2e,
+        "paper_scale_fcc": c2,
         "orientation_accuracy": accuracy,
         "library_simulation": simulation,
         "preprocessing": preprocessing,
-        "precision_path": prec_path,
-        "fft_path": fft_path,
         "serving": serving,
         "p99_scan_row_latency_ms": (serving or {}).get("paced", {}).get("p99_ms"),
-        "kernel_ms": {"polar_transform": round(polar_ms, 4), "match_kernel": round(match_ms, 4)},
     }
     print(json.dumps(line), flush=True)
     return 0

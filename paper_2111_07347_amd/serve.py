@@ -337,3 +337,83 @@ def run_stream(server: Server, rows: list, lib_ids, arrivals, poll_s: float = 2e
         if i < n or not server.sched.idle:
             time.sleep(poll_s)
     return server.results
+
+
+class PinnedIndexer:
+    """End-to-end indexing of a pattern stack held in pinned host memory
+    (the paper's GPU timing counts the transfer of the images to the device
+    and of the results back).
+
+    The stack is cut into chunks. Chunk i + 1 is copied to the device on a
+    copy stream while chunk i is transformed and matched on the compute
+    stream, from two alternating device buffers; each chunk's top-N rows go
+    back to pinned host memory on the compute stream. Both streams have the
+    default priority. Device buffers are allocated once, at construction,
+    and reused by every call."""
+
+    def __init__(self, lib, grid, N: int, chunk: int, H: int, W: int, dtype,
+                 gamma: float = 1.0, subtract: float = 0.0, **match_kw):
+        import torch
+
+        import paper_2111_07347_amd as tm
+        self.tm, self.torch = tm, torch
+        self.lib, self.grid, self.N, self.chunk = lib, grid, N, chunk
+        self.gamma, self.subtract, self.match_kw = gamma, subtract, match_kw
+        dev = torch.device("cuda")
+        self.want_profile = match_kw.get("prefilter_keep", 0.0) > 0.0
+        n_rows = lib.rows()[0] or grid.R
+        self.xbuf = [torch.empty((chunk, H, W), dtype=dtype, device=dev) for _ in range(2)]
+        self.polar = torch.empty((chunk, n_rows, grid.n_theta), dtype=torch.float32, device=dev)
+        self.norms = torch.empty((chunk,), dtype=torch.float64, device=dev)
+        self.prof = (torch.empty((grid.R, chunk), dtype=torch.float32, device=dev)
+                     if self.want_profile else None)
+        self.out = (torch.empty((chunk, N), dtype=torch.int32, device=dev),
+                    torch.empty((chunk, N), dtype=torch.int32, device=dev),
+                    torch.empty((chunk, N), dtype=torch.float32, device=dev))
+        self.copy_s = torch.cuda.Stream()
+        self.comp_s = torch.cuda.Stream()
+
+    def __call__(self, host, results=None):
+        """Index host [B, H, W] (pinned); returns pinned host (template,
+        angle, score) [B, N] after the work has finished."""
+        torch, tm = self.torch, self.tm
+        B = host.shape[0]
+        if results is None:
+            results = tuple(torch.empty((B, self.N), dtype=d, pin_memory=True)
+                            for d in (torch.int32, torch.int32, torch.float32))
+        n_chunks = -(-B // self.chunk)
+        x_free = [None, None]               # compute done reading buffer i
+        for c in range(n_chunks):
+            lo, hi = c * self.chunk, min(B, (c + 1) * self.chunk)
+            n = hi - lo
+            k = c % 2
+            xb = self.xbuf[k][:n]
+            with torch.cuda.stream(self.copy_s):
+                if x_free[k] is not None:
+                    self.copy_s.wait_event(x_free[k])
+                xb.copy_(host[lo:hi], non_blocking=True)
+                copied = torch.cuda.Event()
+                copied.record(self.copy_s)
+            with torch.cuda.stream(self.comp_s):
+                self.comp_s.wait_event(copied)
+                polar, norms = self.polar[:n], self.norms[:n]
+                prof = None
+                if self.want_profile:
+                    prof = self.prof if n == self.chunk else torch.empty(
+                        (self.grid.R, n), dtype=torch.float32, device=xb.device)
+                tm.polar_transform(xb, self.grid, self.gamma, self.subtract, polar_out=polar,
+                                   norm_out=norms, profile_out=prof,
+                                   want_profile=self.want_profile, lib=self.lib)
+                ev = torch.cuda.Event()
+                ev.record(self.comp_s)
+                x_free[k] = ev
+                out = tuple(o[:n] for o in self.out)
+                kw = dict(self.match_kw)
+                if self.want_profile:
+                    kw["profiles"] = prof
+                tm.match_batch(self.lib, polar, norms, self.N, out=out, **kw)
+                for h, o in zip(results, out):
+                    h[lo:hi].copy_(o, non_blocking=True)
+        self.comp_s.synchronize()
+        self.copy_s.synchronize()
+        return results

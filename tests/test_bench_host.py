@@ -55,3 +55,41 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in r.stderr or "one gpu" in r.stderr.lower()
+
+
+def test_parity_rule_on_sample_counts_clear_ranks():
+    """The benchmark's parity rule: ranks whose oracle gap to both
+    neighbours exceeds 1e-4 must match in template (and angle where the
+    angle margin exceeds 1e-4); near-ties are not compared."""
+    import numpy as np
+    import torch
+    N = 3
+    ot = np.array([[5, 7, 9, 11], [1, 2, 3, 4]])
+    os_ = np.array([[10, 20, 30, 40], [1, 2, 3, 4]])
+    oq = np.array([[0.9, 0.8, 0.79995, 0.5], [0.7, 0.6, 0.5, 0.4]])
+    am = np.array([[0.1, 0.1, 0.1], [0.1, 0.00001, 0.1]])
+    # pattern 0: ranks 1 and 2 are a near-tie (swapped on the GPU: fine);
+    # pattern 1: rank 1's angle is a near-tie (different angle: fine)
+    gt = torch.tensor([[5, 9, 7], [1, 2, 3]], dtype=torch.int32)
+    gs = torch.tensor([[10, 30, 20], [1, 99, 3]], dtype=torch.int32)
+    gq = torch.tensor([[0.9, 0.8, 0.79995], [0.7, 0.6, 0.5]], dtype=torch.float32)
+    r = bench.parity_on_sample((gt, gs, gq), [0, 1], (ot, os_, oq, am), N)
+    assert r["ranks_with_template_margin_above_1e-4"] == 4
+    assert r["template_identical_there"] == 1.0
+    assert r["ranks_with_angle_margin_above_1e-4"] == 3
+    assert r["passed"]
+    # a wrong template on a clear rank fails
+    gt2 = gt.clone()
+    gt2[1, 2] = 8
+    r = bench.parity_on_sample((gt2, gs, gq), [0, 1], (ot, os_, oq, am), N)
+    assert not r["passed"] and r["template_identical_there"] == 0.75
+    # a score outside the tolerance fails
+    gq2 = gq.clone()
+    gq2[0, 0] = 0.9 + 1e-4
+    assert not bench.parity_on_sample((gt, gs, gq2), [0, 1], (ot, os_, oq, am), N)["passed"]
+
+
+def test_workload_label_uses_the_actual_batch():
+    import synth
+    lab = bench.workload_label(synth.WORKLOADS[3], 4096)
+    assert "4096 f32 patterns 256x256" in lab and "20000 orthorhombic templates" in lab
