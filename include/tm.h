@@ -346,6 +346,32 @@ int tm_match_batch(const tm_library* lib, const float* polar, const double* norm
                    int32_t* top_template, int32_t* top_angle, float* top_score,
                    float* best_score, int16_t* best_angle, void* hip_stream);
 
+/* Size of the static scratch array of tm_match_batch_static (per GPU). */
+#define TM_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* tm_match_batch_static - tm_match_batch for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation during a run. It takes the same arguments and gives
+ * the same results; it calls no hipMalloc, hipFree or allocating routine.
+ *
+ * The pre-filter's scratch (kept lists [B, n_items] int32, then the score
+ * matrix [B, T] float32 at the next 256-byte boundary) lives in a static
+ * device array of TM_STATIC_SCRATCH_BYTES (64 MiB) that each GPU the library
+ * runs on holds until the process ends. Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (other streams, other threads)
+ * race and must be serialised by the caller. Everything the kernels read
+ * from it is written first in the same call, so no clearing is needed.
+ * The plain path uses no scratch.
+ *
+ * Errors: as tm_match_batch, plus TM_EINVAL when the pre-filter's scratch
+ * exceeds the array (e.g. with T = 20000 base templates and keep 0.1,
+ * B <= 699 patterns per call) and TM_EUNSUPPORTED for the Fourier route
+ * (TM_COARSE_FFT), whose scratch is far larger. */
+int tm_match_batch_static(const tm_library* lib, const float* polar, const double* norms,
+                          const float* profiles, int32_t B, const tm_match_opts* opts, int32_t N,
+                          int32_t* top_template, int32_t* top_angle, float* top_score,
+                          float* best_score, int16_t* best_angle, void* hip_stream);
+
 /* tm_prefilter - the library pre-filter of Section 2.2 (Fig. 3): pattern and
  * template are integrated over the azimuth and correlated by one matrix
  * product; the best-correlating templates are kept for the full search.

@@ -39,7 +39,7 @@ LAUE_GROUPS = {"m-3m": TM_LAUE_M3M, "mmm": TM_LAUE_MMM, "6/mmm": TM_LAUE_6MMM}
 
 EXPORTED = ("tm_load_library", "tm_free_library", "tm_library_info", "tm_library_layout",
             "tm_library_rows", "tm_polar_transform", "tm_polar_transform_rows",
-            "tm_mask_from_mean", "tm_match_batch", "tm_refine_angles", "tm_prefilter", "tm_match_candidates",
+            "tm_mask_from_mean", "tm_match_batch", "tm_match_batch_static", "tm_refine_angles", "tm_prefilter", "tm_match_candidates",
             "tm_fft_scores", "tm_fft_error_bound", "tm_orientations", "tm_ipf_deviation",
             "tm_simulate_library", "tm_preprocess",
             "tm_topn", "tm_last_error", "tm_version")
@@ -90,6 +90,7 @@ def _load():
                                     P, P, I32, P, P, P, P],
         "tm_mask_from_mean": [P, ctypes.c_int, I32, I32, I32, D, I32, I32, P, P],
         "tm_match_batch": [P, P, P, P, I32, ctypes.POINTER(_Opts), I32, P, P, P, P, P, P],
+        "tm_match_batch_static": [P, P, P, P, I32, ctypes.POINTER(_Opts), I32, P, P, P, P, P, P],
         "tm_prefilter": [P, P, I32, I32, I32, P, P],
         "tm_match_candidates": [P, P, P, I32, P, I32, I32, P, P, P, P],
         "tm_fft_scores": [P, P, P, I32, I32, P, P, P],

@@ -34,9 +34,20 @@ int validate_grid(const tm_polar_grid* g);
 // Pre-filter (azimuthally integrated profiles, Fig. 3): per pattern the n_keep
 // base templates with the highest profile correlation, ties to the lower
 // index, written ascending to items [B, n_items]; with mirrors, entries
-// n_keep.. hold the kept templates' mirrors (t + T). Enqueued on s.
+// n_keep.. hold the kept templates' mirrors (t + T). The score matrix [B, T]
+// float32 lives in S when given, else in stream-ordered scratch. Enqueued on s.
 int prefilter_kept(const tm_library* lib, const float* profiles, int32_t B, int32_t n_keep,
-                   int32_t precision, int32_t* items, int32_t n_items, bool mirror, hipStream_t s);
+                   int32_t precision, int32_t* items, int32_t n_items, bool mirror, hipStream_t s,
+                   float* S = nullptr);
+
+// tm_match_batch with its pre-filter scratch taken from [scratch, scratch +
+// scratch_bytes) when scratch is given (then nothing is allocated), else
+// from the stream-ordered allocator.
+int match_batch_impl(const tm_library* lib, const float* polar, const double* norms,
+                     const float* profiles, int32_t B, const tm_match_opts* opts, int32_t N,
+                     int32_t* top_template, int32_t* top_angle, float* top_score,
+                     float* best_score, int16_t* best_angle, void* hip_stream, void* scratch,
+                     size_t scratch_bytes);
 
 // Exact rescoring launch of the match kernel (tm_match.hip): all templates
 // (cand == nullptr) or per-pattern candidate lists of up to n_items ids;

@@ -388,11 +388,16 @@ int tmlib::launch_match(const tm_library* lib, const float* polar, const double*
     return TM_OK;
 }
 
-extern "C" int tm_match_batch(const tm_library* lib, const float* polar, const double* norms,
-                              const float* profiles, int32_t B, const tm_match_opts* opts,
-                              int32_t N, int32_t* top_template, int32_t* top_angle,
-                              float* top_score, float* best_score, int16_t* best_angle,
-                              void* hip_stream) {
+// tm_match_batch and its variant without allocations: scratch == nullptr
+// takes the pre-filter's scratch (kept lists and the score matrix) from the
+// stream-ordered allocator; otherwise it comes from [scratch, scratch +
+// scratch_bytes) and requests that need more, or the Fourier route, are
+// rejected before anything is enqueued.
+int tmlib::match_batch_impl(const tm_library* lib, const float* polar, const double* norms,
+                            const float* profiles, int32_t B, const tm_match_opts* opts,
+                            int32_t N, int32_t* top_template, int32_t* top_angle,
+                            float* top_score, float* best_score, int16_t* best_angle,
+                            void* hip_stream, void* scratch, size_t scratch_bytes) {
     tmlib::clear_error();
     if (!lib) { tmlib::set_error("library is NULL"); return TM_EINVAL; }
     if (B < 0) { tmlib::set_error("B=%d < 0", B); return TM_EINVAL; }
@@ -442,6 +447,22 @@ extern "C" int tm_match_batch(const tm_library* lib, const float* polar, const d
         if (best_score) { tmlib::set_error("per-template outputs are not available with a pre-filter"); return TM_EINVAL; }
         if (!profiles && B > 0) { tmlib::set_error("profiles are required with a pre-filter"); return TM_EINVAL; }
     }
+    if (scratch && coarse == TM_COARSE_FFT) {
+        tmlib::set_error("the Fourier route needs the spectra of a chunk of patterns as scratch "
+                         "(about 2 GiB), more than the static buffer of %zu bytes", scratch_bytes);
+        return TM_EUNSUPPORTED;
+    }
+    // scratch layout of the pre-filter: kept lists [B, n_items] int32, then
+    // (256-byte aligned) the score matrix [B, T] float32
+    const size_t items_bytes = (static_cast<size_t>(B) * (mirror ? 2 * n_keep : n_keep) *
+                                sizeof(int32_t) + 255) / 256 * 256;
+    const size_t scores_bytes = static_cast<size_t>(B) * lib->T * sizeof(float);
+    if (scratch && n_keep > 0 && items_bytes + scores_bytes > scratch_bytes) {
+        tmlib::set_error("B=%d with %d kept of T=%d templates needs %zu bytes of scratch, more "
+                         "than the static buffer of %zu bytes", B, n_keep, lib->T,
+                         items_bytes + scores_bytes, scratch_bytes);
+        return TM_EINVAL;
+    }
     if (B == 0) return TM_OK;
     if (!polar || !norms || !top_template || !top_angle || !top_score) {
         tmlib::set_error("polar, norms and top_* outputs must be non-NULL");
@@ -462,16 +483,34 @@ extern "C" int tm_match_batch(const tm_library* lib, const float* polar, const d
     // pre-filter, then rescore the kept templates (and their mirrors) exactly
     const int32_t n_items = mirror ? 2 * n_keep : n_keep;
     int32_t* items = nullptr;
-    TM_HIP(hipMallocAsync(reinterpret_cast<void**>(&items),
-                          static_cast<size_t>(B) * n_items * sizeof(int32_t), s));
-    int r = tmlib::prefilter_kept(lib, profiles, B, n_keep, prec, items, n_items, mirror, s);
+    float* S = nullptr;
+    if (scratch) {
+        items = static_cast<int32_t*>(scratch);
+        S = reinterpret_cast<float*>(static_cast<char*>(scratch) + items_bytes);
+    } else {
+        TM_HIP(hipMallocAsync(reinterpret_cast<void**>(&items),
+                              static_cast<size_t>(B) * n_items * sizeof(int32_t), s));
+    }
+    int r = tmlib::prefilter_kept(lib, profiles, B, n_keep, prec, items, n_items, mirror, s, S);
     if (!r) r = tmlib::launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score,
                                     nullptr, nullptr, items, n_items, nullptr, nullptr, compact,
                                     s);
     if (!r && n_rescored) r = tmlib::fill_i32(n_rescored, B, n_items, s);
-    hipError_t e = hipFreeAsync(items, s);
-    if (!r && e != hipSuccess) r = tmlib::hip_fail(e, "hipFreeAsync");
+    if (!scratch) {
+        hipError_t e = hipFreeAsync(items, s);
+        if (!r && e != hipSuccess) r = tmlib::hip_fail(e, "hipFreeAsync");
+    }
     return r;
+}
+
+extern "C" int tm_match_batch(const tm_library* lib, const float* polar, const double* norms,
+                              const float* profiles, int32_t B, const tm_match_opts* opts,
+                              int32_t N, int32_t* top_template, int32_t* top_angle,
+                              float* top_score, float* best_score, int16_t* best_angle,
+                              void* hip_stream) {
+    return tmlib::match_batch_impl(lib, polar, norms, profiles, B, opts, N, top_template,
+                                   top_angle, top_score, best_score, best_angle, hip_stream,
+                                   nullptr, 0);
 }
 
 extern "C" int tm_match_candidates(const tm_library* lib, const float* polar, const double* norms,

@@ -233,10 +233,11 @@ int launch_scores(const tm_library* lib, const float* profiles, int32_t B, int32
 
 int tmlib::prefilter_kept(const tm_library* lib, const float* profiles, int32_t B, int32_t n_keep,
                           int32_t precision, int32_t* items, int32_t n_items, bool mirror,
-                          hipStream_t s) {
-    float* S = nullptr;
-    TM_HIP(hipMallocAsync(reinterpret_cast<void**>(&S),
-                          static_cast<size_t>(B) * lib->T * sizeof(float), s));
+                          hipStream_t s, float* S_given) {
+    float* S = S_given;
+    if (!S)
+        TM_HIP(hipMallocAsync(reinterpret_cast<void**>(&S),
+                              static_cast<size_t>(B) * lib->T * sizeof(float), s));
     int r = launch_scores(lib, profiles, B, precision, S, s);
     if (!r) {
         hipLaunchKernelGGL(select_kept, dim3(B), dim3(kSelThreads), 0, s, S, lib->T, n_keep,
@@ -244,8 +245,10 @@ int tmlib::prefilter_kept(const tm_library* lib, const float* profiles, int32_t 
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) r = tmlib::hip_fail(e, "select_kept launch");
     }
-    hipError_t e = hipFreeAsync(S, s);
-    if (!r && e != hipSuccess) r = tmlib::hip_fail(e, "hipFreeAsync");
+    if (!S_given) {
+        hipError_t e = hipFreeAsync(S, s);
+        if (!r && e != hipSuccess) r = tmlib::hip_fail(e, "hipFreeAsync");
+    }
     return r;
 }
 
