@@ -80,6 +80,8 @@ def parse():
                     help="write all R polar rows (default: only the rows the library touches)")
     ap.add_argument("--no-fft", action="store_true",
                     help="skip the Fourier-route (coarse + certified rescoring) leg")
+    ap.add_argument("--no-bound", action="store_true",
+                    help="skip the exact window-bound search leg")
     ap.add_argument("--no-c2", action="store_true",
                     help="skip the paper-scale FCC leg (run beside the default workload)")
     ap.add_argument("--serving-rows", type=int, default=1024,
@@ -366,6 +368,57 @@ def plain_leg(tm, sc, steps, warmup, cid):
     return {"value": round(B * steps / wall, 1), "ms_per_step": round(wall / steps * 1e3, 4),
             "step_device_ms": step_stats(per_step), "polar_ms": round(polar_ms, 4),
             "match_ms": round(match_ms, 4), "roofline": roof, "top": sc.tops()}
+
+
+def bound_leg(tm, sc, plain_top, steps, warmup, cid):
+    """The exact search with window upper bounds (coarse="bound"): every
+    template bounded over 8 windows of shifts, only templates whose bound
+    reaches the N-th best exact score scored exactly; the top-N equals the
+    exhaustive scan's. Timed like the plain path; the bound kernel alone
+    timed with events on the stream; roofline of the bound kernel against
+    its own work (2 flops per template pixel and coarse shift)."""
+    import torch
+    B, cfg = sc.B, sc.cfg
+    nr = torch.empty((B,), dtype=torch.int32, device=sc.x.device)
+    wall, evs, per_step = time_steps(sc.step_fn(tm, coarse="bound", n_rescored=nr), steps, warmup)
+    top = sc.tops()
+    same = bool(torch.equal(top[0], plain_top[0]) and torch.equal(top[1], plain_top[1])
+                and torch.equal(top[2], plain_top[2]))
+    nrn = nr.cpu().numpy()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    e0.record(sc.stream)
+    for _ in range(reps):
+        ub = tm.bound_scores(sc.lib, sc.polar, sc.norms)
+    e1.record(sc.stream)
+    torch.cuda.synchronize()
+    bound_ms = e0.elapsed_time(e1) / reps
+    del ub
+    match_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    flops = 2.0 * B * sc.info["n_spots"] * 8
+    tf = flops / (bound_ms * 1e-3) / 1e12
+    res = {
+        "value": round(B * steps / wall, 1), "unit": "patterns/s",
+        "ms_per_step": round(wall / steps * 1e3, 4), "step_device_ms": step_stats(per_step),
+        "match_ms": round(match_ms, 4), "bound_kernel_ms": round(bound_ms, 4),
+        "rescore_ms": round(match_ms - bound_ms, 4),
+        "top_n_identical_to_exhaustive_fp32": same,
+        "rescored_per_pattern": {"mean": round(float(nrn.mean()), 2),
+                                 "median": float(np.median(nrn)), "max": int(nrn.max()),
+                                 "full_scan_fraction": round(float(np.mean(nrn == sc.lib.n_total)), 6)},
+        "roofline": {"bound": "alu", "kernel": "bound_kernel", "achieved": round(tf, 3),
+                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tf / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                     "kernel_ms": round(bound_ms, 4),
+                     "work_per_launch": {"flops": flops, "patterns": B,
+                                         "template_pixels": sc.info["n_spots"],
+                                         "coarse_shifts": 8},
+                     "nonpacked_fp32": {"peak": FP32_NONPACKED_TFLOPS,
+                                        "frac": round(tf / FP32_NONPACKED_TFLOPS, 4)}},
+    }
+    say(f"bound search: {res['ms_per_step']:.2f} ms/step (bound kernel {bound_ms:.2f} ms), "
+        f"scored exactly {res['rescored_per_pattern']}, identical top-N {same}")
+    return res
 
 
 def precision_sweep(tm, sc, plain_top, precs, keeps, steps, warmup):
@@ -896,6 +949,7 @@ def main():
         accuracy = orientation_accuracy(tm, cfg, sc.lib, sc.polar, sc.norms, plain_top, B)
         say(f"orientation accuracy: {accuracy}")
 
+    bound = None if a.no_bound else bound_leg(tm, sc, plain_top, a.steps, a.warmup, a.config)
     precs = [p for p in a.precisions.split(",") if p]
     keeps = [float(k) for k in a.keeps.split(",") if k]
     prec = precision_sweep(tm, sc, plain_top, precs, keeps, a.prec_steps, 1) if precs else {}
@@ -944,6 +998,9 @@ def main():
     # the metric's comparison: the float32 path against the BF16 path at
     # the same top-1 (and the other reduced-precision paths beside it)
     comparison = {"fp32_patterns_per_s": value}
+    if bound is not None:
+        comparison["fp32_bound_search_patterns_per_s"] = bound["value"]
+        comparison["fp32_bound_search_same_top_n"] = bound["top_n_identical_to_exhaustive_fp32"]
     for name, p in prec.items():
         comparison[f"{name}_prefilter_patterns_per_s"] = p["value"]
         comparison[f"{name}_keep_fraction"] = p["keep_fraction"]
@@ -990,6 +1047,7 @@ def main():
         "kernel_ms": {"polar_transform": plain["polar_ms"], "match_kernel": plain["match_ms"]},
         "parity_on_sample": parity,
         "fp32_vs_reduced_precision": comparison,
+        "bound_search": bound,
         "precision_paths": prec,
         "fourier_path": fourier,
         "end_to_end": e2e,

@@ -105,7 +105,9 @@ enum {
 /* Coarse scorer and rescoring policy of tm_match_batch. */
 enum {
     TM_COARSE_NONE = 0,            /* no coarse scorer */
-    TM_COARSE_FFT = 1              /* Fourier route along theta (tm_fft_scores) */
+    TM_COARSE_FFT = 1,             /* Fourier route along theta (tm_fft_scores) */
+    TM_COARSE_BOUND = 2            /* window upper bounds (tm_bound_scores): an
+                                      exact search with the plain path's result */
 };
 enum {
     TM_RESCORE_CERTIFIED = 0,      /* rescore every template the coarse scorer's
@@ -128,8 +130,13 @@ enum {
  *   coarse            TM_COARSE_NONE, or TM_COARSE_FFT: score every template
  *                     approximately through the Fourier route (Section 2.2;
  *                     tm_fft_scores; the library needs TM_LIB_FFT), then
- *                     rescore candidates exactly in float32. Exclusive with
- *                     the pre-filter.
+ *                     rescore candidates exactly in float32; or
+ *                     TM_COARSE_BOUND: bound every template's best score
+ *                     from above over windows of shifts (tm_bound_scores)
+ *                     and score exactly every template whose bound reaches
+ *                     the N-th best exact score: the same top-N as the plain
+ *                     path, usually after scoring a small fraction of the
+ *                     library exactly. Exclusive with the pre-filter.
  *   rescore_policy    with a coarse scorer: TM_RESCORE_CERTIFIED (default)
  *                     or TM_RESCORE_KEEP.
  *   rescore_keep      TM_RESCORE_KEEP: fraction of the T' templates rescored
@@ -619,6 +626,32 @@ int tm_preprocess(const void* patterns, tm_dtype dtype, int32_t B, int32_t H, in
 int tm_fft_scores(const tm_library* lib, const float* polar, const double* norms, int32_t B,
                   int32_t compact_rows, float* approx_score, int16_t* approx_angle,
                   void* hip_stream);
+
+/* tm_bound_scores - an upper bound of every template's best Q for every
+ * pattern (an exact-search aid, not part of the paper's procedure: it
+ * lets the certified rescoring skip templates that cannot reach the top-N).
+ *
+ * With non-negative template weights, for the window of win = ceil(n_theta
+ * / 8) consecutive shifts starting at S win (S = 0..7, shifts mod n_theta):
+ *   C(s) = sum_i w_i P[j_i, k_i + s] <= sum_i w_i M[j_i, k_i + S win],
+ *   M[j, x] = max(0, max_{0 <= d < win} P[j, (x + d) mod n_theta]),
+ * and the largest of the 8 window sums bounds max_s Q(b, t, s) of Eq. (1).
+ * The window maxima and weights are rounded up to float16 (scaled), summed
+ * in float32, and the stored bound is widened by the worst-case float32
+ * rounding of both the bound and the plain path's own sum, so that
+ *   bound_out[b, t] >= the float32 Q that tm_match_batch computes.
+ *
+ * Arguments
+ *   lib           loaded library (all weights >= 0; the window image of the
+ *                 touched rows, rows x (n_theta + 7 win) float16, must fit
+ *                 128 KiB of LDS, else TM_EUNSUPPORTED).
+ *   polar, norms  as in tm_match_batch; compact_rows as in tm_fft_scores.
+ *   B             >= 0 (0 is a no-op).
+ *   bound_out     device, [B, T'] float32, written. A pattern with a
+ *                 non-finite norm gets 0 (tm_match_batch flags it).
+ * Errors: TM_EINVAL, TM_EUNSUPPORTED, TM_EHIP, TM_ENODEV. */
+int tm_bound_scores(const tm_library* lib, const float* polar, const double* norms, int32_t B,
+                    int32_t compact_rows, float* bound_out, void* hip_stream);
 
 /* tm_fft_error_bound - a-priori bound eps with |Q~ - Q32| <= eps for every
  * template and shift, where Q~ is tm_fft_scores' arithmetic and Q32 the exact

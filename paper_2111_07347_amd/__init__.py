@@ -31,7 +31,7 @@ TM_U16, TM_F32 = 0, 1
 TM_PREC_FP32, TM_PREC_BF16, TM_PREC_FP16, TM_PREC_FP8 = 0, 1, 2, 3
 TM_LIB_MIRROR, TM_LIB_UNIT_INTENSITY, TM_LIB_KEEP_DIRECT_BEAM, TM_LIB_NO_GROUPING = 1, 2, 4, 8
 TM_LIB_FFT = 16
-TM_COARSE_NONE, TM_COARSE_FFT = 0, 1
+TM_COARSE_NONE, TM_COARSE_FFT, TM_COARSE_BOUND = 0, 1, 2
 TM_RESCORE_CERTIFIED, TM_RESCORE_KEEP = 0, 1
 TM_MAX_N = 64
 TM_LAUE_M3M, TM_LAUE_MMM, TM_LAUE_6MMM = 0, 1, 2
@@ -40,7 +40,7 @@ LAUE_GROUPS = {"m-3m": TM_LAUE_M3M, "mmm": TM_LAUE_MMM, "6/mmm": TM_LAUE_6MMM}
 EXPORTED = ("tm_load_library", "tm_free_library", "tm_library_info", "tm_library_layout",
             "tm_library_rows", "tm_polar_transform", "tm_polar_transform_rows",
             "tm_mask_from_mean", "tm_match_batch", "tm_match_batch_static", "tm_refine_angles", "tm_prefilter", "tm_match_candidates",
-            "tm_fft_scores", "tm_fft_error_bound", "tm_orientations", "tm_ipf_deviation",
+            "tm_fft_scores", "tm_fft_error_bound", "tm_bound_scores", "tm_orientations", "tm_ipf_deviation",
             "tm_simulate_library", "tm_preprocess",
             "tm_topn", "tm_last_error", "tm_version")
 
@@ -91,6 +91,7 @@ def _load():
         "tm_mask_from_mean": [P, ctypes.c_int, I32, I32, I32, D, I32, I32, P, P],
         "tm_match_batch": [P, P, P, P, I32, ctypes.POINTER(_Opts), I32, P, P, P, P, P, P],
         "tm_match_batch_static": [P, P, P, P, I32, ctypes.POINTER(_Opts), I32, P, P, P, P, P, P],
+        "tm_bound_scores": [P, P, P, I32, I32, P, P],
         "tm_prefilter": [P, P, I32, I32, I32, P, P],
         "tm_match_candidates": [P, P, P, I32, P, I32, I32, P, P, P, P],
         "tm_fft_scores": [P, P, P, I32, I32, P, P, P],
@@ -341,7 +342,8 @@ def _layout(lib: "Library", polar) -> int:
                      f"{lib.rows()[0]} touched rows")
 
 
-COARSE = {None: TM_COARSE_NONE, "none": TM_COARSE_NONE, "fft": TM_COARSE_FFT}
+COARSE = {None: TM_COARSE_NONE, "none": TM_COARSE_NONE, "fft": TM_COARSE_FFT,
+          "bound": TM_COARSE_BOUND}
 RESCORE = {"certified": TM_RESCORE_CERTIFIED, "keep": TM_RESCORE_KEEP}
 
 
@@ -577,6 +579,21 @@ def preprocess(patterns, r_box: int = 8, frac: float = 0.5, sigma_min: float = 1
                               _ptr(out), _ptr(centre_out), _stream_ptr(stream)),
            "tm_preprocess")
     return out, centre_out
+
+
+def bound_scores(lib: Library, polar, norms, stream=None):
+    """tm_bound_scores: an upper bound of every template's best Q (at least
+    the float32 score tm_match_batch computes) for every pattern, from
+    window maxima of the polar image. Returns [B, T'] f32."""
+    torch = _torch()
+    B = polar.shape[0]
+    compact = _layout(lib, polar)
+    _require(polar, "polar", torch.float32, (B, polar.shape[1], lib.grid.n_theta))
+    _require(norms, "norms", torch.float64, (B,))
+    out = torch.empty((B, lib.n_total), dtype=torch.float32, device=polar.device)
+    _check(_lib.tm_bound_scores(lib._h, _ptr(polar), _ptr(norms), B, compact, _ptr(out),
+                                _stream_ptr(stream)), "tm_bound_scores")
+    return out
 
 
 def fft_scores(lib: Library, polar, norms, with_angle: bool = True, stream=None):

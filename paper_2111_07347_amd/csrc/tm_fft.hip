@@ -24,10 +24,9 @@
 //                 Q(s + n/2) = A - B for s < n/2, so max(Q(s), Q(s + n/2)) =
 //                 A + |B|. Only the per-template maximum and its shift leave
 //                 the chip.
-//   certify_select  after exact rescoring of the approximate top-N: every
-//                 template whose approximate score could still reach the N-th
-//                 best exact score (within the error bound) becomes a
-//                 candidate for exact rescoring.
+// The certified rescoring that follows (tm_certify.hip) scores exactly every
+// template whose approximate score could still reach the N-th best exact
+// score within the error bound.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -55,7 +54,6 @@ constexpr size_t kInvLdsBudget = 160 * 1024 - 2048;
 // (64 patterns already fill the chip) and multi-GiB stream-ordered
 // allocations made on several streams stalled the host for seconds.
 constexpr double kChatBudget = 2.0 * 1024 * 1024 * 1024;
-constexpr int kSelThreads = 256;
 
 // ---------------------------------------------------------------- host side
 
@@ -479,59 +477,6 @@ fft_inverse(const _Float16* __restrict__ Ch, const _Float16* __restrict__ Wg, in
     }
 }
 
-// Candidates of the certified rescoring, one workgroup per pattern: every
-// t' with Qt[b, t'] >= (N-th best exact score of the rescored approximate
-// top-N) - margin, in ascending order. More than cap: the pattern is marked
-// for a full exact scan instead. Waves own contiguous quarters of the row and
-// compact with ballots (two passes: count, then write).
-__global__ void __launch_bounds__(kSelThreads)
-certify_select(const float* __restrict__ Qt, int Tp, const float* __restrict__ q_exact, int N,
-               double margin, int cap, int32_t* __restrict__ cand, int32_t* __restrict__ cnt,
-               int32_t* __restrict__ full, int32_t* __restrict__ n_rescored) {
-    constexpr int W = kSelThreads / 64;
-    __shared__ int wcount[W];
-    const int b = blockIdx.x;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // threshold rounded toward -inf: a template whose approximate score could
-    // reach the N-th best exact score within the bound is never dropped by
-    // the rounding of the subtraction
-    const double thr_d = static_cast<double>(q_exact[static_cast<size_t>(b) * N + N - 1]) - margin;
-    float thr = static_cast<float>(thr_d);
-    if (static_cast<double>(thr) > thr_d) thr = nextafterf(thr, -INFINITY);
-    const float* row = Qt + static_cast<size_t>(b) * Tp;
-    const int lo = static_cast<int>((static_cast<long long>(Tp) * wave) / W);
-    const int hi = static_cast<int>((static_cast<long long>(Tp) * (wave + 1)) / W);
-    int c = 0;
-    for (int base = lo; base < hi; base += 64) {
-        const int t = base + lane;
-        c += __popcll(tmlib::ballot(t < hi && row[t] >= thr));
-    }
-    if (lane == 0) wcount[wave] = c;
-    __syncthreads();
-    int before = 0, total = 0;
-    for (int w = 0; w < W; ++w) {
-        before += (w < wave) ? wcount[w] : 0;
-        total += wcount[w];
-    }
-    const bool over = total > cap;
-    if (!over) {
-        int32_t* out = cand + static_cast<size_t>(b) * cap;
-        int pos = before;
-        for (int base = lo; base < hi; base += 64) {
-            const int t = base + lane;
-            const bool take = t < hi && row[t] >= thr;
-            const unsigned long long m = tmlib::ballot(take);
-            if (take) out[pos + __popcll(m & ((1ull << lane) - 1))] = t;
-            pos += __popcll(m);
-        }
-    }
-    if (threadIdx.x == 0) {
-        cnt[b] = over ? 0 : total;
-        full[b] = over ? 1 : 0;
-        if (n_rescored) n_rescored[b] = over ? Tp : total;
-    }
-}
-
 __global__ void fill_kernel(int32_t* dst, int64_t n, int32_t value) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = value;
@@ -767,39 +712,9 @@ int tmlib::fft_match(const tm_library* lib, const float* polar, const double* no
         const double frac = keep > 0.0 ? keep : 0.1;
         int32_t cap = static_cast<int32_t>(std::ceil(frac * Tp - 1e-9));
         cap = std::max(N, std::min(cap, Tp));
-        int32_t *t0 = nullptr, *s0 = nullptr, *t1 = nullptr, *s1 = nullptr;
-        float *q0 = nullptr, *q1 = nullptr;
-        int32_t *cand = nullptr, *cnt = nullptr, *full = nullptr;
-        const size_t bn = static_cast<size_t>(B) * N;
-        if (!r) r = alloc_async(&t0, bn, s);
-        if (!r) r = alloc_async(&s0, bn, s);
-        if (!r) r = alloc_async(&q0, bn, s);
-        if (!r) r = alloc_async(&t1, bn, s);
-        if (!r) r = alloc_async(&s1, bn, s);
-        if (!r) r = alloc_async(&q1, bn, s);
-        if (!r) r = alloc_async(&cand, static_cast<size_t>(B) * cap, s);
-        if (!r) r = alloc_async(&cnt, B, s);
-        if (!r) r = alloc_async(&full, B, s);
-        // 1. approximate top-N, rescored exactly: N-th best exact score
-        if (!r) r = tmlib::launch_topn(Qt, nullptr, B, Tp, N, t0, s0, q0, s);
-        if (!r) r = tmlib::launch_match(lib, polar, norms, B, N, t1, s1, q1, nullptr, nullptr, t0,
-                                        N, nullptr, nullptr, compact, s);
-        // 2. every template the bound cannot rule out
-        if (!r) {
-            hipLaunchKernelGGL(certify_select, dim3(B), dim3(kSelThreads), 0, s, Qt, Tp, q1, N,
-                               lib->fft_eps, cap, cand, cnt, full, n_rescored);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) r = tmlib::hip_fail(e, "certify_select launch");
-        }
-        // 3. exact rescoring of the candidates; full scans where the set was too large
-        if (!r) r = tmlib::launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score,
-                                        nullptr, nullptr, cand, cap, cnt, nullptr, compact, s);
-        if (!r) r = tmlib::launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score,
-                                        nullptr, nullptr, nullptr, 0, nullptr, full, compact, s);
-        for (void* p : {static_cast<void*>(t0), static_cast<void*>(s0), static_cast<void*>(q0),
-                        static_cast<void*>(t1), static_cast<void*>(s1), static_cast<void*>(q1),
-                        static_cast<void*>(cand), static_cast<void*>(cnt), static_cast<void*>(full)})
-            if (p) (void)hipFreeAsync(p, s);
+        if (!r) r = tmlib::certified_rescore(lib, polar, norms, B, N, N, Qt, lib->fft_eps, cap,
+                                             n_rescored, top_template, top_angle, top_score,
+                                             compact, s);
     }
     if (Qt) (void)hipFreeAsync(Qt, s);
     return r;

@@ -89,6 +89,32 @@ int fft_match(const tm_library* lib, const float* polar, const double* norms, in
 // Fill a device int32 array with a value. Enqueued on s.
 int fill_i32(int32_t* dst, int64_t n, int32_t value, hipStream_t s);
 
+// Exact float32 top-N from per-template estimates Qt [B, T'] of each
+// template's best exact score, every estimate either within `margin` of it
+// or (margin 0) at least that score (tm_certify.hip): the n_first (N <=
+// n_first <= 64) best estimates are scored exactly, then every template
+// whose estimate reaches the N-th best of those exact scores minus the
+// margin; a pattern with more than `cap` such templates is scored in full.
+// n_rescored (optional, [B]) receives the number of templates scored
+// exactly in the second pass. Enqueued on s.
+int certified_rescore(const tm_library* lib, const float* polar, const double* norms, int32_t B,
+                      int32_t N, int32_t n_first, const float* Qt, double margin, int32_t cap,
+                      int32_t* n_rescored, int32_t* top_template, int32_t* top_angle,
+                      float* top_score, bool compact, hipStream_t s);
+
+// Window upper bounds (tm_bound.hip): library data built at load (only when
+// every template weight is non-negative and the window image fits the LDS
+// budget), its release, the bounds of a batch, and the exact search built
+// on them (certified rescoring with margin 0).
+int bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>>& pix,
+                  const std::vector<int32_t>& row_index, hipStream_t s, size_t& bytes);
+void bound_release(tm_library* L);
+int bound_scores_impl(const tm_library* L, const float* polar, const double* norms, int32_t B,
+                      float* Qt, bool compact, hipStream_t s);
+int bound_match(const tm_library* lib, const float* polar, const double* norms, int32_t B,
+                int32_t N, double cap_frac, int32_t* n_rescored, int32_t* top_template,
+                int32_t* top_angle, float* top_score, bool compact, hipStream_t s);
+
 constexpr int kMaxN = TM_MAX_N;
 constexpr int kWave = 64;
 
@@ -159,6 +185,19 @@ struct tm_library {
                                     // rows = the touched polar rows in order
     uint16_t* d_fft_w = nullptr;    // [2 parities][Sh][Fp + 8] float16 inverse tables (x 2^12)
     double* d_fft_dft = nullptr;    // [n_theta][2] cos, sin of 2 pi m / n_theta
+
+    // window upper bounds (tm_bound.hip)
+    bool bound = false;
+    int32_t bnd_win = 0;        // polar columns per coarse shift window
+    int32_t bnd_shifts = 0;     // coarse shifts (lanes per template)
+    int32_t bnd_L = 0;          // window-image row length (halves) in LDS
+    int32_t bnd_chunks = 0;     // chunks of templates scored together by one wave
+    float bnd_dfac = 1.0f;      // 1 / (1 - gamma_n), rounded up, for the bound's float32 sums
+    uint32_t* d_bnd_recs = nullptr;   // units of 16 steps x 8 slots: LDS half offset | float16
+                                      // weight << 16, blocks of 4 steps per slot
+    int32_t* d_bnd_hdr = nullptr;     // [bnd_chunks * 8][4]: template (-1 none), margin factor
+                                      // bits, first unit after the chunk, 0
+    int32_t* d_bnd_part = nullptr;    // [9 + 17]: chunk ranges of 8 and of 16 waves
 
     // host copies used for validation and info
     std::vector<double> tnorm;      // [Tp]

@@ -174,6 +174,7 @@ void release(tm_library* L) {
     (void)hipFree(L->d_prof);
     (void)hipFree(L->d_prof_max);
     tmlib::fft_release(L);
+    tmlib::bound_release(L);
     delete L;
 }
 
@@ -430,6 +431,7 @@ extern "C" int tm_load_library(const double* kx, const double* ky, const double*
     if (!r) r = upload(&L->d_prof, prof, s, bytes);
     if (!r) r = upload(&L->d_prof_max, prof_max, s, bytes);
     if (!r && (flags & TM_LIB_FFT)) r = tmlib::fft_prepare(L, pix, s, bytes);
+    if (!r) r = tmlib::bound_prepare(L, pix, row_index, s, bytes);
     if (!r) {
         hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) r = tmlib::hip_fail(e, "hipStreamSynchronize");

@@ -427,7 +427,7 @@ int tmlib::match_batch_impl(const tm_library* lib, const float* polar, const dou
         policy = opts->rescore_policy;
         rescore_keep = opts->rescore_keep;
         n_rescored = opts->n_rescored;
-        if (coarse != TM_COARSE_NONE && coarse != TM_COARSE_FFT) { tmlib::set_error("unknown coarse scorer %d", coarse); return TM_EINVAL; }
+        if (coarse != TM_COARSE_NONE && coarse != TM_COARSE_FFT && coarse != TM_COARSE_BOUND) { tmlib::set_error("unknown coarse scorer %d", coarse); return TM_EINVAL; }
         if (policy != TM_RESCORE_CERTIFIED && policy != TM_RESCORE_KEEP) { tmlib::set_error("unknown rescore policy %d", policy); return TM_EINVAL; }
         if (!(rescore_keep >= 0.0 && rescore_keep <= 1.0)) { tmlib::set_error("rescore_keep=%g outside [0, 1]", rescore_keep); return TM_EINVAL; }
         if (coarse == TM_COARSE_FFT) {
@@ -435,6 +435,12 @@ int tmlib::match_batch_impl(const tm_library* lib, const float* polar, const dou
             if (!lib->fft) { tmlib::set_error("TM_COARSE_FFT needs a library loaded with TM_LIB_FFT"); return TM_EINVAL; }
             if (policy == TM_RESCORE_KEEP && !(rescore_keep > 0.0)) { tmlib::set_error("TM_RESCORE_KEEP needs rescore_keep > 0"); return TM_EINVAL; }
             if (best_score) { tmlib::set_error("per-template outputs are not available with a coarse scorer"); return TM_EINVAL; }
+        }
+        if (coarse == TM_COARSE_BOUND) {
+            if (keep > 0.0) { tmlib::set_error("the pre-filter and the coarse scorer are exclusive"); return TM_EINVAL; }
+            if (policy != TM_RESCORE_CERTIFIED) { tmlib::set_error("window bounds support the certified rescoring only"); return TM_EINVAL; }
+            if (best_score) { tmlib::set_error("per-template outputs are not available with a coarse scorer"); return TM_EINVAL; }
+            if (!lib->bound) { tmlib::set_error("window bounds are not available for this library (negative template weights, or a window image over 64k columns x rows)"); return TM_EUNSUPPORTED; }
         }
     }
     const bool mirror = lib->Tp == 2 * lib->T;
@@ -450,6 +456,12 @@ int tmlib::match_batch_impl(const tm_library* lib, const float* polar, const dou
     if (scratch && coarse == TM_COARSE_FFT) {
         tmlib::set_error("the Fourier route needs the spectra of a chunk of patterns as scratch "
                          "(about 2 GiB), more than the static buffer of %zu bytes", scratch_bytes);
+        return TM_EUNSUPPORTED;
+    }
+    if (scratch && coarse == TM_COARSE_BOUND) {
+        tmlib::set_error("the window-bound search needs per-template bounds [B, T'] and candidate "
+                         "lists as stream-ordered scratch; not available with the static buffer "
+                         "of %zu bytes", scratch_bytes);
         return TM_EUNSUPPORTED;
     }
     // scratch layout of the pre-filter: kept lists [B, n_items] int32, then
@@ -473,6 +485,9 @@ int tmlib::match_batch_impl(const tm_library* lib, const float* polar, const dou
     if (coarse == TM_COARSE_FFT)
         return tmlib::fft_match(lib, polar, norms, B, N, policy, rescore_keep, n_rescored,
                                 top_template, top_angle, top_score, compact, s);
+    if (coarse == TM_COARSE_BOUND)
+        return tmlib::bound_match(lib, polar, norms, B, N, rescore_keep, n_rescored, top_template,
+                                  top_angle, top_score, compact, s);
     if (n_keep == 0) {
         int r = tmlib::launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score,
                                     best_score, best_angle, nullptr, 0, nullptr, nullptr, compact,

@@ -1,0 +1,163 @@
+"""GPU: the window upper bounds of every template's best score
+(tm_bound_scores) and the exact search built on them (tm_match_batch with
+coarse = TM_COARSE_BOUND), which must return the plain path's top-N.
+
+The bound's definition: with M[j, x] = max(0, max_{0 <= d < win} P[j, x + d])
+(win = ceil(n_theta / 8), columns mod n_theta) the largest of the 8 window
+sums sum_i w_i M[j_i, k_i + S win] / ||P|| bounds max_s Q(t, s). The tests
+check that every bound is at least the plain path's float32 best score of
+its template, and that it is that window sum (computed here in float64 from
+the same polar image) up to the documented float16 rounding up and float32
+margins. Runs only on an MI355X (marked gpu)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import small_library
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2111_07347_amd as tm
+    return tm
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _setup(tm, cfg, lib_np, idx, **polar_kw):
+    import torch
+    grid = tm.PolarGrid(R=cfg.R, n_theta=cfg.n_theta, cx=cfg.cx, cy=cfg.cy)
+    lib = tm.Library(lib_np["kx"], lib_np["ky"], lib_np["intensity"], lib_np["offsets"],
+                     synth.px_per_inv_A(cfg), grid)
+    imgs = synth.make_patterns(cfg, lib_np, idx)
+    x = torch.from_numpy(np.ascontiguousarray(imgs)).cuda()
+    polar, norms, prof = tm.polar_transform(x, grid, lib=lib, **polar_kw)
+    return lib, grid, imgs, polar, norms
+
+
+def _window_bounds64(P_rows, rows, olib, pn):
+    """float64 window bounds [T'] of one pattern from its compact polar rows."""
+    n = olib.n_theta
+    win = -(-n // 8)
+    R = olib.R
+    P = np.zeros((R, n))
+    P[rows] = P_rows
+    M = np.max(np.stack([np.roll(P, -d, axis=1) for d in range(win)]), axis=0)
+    M = np.maximum(M, 0.0)
+    cols = (olib.K[:, None] + win * np.arange(8)[None, :]) % n
+    vals = M[olib.J[:, None], cols] * (olib.Wt / olib.tnorm[olib.tid])[:, None]
+    ub = np.zeros((olib.n_total, 8))
+    np.add.at(ub, olib.tid, vals)
+    return ub.max(axis=1) / pn
+
+
+@pytest.mark.parametrize("case", ["plain", "gamma_subtract"])
+def test_bounds_hold_and_equal_window_sums(tm, c1, c1_lib, case):
+    kw = {} if case == "plain" else dict(gamma=0.5, subtract=0.05)
+    _say("window bounds c1 B=48", case)
+    lib, grid, imgs, polar, norms = _setup(tm, c1, c1_lib, range(48), **kw)
+    ub = tm.bound_scores(lib, polar, norms).cpu().numpy()
+    tt, ts, tq, bq, bs = (o.cpu().numpy() for o in tm.match_batch(lib, polar, norms, 5,
+                                                                  with_best=True))
+    assert (ub >= bq).all(), float((bq - ub).max())
+    olib = oracle.OracleLibrary.build(c1_lib, synth.px_per_inv_A(c1), c1.R, c1.n_theta)
+    rows = np.unique(olib.J)                 # the touched rows, in compact order
+    assert len(rows) == lib.rows()[0]
+    P32 = polar.cpu().numpy().astype(np.float64)
+    pn = norms.cpu().numpy()
+    A = np.abs(P32).max(axis=(1, 2))
+    wsum = np.zeros(olib.n_total)
+    np.add.at(wsum, olib.tid, olib.Wt / olib.tnorm[olib.tid])
+    cnt = np.bincount(olib.tid, minlength=olib.n_total)
+    gam = cnt * 2.0 ** -24 / (1 - cnt * 2.0 ** -24)
+    for b in range(len(imgs)):
+        u64 = _window_bounds64(P32[b], rows, olib, pn[b])
+        margin = gam * wsum * A[b] / pn[b]
+        # at least the window sum; at most float16 rounding up of the window
+        # maxima and the weights (2^-10 relative each) plus the float32 margins
+        assert (ub[b] >= u64 * (1 - 1e-7)).all()
+        assert (ub[b] <= u64 * (1 + 2.5e-3) + 2.5 * margin + 1e-12).all()
+
+
+def test_bound_search_equals_plain_c1(tm, c1, c1_lib):
+    import torch
+    _say("bound search c1 B=64 (+ a blank and a rolled pattern)")
+    lib, grid, imgs, polar, norms = _setup(tm, c1, c1_lib, range(64))
+    # a blank pattern (zero norm: every template scores 0, scored in full)
+    # and a pattern whose polar image is rolled by one column
+    polar = torch.cat([polar, torch.zeros_like(polar[:1]), torch.roll(polar[3:4], 1, dims=2)])
+    norms = torch.cat([norms, torch.zeros_like(norms[:1]), norms[3:4]])
+    B = polar.shape[0]
+    nr = torch.empty(B, dtype=torch.int32, device="cuda")
+    for N in (1, 5, 17):
+        pt, ps, pq = (o.cpu().numpy() for o in tm.match_batch(lib, polar, norms, N))
+        bt, bs, bq = (o.cpu().numpy() for o in tm.match_batch(lib, polar, norms, N,
+                                                              coarse="bound", n_rescored=nr))
+        assert np.array_equal(bt, pt) and np.array_equal(bs, ps)
+        assert np.array_equal(bq, pq)
+        n = nr.cpu().numpy()
+        assert n[64] == lib.n_total                       # blank: every template
+        assert (n[:64] >= N).all()
+        if N <= 5:
+            # deep ranks (N = 17 of 600 templates) sit among noise-level
+            # scores that many bounds reach: full scans are legitimate there
+            assert np.mean(n[:64] < lib.n_total) >= 0.9
+        _say(f"N={N}: templates scored exactly per pattern: median {np.median(n[:64]):.0f}, "
+             f"max {n[:64].max()} of {lib.n_total}")
+
+
+def test_bound_search_c3_sample(tm):
+    """The 20 000-template orthorhombic library: 256 patterns."""
+    import torch
+    cfg = synth.WORKLOADS[3]
+    lib_np = synth.make_library(cfg)
+    _say("bound search c3 B=256")
+    lib, grid, imgs, polar, norms = _setup(tm, cfg, lib_np, range(0, 256 * 61, 61))
+    nr = torch.empty(256, dtype=torch.int32, device="cuda")
+    pt, ps, pq = (o.cpu().numpy() for o in tm.match_batch(lib, polar, norms, cfg.N))
+    bt, bs, bq = (o.cpu().numpy() for o in tm.match_batch(lib, polar, norms, cfg.N,
+                                                          coarse="bound", n_rescored=nr))
+    assert np.array_equal(bt, pt) and np.array_equal(bs, ps) and np.array_equal(bq, pq)
+    n = nr.cpu().numpy()
+    _say(f"templates scored exactly per pattern: mean {n.mean():.1f}, max {n.max()} of "
+         f"{lib.n_total}")
+    assert np.median(n) < 0.01 * lib.n_total
+
+
+def test_bound_search_refusals(tm, c1, c1_lib):
+    import torch
+    grid = tm.PolarGrid(R=c1.R, n_theta=c1.n_theta, cx=c1.cx, cy=c1.cy)
+    px = synth.px_per_inv_A(c1)
+    neg = small_library(6, seed=3)
+    neg["intensity"][2] = -0.5
+    _say("bound search: negative weights, static entry, with a pre-filter")
+    nlib = tm.Library(neg["kx"], neg["ky"], neg["intensity"], neg["offsets"], px, grid)
+    p = torch.zeros((2, c1.R, c1.n_theta), dtype=torch.float32, device="cuda")
+    nrm = torch.ones(2, dtype=torch.float64, device="cuda")
+    with pytest.raises(tm.TMError) as e:
+        tm.bound_scores(nlib, p, nrm)
+    assert e.value.code == tm.TM_EUNSUPPORTED
+    with pytest.raises(tm.TMError) as e:
+        tm.match_batch(nlib, p, nrm, 3, coarse="bound")
+    assert e.value.code == tm.TM_EUNSUPPORTED
+    lib = tm.Library(c1_lib["kx"], c1_lib["ky"], c1_lib["intensity"], c1_lib["offsets"], px, grid)
+    o = tm._Opts(coarse=tm.TM_COARSE_BOUND)
+    out = torch.empty((2, 5), dtype=torch.int32, device="cuda")
+    r = tm._lib.tm_match_batch_static(lib._h, p.data_ptr(), nrm.data_ptr(), None, 2,
+                                      ctypes.byref(o), 5, out.data_ptr(), out.data_ptr(),
+                                      out.data_ptr(), None, None, None)
+    assert r == tm.TM_EUNSUPPORTED
+    o = tm._Opts(coarse=tm.TM_COARSE_BOUND, prefilter_keep=0.5)
+    r = tm._lib.tm_match_batch(lib._h, p.data_ptr(), nrm.data_ptr(), p.data_ptr(), 2,
+                               ctypes.byref(o), 5, out.data_ptr(), out.data_ptr(), out.data_ptr(),
+                               None, None, None)
+    assert r == tm.TM_EINVAL
