@@ -372,7 +372,7 @@ def plain_leg(tm, sc, steps, warmup, cid):
 
 def bound_leg(tm, sc, plain_top, steps, warmup, cid):
     """The exact search with window upper bounds (coarse="bound"): every
-    template bounded over 8 windows of shifts, only templates whose bound
+    template bounded over 4 windows of shifts, only templates whose bound
     reaches the N-th best exact score scored exactly; the top-N equals the
     exhaustive scan's. Timed like the plain path; the bound kernel alone
     timed with events on the stream; roofline of the bound kernel against
@@ -395,7 +395,7 @@ def bound_leg(tm, sc, plain_top, steps, warmup, cid):
     bound_ms = e0.elapsed_time(e1) / reps
     del ub
     match_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-    flops = 2.0 * B * sc.info["n_spots"] * 8
+    flops = 2.0 * B * sc.info["n_spots"] * 4
     tf = flops / (bound_ms * 1e-3) / 1e12
     res = {
         "value": round(B * steps / wall, 1), "unit": "patterns/s",
@@ -412,7 +412,7 @@ def bound_leg(tm, sc, plain_top, steps, warmup, cid):
                      "kernel_ms": round(bound_ms, 4),
                      "work_per_launch": {"flops": flops, "patterns": B,
                                          "template_pixels": sc.info["n_spots"],
-                                         "coarse_shifts": 8},
+                                         "coarse_shifts": 4},
                      "nonpacked_fp32": {"peak": FP32_NONPACKED_TFLOPS,
                                         "frac": round(tf / FP32_NONPACKED_TFLOPS, 4)}},
     }

@@ -632,10 +632,10 @@ int tm_fft_scores(const tm_library* lib, const float* polar, const double* norms
  * lets the certified rescoring skip templates that cannot reach the top-N).
  *
  * With non-negative template weights, for the window of win = ceil(n_theta
- * / 8) consecutive shifts starting at S win (S = 0..7, shifts mod n_theta):
+ * / 4) consecutive shifts starting at S win (S = 0..3, shifts mod n_theta):
  *   C(s) = sum_i w_i P[j_i, k_i + s] <= sum_i w_i M[j_i, k_i + S win],
  *   M[j, x] = max(0, max_{0 <= d < win} P[j, (x + d) mod n_theta]),
- * and the largest of the 8 window sums bounds max_s Q(b, t, s) of Eq. (1).
+ * and the largest of the 4 window sums bounds max_s Q(b, t, s) of Eq. (1).
  * The window maxima and weights are rounded up to float16 (scaled), summed
  * in float32, and the stored bound is widened by the worst-case float32
  * rounding of both the bound and the plain path's own sum, so that
@@ -643,8 +643,9 @@ int tm_fft_scores(const tm_library* lib, const float* polar, const double* norms
  *
  * Arguments
  *   lib           loaded library (all weights >= 0; the window image of the
- *                 touched rows, rows x (n_theta + 7 win) float16, must fit
- *                 128 KiB of LDS, else TM_EUNSUPPORTED).
+ *                 touched rows, rows x (7 win, or n_theta + 3 win when
+ *                 n_theta is not a multiple of 4) float16, must fit 128 KiB
+ *                 of LDS, else TM_EUNSUPPORTED).
  *   polar, norms  as in tm_match_batch; compact_rows as in tm_fft_scores.
  *   B             >= 0 (0 is a no-op).
  *   bound_out     device, [B, T'] float32, written. A pattern with a

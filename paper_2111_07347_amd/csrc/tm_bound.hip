@@ -32,16 +32,22 @@
 // which is at least the plain path's float32 Q_t of every template.
 //
 // Kernel layout (one workgroup per pattern):
-//   * the window image M of the library's touched rows is built in LDS as
-//     float16 rows of n_theta + (S_n - 1) win columns (the halo makes every
-//     read contiguous: no modulo);
-//   * a wave scores 8 templates at a time, lane = 8 slot + coarse shift S
-//     (8 coarse shifts of win = ceil(n_theta / 8) columns); templates are
-//     sorted by pixel count and their records interleaved per chunk of 8 in
-//     blocks of 4 steps (whole units of 16 steps, zero-weight padding), so
-//     a wave-wide 16-byte load fetches 4 records per slot (128 contiguous
-//     bytes), all slots run the same number of steps, and each unit's
-//     records load one unit of work ahead of their use;
+//   * the window image M of the library's touched rows is built in LDS in
+//     float16. When n_theta = 4 win, each row holds per phase p < win the 7
+//     values M[p + win W] (W = 0..6, columns mod n_theta), so the 4 coarse
+//     shifts of a pixel at column q win + p are the 4 consecutive values
+//     from slot q (8 bytes: few bank conflicts); otherwise rows of
+//     n_theta + 3 win columns are read at k + win S (the halo avoids any
+//     modulo);
+//   * a wave scores 16 templates at a time, lane = 4 slot + coarse shift S
+//     (4 coarse shifts of win = ceil(n_theta / 4) columns); templates are
+//     sorted by pixel count and their records interleaved per chunk of 16 in
+//     blocks of 4 steps (whole units of 8 steps, zero-weight padding), all
+//     slots of a chunk running the same number of steps;
+//   * records reach the wave through LDS: each 512-byte unit is loaded with
+//     distinct addresses by the whole wave (no broadcast loads), written to
+//     one of two LDS buffers a unit ahead of its use and read back by the
+//     slots;
 //   * per record: one LDS read of a float16 window maximum and one mixed
 //     float16 x float16 + float32 multiply-add.
 #include <algorithm>
@@ -54,8 +60,13 @@
 
 namespace {
 
-constexpr int kShifts = 8;                 // coarse shifts per template
+constexpr int kShifts = 4;                 // coarse shifts per template
 constexpr int kSlots = 64 / kShifts;       // templates per wave step
+constexpr int kBlk = 4;                    // steps per block of records (one 16-byte read)
+constexpr int kUnitSteps = 8;              // steps per unit (the stream's granularity)
+constexpr int kUnitBlocks = kUnitSteps / kBlk;
+constexpr int kWslots = 2 * kShifts - 1;   // window values per phase (blocked layout)
+constexpr int kRing = 8;                   // chunks per result flush
 constexpr int kWeightExp = 10;             // float16 weights carry w * 2^10
 constexpr int kImageExp = 14;              // window maxima scaled below 2^14
 constexpr size_t kLdsBudget = 128 * 1024;  // window image (16-bit offsets)
@@ -94,44 +105,71 @@ __device__ __forceinline__ uint16_t f16_up(float x) {
     return b;
 }
 
-// Records of one 16-step unit (4 blocks of 4 steps) of a slot.
-__device__ __forceinline__ void load_unit(u32x4 (&R)[4], const u32x4* rp, int uu) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) R[k] = rp[(static_cast<size_t>(uu) * 4 + k) * kSlots];
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// One unit of records (8 steps x 16 slots, 512 bytes) loaded with distinct addresses:
+// lane l holds bytes 8 l .. 8 l + 7.
+__device__ __forceinline__ u32x2 load_unit(const u32x2* units, int uu, int lane) {
+    return units[static_cast<size_t>(uu) * 64 + lane];
 }
 
-// Sum of weight x window maximum over one unit's 16 records (all LDS reads
-// of the unit in flight before the multiply-adds).
-__device__ __forceinline__ float score_unit(const u32x4 (&R)[4], const uint16_t* mrow, float acc) {
-    float v[16];
+typedef __attribute__((address_space(3))) const uint16_t lds_u16;
+
+// LDS byte address of a record's window value for this lane: the record's
+// 16-bit half offset times 2 plus the lane's base, in one multiply-add of
+// the low 16 bits (v_mad_u32_u16).
+__device__ __forceinline__ uint32_t rec_addr(uint32_t rec, uint32_t lane_base) {
+    uint32_t a;
+    asm("v_mad_u32_u16 %0, %1, 2, %2" : "=v"(a) : "v"(rec), "v"(lane_base));
+    return a;
+}
+
+// Sum of weight x window maximum over one unit's records, read from the
+// wave's LDS copy of the unit (block k of this slot: 16 bytes at
+// (kSlots k + slot) 16; the lanes of a slot read the same bytes), all window
+// reads in flight before the multiply-adds.
+__device__ __forceinline__ float score_unit(const u32x4* buf, int slot, uint32_t lane_base,
+                                            float acc, uint32_t& chunk_done) {
+    u32x4 R[kUnitBlocks];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < kUnitBlocks; ++k) R[k] = buf[k * kSlots + slot];
+    // the last record's weight sign bit marks a chunk's last unit
+    chunk_done = R[kUnitBlocks - 1][kBlk - 1] >> 31;
+    R[kUnitBlocks - 1][kBlk - 1] &= 0x7fffffffu;
+    float v[kUnitSteps];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[4 * k + u] = h2f(mrow[R[k][u] & 0xffffu]);
+    for (int k = 0; k < kUnitBlocks; ++k)
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+        for (int u = 0; u < kBlk; ++u)
+            v[kBlk * k + u] = h2f(*reinterpret_cast<lds_u16*>(
+                static_cast<uintptr_t>(rec_addr(R[k][u], lane_base))));
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc = fmaf(h2f(R[k][u] >> 16), v[4 * k + u], acc);
+    for (int k = 0; k < kUnitBlocks; ++k)
+#pragma unroll
+        for (int u = 0; u < kBlk; ++u) acc = fmaf(h2f(R[k][u] >> 16), v[kBlk * k + u], acc);
     return acc;
 }
 
 template <int NW>
 __global__ void __launch_bounds__(NW * 64)
 bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, int Rs, int n,
-             const int* __restrict__ rows, int n_rows, int Lrow, int win,
-             const uint32_t* __restrict__ recs, const int4* __restrict__ hdr,
-             const int* __restrict__ part, int Tp, float dfac, float* __restrict__ Qt) {
-    extern __shared__ uint16_t m16[];
+             const int* __restrict__ rows, int n_rows, int Lrow, int win, int blocked,
+             const uint32_t* __restrict__ recs, const int* __restrict__ chunk_end,
+             const int* __restrict__ part, int n_chunks, float* __restrict__ raw,
+             float4* __restrict__ pat) {
+    extern __shared__ uint16_t m16[];        // window image
     __shared__ float red[NW];
+    __shared__ u32x4 rbuf[NW][2][kUnitBlocks * kSlots];   // per wave: two units of records
+    __shared__ float res[NW][kRing][kSlots];  // per wave: window maxima of kRing chunks
     const int b = blockIdx.x;
     const int lane = threadIdx.x & 63;
     const int wave = tmlib::uniform(threadIdx.x >> 6);
     const float* src = polar + static_cast<size_t>(b) * Rs * n;
-    float* qrow = Qt + static_cast<size_t>(b) * Tp;
+    float* rrow = raw + static_cast<size_t>(b) * n_chunks * kSlots;
     const double pn = norms[b];
     // a non-finite norm: the exact scorer flags the pattern; bounds are moot
     if ((__double_as_longlong(pn) & 0x7ff0000000000000LL) == 0x7ff0000000000000LL) {
-        for (int t = threadIdx.x; t < Tp; t += NW * 64) qrow[t] = 0.0f;
+        if (threadIdx.x == 0) pat[b] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         return;
     }
     // 1. A = max |P| over the touched rows, and the image scale
@@ -198,20 +236,27 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
                 const int x = x0 + d;
                 if (d < o && x < n) {
                     const uint16_t h = f16_up(out[d] * scale);
-                    dst[x] = h;
-                    if (x + n < Lrow) dst[x + n] = h;
+                    if (blocked) {
+                        // phase p = x mod win, window W0 = x div win, at W0
+                        // and (for W0 < 3) W0 + 4 of the phase's 7 slots
+                        const int W0 = x / win, p = x - W0 * win;
+                        dst[p * kWslots + W0] = h;
+                        if (W0 < kShifts - 1) dst[p * kWslots + W0 + kShifts] = h;
+                    } else {
+                        dst[x] = h;
+                        if (x + n < Lrow) dst[x + n] = h;
+                    }
                 }
             }
         }
     }
     __syncthreads();
-    // 3. bounds, 8 templates per wave step
-    const int slot = lane >> 3;
-    const int S = lane & 7;
-    const uint32_t soff = static_cast<uint32_t>(S * win);
-    // float factors of the stored bound: every operand is non-negative and
-    // each of the five float operations rounds by at most 2^-24, which the
-    // final factor 1 + 2^-19 more than restores (invP, dfac rounded up)
+    // 3. bounds, kSlots templates per wave step
+    const int slot = lane / kShifts;
+    const int S = lane % kShifts;
+    const uint32_t soff = static_cast<uint32_t>(blocked ? S : S * win);
+    // per-pattern factors of the stored bound (bound_finalize): the largest
+    // |P|, the image and weight scale, 1 / ||P|| rounded up
     float invP = 0.0f;
     if (pn > 0.0) {
         const double ip = 1.0 / pn;
@@ -219,47 +264,90 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
         if (static_cast<double>(invP) < ip) invP = nextafterf(invP, INFINITY);
     }
     const float out_scale = 1.0f / (scale * static_cast<float>(1 << kWeightExp));   // power of 2
-    const uint16_t* mrow = m16 + soff;
+    if (threadIdx.x == 0) pat[b] = make_float4(A, out_scale, invP, 1.0f);
+    const uint32_t lane_base =
+        static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_u16*)m16)) + 2u * soff;
     // the wave's chunks [c_begin, c_end) hold about 1/NW of the records; the
     // wave streams their units in order, one accumulator per template
     const int c_begin = part[wave], c_end = part[wave + 1];
     if (c_begin >= c_end) return;
-    const u32x4* rp = reinterpret_cast<const u32x4*>(recs) + slot;
-    int4 h = hdr[c_begin * kSlots + slot];     // template, margin factor, end unit
-    const int u_begin = (c_begin == 0) ? 0 : hdr[(c_begin - 1) * kSlots].z;
-    const int u_end = hdr[(c_end - 1) * kSlots].z;
+    const u32x2* units = reinterpret_cast<const u32x2*>(recs);
+    u32x2* wb0 = reinterpret_cast<u32x2*>(&rbuf[wave][0][0]);
+    u32x2* wb1 = reinterpret_cast<u32x2*>(&rbuf[wave][1][0]);
+    const int u_begin = (c_begin == 0) ? 0 : chunk_end[c_begin - 1];
+    const int u_end = chunk_end[c_end - 1];
     int c = c_begin;
     float acc = 0.0f;
+    // A chunk's last unit carries a flag (bit 31 of every slot's last record,
+    // a weight's sign bit, always 0 otherwise): no memory access in the
+    // stream besides the records. Each chunk's window maxima go to the
+    // wave's LDS ring and leave for memory kRing chunks at a time.
+    int ring0 = c_begin;                        // first chunk held by the ring
+    auto flush = [&]() {
+        for (int i = lane; i < (c - ring0) * kSlots; i += 64)
+            rrow[static_cast<size_t>(ring0) * kSlots + i] = res[wave][i / kSlots][i % kSlots];
+        ring0 = c;
+    };
     auto finish = [&]() {
         float m = acc;
-        m = fmaxf(m, __shfl_xor(m, 1, 64));
-        m = fmaxf(m, __shfl_xor(m, 2, 64));
-        m = fmaxf(m, __shfl_xor(m, 4, 64));
-        if (S == 0 && h.x >= 0)
-            qrow[h.x] = ((m * out_scale) * dfac + __int_as_float(h.y) * A) * invP * (1.0f + 0x1p-19f);
+#pragma unroll
+        for (int x = 1; x < kShifts; x <<= 1) m = fmaxf(m, __shfl_xor(m, x, 64));
+        if (S == 0) res[wave][c - ring0][slot] = m;
         acc = 0.0f;
         ++c;
-        if (c < c_end) h = hdr[c * kSlots + slot];
+        if (c - ring0 == kRing) flush();
     };
-    u32x4 X[4], Y[4];
-    load_unit(X, rp, u_begin);
+    // Records stream through the wave's two LDS unit buffers: each unit is
+    // loaded with distinct addresses two units ahead, written to LDS one unit
+    // ahead, and read back by each slot's lanes (the wave's own LDS
+    // accesses complete in order, so no barrier is needed).
+    const int last = u_end - 1;
+    u32x2 ga = load_unit(units, u_begin, lane);
+    u32x2 gb = load_unit(units, min(u_begin + 1, last), lane);
     __builtin_amdgcn_sched_barrier(0);
-    load_unit(Y, rp, min(u_begin + 1, u_end - 1));
-    __builtin_amdgcn_sched_barrier(0);
-    for (int u = u_begin; u < u_end; u += 2) {
-        // each unit's records load one unit of work ahead of their use (the
-        // last units are loaded again at the end: in bounds, unused)
-        acc = score_unit(X, mrow, acc);
-        if (u + 1 == h.z) finish();
-        load_unit(X, rp, min(u + 2, u_end - 1));
+    wb0[lane] = ga;
+    int u = u_begin;
+    for (; u + 1 < u_end; u += 2) {
+        // buffer 0 holds unit u; gb (in flight) unit u + 1
+        ga = load_unit(units, min(u + 2, last), lane);
         __builtin_amdgcn_sched_barrier(0);
-        if (u + 1 < u_end) {
-            acc = score_unit(Y, mrow, acc);
-            if (u + 2 == h.z) finish();
-        }
-        load_unit(Y, rp, min(u + 3, u_end - 1));
+        wb1[lane] = gb;
+        uint32_t end0;
+        acc = score_unit(&rbuf[wave][0][0], slot, lane_base, acc, end0);
+        if (__builtin_amdgcn_readfirstlane(end0)) finish();
+        // buffer 1 holds unit u + 1; ga (in flight) unit u + 2
+        gb = load_unit(units, min(u + 3, last), lane);
         __builtin_amdgcn_sched_barrier(0);
+        wb0[lane] = ga;
+        uint32_t end1;
+        acc = score_unit(&rbuf[wave][1][0], slot, lane_base, acc, end1);
+        if (__builtin_amdgcn_readfirstlane(end1)) finish();
     }
+    if (u < u_end) {                           // an odd last unit, in buffer 0
+        uint32_t end0;
+        acc = score_unit(&rbuf[wave][0][0], slot, lane_base, acc, end0);
+        if (__builtin_amdgcn_readfirstlane(end0)) finish();
+    }
+    if (c > ring0) flush();
+}
+
+// Bounds in template order: Q^_t = ((m_t out_scale) dfac + c_t A) invP
+// (1 + 2^-19), from each chunk slot's window maximum m_t and the pattern's
+// factors (every operand non-negative; five float roundings of at most
+// 2^-24 each are more than restored by the last factor). A pattern with a
+// non-finite norm gets 0.
+__global__ void __launch_bounds__(256)
+bound_finalize(const float* __restrict__ raw, const float4* __restrict__ pat,
+               const int2* __restrict__ tc, int n_cs, int Tp, float dfac, float* __restrict__ Qt) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int b = blockIdx.y;
+    if (i >= n_cs) return;
+    const int2 e = tc[i];
+    if (e.x < 0) return;
+    const float4 p = pat[b];
+    const float m = raw[static_cast<size_t>(b) * n_cs + i];
+    Qt[static_cast<size_t>(b) * Tp + e.x] =
+        p.w != 0.0f ? ((m * p.y) * dfac + __int_as_float(e.y) * p.x) * p.z * (1.0f + 0x1p-19f) : 0.0f;
 }
 
 }  // namespace
@@ -275,7 +363,13 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
         for (const HostPixel& p : v)
             if (!(p.w >= 0.0)) return TM_OK;           // bounds need non-negative weights
     const int win = (n + kShifts - 1) / kShifts;
-    int Lrow = n + (kShifts - 1) * win;
+    // Window image layout. Blocked (n_theta = 4 win): per row and phase
+    // p < win, 7 slots W holding M[p + win W mod n]; a pixel at column
+    // k = q win + p reads slots q + S for the 4 coarse shifts S: 8
+    // consecutive bytes per template and step, few LDS bank conflicts.
+    // Otherwise rows of n + 3 win columns (a halo past n) read at k + win S.
+    const bool blocked = (n % kShifts) == 0;
+    int Lrow = blocked ? win * kWslots : n + (kShifts - 1) * win;
     Lrow += Lrow & 1;
     const size_t halves = static_cast<size_t>(std::max(L->n_rows, 1)) * Lrow;
     if (halves * 2 > kLdsBudget || halves > 65536) return TM_OK;   // window image too large
@@ -294,7 +388,8 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
             const int k = is_mirror ? (n - p.k) % n : p.k;
             const float w32 = nrm > 0.0 ? static_cast<float>(p.w / nrm) : 0.0f;
             wsum += w32;
-            const uint32_t off = static_cast<uint32_t>(row_index[p.j]) * Lrow + k;
+            const uint32_t off = static_cast<uint32_t>(row_index[p.j]) * Lrow +
+                                 (blocked ? (k % win) * kWslots + k / win : k);
             const uint32_t w16 = half_up(std::ldexp(w32, kWeightExp));
             tr[tt].push_back(off | (w16 << 16));
         }
@@ -308,9 +403,10 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t b) { return cnt[a] > cnt[b]; });
     const int32_t n_chunks = (Tp + kSlots - 1) / kSlots;
-    // header per (chunk, slot): template (-1 none), margin factor bits, first
-    // unit after the chunk
-    std::vector<int32_t> hdr(static_cast<size_t>(n_chunks) * kSlots * 4, 0);
+    // per (chunk, slot): template (-1 none) and margin factor bits; per
+    // chunk: its first unit after it
+    std::vector<int32_t> tc(static_cast<size_t>(n_chunks) * kSlots * 2, 0);
+    std::vector<int32_t> cend(n_chunks, 0);
     std::vector<uint32_t> recs;
     std::vector<int64_t> chunk_end(n_chunks);
     for (int32_t c = 0; c < n_chunks; ++c) {
@@ -321,19 +417,66 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
             tid[sl] = idx < Tp ? order[idx] : -1;
             if (tid[sl] >= 0) m = std::max(m, cnt[tid[sl]]);
         }
-        m = std::max(16, (m + 15) / 16 * 16);                    // whole 16-step units
-        for (int q = 0; q < m; q += 4)
+        m = std::max(kUnitSteps, (m + kUnitSteps - 1) / kUnitSteps * kUnitSteps);   // whole units
+        // per step, one record per slot; in the blocked layout the records of
+        // a step are chosen so that the slots' 16-byte reads fall on distinct
+        // LDS banks where possible (a template's records may come in any
+        // order: the bound's sum and its margin do not depend on it)
+        std::vector<std::vector<uint32_t>> step(m, std::vector<uint32_t>(kSlots, 0u));
+        if (blocked) {
+            std::vector<std::vector<uint32_t>> left(kSlots);
             for (int sl = 0; sl < kSlots; ++sl)
-                for (int i = q; i < q + 4; ++i)
-                    recs.push_back(tid[sl] >= 0 && i < cnt[tid[sl]] ? tr[tid[sl]][i] : 0u);
-        chunk_end[c] = static_cast<int64_t>(recs.size() / (16 * kSlots));
+                if (tid[sl] >= 0) left[sl] = tr[tid[sl]];
+            auto banks = [](uint32_t rec) {          // 32 banks of 4 bytes
+                const uint32_t h0 = rec & 0xffffu;
+                uint32_t mask = 0;
+                for (uint32_t d = h0 / 2; d <= (h0 + kShifts - 1) / 2; ++d) mask |= 1u << (d % 32);
+                return mask;
+            };
+            for (int i = 0; i < m; ++i) {
+                uint32_t used = 0;
+                for (int sl = 0; sl < kSlots; ++sl) {
+                    auto& L_ = left[sl];
+                    if (L_.empty()) {
+                        // padding (weight 0): a read on free banks
+                        uint32_t pad = 0;
+                        for (uint32_t h = 0; h < 64 && h + kShifts <= halves; h += 8)
+                            if (!(banks(h) & used)) { pad = h; break; }
+                        step[i][sl] = pad;
+                        used |= banks(pad);
+                        continue;
+                    }
+                    size_t best = 0;
+                    int best_c = 99;
+                    const size_t lim = std::min<size_t>(L_.size(), 24);
+                    for (size_t e = 0; e < lim && best_c > 0; ++e) {
+                        const int c_ = __builtin_popcount(banks(L_[e]) & used);
+                        if (c_ < best_c) { best_c = c_; best = e; }
+                    }
+                    step[i][sl] = L_[best];
+                    used |= banks(L_[best]);
+                    L_.erase(L_.begin() + static_cast<long>(best));
+                }
+            }
+        } else {
+            for (int i = 0; i < m; ++i)
+                for (int sl = 0; sl < kSlots; ++sl)
+                    step[i][sl] = tid[sl] >= 0 && i < cnt[tid[sl]] ? tr[tid[sl]][i] : 0u;
+        }
+        // the last step's records carry the chunk-end flag (a weight's sign
+        // bit; weights are non-negative)
+        for (int sl = 0; sl < kSlots; ++sl) step[m - 1][sl] |= 0x80000000u;
+        for (int q = 0; q < m; q += kBlk)
+            for (int sl = 0; sl < kSlots; ++sl)
+                for (int i = q; i < q + kBlk; ++i) recs.push_back(step[i][sl]);
+        chunk_end[c] = static_cast<int64_t>(recs.size() / (kUnitSteps * kSlots));
         if (chunk_end[c] > INT32_MAX / 8) return TM_OK;
+        cend[c] = static_cast<int32_t>(chunk_end[c]);
         for (int sl = 0; sl < kSlots; ++sl) {
-            int32_t* hp = &hdr[(static_cast<size_t>(c) * kSlots + sl) * 4];
+            int32_t* hp = &tc[(static_cast<size_t>(c) * kSlots + sl) * 2];
             hp[0] = tid[sl];
             const float cf = tid[sl] >= 0 ? cfac[tid[sl]] : 0.0f;
             std::memcpy(&hp[1], &cf, 4);
-            hp[2] = static_cast<int32_t>(chunk_end[c]);
         }
     }
     // chunk ranges of the waves of an 8-wave and a 16-wave workgroup, each
@@ -363,11 +506,13 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
         return TM_OK;
     };
     if (int r = up(&L->d_bnd_recs, recs)) return r;
-    if (int r = up(&L->d_bnd_hdr, hdr)) return r;
+    if (int r = up(&L->d_bnd_end, cend)) return r;
+    if (int r = up(&L->d_bnd_tc, tc)) return r;
     if (int r = up(&L->d_bnd_part, part)) return r;
     L->bnd_win = win;
     L->bnd_shifts = kShifts;
     L->bnd_L = Lrow;
+    L->bnd_blocked = blocked;
     L->bnd_chunks = n_chunks;
     L->bnd_dfac = static_cast<float>(1.0 / (1.0 - gamma32(nmax)) * (1.0 + 0x1p-22));
     L->bound = true;
@@ -376,10 +521,12 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
 
 void tmlib::bound_release(tm_library* L) {
     (void)hipFree(L->d_bnd_recs);
-    (void)hipFree(L->d_bnd_hdr);
+    (void)hipFree(L->d_bnd_end);
+    (void)hipFree(L->d_bnd_tc);
     (void)hipFree(L->d_bnd_part);
     L->d_bnd_recs = nullptr;
-    L->d_bnd_hdr = nullptr;
+    L->d_bnd_end = nullptr;
+    L->d_bnd_tc = nullptr;
     L->d_bnd_part = nullptr;
     L->bound = false;
 }
@@ -391,19 +538,36 @@ int tmlib::bound_scores_impl(const tm_library* L, const float* polar, const doub
     const size_t lds = static_cast<size_t>(std::max(L->n_rows, 1)) * L->bnd_L * sizeof(uint16_t);
     const int Rs = compact ? L->n_rows : L->R;
     const int* rows = compact ? nullptr : L->d_rows;
+    const int n_cs = L->bnd_chunks * kSlots;
+    // scratch: per pattern the chunk slots' window maxima and four factors
+    float* raw = nullptr;
+    TM_HIP(hipMallocAsync(reinterpret_cast<void**>(&raw),
+                          static_cast<size_t>(B) * n_cs * sizeof(float) + static_cast<size_t>(B) * 16 + 16,
+                          s));
+    // the factors start at the next 16-byte boundary after the maxima
+    const size_t nraw = (static_cast<size_t>(B) * n_cs + 3) / 4 * 4;
+    float4* pat = reinterpret_cast<float4*>(raw + nraw);
     auto launch = [&](auto kern, int nw) -> int {
         TM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    static_cast<int>(lds)));
         hipLaunchKernelGGL(kern, dim3(B), dim3(nw * 64), lds, s, polar, norms, Rs, L->n_theta, rows,
-                           L->n_rows, L->bnd_L, L->bnd_win, L->d_bnd_recs,
-                           reinterpret_cast<const int4*>(L->d_bnd_hdr),
-                           L->d_bnd_part + (nw == 8 ? 0 : 9), L->Tp, L->bnd_dfac, Qt);
+                           L->n_rows, L->bnd_L, L->bnd_win, L->bnd_blocked ? 1 : 0, L->d_bnd_recs,
+                           L->d_bnd_end, L->d_bnd_part + (nw == 8 ? 0 : 9), L->bnd_chunks, raw, pat);
         TM_HIP(hipGetLastError());
         return TM_OK;
     };
     // one workgroup per CU when the image fills the LDS: use every wave slot
-    return lds > 64 * 1024 ? launch(bound_kernel<16>, 16) : launch(bound_kernel<8>, 8);
+    int r = lds > 64 * 1024 ? launch(bound_kernel<16>, 16) : launch(bound_kernel<8>, 8);
+    if (!r) {
+        hipLaunchKernelGGL(bound_finalize, dim3((n_cs + 255) / 256, B), dim3(256), 0, s, raw, pat,
+                           reinterpret_cast<const int2*>(L->d_bnd_tc), n_cs, L->Tp, L->bnd_dfac, Qt);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) r = tmlib::hip_fail(e, "bound_finalize launch");
+    }
+    hipError_t e = hipFreeAsync(raw, s);
+    if (!r && e != hipSuccess) r = tmlib::hip_fail(e, "hipFreeAsync");
+    return r;
 }
 
 int tmlib::bound_match(const tm_library* lib, const float* polar, const double* norms, int32_t B,

@@ -191,12 +191,14 @@ struct tm_library {
     int32_t bnd_win = 0;        // polar columns per coarse shift window
     int32_t bnd_shifts = 0;     // coarse shifts (lanes per template)
     int32_t bnd_L = 0;          // window-image row length (halves) in LDS
+    bool bnd_blocked = false;   // phase-blocked rows (n_theta = 8 win), else halo rows
     int32_t bnd_chunks = 0;     // chunks of templates scored together by one wave
     float bnd_dfac = 1.0f;      // 1 / (1 - gamma_n), rounded up, for the bound's float32 sums
     uint32_t* d_bnd_recs = nullptr;   // units of 16 steps x 8 slots: LDS half offset | float16
                                       // weight << 16, blocks of 4 steps per slot
-    int32_t* d_bnd_hdr = nullptr;     // [bnd_chunks * 8][4]: template (-1 none), margin factor
-                                      // bits, first unit after the chunk, 0
+    int32_t* d_bnd_end = nullptr;     // [bnd_chunks]: first unit after each chunk
+    int32_t* d_bnd_tc = nullptr;      // [bnd_chunks * 8][2]: template (-1 none), margin
+                                      // factor bits
     int32_t* d_bnd_part = nullptr;    // [9 + 17]: chunk ranges of 8 and of 16 waves
 
     // host copies used for validation and info
