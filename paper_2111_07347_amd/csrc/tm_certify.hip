@@ -7,6 +7,7 @@
 // final top-N has an estimate of at least q_N - margin. Those templates are then scored exactly and ranked
 // again; a pattern with more candidates than a cap is scored in full.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 
 #include "tm_device.h"
@@ -69,6 +70,157 @@ certify_select(const float* __restrict__ Qt, int Tp, const float* __restrict__ q
     }
 }
 
+// Split launches of the exact scorer: a pattern with many items (candidates,
+// or every group in a full scan) is cut into tasks of about kChunk* items,
+// each scored by its own workgroup into a partial top-N list, and the lists
+// are merged; the other patterns keep one task that writes its output rows.
+// Split tasks come first, so the longest work starts first.
+constexpr int kPlanThreads = 1024;
+constexpr int kSlotBudget = 16384;       // partial lists per launch
+constexpr int kChunkCand = 512;          // candidate entries per task
+constexpr int kChunkFull = 256;          // groups per task in a full scan
+constexpr int kSplitGrid = 2048;         // workgroups of a split launch
+
+// Exclusive prefix sums over the workgroup of three per-thread counts; also
+// returns the totals. All threads call.
+__device__ int3 block_scan3(int3 v, int3& total) {
+    __shared__ int3 part[kPlanThreads / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int3 inc = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int x = __shfl_up(inc.x, d, 64), y = __shfl_up(inc.y, d, 64),
+                  z = __shfl_up(inc.z, d, 64);
+        if (lane >= d) { inc.x += x; inc.y += y; inc.z += z; }
+    }
+    if (lane == 63) part[wave] = inc;
+    __syncthreads();
+    int3 before = make_int3(0, 0, 0);
+    total = make_int3(0, 0, 0);
+    for (int w = 0; w < kPlanThreads / 64; ++w) {
+        const int3 p = part[w];
+        if (w < wave) { before.x += p.x; before.y += p.y; before.z += p.z; }
+        total.x += p.x; total.y += p.y; total.z += p.z;
+    }
+    __syncthreads();
+    return make_int3(before.x + inc.x - v.x, before.y + inc.y - v.y, before.z + inc.z - v.z);
+}
+
+// Plan one split launch over the patterns with (full[b] != 0) == want_full:
+// pattern b has n_b = cnt[b] items (clamped to [0, n_items]), or n_items
+// when cnt is null. Patterns with more than `chunk` items are split into
+// min(ceil(n_b / chunk), slots / n_split) tasks of near-equal ranges when
+// that is at least 2 (n_split: the patterns over `chunk`); the others get
+// one task. Writes tasks, merges (pattern, first slot, tasks) and meta
+// (task count, merge count, two zeroed counters). One workgroup.
+__global__ void __launch_bounds__(kPlanThreads)
+plan_split(const int32_t* __restrict__ full, int want_full, const int32_t* __restrict__ cnt,
+           int n_items, int B, int chunk, int slots, int4* __restrict__ tasks,
+           int4* __restrict__ merges, int32_t* __restrict__ meta) {
+    __shared__ int n_over;
+    const int per = (B + kPlanThreads - 1) / kPlanThreads;
+    const int b0 = min(B, static_cast<int>(threadIdx.x) * per), b1 = min(B, b0 + per);
+    auto items = [&](int b) { return cnt ? min(max(cnt[b], 0), n_items) : n_items; };
+    auto active = [&](int b) { return (full[b] != 0) == (want_full != 0); };
+    if (threadIdx.x == 0) n_over = 0;
+    __syncthreads();
+    int over = 0;
+    for (int b = b0; b < b1; ++b) over += (active(b) && items(b) > chunk) ? 1 : 0;
+    if (over) atomicAdd(&n_over, over);
+    __syncthreads();
+    const int s_max = n_over > 0 ? slots / n_over : 0;
+    auto splits = [&](int b) {
+        const int n = items(b);
+        return (n > chunk && s_max >= 2) ? min((n + chunk - 1) / chunk, s_max) : 1;
+    };
+    // per thread: split tasks, single tasks, merges
+    int3 c = make_int3(0, 0, 0);
+    for (int b = b0; b < b1; ++b) {
+        if (!active(b)) continue;
+        const int sb = splits(b);
+        if (sb > 1) { c.x += sb; c.z += 1; } else { c.y += 1; }
+    }
+    int3 tot;
+    int3 off = block_scan3(c, tot);
+    for (int b = b0; b < b1; ++b) {
+        if (!active(b)) continue;
+        const int n = items(b), sb = splits(b);
+        if (sb > 1) {
+            merges[off.z++] = make_int4(b, off.x, sb, 0);
+            for (int i = 0; i < sb; ++i) {
+                const int lo = static_cast<int>(static_cast<long long>(n) * i / sb);
+                const int hi = static_cast<int>(static_cast<long long>(n) * (i + 1) / sb);
+                tasks[off.x] = make_int4(b, lo, hi, off.x);
+                ++off.x;
+            }
+        } else {
+            tasks[tot.x + off.y++] = make_int4(b, 0, n, -1);
+        }
+    }
+    if (threadIdx.x == 0) {
+        meta[0] = tot.x + tot.y;
+        meta[1] = tot.z;
+        meta[2] = 0;
+        meta[3] = 0;
+    }
+}
+
+// Merge the partial lists of each split pattern into its output rows (one
+// wave per pattern; ranking as in the scorer: score descending, ties to the
+// lower template index). A pattern with a non-finite norm is flagged as the
+// scorer flags it.
+__global__ void __launch_bounds__(256)
+merge_split(const int4* __restrict__ merges, const int32_t* __restrict__ meta,
+            const double* __restrict__ norms, int N, const int32_t* __restrict__ pt,
+            const int32_t* __restrict__ ps, const float* __restrict__ pq,
+            int32_t* __restrict__ top_t, int32_t* __restrict__ top_s, float* __restrict__ top_q) {
+    const int lane = threadIdx.x & 63;
+    const int n_merge = meta[1];
+    for (int m = (blockIdx.x * 256 + threadIdx.x) >> 6; m < n_merge; m += gridDim.x * 4) {
+        const int4 g = merges[m];
+        int32_t* ot = top_t + static_cast<size_t>(g.x) * N;
+        int32_t* os = top_s + static_cast<size_t>(g.x) * N;
+        float* oq = top_q + static_cast<size_t>(g.x) * N;
+        const double pn = norms[g.x];
+        if ((__double_as_longlong(pn) & 0x7ff0000000000000LL) == 0x7ff0000000000000LL) {
+            for (int i = lane; i < N; i += 64) {
+                ot[i] = -1;
+                os[i] = -1;
+                oq[i] = __int_as_float(0x7fc00000);
+            }
+            continue;
+        }
+        const size_t e0 = static_cast<size_t>(g.y) * N;
+        const int ne = g.z * N;
+        float prev_q = INFINITY;
+        int prev_t = -1;
+        for (int r = 0; r < N; ++r) {
+            float bq = -INFINITY;
+            int bt = INT_MAX, bs = 0;
+            for (int c = lane; c < ne; c += 64) {
+                const float q = pq[e0 + c];
+                const int t = pt[e0 + c];
+                const bool after = (q < prev_q) || (q == prev_q && t > prev_t);
+                const bool better = (q > bq) || (q == bq && t < bt);
+                if (after && better) { bq = q; bt = t; bs = ps[e0 + c]; }
+            }
+#pragma unroll
+            for (int x = 32; x >= 1; x >>= 1) {
+                const float oq2 = __shfl_xor(bq, x, 64);
+                const int ot2 = __shfl_xor(bt, x, 64);
+                const int os2 = __shfl_xor(bs, x, 64);
+                if (oq2 > bq || (oq2 == bq && ot2 < bt)) { bq = oq2; bt = ot2; bs = os2; }
+            }
+            if (lane == 0) {
+                ot[r] = bt;
+                os[r] = bs;
+                oq[r] = bq;
+            }
+            prev_q = bq;
+            prev_t = bt;
+        }
+    }
+}
+
 template <typename T>
 int alloc_async(T** p, size_t count, hipStream_t s) {
     *p = nullptr;
@@ -115,14 +267,45 @@ int tmlib::certified_rescore(const tm_library* lib, const float* polar, const do
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) r = tmlib::hip_fail(e, "certify_select launch");
     }
-    // 3. exact scores of the candidates; full scans where the set was too large
-    if (!r) r = tmlib::launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score,
-                                    nullptr, nullptr, cand, cap, cnt, nullptr, compact, s);
-    if (!r) r = tmlib::launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score,
-                                    nullptr, nullptr, nullptr, 0, nullptr, full, compact, s);
+    // 3. exact scores of the candidates; full scans where the set was too
+    // large. Both passes are split launches: long candidate lists and full
+    // scans are spread over many workgroups.
+    int4 *tasks = nullptr, *merges = nullptr;
+    int32_t *meta = nullptr, *pt = nullptr, *ps = nullptr;
+    float* pq = nullptr;
+    const int slots = kSlotBudget;
+    if (!r) r = alloc_async(&tasks, static_cast<size_t>(B) + slots, s);
+    if (!r) r = alloc_async(&merges, B, s);
+    if (!r) r = alloc_async(&meta, 4, s);
+    if (!r) r = alloc_async(&pt, static_cast<size_t>(slots) * N, s);
+    if (!r) r = alloc_async(&ps, static_cast<size_t>(slots) * N, s);
+    if (!r) r = alloc_async(&pq, static_cast<size_t>(slots) * N, s);
+    const int grid = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(B) + slots, kSplitGrid));
+    const tmlib::SplitWork work{tasks, meta, pt, ps, pq, grid};
+    auto pass = [&](bool want_full) -> int {
+        hipLaunchKernelGGL(plan_split, dim3(1), dim3(kPlanThreads), 0, s, full, want_full ? 1 : 0,
+                           want_full ? nullptr : cnt, want_full ? lib->n_groups : cap, B,
+                           want_full ? kChunkFull : kChunkCand, slots, tasks, merges, meta);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return tmlib::hip_fail(e, "plan_split launch");
+        if (int rr = tmlib::launch_match(lib, polar, norms, B, N, top_template, top_angle, top_score,
+                                         nullptr, nullptr, want_full ? nullptr : cand,
+                                         want_full ? 0 : cap, nullptr, nullptr, compact, s, &work))
+            return rr;
+        const int mgrid = std::max(1, std::min((B + 3) / 4, 256));
+        hipLaunchKernelGGL(merge_split, dim3(mgrid), dim3(256), 0, s, merges, meta, norms, N, pt, ps,
+                           pq, top_template, top_angle, top_score);
+        e = hipGetLastError();
+        if (e != hipSuccess) return tmlib::hip_fail(e, "merge_split launch");
+        return TM_OK;
+    };
+    if (!r) r = pass(false);
+    if (!r) r = pass(true);
     for (void* p : {static_cast<void*>(t0), static_cast<void*>(s0), static_cast<void*>(q0),
                     static_cast<void*>(t1), static_cast<void*>(s1), static_cast<void*>(q1),
-                    static_cast<void*>(cand), static_cast<void*>(cnt), static_cast<void*>(full)})
+                    static_cast<void*>(cand), static_cast<void*>(cnt), static_cast<void*>(full),
+                    static_cast<void*>(tasks), static_cast<void*>(merges), static_cast<void*>(meta),
+                    static_cast<void*>(pt), static_cast<void*>(ps), static_cast<void*>(pq)})
         if (p) (void)hipFreeAsync(p, s);
     return r;
 }

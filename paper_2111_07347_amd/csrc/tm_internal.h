@@ -49,16 +49,33 @@ int match_batch_impl(const tm_library* lib, const float* polar, const double* no
                      float* best_score, int16_t* best_angle, void* hip_stream, void* scratch,
                      size_t scratch_bytes);
 
+// A split launch of the match kernel, planned on the device (tm_certify.hip):
+// workgroups claim tasks in order from a counter; task x = pattern, [y, z) =
+// its range of items (groups, or entries of its candidate row), w = the slot
+// of its partial top-N list (-1: the pattern's own output rows). meta[0]
+// holds the task count and meta[2] the claim counter (zeroed by the
+// planner). grid: workgroups launched.
+struct SplitWork {
+    const int4* tasks;
+    int32_t* meta;
+    int32_t* part_t;
+    int32_t* part_s;
+    float* part_q;
+    int32_t grid;
+};
+
 // Exact rescoring launch of the match kernel (tm_match.hip): all templates
 // (cand == nullptr) or per-pattern candidate lists of up to n_items ids;
 // cand_count (optional, [B]) limits each pattern's list; pat_mask (optional,
 // [B]) skips patterns whose entry is 0; compact: polar holds only the
-// library's touched rows, in order ([B, n_rows, n_theta]). Enqueued on s.
+// library's touched rows, in order ([B, n_rows, n_theta]); split (optional)
+// runs the planned tasks instead of one workgroup per pattern (cand_count,
+// pat_mask and best_* unused). Enqueued on s.
 int launch_match(const tm_library* lib, const float* polar, const double* norms, int32_t B,
                  int32_t N, int32_t* top_template, int32_t* top_angle, float* top_score,
                  float* best_score, int16_t* best_angle, const int32_t* cand, int32_t n_items,
                  const int32_t* cand_count, const int32_t* pat_mask, bool compact,
-                 hipStream_t s);
+                 hipStream_t s, const SplitWork* split = nullptr);
 
 // Top-N over per-template scores [B, T] (tm_topn's kernel); best_angle may be
 // null (angles reported as 0). Enqueued on s.

@@ -167,146 +167,173 @@ match_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
              int N, int* __restrict__ top_t, int* __restrict__ top_s, float* __restrict__ top_q,
              float* __restrict__ best_q, short* __restrict__ best_s,
              const int* __restrict__ cand, const int* __restrict__ cand_cnt,
-             const int* __restrict__ pat_mask) {
+             const int* __restrict__ pat_mask, tmlib::SplitWork split) {
     extern __shared__ float lds[];
+    __shared__ int claimed;
     constexpr int NCLS = NARROW ? K : 1;
-    // patterns masked out are left untouched (the whole workgroup returns)
-    if (pat_mask && pat_mask[blockIdx.x] == 0) return;
-    // candidate mode (G = 1 only): item i of pattern b is template cand[b, i],
-    // whose records are the per-template segments; ids outside [0, Tp) are
-    // skipped; cand_cnt[b] (optional) limits the row to its first entries
-    const int* items = cand ? cand + static_cast<size_t>(blockIdx.x) * n_groups : nullptr;
-    if (cand && cand_cnt) n_groups = min(n_groups, max(0, cand_cnt[blockIdx.x]));
-    const int b = blockIdx.x;
     const int lane = threadIdx.x & 63;
     const int wave = tmlib::uniform(threadIdx.x >> 6);
-    const float* src = polar + static_cast<size_t>(b) * R * n_theta;
     const Rec<G>* rec = reinterpret_cast<const Rec<G>*>(recs);
-
-    auto stage = [&](int band) {
-        const int r0 = band_off[band], r1 = band_off[band + 1];
-        for (int r = r0 + wave; r < r1; r += NW) {
-            const int prow = rows ? rows[r] : r;   // compact polar: row r is touched row r
-            const float* row = src + static_cast<size_t>(prow) * n_theta;
-            float* dst = lds + (r - r0) * row_width;
-            for (int c = lane; c < row_width; c += 64) {
-                int cc = c;
-                while (cc >= n_theta) cc -= n_theta;
-                dst[c] = row[cc];
-            }
-        }
-    };
-
-    const double pn = norms[b];
-    // a polar image holding a non-finite value has a non-finite norm: its
-    // rows are reported as template -1, angle -1, score NaN (and NaN / -1
-    // per template). Tested on the bits, which the device build's
-    // no-NaN assumption cannot fold away.
-    if ((__double_as_longlong(pn) & 0x7ff0000000000000LL) == 0x7ff0000000000000LL) {
-        if (best_q)
-            for (int t = threadIdx.x; t < Tp; t += NW * 64) {
-                best_q[static_cast<size_t>(b) * Tp + t] = __int_as_float(0x7fc00000);
-                best_s[static_cast<size_t>(b) * Tp + t] = -1;
-            }
-        for (int i = threadIdx.x; i < N; i += NW * 64) {
-            top_t[static_cast<size_t>(b) * N + i] = -1;
-            top_s[static_cast<size_t>(b) * N + i] = -1;
-            top_q[static_cast<size_t>(b) * N + i] = __int_as_float(0x7fc00000);
-        }
-        return;
-    }
-    const float invP = pn > 0.0 ? static_cast<float>(1.0 / pn) : 0.0f;
+    const bool write_all = best_q != nullptr;
     // the last slot of lanes past n_theta holds no shift: start it at -inf
     const float lastinit = (64 * (K - 1) + lane < n_theta) ? 0.0f : -INFINITY;
-    const bool write_all = best_q != nullptr;
-    const size_t best_off = static_cast<size_t>(b) * Tp;
-    tmlib::TopState st = tmlib::topn_init();
 
-    if (n_bands == 1) {
-        stage(0);
-        __syncthreads();
-    }
-    for (int c0 = 0; c0 < n_groups; c0 += NW * M) {
-        const int gb = c0 + wave * M;
-        int mem[M][G];
+    // Items [lo, hi) of pattern b (groups, or in candidate mode (G = 1 only)
+    // entries of the pattern's candidate row: item i is template cand[b, i],
+    // whose records are the per-template segments; ids outside [0, Tp) are
+    // skipped), their top-N written to out_*[0, N).
+    auto run = [&](int b, int lo, int hi, int* __restrict__ out_t, int* __restrict__ out_s,
+                   float* __restrict__ out_q) {
+        const int* items = cand ? cand + static_cast<size_t>(b) * n_groups : nullptr;
+        const float* src = polar + static_cast<size_t>(b) * R * n_theta;
+        auto stage = [&](int band) {
+            const int r0 = band_off[band], r1 = band_off[band + 1];
+            for (int r = r0 + wave; r < r1; r += NW) {
+                const int prow = rows ? rows[r] : r;   // compact polar: row r is touched row r
+                const float* row = src + static_cast<size_t>(prow) * n_theta;
+                float* dst = lds + (r - r0) * row_width;
+                for (int c = lane; c < row_width; c += 64) {
+                    int cc = c;
+                    while (cc >= n_theta) cc -= n_theta;
+                    dst[c] = row[cc];
+                }
+            }
+        };
+
+        const double pn = norms[b];
+        // a polar image holding a non-finite value has a non-finite norm: its
+        // rows are reported as template -1, angle -1, score NaN (and NaN / -1
+        // per template). Tested on the bits, which the device build's
+        // no-NaN assumption cannot fold away.
+        if ((__double_as_longlong(pn) & 0x7ff0000000000000LL) == 0x7ff0000000000000LL) {
+            if (best_q)
+                for (int t = threadIdx.x; t < Tp; t += NW * 64) {
+                    best_q[static_cast<size_t>(b) * Tp + t] = __int_as_float(0x7fc00000);
+                    best_s[static_cast<size_t>(b) * Tp + t] = -1;
+                }
+            for (int i = threadIdx.x; i < N; i += NW * 64) {
+                out_t[i] = -1;
+                out_s[i] = -1;
+                out_q[i] = __int_as_float(0x7fc00000);
+            }
+            return;
+        }
+        const float invP = pn > 0.0 ? static_cast<float>(1.0 / pn) : 0.0f;
+        const size_t best_off = static_cast<size_t>(b) * Tp;
+        tmlib::TopState st = tmlib::topn_init();
+
+        if (n_bands == 1) {
+            stage(0);
+            __syncthreads();
+        }
+        for (int c0 = lo; c0 < hi; c0 += NW * M) {
+            const int gb = c0 + wave * M;
+            int mem[M][G];
 #pragma unroll
-        for (int m = 0; m < M; ++m)
+            for (int m = 0; m < M; ++m)
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                int t = -1;
-                if (gb + m < n_groups) {
-                    if (G == 1 && items) {
-                        t = items[gb + m];
-                        t = (t >= 0 && t < Tp) ? t : -1;
-                    } else {
-                        t = members[static_cast<size_t>(gb + m) * G + g];
+                for (int g = 0; g < G; ++g) {
+                    int t = -1;
+                    if (gb + m < hi) {
+                        if (G == 1 && items) {
+                            t = items[gb + m];
+                            t = (t >= 0 && t < Tp) ? t : -1;
+                        } else {
+                            t = members[static_cast<size_t>(gb + m) * G + g];
+                        }
+                    }
+                    mem[m][g] = t;
+                }
+            float acc[M][G][K];
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+#pragma unroll
+                    for (int k = 0; k < K - 1; ++k) acc[m][g][k] = 0.0f;
+                    acc[m][g][K - 1] = lastinit;
+                }
+            for (int band = 0; band < n_bands; ++band) {
+                if (n_bands > 1) {
+                    __syncthreads();
+                    stage(band);
+                    __syncthreads();
+                }
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    const int grp = (G == 1 && items) ? mem[m][0] : (gb + m < hi ? gb + m : -1);
+                    if (grp >= 0) {
+                        const int* sg = seg + (static_cast<size_t>(grp) * n_bands + band) * NCLS;
+                        accumulate_segments<K, G, NARROW, batch_size<K, G, M, NW>()>(
+                            rec, sg, lds, lane, n_theta, acc[m]);
                     }
                 }
-                mem[m][g] = t;
             }
-        float acc[M][G][K];
+            // a template needs the full reduction only if some lane's maximum
+            // can enter the wave's list. One test per group against the
+            // largest lane maximum of its members (absent members hold zeros,
+            // which cannot exceed a real member's maximum unless every score
+            // is <= 0) is a superset of the exact test; ties and members that
+            // fail are sorted out below.
+            float mx[M][G];
+            float gmx = -INFINITY;
 #pragma unroll
-        for (int m = 0; m < M; ++m)
+            for (int m = 0; m < M; ++m)
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-#pragma unroll
-                for (int k = 0; k < K - 1; ++k) acc[m][g][k] = 0.0f;
-                acc[m][g][K - 1] = lastinit;
-            }
-        for (int band = 0; band < n_bands; ++band) {
-            if (n_bands > 1) {
-                __syncthreads();
-                stage(band);
-                __syncthreads();
-            }
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                const int grp = (G == 1 && items) ? mem[m][0] : (gb + m < n_groups ? gb + m : -1);
-                if (grp >= 0) {
-                    const int* sg = seg + (static_cast<size_t>(grp) * n_bands + band) * NCLS;
-                    accumulate_segments<K, G, NARROW, batch_size<K, G, M, NW>()>(rec, sg, lds, lane,
-                                                                               n_theta, acc[m]);
+                for (int g = 0; g < G; ++g) {
+                    mx[m][g] = lane_max<K>(acc[m][g]);
+                    gmx = fmaxf(gmx, mx[m][g]);
                 }
-            }
+            if (!tmlib::ballot(gmx * invP >= st.thr) && !write_all) continue;
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const int t = mem[m][g];
+                    if (t < 0) continue;
+                    const float q = mx[m][g] * invP;
+                    if (!write_all && !tmlib::ballot(tmlib::topn_beats(st, q, t))) continue;
+                    finalize_slow<K>(acc[m][g], mx[m][g], t, lane, invP, N, st, write_all,
+                                     best_q, best_s, best_off);
+                }
         }
-        // a template needs the full reduction only if some lane's maximum
-        // can enter the wave's list. One test per group against the largest
-        // lane maximum of its members (absent members hold zeros, which
-        // cannot exceed a real member's maximum unless every score is <= 0)
-        // is a superset of the exact test; ties and members that fail are
-        // sorted out below.
-        float mx[M][G];
-        float gmx = -INFINITY;
-#pragma unroll
-        for (int m = 0; m < M; ++m)
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                mx[m][g] = lane_max<K>(acc[m][g]);
-                gmx = fmaxf(gmx, mx[m][g]);
-            }
-        if (!tmlib::ballot(gmx * invP >= st.thr) && !write_all) continue;
-#pragma unroll
-        for (int m = 0; m < M; ++m)
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int t = mem[m][g];
-                if (t < 0) continue;
-                const float q = mx[m][g] * invP;
-                if (!write_all && !tmlib::ballot(tmlib::topn_beats(st, q, t))) continue;
-                finalize_slow<K>(acc[m][g], mx[m][g], t, lane, invP, N, st, write_all, best_q,
-                                 best_s, best_off);
-            }
-    }
 
-    __syncthreads();
-    tmlib::topn_merge_write<NW>(st, lds, wave, lane, N, top_t + static_cast<size_t>(b) * N,
-                                    top_s + static_cast<size_t>(b) * N,
-                                    top_q + static_cast<size_t>(b) * N);
+        __syncthreads();
+        tmlib::topn_merge_write<NW>(st, lds, wave, lane, N, out_t, out_s, out_q);
+    };
+
+    if (!split.tasks) {
+        const int b = blockIdx.x;
+        // patterns masked out are left untouched (the whole workgroup returns);
+        // cand_cnt[b] (optional) limits a candidate row to its first entries
+        if (pat_mask && pat_mask[b] == 0) return;
+        const int hi = (cand && cand_cnt) ? min(n_groups, max(0, cand_cnt[b])) : n_groups;
+        run(b, 0, hi, top_t + static_cast<size_t>(b) * N, top_s + static_cast<size_t>(b) * N,
+            top_q + static_cast<size_t>(b) * N);
+        return;
+    }
+    // split launch: claim tasks in order until none is left (every workgroup
+    // ends once the counter passes the task count)
+    const int n_tasks = split.meta[0];
+    for (;;) {
+        __syncthreads();                       // the previous task's LDS use is over
+        if (threadIdx.x == 0) claimed = atomicAdd(&split.meta[2], 1);
+        __syncthreads();
+        const int task = claimed;
+        if (task >= n_tasks) return;
+        const int4 w = split.tasks[task];
+        const size_t o = static_cast<size_t>(w.w >= 0 ? w.w : w.x) * N;
+        int* ot = (w.w >= 0 ? split.part_t : top_t) + o;
+        int* os = (w.w >= 0 ? split.part_s : top_s) + o;
+        float* oq = (w.w >= 0 ? split.part_q : top_q) + o;
+        run(w.x, w.y, w.z, ot, os, oq);
+    }
 }
 
 using MatchFn = void (*)(const float*, const double*, int, int, const int*, const int*, int, int,
                          const uint32_t*, const int*, const int*, int, int, int, int*, int*,
-                         float*, float*, short*, const int*, const int*, const int*);
+                         float*, float*, short*, const int*, const int*, const int*,
+                         tmlib::SplitWork);
 
 // Groups held per wave while rows stream through LDS in bands.
 template <int K, int G>
@@ -362,7 +389,7 @@ int tmlib::launch_match(const tm_library* lib, const float* polar, const double*
                         int32_t N, int32_t* top_template, int32_t* top_angle, float* top_score,
                         float* best_score, int16_t* best_angle, const int32_t* cand,
                         int32_t n_items, const int32_t* cand_count, const int32_t* pat_mask,
-                        bool compact, hipStream_t s) {
+                        bool compact, hipStream_t s, const tmlib::SplitWork* split) {
     const int K = tmlib::slots_for(lib->n_theta);
     const bool multi = lib->n_bands > 1;
     const int G = cand ? 1 : lib->group;
@@ -378,12 +405,13 @@ int tmlib::launch_match(const tm_library* lib, const float* polar, const double*
     const uint32_t* recs = cand ? lib->recs_single() : lib->d_recs;
     const int32_t* seg = cand ? lib->seg_single() : lib->d_seg;
     const int32_t n_groups = cand ? n_items : lib->n_groups;
-    hipLaunchKernelGGL(fn, dim3(B), dim3(nw * 64), lds_bytes, s, polar, norms,
+    const tmlib::SplitWork work = split ? *split : tmlib::SplitWork{};
+    hipLaunchKernelGGL(fn, dim3(split ? split->grid : B), dim3(nw * 64), lds_bytes, s, polar, norms,
                        compact ? lib->n_rows : lib->R, lib->n_theta,
                        compact ? nullptr : lib->d_rows, lib->d_band_off, lib->n_bands, lib->row_width,
                        recs, seg, lib->d_members, n_groups, lib->Tp, N, top_template, top_angle,
                        top_score, best_score, reinterpret_cast<short*>(best_angle), cand,
-                       cand_count, pat_mask);
+                       cand_count, pat_mask, work);
     TM_HIP(hipGetLastError());
     return TM_OK;
 }

@@ -162,3 +162,35 @@ def test_bound_search_refusals(tm, c1, c1_lib):
                                ctypes.byref(o), 5, out.data_ptr(), out.data_ptr(), out.data_ptr(),
                                None, None, None)
     assert r == tm.TM_EINVAL
+
+
+@pytest.mark.parametrize("cap_frac", [0.004, 0.5])
+def test_bound_search_split_passes_c2(tm, cap_frac):
+    """The 4000-template library (1334 groups of 3), 192 patterns plus two
+    blank ones and one with a non-finite norm. A cap of 0.4% of T' sends
+    most patterns to full scans, each cut into several tasks whose partial
+    lists are merged; a cap of 50% lets candidate lists grow past one task.
+    Either way the result is the plain path's, bit for bit."""
+    import torch
+    cfg = synth.WORKLOADS[2]
+    lib_np = synth.make_library(cfg)
+    _say(f"bound search c2 B=195 cap_frac={cap_frac} (split passes)")
+    lib, grid, imgs, polar, norms = _setup(tm, cfg, lib_np, range(0, 192 * 83, 83))
+    polar = torch.cat([polar, torch.zeros_like(polar[:2]), polar[5:6].clone()])
+    norms = torch.cat([norms, torch.zeros_like(norms[:2]), torch.full_like(norms[:1], float("nan"))])
+    polar[-1, 0, 0] = float("nan")
+    B = polar.shape[0]
+    nr = torch.empty(B, dtype=torch.int32, device="cuda")
+    pt, ps, pq = (o.cpu().numpy() for o in tm.match_batch(lib, polar, norms, cfg.N))
+    bt, bs, bq = (o.cpu().numpy() for o in tm.match_batch(lib, polar, norms, cfg.N, coarse="bound",
+                                                          rescore_keep=cap_frac, n_rescored=nr))
+    assert np.array_equal(bt, pt) and np.array_equal(bs, ps)
+    assert np.array_equal(bq.view(np.int32), pq.view(np.int32))
+    assert (pt[-1] == -1).all() and np.isnan(pq[-1]).all()
+    n = nr.cpu().numpy()
+    full = int((n == lib.n_total).sum())
+    _say(f"full scans {full} of {B}; candidates per pattern max {n[n < lib.n_total].max()}")
+    if cap_frac < 0.01:
+        assert full >= B // 2
+    else:
+        assert n[n < lib.n_total].max() > 512
