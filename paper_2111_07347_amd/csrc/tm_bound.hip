@@ -19,37 +19,47 @@
 // exactly, and the result is the plain path's top-N (same float32 sums in
 // the same order, so the same bits).
 //
-// Rigour in finite precision. The bound is evaluated with M scaled by a
-// power of two and rounded up to float16, the weights (times 2^10) rounded
-// up to float16, float32 products (exact) and float32 sums of non-negative
-// terms (relative error at most gamma_n); the plain path's own float32 sum
-// may exceed the exact C(s) by gamma_n sum_i w_i |P_i| <= gamma_n (sum_i
-// w_i) A, A = max |P| over the library's rows. The stored bound is
+// Rigour in finite precision. The plain path's own float32 sum may exceed
+// the exact C(s) by gamma_n sum_i w_i |P_i| <= gamma_n (sum_i w_i) A, A =
+// max |P| over the library's rows, so the bound adds c_t A, c_t =
+// gamma_{n_t} sum_i w_i. The kernel evaluates
 //
-//   Q^_t = ((UB_t / scale) / (1 - gamma_nmax) + gamma_{n_t} (sum w) A)
-//          * (1 / ||P||) * (1 + 2^-20),   rounded up,
+//   U_t = sum_i w^_i M^_i + c^_t A^   (float32 sums of non-negative terms)
 //
-// which is at least the plain path's float32 Q_t of every template.
+// with M and A scaled by a power of two and rounded up to float16 (M^, A^)
+// and the weights and c_t times 2^10 rounded up to float16 (w^, c^); the
+// products are exact and the float32 sum of n_t + 1 terms is within
+// gamma_{n_t + 1} of the exact one. The stored bound is
+//
+//   Q^_t = (U_t / (scale 2^10)) / (1 - gamma_{nmax + 1}) / ||P|| * (1 + 2^-19),
+//
+// rounded up, which is at least the plain path's float32 Q_t of every
+// template.
 //
 // Kernel layout (one workgroup per pattern):
 //   * the window image M of the library's touched rows is built in LDS in
-//     float16. When n_theta = 4 win, each row holds per phase p < win the 7
-//     values M[p + win W] (W = 0..6, columns mod n_theta), so the 4 coarse
-//     shifts of a pixel at column q win + p are the 4 consecutive values
-//     from slot q (8 bytes: few bank conflicts); otherwise rows of
-//     n_theta + 3 win columns are read at k + win S (the halo avoids any
-//     modulo);
-//   * a wave scores 16 templates at a time, lane = 4 slot + coarse shift S
-//     (4 coarse shifts of win = ceil(n_theta / 4) columns); templates are
-//     sorted by pixel count and their records interleaved per chunk of 16 in
-//     blocks of 4 steps (whole units of 8 steps, zero-weight padding), all
-//     slots of a chunk running the same number of steps;
-//   * records reach the wave through LDS: each 512-byte unit is loaded with
-//     distinct addresses by the whole wave (no broadcast loads), written to
-//     one of two LDS buffers a unit ahead of its use and read back by the
-//     slots;
-//   * per record: one LDS read of a float16 window maximum and one mixed
-//     float16 x float16 + float32 multiply-add.
+//     float16, rows of n_theta + 3 win columns (a halo past n_theta), so the
+//     4 coarse shifts of a pixel at column k read columns k + win S without
+//     any modulo;
+//   * a lane scores one template over the 4 coarse shifts S (windows of
+//     win = ceil(n_theta / 4) columns), a wave 64 templates at a time:
+//     templates are sorted by pixel count and cut into chunks of 64, all
+//     lanes of a chunk running the same number of steps (zero-weight
+//     padding to whole units of 4 steps);
+//   * a lane's records come 4 at a time in one 16-byte load (a wave loads
+//     1 KiB of consecutive bytes per unit, 3 units ahead of their use); the
+//     last unit of a chunk carries a flag (the sign bit of its last weights,
+//     cleared before use);
+//   * each template's margin term (below) is one more record: its weight
+//     the margin factor, its window maxima read from an extra image row
+//     that holds the largest |P| (scaled, rounded up) in every column;
+//   * per record: one address multiply-add, 4 LDS reads of a float16 window
+//     maximum and 4 mixed float16 x float16 + float32 multiply-adds; the
+//     library orders each step's records over the lanes so that the reads
+//     of a half-wave fall on distinct LDS banks (or the same dword) where
+//     possible, which sets the kernel's speed: it is bound by LDS reads;
+//   * a chunk's bounds leave as one coalesced 256-byte store, in chunk-slot
+//     order (the library's slot -> template map goes with them).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -61,17 +71,16 @@
 namespace {
 
 constexpr int kShifts = 4;                 // coarse shifts per template
-constexpr int kSlots = 64 / kShifts;       // templates per wave step
-constexpr int kBlk = 4;                    // steps per block of records (one 16-byte read)
-constexpr int kUnitSteps = 8;              // steps per unit (the stream's granularity)
-constexpr int kUnitBlocks = kUnitSteps / kBlk;
-constexpr int kWslots = 2 * kShifts - 1;   // window values per phase (blocked layout)
-constexpr int kRing = 8;                   // chunks per result flush
+constexpr int kLanes = 64;                 // templates per chunk, one per lane
+constexpr int kUnitSteps = 4;              // records per lane and unit (one 16-byte load)
+constexpr int kBanks = 32;                 // LDS banks of 4 bytes, per half-wave
+constexpr int kChoices = 64;               // records tried per lane and step
 constexpr int kWeightExp = 10;             // float16 weights carry w * 2^10
 constexpr int kImageExp = 14;              // window maxima scaled below 2^14
 constexpr size_t kLdsBudget = 128 * 1024;  // window image (16-bit offsets)
 constexpr int kFirst = 32;                 // best bounds scored exactly first
 constexpr int kMaxCols = 12;               // window columns per lane (n_theta <= 768)
+constexpr uint32_t kFlag = 0x80000000u;    // chunk end: sign bit of a unit's last weights
 
 // ---------------------------------------------------------------- host side
 
@@ -92,6 +101,7 @@ uint16_t half_up(float x) {
 // ---------------------------------------------------------------- device side
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) const uint16_t lds_u16;
 
 __device__ __forceinline__ float h2f(uint32_t bits16) {
     return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(bits16)));
@@ -105,71 +115,50 @@ __device__ __forceinline__ uint16_t f16_up(float x) {
     return b;
 }
 
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-
-// One unit of records (8 steps x 16 slots, 512 bytes) loaded with distinct addresses:
-// lane l holds bytes 8 l .. 8 l + 7.
-__device__ __forceinline__ u32x2 load_unit(const u32x2* units, int uu, int lane) {
-    return units[static_cast<size_t>(uu) * 64 + lane];
-}
-
-typedef __attribute__((address_space(3))) const uint16_t lds_u16;
-
-// LDS byte address of a record's window value for this lane: the record's
-// 16-bit half offset times 2 plus the lane's base, in one multiply-add of
-// the low 16 bits (v_mad_u32_u16).
-__device__ __forceinline__ uint32_t rec_addr(uint32_t rec, uint32_t lane_base) {
+// LDS byte address of a record's first window value: the record's 16-bit
+// half offset times 2 plus the image base, in one multiply-add of the low
+// 16 bits (v_mad_u32_u16).
+__device__ __forceinline__ uint32_t rec_addr(uint32_t rec, uint32_t base) {
     uint32_t a;
-    asm("v_mad_u32_u16 %0, %1, 2, %2" : "=v"(a) : "v"(rec), "v"(lane_base));
+    asm("v_mad_u32_u16 %0, %1, 2, %2" : "=v"(a) : "v"(rec), "v"(base));
     return a;
 }
 
-// Sum of weight x window maximum over one unit's records, read from the
-// wave's LDS copy of the unit (block k of this slot: 16 bytes at
-// (kSlots k + slot) 16; the lanes of a slot read the same bytes), all window
-// reads in flight before the multiply-adds.
-__device__ __forceinline__ float score_unit(const u32x4* buf, int slot, uint32_t lane_base,
-                                            float acc, uint32_t& chunk_done) {
-    u32x4 R[kUnitBlocks];
+// One unit of a lane's records (4 steps): the 4 coarse shifts' window
+// maxima of each record (win halves apart), all LDS reads in flight before
+// the multiply-adds.
+__device__ __forceinline__ void score_unit(const u32x4 R, uint32_t base, int win,
+                                           float (&acc)[kShifts]) {
+    float v[kUnitSteps][kShifts];
 #pragma unroll
-    for (int k = 0; k < kUnitBlocks; ++k) R[k] = buf[k * kSlots + slot];
-    // the last record's weight sign bit marks a chunk's last unit
-    chunk_done = R[kUnitBlocks - 1][kBlk - 1] >> 31;
-    R[kUnitBlocks - 1][kBlk - 1] &= 0x7fffffffu;
-    float v[kUnitSteps];
+    for (int u = 0; u < kUnitSteps; ++u) {
+        lds_u16* p = reinterpret_cast<lds_u16*>(static_cast<uintptr_t>(rec_addr(R[u], base)));
 #pragma unroll
-    for (int k = 0; k < kUnitBlocks; ++k)
+        for (int S = 0; S < kShifts; ++S) v[u][S] = h2f(p[S * win]);
+    }
 #pragma unroll
-        for (int u = 0; u < kBlk; ++u)
-            v[kBlk * k + u] = h2f(*reinterpret_cast<lds_u16*>(
-                static_cast<uintptr_t>(rec_addr(R[k][u], lane_base))));
+    for (int u = 0; u < kUnitSteps; ++u)
 #pragma unroll
-    for (int k = 0; k < kUnitBlocks; ++k)
-#pragma unroll
-        for (int u = 0; u < kBlk; ++u) acc = fmaf(h2f(R[k][u] >> 16), v[kBlk * k + u], acc);
-    return acc;
+        for (int S = 0; S < kShifts; ++S) acc[S] = fmaf(h2f(R[u] >> 16), v[u][S], acc[S]);
 }
 
 template <int NW>
 __global__ void __launch_bounds__(NW * 64)
 bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, int Rs, int n,
-             const int* __restrict__ rows, int n_rows, int Lrow, int win, int blocked,
-             const uint32_t* __restrict__ recs, const int* __restrict__ chunk_end,
-             const int* __restrict__ part, int n_chunks, float* __restrict__ raw,
-             float4* __restrict__ pat) {
+             const int* __restrict__ rows, int n_rows, int Lrow, int win,
+             const u32x4* __restrict__ recs, const int* __restrict__ chunk_end,
+             const int* __restrict__ part, int n_cs, float dfac, float* __restrict__ Qc) {
     extern __shared__ uint16_t m16[];        // window image
     __shared__ float red[NW];
-    __shared__ u32x4 rbuf[NW][2][kUnitBlocks * kSlots];   // per wave: two units of records
-    __shared__ float res[NW][kRing][kSlots];  // per wave: window maxima of kRing chunks
     const int b = blockIdx.x;
     const int lane = threadIdx.x & 63;
     const int wave = tmlib::uniform(threadIdx.x >> 6);
     const float* src = polar + static_cast<size_t>(b) * Rs * n;
-    float* rrow = raw + static_cast<size_t>(b) * n_chunks * kSlots;
+    float* qrow = Qc + static_cast<size_t>(b) * n_cs;
     const double pn = norms[b];
-    // a non-finite norm: the exact scorer flags the pattern; bounds are moot
+    // a non-finite norm: the exact scorer flags the pattern; bounds 0
     if ((__double_as_longlong(pn) & 0x7ff0000000000000LL) == 0x7ff0000000000000LL) {
-        if (threadIdx.x == 0) pat[b] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        for (int i = threadIdx.x; i < n_cs; i += NW * 64) qrow[i] = 0.0f;
         return;
     }
     // 1. A = max |P| over the touched rows, and the image scale
@@ -192,7 +181,7 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
     // columns x0 = o l .. x0 + o - 1 of [0, n) from the o + win - 1 values
     // they span: the maximum of the part every window shares, then the
     // head's suffix maxima and the tail's prefix maxima; each column is
-    // stored at x and, inside the halo, at x + n.
+    // stored at x and, inside the halo, at x + n (and x + 2n for n < 6).
     const int o = (n + 63) / 64;                 // columns per lane (<= kMaxCols)
     for (int r = wave; r < n_rows; r += NW) {
         const float* row = src + static_cast<size_t>(rows ? rows[r] : r) * n;
@@ -236,27 +225,24 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
                 const int x = x0 + d;
                 if (d < o && x < n) {
                     const uint16_t h = f16_up(out[d] * scale);
-                    if (blocked) {
-                        // phase p = x mod win, window W0 = x div win, at W0
-                        // and (for W0 < 3) W0 + 4 of the phase's 7 slots
-                        const int W0 = x / win, p = x - W0 * win;
-                        dst[p * kWslots + W0] = h;
-                        if (W0 < kShifts - 1) dst[p * kWslots + W0 + kShifts] = h;
-                    } else {
-                        dst[x] = h;
-                        if (x + n < Lrow) dst[x + n] = h;
-                    }
+                    for (int xx = x; xx < Lrow; xx += n) dst[xx] = h;
                 }
             }
         }
     }
     __syncthreads();
-    // 3. bounds, kSlots templates per wave step
-    const int slot = lane / kShifts;
-    const int S = lane % kShifts;
-    const uint32_t soff = static_cast<uint32_t>(blocked ? S : S * win);
-    // per-pattern factors of the stored bound (bound_finalize): the largest
-    // |P|, the image and weight scale, 1 / ||P|| rounded up
+    // the extra row n_rows: A scaled, rounded up (the margin records' value)
+    {
+        const uint16_t h = f16_up(A * scale);
+        uint16_t* dst = m16 + static_cast<size_t>(n_rows) * Lrow;
+        for (int x = threadIdx.x; x < Lrow; x += NW * 64) dst[x] = h;
+    }
+    __syncthreads();
+    // 3. bounds: per template Q^ = ((m out_scale) dfac) invP (1 + 2^-19), m
+    // the largest of its 4 window sums (margin record included), out_scale
+    // = 1 / (scale 2^10) a power of 2, invP = 1 / ||P|| rounded up (every
+    // operand non-negative; the three roundings are more than restored by
+    // the last factor)
     float invP = 0.0f;
     if (pn > 0.0) {
         const double ip = 1.0 / pn;
@@ -264,90 +250,69 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
         if (static_cast<double>(invP) < ip) invP = nextafterf(invP, INFINITY);
     }
     const float out_scale = 1.0f / (scale * static_cast<float>(1 << kWeightExp));   // power of 2
-    if (threadIdx.x == 0) pat[b] = make_float4(A, out_scale, invP, 1.0f);
-    const uint32_t lane_base =
-        static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_u16*)m16)) + 2u * soff;
-    // the wave's chunks [c_begin, c_end) hold about 1/NW of the records; the
-    // wave streams their units in order, one accumulator per template
+    const uint32_t base = static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_u16*)m16));
+    // the wave's chunks [c_begin, c_end) hold about 1/NW of the units
     const int c_begin = part[wave], c_end = part[wave + 1];
     if (c_begin >= c_end) return;
-    const u32x2* units = reinterpret_cast<const u32x2*>(recs);
-    u32x2* wb0 = reinterpret_cast<u32x2*>(&rbuf[wave][0][0]);
-    u32x2* wb1 = reinterpret_cast<u32x2*>(&rbuf[wave][1][0]);
     const int u_begin = (c_begin == 0) ? 0 : chunk_end[c_begin - 1];
     const int u_end = chunk_end[c_end - 1];
-    int c = c_begin;
-    float acc = 0.0f;
-    // A chunk's last unit carries a flag (bit 31 of every slot's last record,
-    // a weight's sign bit, always 0 otherwise): no memory access in the
-    // stream besides the records. Each chunk's window maxima go to the
-    // wave's LDS ring and leave for memory kRing chunks at a time.
-    int ring0 = c_begin;                        // first chunk held by the ring
-    auto flush = [&]() {
-        for (int i = lane; i < (c - ring0) * kSlots; i += 64)
-            rrow[static_cast<size_t>(ring0) * kSlots + i] = res[wave][i / kSlots][i % kSlots];
-        ring0 = c;
-    };
-    auto finish = [&]() {
-        float m = acc;
-#pragma unroll
-        for (int x = 1; x < kShifts; x <<= 1) m = fmaxf(m, __shfl_xor(m, x, 64));
-        if (S == 0) res[wave][c - ring0][slot] = m;
-        acc = 0.0f;
-        ++c;
-        if (c - ring0 == kRing) flush();
-    };
-    // Records stream through the wave's two LDS unit buffers: each unit is
-    // loaded with distinct addresses two units ahead, written to LDS one unit
-    // ahead, and read back by each slot's lanes (the wave's own LDS
-    // accesses complete in order, so no barrier is needed).
     const int last = u_end - 1;
-    u32x2 ga = load_unit(units, u_begin, lane);
-    u32x2 gb = load_unit(units, min(u_begin + 1, last), lane);
-    __builtin_amdgcn_sched_barrier(0);
-    wb0[lane] = ga;
+    const u32x4* U = recs + lane;
+    int c = c_begin;
+    float acc[kShifts];
+#pragma unroll
+    for (int S = 0; S < kShifts; ++S) acc[S] = 0.0f;
+    auto process = [&](u32x4 R) {
+        const uint32_t flag = __builtin_amdgcn_readfirstlane(R[3]) & kFlag;
+        R[3] &= ~kFlag;
+        score_unit(R, base, win, acc);
+        if (flag) {
+            float m = acc[0];
+#pragma unroll
+            for (int S = 1; S < kShifts; ++S) m = fmaxf(m, acc[S]);
+            qrow[static_cast<size_t>(c) * kLanes + lane] =
+                ((m * out_scale) * dfac) * invP * (1.0f + 0x1p-19f);
+            ++c;
+#pragma unroll
+            for (int S = 0; S < kShifts; ++S) acc[S] = 0.0f;
+        }
+    };
+    // units stream through four registers: each is scored, then reloaded
+    // with the unit 4 places on, so 3 loads are in flight while a unit is
+    // scored (loads past the last unit repeat it and are not used)
+    u32x4 g0 = U[static_cast<size_t>(u_begin) * kLanes];
+    u32x4 g1 = U[static_cast<size_t>(min(u_begin + 1, last)) * kLanes];
+    u32x4 g2 = U[static_cast<size_t>(min(u_begin + 2, last)) * kLanes];
+    u32x4 g3 = U[static_cast<size_t>(min(u_begin + 3, last)) * kLanes];
     int u = u_begin;
-    for (; u + 1 < u_end; u += 2) {
-        // buffer 0 holds unit u; gb (in flight) unit u + 1
-        ga = load_unit(units, min(u + 2, last), lane);
+    for (; u + 4 <= u_end; u += 4) {
+        process(g0);
+        g0 = U[static_cast<size_t>(min(u + 4, last)) * kLanes];
         __builtin_amdgcn_sched_barrier(0);
-        wb1[lane] = gb;
-        uint32_t end0;
-        acc = score_unit(&rbuf[wave][0][0], slot, lane_base, acc, end0);
-        if (__builtin_amdgcn_readfirstlane(end0)) finish();
-        // buffer 1 holds unit u + 1; ga (in flight) unit u + 2
-        gb = load_unit(units, min(u + 3, last), lane);
+        process(g1);
+        g1 = U[static_cast<size_t>(min(u + 5, last)) * kLanes];
         __builtin_amdgcn_sched_barrier(0);
-        wb0[lane] = ga;
-        uint32_t end1;
-        acc = score_unit(&rbuf[wave][1][0], slot, lane_base, acc, end1);
-        if (__builtin_amdgcn_readfirstlane(end1)) finish();
+        process(g2);
+        g2 = U[static_cast<size_t>(min(u + 6, last)) * kLanes];
+        __builtin_amdgcn_sched_barrier(0);
+        process(g3);
+        g3 = U[static_cast<size_t>(min(u + 7, last)) * kLanes];
+        __builtin_amdgcn_sched_barrier(0);
     }
-    if (u < u_end) {                           // an odd last unit, in buffer 0
-        uint32_t end0;
-        acc = score_unit(&rbuf[wave][0][0], slot, lane_base, acc, end0);
-        if (__builtin_amdgcn_readfirstlane(end0)) finish();
-    }
-    if (c > ring0) flush();
+    if (u < u_end) process(g0);
+    if (u + 1 < u_end) process(g1);
+    if (u + 2 < u_end) process(g2);
 }
 
-// Bounds in template order: Q^_t = ((m_t out_scale) dfac + c_t A) invP
-// (1 + 2^-19), from each chunk slot's window maximum m_t and the pattern's
-// factors (every operand non-negative; five float roundings of at most
-// 2^-24 each are more than restored by the last factor). A pattern with a
-// non-finite norm gets 0.
+// Bounds from chunk-slot order to template order.
 __global__ void __launch_bounds__(256)
-bound_finalize(const float* __restrict__ raw, const float4* __restrict__ pat,
-               const int2* __restrict__ tc, int n_cs, int Tp, float dfac, float* __restrict__ Qt) {
+bound_permute(const float* __restrict__ Qc, const int* __restrict__ tid, int n_cs, int Tp,
+              float* __restrict__ Qt) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int b = blockIdx.y;
     if (i >= n_cs) return;
-    const int2 e = tc[i];
-    if (e.x < 0) return;
-    const float4 p = pat[b];
-    const float m = raw[static_cast<size_t>(b) * n_cs + i];
-    Qt[static_cast<size_t>(b) * Tp + e.x] =
-        p.w != 0.0f ? ((m * p.y) * dfac + __int_as_float(e.y) * p.x) * p.z * (1.0f + 0x1p-19f) : 0.0f;
+    const int t = tid[i];
+    if (t >= 0) Qt[static_cast<size_t>(b) * Tp + t] = Qc[static_cast<size_t>(b) * n_cs + i];
 }
 
 }  // namespace
@@ -363,21 +328,19 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
         for (const HostPixel& p : v)
             if (!(p.w >= 0.0)) return TM_OK;           // bounds need non-negative weights
     const int win = (n + kShifts - 1) / kShifts;
-    // Window image layout. Blocked (n_theta = 4 win): per row and phase
-    // p < win, 7 slots W holding M[p + win W mod n]; a pixel at column
-    // k = q win + p reads slots q + S for the 4 coarse shifts S: 8
-    // consecutive bytes per template and step, few LDS bank conflicts.
-    // Otherwise rows of n + 3 win columns (a halo past n) read at k + win S.
-    const bool blocked = (n % kShifts) == 0;
-    int Lrow = blocked ? win * kWslots : n + (kShifts - 1) * win;
+    // window image rows of n + 3 win columns (a halo past n), read at
+    // k + win S for the 4 coarse shifts S
+    const uint32_t sstride = static_cast<uint32_t>(win);
+    int Lrow = n + (kShifts - 1) * win;
     Lrow += Lrow & 1;
-    const size_t halves = static_cast<size_t>(std::max(L->n_rows, 1)) * Lrow;
+    // rows: the touched ones, then one holding A (the margin records' value)
+    const size_t halves = static_cast<size_t>(L->n_rows + 1) * Lrow;
     if (halves * 2 > kLdsBudget || halves > 65536) return TM_OK;   // window image too large
+    const uint32_t a_row = static_cast<uint32_t>(L->n_rows) * Lrow;
 
     // per template: records (offset, float16 weight), pixel count, margin factor
     std::vector<std::vector<uint32_t>> tr(Tp);
     std::vector<int32_t> cnt(Tp, 0);
-    std::vector<float> cfac(Tp, 0.0f);
     int nmax = 0;
     for (int32_t tt = 0; tt < Tp; ++tt) {
         const int32_t t = tt < T ? tt : tt - T;
@@ -389,105 +352,114 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
             const float w32 = nrm > 0.0 ? static_cast<float>(p.w / nrm) : 0.0f;
             wsum += w32;
             const uint32_t off = static_cast<uint32_t>(row_index[p.j]) * Lrow +
-                                 (blocked ? (k % win) * kWslots + k / win : k);
+                                 static_cast<uint32_t>(k);
             const uint32_t w16 = half_up(std::ldexp(w32, kWeightExp));
             tr[tt].push_back(off | (w16 << 16));
         }
         cnt[tt] = static_cast<int32_t>(pix[t].size());
         nmax = std::max(nmax, cnt[tt]);
-        cfac[tt] = static_cast<float>(gamma32(cnt[tt]) * wsum * (1.0 + 0x1p-20));
+        // the margin record: weight c_t 2^10 (rounded up), value A
+        const double cf = gamma32(cnt[tt]) * wsum * (1.0 + 0x1p-20);
+        const uint32_t c16 = half_up(static_cast<float>(std::ldexp(cf, kWeightExp) * (1.0 + 0x1p-20)));
+        tr[tt].push_back(a_row | (c16 << 16));   // one place for all: a broadcast read
+        ++cnt[tt];
     }
-    // chunks of kSlots templates of similar size, records interleaved per step
+    // chunks of 64 templates of similar size
     std::vector<int32_t> order(Tp);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t b) { return cnt[a] > cnt[b]; });
-    const int32_t n_chunks = (Tp + kSlots - 1) / kSlots;
-    // per (chunk, slot): template (-1 none) and margin factor bits; per
-    // chunk: its first unit after it
-    std::vector<int32_t> tc(static_cast<size_t>(n_chunks) * kSlots * 2, 0);
+    const int32_t n_chunks = (Tp + kLanes - 1) / kLanes;
+    std::vector<int32_t> tid(static_cast<size_t>(n_chunks) * kLanes, -1);
     std::vector<int32_t> cend(n_chunks, 0);
     std::vector<uint32_t> recs;
-    std::vector<int64_t> chunk_end(n_chunks);
+    // LDS bank model of the window reads: kBanks banks of 4 bytes, lanes
+    // grouped in half-waves; the dword of a record's read at shift S
+    const int nbanks = kBanks, group = kLanes / 2;
+    auto dword = [&](uint32_t rec, int S) { return ((rec & 0xffffu) + S * sstride) / 2; };
     for (int32_t c = 0; c < n_chunks; ++c) {
         int m = 0;
-        int32_t tid[kSlots];
-        for (int sl = 0; sl < kSlots; ++sl) {
-            const int32_t idx = c * kSlots + sl;
-            tid[sl] = idx < Tp ? order[idx] : -1;
-            if (tid[sl] >= 0) m = std::max(m, cnt[tid[sl]]);
+        for (int l = 0; l < kLanes; ++l) {
+            const int32_t idx = c * kLanes + l;
+            tid[idx] = idx < Tp ? order[idx] : -1;
+            if (tid[idx] >= 0) m = std::max(m, cnt[tid[idx]]);
         }
         m = std::max(kUnitSteps, (m + kUnitSteps - 1) / kUnitSteps * kUnitSteps);   // whole units
-        // per step, one record per slot; in the blocked layout the records of
-        // a step are chosen so that the slots' 16-byte reads fall on distinct
-        // LDS banks where possible (a template's records may come in any
-        // order: the bound's sum and its margin do not depend on it)
-        std::vector<std::vector<uint32_t>> step(m, std::vector<uint32_t>(kSlots, 0u));
-        if (blocked) {
-            std::vector<std::vector<uint32_t>> left(kSlots);
-            for (int sl = 0; sl < kSlots; ++sl)
-                if (tid[sl] >= 0) left[sl] = tr[tid[sl]];
-            auto banks = [](uint32_t rec) {          // 32 banks of 4 bytes
-                const uint32_t h0 = rec & 0xffffu;
-                uint32_t mask = 0;
-                for (uint32_t d = h0 / 2; d <= (h0 + kShifts - 1) / 2; ++d) mask |= 1u << (d % 32);
-                return mask;
-            };
-            for (int i = 0; i < m; ++i) {
-                uint32_t used = 0;
-                for (int sl = 0; sl < kSlots; ++sl) {
-                    auto& L_ = left[sl];
-                    if (L_.empty()) {
-                        // padding (weight 0): a read on free banks
-                        uint32_t pad = 0;
-                        for (uint32_t h = 0; h < 64 && h + kShifts <= halves; h += 8)
-                            if (!(banks(h) & used)) { pad = h; break; }
-                        step[i][sl] = pad;
-                        used |= banks(pad);
-                        continue;
+        // per step one record per lane, chosen so that the lanes of each
+        // half-wave read distinct banks where possible (a template's records
+        // may come in any order: the bound's sum and its margin do not
+        // depend on it); padding (weight 0) reads a free bank of row 0
+        std::vector<std::vector<uint32_t>> left(kLanes);
+        for (int l = 0; l < kLanes; ++l)
+            if (tid[c * kLanes + l] >= 0) left[l] = tr[tid[c * kLanes + l]];
+        std::vector<uint32_t> step(static_cast<size_t>(m) * kLanes, 0u);
+        for (int i = 0; i < m; ++i) {
+            // per shift and bank: the first dword read there and the number
+            // of distinct dwords (a second lane on the same dword is free)
+            std::vector<uint32_t> first(static_cast<size_t>(kShifts) * nbanks);
+            std::vector<uint8_t> ndist(static_cast<size_t>(kShifts) * nbanks);
+            for (int l = 0; l < kLanes; ++l) {
+                if (l % group == 0) std::fill(ndist.begin(), ndist.end(), 0);
+                auto cost = [&](uint32_t rec) {
+                    int k = 0;
+                    for (int S = 0; S < kShifts; ++S) {
+                        const uint32_t d = dword(rec, S);
+                        const size_t ix = static_cast<size_t>(S) * nbanks + d % nbanks;
+                        if (ndist[ix] && first[ix] != d) k += ndist[ix];
                     }
-                    size_t best = 0;
+                    return k;
+                };
+                auto take = [&](uint32_t rec) {
+                    for (int S = 0; S < kShifts; ++S) {
+                        const uint32_t d = dword(rec, S);
+                        const size_t ix = static_cast<size_t>(S) * nbanks + d % nbanks;
+                        if (!ndist[ix]) { first[ix] = d; ndist[ix] = 1; }
+                        else if (first[ix] != d && ndist[ix] < 255) ++ndist[ix];
+                    }
+                    step[static_cast<size_t>(i) * kLanes + l] = rec;
+                };
+                auto& L_ = left[l];
+                if (L_.empty()) {
+                    uint32_t pad = 0;
                     int best_c = 99;
-                    const size_t lim = std::min<size_t>(L_.size(), 24);
-                    for (size_t e = 0; e < lim && best_c > 0; ++e) {
-                        const int c_ = __builtin_popcount(banks(L_[e]) & used);
-                        if (c_ < best_c) { best_c = c_; best = e; }
+                    for (uint32_t h = 0; h < 64 && h + (kShifts - 1) * sstride < static_cast<uint32_t>(Lrow); h += 2) {
+                        const int k = cost(h);
+                        if (k < best_c) { best_c = k; pad = h; }
+                        if (k == 0) break;
                     }
-                    step[i][sl] = L_[best];
-                    used |= banks(L_[best]);
-                    L_.erase(L_.begin() + static_cast<long>(best));
+                    take(pad);
+                    continue;
                 }
+                size_t best = 0;
+                int best_c = 99;
+                const size_t lim = std::min<size_t>(L_.size(), kChoices);
+                for (size_t e = 0; e < lim && best_c > 0; ++e) {
+                    const int k = cost(L_[e]);
+                    if (k < best_c) { best_c = k; best = e; }
+                }
+                take(L_[best]);
+                L_.erase(L_.begin() + static_cast<long>(best));
             }
-        } else {
-            for (int i = 0; i < m; ++i)
-                for (int sl = 0; sl < kSlots; ++sl)
-                    step[i][sl] = tid[sl] >= 0 && i < cnt[tid[sl]] ? tr[tid[sl]][i] : 0u;
         }
-        // the last step's records carry the chunk-end flag (a weight's sign
-        // bit; weights are non-negative)
-        for (int sl = 0; sl < kSlots; ++sl) step[m - 1][sl] |= 0x80000000u;
-        for (int q = 0; q < m; q += kBlk)
-            for (int sl = 0; sl < kSlots; ++sl)
-                for (int i = q; i < q + kBlk; ++i) recs.push_back(step[i][sl]);
-        chunk_end[c] = static_cast<int64_t>(recs.size() / (kUnitSteps * kSlots));
-        if (chunk_end[c] > INT32_MAX / 8) return TM_OK;
-        cend[c] = static_cast<int32_t>(chunk_end[c]);
-        for (int sl = 0; sl < kSlots; ++sl) {
-            int32_t* hp = &tc[(static_cast<size_t>(c) * kSlots + sl) * 2];
-            hp[0] = tid[sl];
-            const float cf = tid[sl] >= 0 ? cfac[tid[sl]] : 0.0f;
-            std::memcpy(&hp[1], &cf, 4);
-        }
+        // the chunk's last records carry the flag (a weight's sign bit)
+        for (int l = 0; l < kLanes; ++l) step[static_cast<size_t>(m - 1) * kLanes + l] |= kFlag;
+        for (int q = 0; q < m; q += kUnitSteps)
+            for (int l = 0; l < kLanes; ++l)
+                for (int i = q; i < q + kUnitSteps; ++i)
+                    recs.push_back(step[static_cast<size_t>(i) * kLanes + l]);
+        const int64_t units = static_cast<int64_t>(recs.size() / (kUnitSteps * kLanes));
+        if (units > INT32_MAX / kLanes) return TM_OK;
+        cend[c] = static_cast<int32_t>(units);
     }
     // chunk ranges of the waves of an 8-wave and a 16-wave workgroup, each
     // about 1/NW of the units (chunks are contiguous per wave)
     std::vector<int32_t> part;
-    const int64_t units = n_chunks ? chunk_end[n_chunks - 1] : 0;
+    const int64_t units = n_chunks ? cend[n_chunks - 1] : 0;
     for (int nw : {8, 16}) {
         for (int w = 0; w <= nw; ++w) {
             const int64_t target = units * w / nw;
             int32_t c = 0;
-            while (c < n_chunks && (c == 0 ? 0 : chunk_end[c - 1]) < target) ++c;
+            while (c < n_chunks && (c == 0 ? 0 : cend[c - 1]) < target) ++c;
             part.push_back(w == nw ? n_chunks : c);
         }
     }
@@ -507,14 +479,13 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
     };
     if (int r = up(&L->d_bnd_recs, recs)) return r;
     if (int r = up(&L->d_bnd_end, cend)) return r;
-    if (int r = up(&L->d_bnd_tc, tc)) return r;
+    if (int r = up(&L->d_bnd_tid, tid)) return r;
     if (int r = up(&L->d_bnd_part, part)) return r;
     L->bnd_win = win;
     L->bnd_shifts = kShifts;
     L->bnd_L = Lrow;
-    L->bnd_blocked = blocked;
     L->bnd_chunks = n_chunks;
-    L->bnd_dfac = static_cast<float>(1.0 / (1.0 - gamma32(nmax)) * (1.0 + 0x1p-22));
+    L->bnd_dfac = static_cast<float>(1.0 / (1.0 - gamma32(nmax + 1)) * (1.0 + 0x1p-22));
     L->bound = true;
     return TM_OK;
 }
@@ -522,11 +493,11 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
 void tmlib::bound_release(tm_library* L) {
     (void)hipFree(L->d_bnd_recs);
     (void)hipFree(L->d_bnd_end);
-    (void)hipFree(L->d_bnd_tc);
+    (void)hipFree(L->d_bnd_tid);
     (void)hipFree(L->d_bnd_part);
     L->d_bnd_recs = nullptr;
     L->d_bnd_end = nullptr;
-    L->d_bnd_tc = nullptr;
+    L->d_bnd_tid = nullptr;
     L->d_bnd_part = nullptr;
     L->bound = false;
 }
@@ -534,39 +505,40 @@ void tmlib::bound_release(tm_library* L) {
 // ------------------------------------------------------------ launches
 
 int tmlib::bound_scores_impl(const tm_library* L, const float* polar, const double* norms,
-                             int32_t B, float* Qt, bool compact, hipStream_t s) {
-    const size_t lds = static_cast<size_t>(std::max(L->n_rows, 1)) * L->bnd_L * sizeof(uint16_t);
+                             int32_t B, float* out, bool template_order, bool compact,
+                             hipStream_t s) {
+    const size_t lds = static_cast<size_t>(L->n_rows + 1) * L->bnd_L * sizeof(uint16_t);
     const int Rs = compact ? L->n_rows : L->R;
     const int* rows = compact ? nullptr : L->d_rows;
-    const int n_cs = L->bnd_chunks * kSlots;
-    // scratch: per pattern the chunk slots' window maxima and four factors
-    float* raw = nullptr;
-    TM_HIP(hipMallocAsync(reinterpret_cast<void**>(&raw),
-                          static_cast<size_t>(B) * n_cs * sizeof(float) + static_cast<size_t>(B) * 16 + 16,
-                          s));
-    // the factors start at the next 16-byte boundary after the maxima
-    const size_t nraw = (static_cast<size_t>(B) * n_cs + 3) / 4 * 4;
-    float4* pat = reinterpret_cast<float4*>(raw + nraw);
+    const int n_cs = L->bnd_chunks * kLanes;
+    float* Qc = out;
+    if (template_order)
+        TM_HIP(hipMallocAsync(reinterpret_cast<void**>(&Qc),
+                              std::max<size_t>(static_cast<size_t>(B) * n_cs, 1) * sizeof(float), s));
     auto launch = [&](auto kern, int nw) -> int {
         TM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    static_cast<int>(lds)));
         hipLaunchKernelGGL(kern, dim3(B), dim3(nw * 64), lds, s, polar, norms, Rs, L->n_theta, rows,
-                           L->n_rows, L->bnd_L, L->bnd_win, L->bnd_blocked ? 1 : 0, L->d_bnd_recs,
-                           L->d_bnd_end, L->d_bnd_part + (nw == 8 ? 0 : 9), L->bnd_chunks, raw, pat);
+                           L->n_rows, L->bnd_L, L->bnd_win,
+                           reinterpret_cast<const u32x4*>(L->d_bnd_recs), L->d_bnd_end,
+                           L->d_bnd_part + (nw == 8 ? 0 : 9), n_cs, L->bnd_dfac, Qc);
         TM_HIP(hipGetLastError());
         return TM_OK;
     };
     // one workgroup per CU when the image fills the LDS: use every wave slot
-    int r = lds > 64 * 1024 ? launch(bound_kernel<16>, 16) : launch(bound_kernel<8>, 8);
-    if (!r) {
-        hipLaunchKernelGGL(bound_finalize, dim3((n_cs + 255) / 256, B), dim3(256), 0, s, raw, pat,
-                           reinterpret_cast<const int2*>(L->d_bnd_tc), n_cs, L->Tp, L->bnd_dfac, Qt);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) r = tmlib::hip_fail(e, "bound_finalize launch");
+    const bool whole = lds > 64 * 1024;
+    int r = whole ? launch(bound_kernel<16>, 16) : launch(bound_kernel<8>, 8);
+    if (template_order) {
+        if (!r) {
+            hipLaunchKernelGGL(bound_permute, dim3((n_cs + 255) / 256, B), dim3(256), 0, s, Qc,
+                               L->d_bnd_tid, n_cs, L->Tp, out);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) r = tmlib::hip_fail(e, "bound_permute launch");
+        }
+        hipError_t e = hipFreeAsync(Qc, s);
+        if (!r && e != hipSuccess) r = tmlib::hip_fail(e, "hipFreeAsync");
     }
-    hipError_t e = hipFreeAsync(raw, s);
-    if (!r && e != hipSuccess) r = tmlib::hip_fail(e, "hipFreeAsync");
     return r;
 }
 
@@ -574,18 +546,19 @@ int tmlib::bound_match(const tm_library* lib, const float* polar, const double* 
                        int32_t N, double cap_frac, int32_t* n_rescored, int32_t* top_template,
                        int32_t* top_angle, float* top_score, bool compact, hipStream_t s) {
     const int Tp = lib->Tp;
-    float* Qt = nullptr;
-    TM_HIP(hipMallocAsync(reinterpret_cast<void**>(&Qt), static_cast<size_t>(B) * Tp * sizeof(float), s));
-    int r = bound_scores_impl(lib, polar, norms, B, Qt, compact, s);
+    const int n_cs = lib->bnd_chunks * kLanes;
+    float* Qc = nullptr;
+    TM_HIP(hipMallocAsync(reinterpret_cast<void**>(&Qc), static_cast<size_t>(B) * n_cs * sizeof(float), s));
+    int r = bound_scores_impl(lib, polar, norms, B, Qc, false, compact, s);
     const double frac = cap_frac > 0.0 ? cap_frac : 0.1;
     int32_t cap = static_cast<int32_t>(std::ceil(frac * Tp - 1e-9));
     cap = std::max(N, std::min(cap, Tp));
     // the bound ranks templates less sharply than the exact score: score the
     // 32 best bounds exactly first, so that the threshold starts high
-    if (!r) r = tmlib::certified_rescore(lib, polar, norms, B, N, std::max(N, kFirst), Qt, 0.0,
-                                         cap, n_rescored, top_template, top_angle, top_score,
-                                         compact, s);
-    hipError_t e = hipFreeAsync(Qt, s);
+    if (!r) r = tmlib::certified_rescore(lib, polar, norms, B, N, std::max(N, kFirst), Qc, n_cs,
+                                         lib->d_bnd_tid, 0.0, cap, n_rescored, top_template,
+                                         top_angle, top_score, compact, s);
+    hipError_t e = hipFreeAsync(Qc, s);
     if (!r && e != hipSuccess) r = tmlib::hip_fail(e, "hipFreeAsync");
     return r;
 }
@@ -610,6 +583,6 @@ extern "C" int tm_bound_scores(const tm_library* lib, const float* polar, const 
         return TM_EINVAL;
     }
     if (int r = tmlib::require_device()) return r;
-    return tmlib::bound_scores_impl(lib, polar, norms, B, bound_out, compact_rows == 1,
+    return tmlib::bound_scores_impl(lib, polar, norms, B, bound_out, true, compact_rows == 1,
                                     static_cast<hipStream_t>(hip_stream));
 }

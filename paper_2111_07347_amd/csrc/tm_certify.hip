@@ -18,14 +18,17 @@ namespace {
 constexpr int kSelThreads = 256;
 
 // Candidates of the certified rescoring, one workgroup per pattern: every
-// t' with Qt[b, t'] >= (N-th best exact score of the rescored approximate
-// top-N) - margin, in ascending order. More than cap: the pattern is marked
-// for a full exact scan instead. Waves own contiguous quarters of the row and
-// compact with ballots (two passes: count, then write).
+// column c with Qt[b, c] >= (N-th best exact score of the rescored
+// approximate top-N) - margin, written as its template (map[c], or c), in
+// ascending column order (columns without a template are skipped). More
+// than cap: the pattern is marked for a full
+// exact scan instead. Waves own contiguous quarters of the row and compact
+// with ballots (two passes: count, then write).
 __global__ void __launch_bounds__(kSelThreads)
-certify_select(const float* __restrict__ Qt, int Tp, const float* __restrict__ q_exact, int N,
-               double margin, int cap, int32_t* __restrict__ cand, int32_t* __restrict__ cnt,
-               int32_t* __restrict__ full, int32_t* __restrict__ n_rescored) {
+certify_select(const float* __restrict__ Qt, int Tp, const int32_t* __restrict__ map,
+               const float* __restrict__ q_exact, int N, double margin, int cap,
+               int32_t* __restrict__ cand, int32_t* __restrict__ cnt, int32_t* __restrict__ full,
+               int32_t* __restrict__ n_rescored, int n_templates) {
     constexpr int W = kSelThreads / 64;
     __shared__ int wcount[W];
     const int b = blockIdx.x;
@@ -42,7 +45,7 @@ certify_select(const float* __restrict__ Qt, int Tp, const float* __restrict__ q
     int c = 0;
     for (int base = lo; base < hi; base += 64) {
         const int t = base + lane;
-        c += __popcll(tmlib::ballot(t < hi && row[t] >= thr));
+        c += __popcll(tmlib::ballot(t < hi && row[t] >= thr && (!map || map[t] >= 0)));
     }
     if (lane == 0) wcount[wave] = c;
     __syncthreads();
@@ -57,16 +60,16 @@ certify_select(const float* __restrict__ Qt, int Tp, const float* __restrict__ q
         int pos = before;
         for (int base = lo; base < hi; base += 64) {
             const int t = base + lane;
-            const bool take = t < hi && row[t] >= thr;
+            const bool take = t < hi && row[t] >= thr && (!map || map[t] >= 0);
             const unsigned long long m = tmlib::ballot(take);
-            if (take) out[pos + __popcll(m & ((1ull << lane) - 1))] = t;
+            if (take) out[pos + __popcll(m & ((1ull << lane) - 1))] = map ? map[t] : t;
             pos += __popcll(m);
         }
     }
     if (threadIdx.x == 0) {
         cnt[b] = over ? 0 : total;
         full[b] = over ? 1 : 0;
-        if (n_rescored) n_rescored[b] = over ? Tp : total;
+        if (n_rescored) n_rescored[b] = over ? n_templates : total;
     }
 }
 
@@ -221,6 +224,13 @@ merge_split(const int4* __restrict__ merges, const int32_t* __restrict__ meta,
     }
 }
 
+// Column indices to templates, in place (-1 stays -1).
+__global__ void __launch_bounds__(256)
+map_columns(int32_t* __restrict__ idx, size_t n, const int32_t* __restrict__ map) {
+    const size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i < n && idx[i] >= 0) idx[i] = map[idx[i]];
+}
+
 template <typename T>
 int alloc_async(T** p, size_t count, hipStream_t s) {
     *p = nullptr;
@@ -236,9 +246,10 @@ int alloc_async(T** p, size_t count, hipStream_t s) {
 }  // namespace
 
 int tmlib::certified_rescore(const tm_library* lib, const float* polar, const double* norms,
-                             int32_t B, int32_t N, int32_t n_first, const float* Qt, double margin,
-                             int32_t cap, int32_t* n_rescored, int32_t* top_template,
-                             int32_t* top_angle, float* top_score, bool compact, hipStream_t s) {
+                             int32_t B, int32_t N, int32_t n_first, const float* Qt,
+                             int32_t n_cols, const int32_t* map, double margin, int32_t cap,
+                             int32_t* n_rescored, int32_t* top_template, int32_t* top_angle,
+                             float* top_score, bool compact, hipStream_t s) {
     const int Tp = lib->Tp;
     n_first = std::max(N, std::min(n_first, std::min(tmlib::kMaxN, Tp)));
     int r = TM_OK;
@@ -257,13 +268,20 @@ int tmlib::certified_rescore(const tm_library* lib, const float* polar, const do
     if (!r) r = alloc_async(&cnt, B, s);
     if (!r) r = alloc_async(&full, B, s);
     // 1. the n_first best estimates, scored exactly: their N-th best, q_N
-    if (!r) r = tmlib::launch_topn(Qt, nullptr, B, Tp, n_first, t0, s0, q0, s);
+    if (!r) r = tmlib::launch_topn(Qt, nullptr, B, n_cols, n_first, t0, s0, q0, s);
+    if (!r && map) {
+        const size_t n = bf;
+        hipLaunchKernelGGL(map_columns, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s,
+                           t0, n, map);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) r = tmlib::hip_fail(e, "map_columns launch");
+    }
     if (!r) r = tmlib::launch_match(lib, polar, norms, B, N, t1, s1, q1, nullptr, nullptr, t0,
                                     n_first, nullptr, nullptr, compact, s);
     // 2. every template whose estimate reaches q_N - margin
     if (!r) {
-        hipLaunchKernelGGL(certify_select, dim3(B), dim3(kSelThreads), 0, s, Qt, Tp, q1, N, margin,
-                           cap, cand, cnt, full, n_rescored);
+        hipLaunchKernelGGL(certify_select, dim3(B), dim3(kSelThreads), 0, s, Qt, n_cols, map, q1, N,
+                           margin, cap, cand, cnt, full, n_rescored, Tp);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) r = tmlib::hip_fail(e, "certify_select launch");
     }

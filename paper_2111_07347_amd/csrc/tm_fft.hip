@@ -712,9 +712,9 @@ int tmlib::fft_match(const tm_library* lib, const float* polar, const double* no
         const double frac = keep > 0.0 ? keep : 0.1;
         int32_t cap = static_cast<int32_t>(std::ceil(frac * Tp - 1e-9));
         cap = std::max(N, std::min(cap, Tp));
-        if (!r) r = tmlib::certified_rescore(lib, polar, norms, B, N, N, Qt, lib->fft_eps, cap,
-                                             n_rescored, top_template, top_angle, top_score,
-                                             compact, s);
+        if (!r) r = tmlib::certified_rescore(lib, polar, norms, B, N, N, Qt, Tp, nullptr,
+                                             lib->fft_eps, cap, n_rescored, top_template,
+                                             top_angle, top_score, compact, s);
     }
     if (Qt) (void)hipFreeAsync(Qt, s);
     return r;

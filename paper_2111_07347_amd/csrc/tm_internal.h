@@ -114,10 +114,14 @@ int fill_i32(int32_t* dst, int64_t n, int32_t value, hipStream_t s);
 // margin; a pattern with more than `cap` such templates is scored in full.
 // n_rescored (optional, [B]) receives the number of templates scored
 // exactly in the second pass. Enqueued on s.
+// With map (optional) the estimates come in another column order: Qt is
+// [B, n_cols] and column c holds template map[c] (-1: no template, estimate
+// -inf); without it n_cols = T'.
 int certified_rescore(const tm_library* lib, const float* polar, const double* norms, int32_t B,
-                      int32_t N, int32_t n_first, const float* Qt, double margin, int32_t cap,
-                      int32_t* n_rescored, int32_t* top_template, int32_t* top_angle,
-                      float* top_score, bool compact, hipStream_t s);
+                      int32_t N, int32_t n_first, const float* Qt, int32_t n_cols,
+                      const int32_t* map, double margin, int32_t cap, int32_t* n_rescored,
+                      int32_t* top_template, int32_t* top_angle, float* top_score, bool compact,
+                      hipStream_t s);
 
 // Window upper bounds (tm_bound.hip): library data built at load (only when
 // every template weight is non-negative and the window image fits the LDS
@@ -126,8 +130,11 @@ int certified_rescore(const tm_library* lib, const float* polar, const double* n
 int bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>>& pix,
                   const std::vector<int32_t>& row_index, hipStream_t s, size_t& bytes);
 void bound_release(tm_library* L);
+// Bounds in chunk-slot order (Qc [B, bnd_chunks * 64], -inf for empty
+// slots; d_bnd_tid maps slots to templates) or, with template_order, in
+// template order (Qt [B, T']).
 int bound_scores_impl(const tm_library* L, const float* polar, const double* norms, int32_t B,
-                      float* Qt, bool compact, hipStream_t s);
+                      float* out, bool template_order, bool compact, hipStream_t s);
 int bound_match(const tm_library* lib, const float* polar, const double* norms, int32_t B,
                 int32_t N, double cap_frac, int32_t* n_rescored, int32_t* top_template,
                 int32_t* top_angle, float* top_score, bool compact, hipStream_t s);
@@ -206,16 +213,15 @@ struct tm_library {
     // window upper bounds (tm_bound.hip)
     bool bound = false;
     int32_t bnd_win = 0;        // polar columns per coarse shift window
-    int32_t bnd_shifts = 0;     // coarse shifts (lanes per template)
+    int32_t bnd_shifts = 0;     // coarse shifts per template
     int32_t bnd_L = 0;          // window-image row length (halves) in LDS
-    bool bnd_blocked = false;   // phase-blocked rows (n_theta = 8 win), else halo rows
-    int32_t bnd_chunks = 0;     // chunks of templates scored together by one wave
+    int32_t bnd_chunks = 0;     // chunks of 64 templates (one per lane) scored by one wave
     float bnd_dfac = 1.0f;      // 1 / (1 - gamma_n), rounded up, for the bound's float32 sums
-    uint32_t* d_bnd_recs = nullptr;   // units of 16 steps x 8 slots: LDS half offset | float16
-                                      // weight << 16, blocks of 4 steps per slot
+    uint32_t* d_bnd_recs = nullptr;   // units of 4 steps x 64 lanes: LDS half offset | float16
+                                      // weight << 16, 16 bytes per lane
     int32_t* d_bnd_end = nullptr;     // [bnd_chunks]: first unit after each chunk
-    int32_t* d_bnd_tc = nullptr;      // [bnd_chunks * 8][2]: template (-1 none), margin
-                                      // factor bits
+    int32_t* d_bnd_tid = nullptr;     // [bnd_chunks * 64]: template of each chunk slot, -1 none
+    float* d_bnd_cfac = nullptr;      // [bnd_chunks * 64]: margin factor, -1 for no template
     int32_t* d_bnd_part = nullptr;    // [9 + 17]: chunk ranges of 8 and of 16 waves
 
     // host copies used for validation and info
