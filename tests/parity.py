@@ -38,18 +38,25 @@ class PatternRef:
     """FP64 oracle results for one pattern (full per-template table)."""
 
     def __init__(self, P64: np.ndarray, olib: "oracle.OracleLibrary", pnorm: float | None = None,
-                 templates=None):
+                 templates=None, best=None, arg=None):
+        """best, arg (optional): the oracle's match_exact64 of the whole
+        library for this pattern, computed elsewhere (oracle_best_pool)."""
         self.P = P64
         self.olib = olib
         self.pnorm = oracle.norm64(P64) if pnorm is None else pnorm
         lib = olib if templates is None else olib.subset(templates)
         self.ids = np.arange(olib.n_total) if templates is None else np.asarray(templates)
-        self.Q = oracle.scores64(P64, lib, self.pnorm) if lib.n_total <= 6000 else None
-        if self.Q is not None:
-            self.best = self.Q.max(axis=1)
-            self.arg = self.Q.argmax(axis=1)
+        if best is not None:
+            assert templates is None
+            self.Q = None
+            self.best, self.arg = np.asarray(best), np.asarray(arg)
         else:
-            self.best, self.arg = oracle.match_exact64(P64, lib, self.pnorm)
+            self.Q = oracle.scores64(P64, lib, self.pnorm) if lib.n_total <= 6000 else None
+            if self.Q is not None:
+                self.best = self.Q.max(axis=1)
+                self.arg = self.Q.argmax(axis=1)
+            else:
+                self.best, self.arg = oracle.match_exact64(P64, lib, self.pnorm)
         self.order = np.lexsort((self.ids, -self.best))
         self._pos = {int(t): i for i, t in enumerate(self.ids)}
 
@@ -102,3 +109,35 @@ def check_topn(ref: PatternRef, gt, gs, gq, margin: float, tight: bool = True):
             if am > need:
                 assert int(gs[r]) == int(ref.arg[i]), f"rank {r}: gpu angle {gs[r]} oracle {ref.arg[i]}"
     return exact
+
+
+# ------------------------------------------------------------------ oracle pool
+# The oracle's exact search over tens of thousands of templates takes half a
+# minute or more per pattern on one core; full-size parity tests spread the
+# sampled patterns over worker processes (spawned: no GPU state is shared).
+# Each worker builds the workload's oracle library once.
+
+_POOL = {}
+
+
+def _pool_init(cid):
+    import synth
+    cfg = synth.WORKLOADS[cid]
+    lib_np = synth.make_library(cfg)
+    _POOL["cfg"] = cfg
+    _POOL["olib"] = oracle.OracleLibrary.build(lib_np, synth.px_per_inv_A(cfg), cfg.R, cfg.n_theta)
+
+
+def _pool_best(img):
+    cfg, olib = _POOL["cfg"], _POOL["olib"]
+    P = oracle.polar64(np.asarray(img, dtype=np.float64), cfg.R, cfg.n_theta)
+    return oracle.match_exact64(P, olib, oracle.norm64(P))
+
+
+def oracle_best_pool(cid, imgs, workers=16):
+    """(best, arg) of oracle.match_exact64 for each image of workload cid."""
+    import multiprocessing
+    ctx = multiprocessing.get_context("spawn")
+    with ctx.Pool(max(1, min(workers, len(imgs))), initializer=_pool_init,
+                  initargs=(cid,)) as pool:
+        return pool.map(_pool_best, [np.asarray(im) for im in imgs], chunksize=1)

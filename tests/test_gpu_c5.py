@@ -1,13 +1,13 @@
 """GPU parity on the large multi-phase library (50 000 templates: FCC, HCP,
 orthorhombic; 100 000 with mirrors; uint16 Poisson patterns; top-10):
-plain path against the FP64 oracle on sampled patterns, and the FP8
+plain path against the FP64 oracle on 8 sampled patterns, and the FP8
 pre-filter path's entries are exact scores. Runs only on an MI355X."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from parity import PatternRef, check_topn, scores_close
+from parity import PatternRef, check_topn, oracle_best_pool, scores_close
 
 pytestmark = pytest.mark.gpu
 
@@ -27,7 +27,7 @@ def c5():
     px = synth.px_per_inv_A(cfg)
     lib = tm.Library(lib_np["kx"], lib_np["ky"], lib_np["intensity"], lib_np["offsets"], px, grid)
     olib = oracle.OracleLibrary.build(lib_np, px, cfg.R, cfg.n_theta)
-    idx = [0, 1023, 65536, 262143]
+    idx = [0, 17, 1023, 65536, 130000, 200000, 250001, 262143]
     imgs = synth.make_patterns(cfg, lib_np, idx)
     x = torch.from_numpy(imgs.view(np.int16)).cuda()
     polar, norms, prof = tm.polar_transform(x, grid)
@@ -35,11 +35,15 @@ def c5():
 
 
 def test_c5_plain_matches_oracle(c5):
+    """8 patterns spread over the scan against the oracle's exact search
+    (about 40 s per pattern; one worker process per pattern)."""
     tm, cfg, lib, olib, idx, imgs, polar, norms, prof = c5
     _say("C5 plain", idx, "layout", lib.layout())
     tt, ts, tq = (o.cpu().numpy() for o in tm.match_batch(lib, polar, norms, cfg.N))
-    for b in (0, 3):
-        ref = PatternRef(oracle.polar64(imgs[b].astype(np.float64), cfg.R, cfg.n_theta), olib)
+    bests = oracle_best_pool(5, list(imgs), workers=len(idx))
+    for b, (best, arg) in enumerate(bests):
+        ref = PatternRef(oracle.polar64(imgs[b].astype(np.float64), cfg.R, cfg.n_theta), olib,
+                         best=best, arg=arg)
         check_topn(ref, tt[b], ts[b], tq[b], margin=1e-4)
 
 
