@@ -643,9 +643,8 @@ int tm_fft_scores(const tm_library* lib, const float* polar, const double* norms
  *
  * Arguments
  *   lib           loaded library (all weights >= 0; the window image of the
- *                 touched rows, rows x (7 win, or n_theta + 3 win when
- *                 n_theta is not a multiple of 4) float16, must fit 128 KiB
- *                 of LDS, else TM_EUNSUPPORTED).
+ *                 touched rows plus one, (rows + 1) x (n_theta + 3 win)
+ *                 float16, must fit 128 KiB of LDS, else TM_EUNSUPPORTED).
  *   polar, norms  as in tm_match_batch; compact_rows as in tm_fft_scores.
  *   B             >= 0 (0 is a no-op).
  *   bound_out     device, [B, T'] float32, written. A pattern with a
@@ -653,6 +652,30 @@ int tm_fft_scores(const tm_library* lib, const float* polar, const double* norms
  * Errors: TM_EINVAL, TM_EUNSUPPORTED, TM_EHIP, TM_ENODEV. */
 int tm_bound_scores(const tm_library* lib, const float* polar, const double* norms, int32_t B,
                     int32_t compact_rows, float* bound_out, void* hip_stream);
+
+/* tm_bound_scores_slots - the bounds of tm_bound_scores in the order the
+ * kernel produces them (no reordering pass): chunk-slot order, slot
+ * c * 64 + l holding template slot_template[c * 64 + l].
+ *   bound_out      device, [B, chunks * 64] float32 (chunks from
+ *                  tm_bound_layout), written; slots without a template
+ *                  (slot_template -1) get the bound of an empty template, 0.
+ *   slot_template  host, nullable, [chunks * 64] int32, written: the
+ *                  template of each slot, -1 for none.
+ * Other arguments and errors as tm_bound_scores. */
+int tm_bound_scores_slots(const tm_library* lib, const float* polar, const double* norms,
+                          int32_t B, int32_t compact_rows, float* bound_out,
+                          int32_t* slot_template, void* hip_stream);
+
+/* tm_bound_layout - the window-bound data of a library, for work accounting
+ * (the same exact-search aid as tm_bound_scores).
+ *   chunks  out (nullable): chunks of 64 templates, one template per lane.
+ *   units   out (nullable): record units per pattern (each 4 records per
+ *           lane, 1 KiB per wave; a chunk's templates are padded to its
+ *           largest pixel count plus the margin record).
+ *   win     out (nullable): shifts per coarse window, ceil(n_theta / 4).
+ * Errors: TM_EINVAL (lib NULL), TM_EUNSUPPORTED (no window bounds for this
+ * library: a negative weight or an image over the LDS budget). */
+int tm_bound_layout(const tm_library* lib, int32_t* chunks, int64_t* units, int32_t* win);
 
 /* tm_fft_error_bound - a-priori bound eps with |Q~ - Q32| <= eps for every
  * template and shift, where Q~ is tm_fft_scores' arithmetic and Q32 the exact

@@ -40,7 +40,7 @@ LAUE_GROUPS = {"m-3m": TM_LAUE_M3M, "mmm": TM_LAUE_MMM, "6/mmm": TM_LAUE_6MMM}
 EXPORTED = ("tm_load_library", "tm_free_library", "tm_library_info", "tm_library_layout",
             "tm_library_rows", "tm_polar_transform", "tm_polar_transform_rows",
             "tm_mask_from_mean", "tm_match_batch", "tm_match_batch_static", "tm_refine_angles", "tm_prefilter", "tm_match_candidates",
-            "tm_fft_scores", "tm_fft_error_bound", "tm_bound_scores", "tm_orientations", "tm_ipf_deviation",
+            "tm_fft_scores", "tm_fft_error_bound", "tm_bound_scores", "tm_bound_scores_slots", "tm_bound_layout", "tm_orientations", "tm_ipf_deviation",
             "tm_simulate_library", "tm_preprocess",
             "tm_topn", "tm_last_error", "tm_version")
 
@@ -92,6 +92,8 @@ def _load():
         "tm_match_batch": [P, P, P, P, I32, ctypes.POINTER(_Opts), I32, P, P, P, P, P, P],
         "tm_match_batch_static": [P, P, P, P, I32, ctypes.POINTER(_Opts), I32, P, P, P, P, P, P],
         "tm_bound_scores": [P, P, P, I32, I32, P, P],
+        "tm_bound_layout": [P, P, P, P],
+        "tm_bound_scores_slots": [P, P, P, I32, I32, P, P, P],
         "tm_prefilter": [P, P, I32, I32, I32, P, P],
         "tm_match_candidates": [P, P, P, I32, P, I32, I32, P, P, P, P],
         "tm_fft_scores": [P, P, P, I32, I32, P, P, P],
@@ -227,6 +229,14 @@ class Library:
         n_theta = self.grid.n_theta
         return {"group": g.value, "n_bands": nb.value, "n_rows": nr.value, "n_records": rec.value,
                 "row_width": rw.value, "narrow": rw.value == n_theta + 63}
+
+    def bound_layout(self):
+        """tm_bound_layout: the window-bound data's chunks, record units per
+        pattern and coarse window width (TMError if the library has none)."""
+        ch, un, w = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+        _check(_lib.tm_bound_layout(self._h, ctypes.byref(ch), ctypes.byref(un), ctypes.byref(w)),
+               "tm_bound_layout")
+        return {"chunks": ch.value, "units": un.value, "win": w.value}
 
     def rows(self):
         """tm_library_rows: (number of polar rows the templates touch, device
@@ -594,6 +604,26 @@ def bound_scores(lib: Library, polar, norms, stream=None):
     _check(_lib.tm_bound_scores(lib._h, _ptr(polar), _ptr(norms), B, compact, _ptr(out),
                                 _stream_ptr(stream)), "tm_bound_scores")
     return out
+
+
+def bound_scores_slots(lib: Library, polar, norms, out=None, stream=None):
+    """tm_bound_scores_slots: the same bounds in the kernel's chunk-slot
+    order. Returns ([B, chunks * 64] f32, slot -> template [chunks * 64]
+    int32 numpy array, -1 for empty slots)."""
+    torch = _torch()
+    B = polar.shape[0]
+    compact = _layout(lib, polar)
+    _require(polar, "polar", torch.float32, (B, polar.shape[1], lib.grid.n_theta))
+    _require(norms, "norms", torch.float64, (B,))
+    n_cs = lib.bound_layout()["chunks"] * 64
+    if out is None:
+        out = torch.empty((B, n_cs), dtype=torch.float32, device=polar.device)
+    _require(out, "bound_out", torch.float32, (B, n_cs))
+    slots = np.empty(n_cs, dtype=np.int32)
+    _check(_lib.tm_bound_scores_slots(lib._h, _ptr(polar), _ptr(norms), B, compact, _ptr(out),
+                                      slots.ctypes.data, _stream_ptr(stream)),
+           "tm_bound_scores_slots")
+    return out, slots
 
 
 def fft_scores(lib: Library, polar, norms, with_angle: bool = True, stream=None):

@@ -480,11 +480,13 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
     if (int r = up(&L->d_bnd_recs, recs)) return r;
     if (int r = up(&L->d_bnd_end, cend)) return r;
     if (int r = up(&L->d_bnd_tid, tid)) return r;
+    L->bnd_tid = tid;
     if (int r = up(&L->d_bnd_part, part)) return r;
     L->bnd_win = win;
     L->bnd_shifts = kShifts;
     L->bnd_L = Lrow;
     L->bnd_chunks = n_chunks;
+    L->bnd_units = units;
     L->bnd_dfac = static_cast<float>(1.0 / (1.0 - gamma32(nmax + 1)) * (1.0 + 0x1p-22));
     L->bound = true;
     return TM_OK;
@@ -565,24 +567,58 @@ int tmlib::bound_match(const tm_library* lib, const float* polar, const double* 
 
 // --------------------------------------------------------------- C ABI
 
-extern "C" int tm_bound_scores(const tm_library* lib, const float* polar, const double* norms,
-                               int32_t B, int32_t compact_rows, float* bound_out,
-                               void* hip_stream) {
+namespace {
+
+int bound_scores_entry(const tm_library* lib, const float* polar, const double* norms, int32_t B,
+                       int32_t compact_rows, float* bound_out, bool template_order,
+                       int32_t* slot_template, void* hip_stream) {
     tmlib::clear_error();
     if (!lib) { tmlib::set_error("library is NULL"); return TM_EINVAL; }
     if (B < 0) { tmlib::set_error("B=%d < 0", B); return TM_EINVAL; }
     if (compact_rows != 0 && compact_rows != 1) { tmlib::set_error("compact_rows=%d must be 0 or 1", compact_rows); return TM_EINVAL; }
     if (!lib->bound) {
         tmlib::set_error("window bounds need non-negative template weights and a window image "
-                         "of at most 64k columns x rows");
+                         "within the LDS budget");
         return TM_EUNSUPPORTED;
     }
+    if (slot_template) std::copy(lib->bnd_tid.begin(), lib->bnd_tid.end(), slot_template);
     if (B == 0) return TM_OK;
     if (!polar || !norms || !bound_out) {
         tmlib::set_error("polar, norms and bound_out must be non-NULL");
         return TM_EINVAL;
     }
     if (int r = tmlib::require_device()) return r;
-    return tmlib::bound_scores_impl(lib, polar, norms, B, bound_out, true, compact_rows == 1,
-                                    static_cast<hipStream_t>(hip_stream));
+    return tmlib::bound_scores_impl(lib, polar, norms, B, bound_out, template_order,
+                                    compact_rows == 1, static_cast<hipStream_t>(hip_stream));
+}
+
+}  // namespace
+
+extern "C" int tm_bound_scores(const tm_library* lib, const float* polar, const double* norms,
+                               int32_t B, int32_t compact_rows, float* bound_out,
+                               void* hip_stream) {
+    return bound_scores_entry(lib, polar, norms, B, compact_rows, bound_out, true, nullptr,
+                              hip_stream);
+}
+
+extern "C" int tm_bound_scores_slots(const tm_library* lib, const float* polar,
+                                     const double* norms, int32_t B, int32_t compact_rows,
+                                     float* bound_out, int32_t* slot_template,
+                                     void* hip_stream) {
+    return bound_scores_entry(lib, polar, norms, B, compact_rows, bound_out, false,
+                              slot_template, hip_stream);
+}
+
+extern "C" int tm_bound_layout(const tm_library* lib, int32_t* chunks, int64_t* units,
+                               int32_t* win) {
+    tmlib::clear_error();
+    if (!lib) { tmlib::set_error("library is NULL"); return TM_EINVAL; }
+    if (!lib->bound) {
+        tmlib::set_error("this library has no window bounds");
+        return TM_EUNSUPPORTED;
+    }
+    if (chunks) *chunks = lib->bnd_chunks;
+    if (units) *units = lib->bnd_units;
+    if (win) *win = lib->bnd_win;
+    return TM_OK;
 }

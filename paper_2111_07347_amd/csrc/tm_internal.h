@@ -216,11 +216,13 @@ struct tm_library {
     int32_t bnd_shifts = 0;     // coarse shifts per template
     int32_t bnd_L = 0;          // window-image row length (halves) in LDS
     int32_t bnd_chunks = 0;     // chunks of 64 templates (one per lane) scored by one wave
+    int64_t bnd_units = 0;      // record units per pattern (all chunks)
     float bnd_dfac = 1.0f;      // 1 / (1 - gamma_n), rounded up, for the bound's float32 sums
     uint32_t* d_bnd_recs = nullptr;   // units of 4 steps x 64 lanes: LDS half offset | float16
                                       // weight << 16, 16 bytes per lane
     int32_t* d_bnd_end = nullptr;     // [bnd_chunks]: first unit after each chunk
     int32_t* d_bnd_tid = nullptr;     // [bnd_chunks * 64]: template of each chunk slot, -1 none
+    std::vector<int32_t> bnd_tid;     // host copy
     float* d_bnd_cfac = nullptr;      // [bnd_chunks * 64]: margin factor, -1 for no template
     int32_t* d_bnd_part = nullptr;    // [9 + 17]: chunk ranges of 8 and of 16 waves
 

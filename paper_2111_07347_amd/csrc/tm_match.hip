@@ -186,16 +186,33 @@ match_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
                    float* __restrict__ out_q) {
         const int* items = cand ? cand + static_cast<size_t>(b) * n_groups : nullptr;
         const float* src = polar + static_cast<size_t>(b) * R * n_theta;
+        // rows of the band into LDS, each followed by its wraparound; loads
+        // are issued 16 at a time per lane (two rows x 8 columns) before
+        // their stores, so their latencies overlap
         auto stage = [&](int band) {
             const int r0 = band_off[band], r1 = band_off[band + 1];
-            for (int r = r0 + wave; r < r1; r += NW) {
-                const int prow = rows ? rows[r] : r;   // compact polar: row r is touched row r
-                const float* row = src + static_cast<size_t>(prow) * n_theta;
-                float* dst = lds + (r - r0) * row_width;
-                for (int c = lane; c < row_width; c += 64) {
-                    int cc = c;
-                    while (cc >= n_theta) cc -= n_theta;
-                    dst[c] = row[cc];
+            for (int ra = r0 + wave; ra < r1; ra += 2 * NW) {
+                const int rb = ra + NW;
+                const float* rowa = src + static_cast<size_t>(rows ? rows[ra] : ra) * n_theta;
+                const float* rowb =
+                    rb < r1 ? src + static_cast<size_t>(rows ? rows[rb] : rb) * n_theta : rowa;
+                for (int c0 = 0; c0 < row_width; c0 += 8 * 64) {
+                    float va[8], vb[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int c = c0 + lane + 64 * u;
+                        const int cc = (c < row_width ? c : 0) % n_theta;
+                        va[u] = rowa[cc];
+                        vb[u] = rowb[cc];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int c = c0 + lane + 64 * u;
+                        if (c < row_width) {
+                            lds[(ra - r0) * row_width + c] = va[u];
+                            if (rb < r1) lds[(rb - r0) * row_width + c] = vb[u];
+                        }
+                    }
                 }
             }
         };

@@ -194,3 +194,17 @@ def test_bound_search_split_passes_c2(tm, cap_frac):
         assert full >= B // 2
     else:
         assert n[n < lib.n_total].max() > 512
+
+
+def test_bound_slots_order_equals_template_order(tm, c1, c1_lib):
+    """tm_bound_scores_slots: the kernel's chunk-slot order with its slot map
+    holds exactly tm_bound_scores' values; empty slots hold 0."""
+    _say("bound slots vs template order, c1 B=16")
+    lib, grid, imgs, polar, norms = _setup(tm, c1, c1_lib, range(16))
+    ub = tm.bound_scores(lib, polar, norms).cpu().numpy()
+    us, slots = tm.bound_scores_slots(lib, polar, norms)
+    us = us.cpu().numpy()
+    assert sorted(slots[slots >= 0].tolist()) == list(range(lib.n_total))
+    assert np.array_equal(us[:, slots >= 0], ub[:, slots[slots >= 0]])
+    assert (us[:, slots < 0] == 0).all()
+    assert lib.bound_layout()["chunks"] * 64 == len(slots)
