@@ -124,25 +124,34 @@ __device__ __forceinline__ uint32_t rec_addr(uint32_t rec, uint32_t base) {
     return a;
 }
 
-// One unit of a lane's records (4 steps): the 4 coarse shifts' window
-// maxima of each record (win halves apart), all LDS reads in flight before
-// the multiply-adds.
-__device__ __forceinline__ void score_unit(const u32x4 R, uint32_t base, int win,
-                                           float (&acc)[kShifts]) {
-    float v[kUnitSteps][kShifts];
+// The LDS reads of one unit of a lane's records (4 steps): the 4 coarse
+// shifts' window maxima of each record (win halves apart), issued without
+// waiting; the address uses only a record's low 16 bits (the end flag in
+// bit 31 does not matter here).
+template <int WIN>
+__device__ __forceinline__ void read_unit(const u32x4 R, uint32_t base, int win,
+                                          float (&v)[kUnitSteps * kShifts]) {
 #pragma unroll
     for (int u = 0; u < kUnitSteps; ++u) {
         lds_u16* p = reinterpret_cast<lds_u16*>(static_cast<uintptr_t>(rec_addr(R[u], base)));
 #pragma unroll
-        for (int S = 0; S < kShifts; ++S) v[u][S] = h2f(p[S * win]);
+        for (int S = 0; S < kShifts; ++S) v[u * kShifts + S] = h2f(p[S * (WIN ? WIN : win)]);
     }
+}
+
+// The multiply-adds of one unit (weights without the end flag).
+__device__ __forceinline__ void fma_unit(const u32x4 R, const float (&v)[kUnitSteps * kShifts],
+                                         float (&acc)[kShifts]) {
 #pragma unroll
     for (int u = 0; u < kUnitSteps; ++u)
 #pragma unroll
-        for (int S = 0; S < kShifts; ++S) acc[S] = fmaf(h2f(R[u] >> 16), v[u][S], acc[S]);
+        for (int S = 0; S < kShifts; ++S)
+            acc[S] = fmaf(h2f(R[u] >> 16), v[u * kShifts + S], acc[S]);
 }
 
-template <int NW>
+// WIN > 0: the window width as a constant (the reads' offsets become
+// immediates of the LDS instructions); 0: taken from win.
+template <int NW, int WIN>
 __global__ void __launch_bounds__(NW * 64)
 bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, int Rs, int n,
              const int* __restrict__ rows, int n_rows, int Lrow, int win,
@@ -262,10 +271,12 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
     float acc[kShifts];
 #pragma unroll
     for (int S = 0; S < kShifts; ++S) acc[S] = 0.0f;
-    auto process = [&](u32x4 R) {
+    // consume a unit whose reads are in v: multiply-adds, then at a chunk's
+    // end its bounds (one coalesced store) and fresh accumulators
+    auto consume = [&](u32x4 R, const float (&v)[kUnitSteps * kShifts]) {
         const uint32_t flag = __builtin_amdgcn_readfirstlane(R[3]) & kFlag;
         R[3] &= ~kFlag;
-        score_unit(R, base, win, acc);
+        fma_unit(R, v, acc);
         if (flag) {
             float m = acc[0];
 #pragma unroll
@@ -277,28 +288,50 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
             for (int S = 0; S < kShifts; ++S) acc[S] = 0.0f;
         }
     };
-    // units stream through four registers: each is scored, then reloaded
-    // with the unit 4 places on, so 3 loads are in flight while a unit is
-    // scored (loads past the last unit repeat it and are not used)
+    // Units stream through four registers g0..g3, each reloaded with the
+    // unit 4 places on once consumed (loads past the last unit repeat it and
+    // are not used). In the main loop the LDS reads of unit u + 1 are issued
+    // before unit u is consumed, into the other of two value sets; the
+    // pipeline fills and drains within each 8-unit iteration, so no read is
+    // in flight across the loop's back edge.
     u32x4 g0 = U[static_cast<size_t>(u_begin) * kLanes];
     u32x4 g1 = U[static_cast<size_t>(min(u_begin + 1, last)) * kLanes];
     u32x4 g2 = U[static_cast<size_t>(min(u_begin + 2, last)) * kLanes];
     u32x4 g3 = U[static_cast<size_t>(min(u_begin + 3, last)) * kLanes];
+    float va[kUnitSteps * kShifts], vb[kUnitSteps * kShifts];
+    auto ld = [&](int k) { return U[static_cast<size_t>(min(k, last)) * kLanes]; };
+#define TM_BOUND_SB __builtin_amdgcn_sched_barrier(0)
     int u = u_begin;
-    for (; u + 4 <= u_end; u += 4) {
-        process(g0);
-        g0 = U[static_cast<size_t>(min(u + 4, last)) * kLanes];
-        __builtin_amdgcn_sched_barrier(0);
-        process(g1);
-        g1 = U[static_cast<size_t>(min(u + 5, last)) * kLanes];
-        __builtin_amdgcn_sched_barrier(0);
-        process(g2);
-        g2 = U[static_cast<size_t>(min(u + 6, last)) * kLanes];
-        __builtin_amdgcn_sched_barrier(0);
-        process(g3);
-        g3 = U[static_cast<size_t>(min(u + 7, last)) * kLanes];
-        __builtin_amdgcn_sched_barrier(0);
+    for (; u + 8 <= u_end; u += 8) {
+        read_unit<WIN>(g0, base, win, va); TM_BOUND_SB;
+        read_unit<WIN>(g1, base, win, vb); TM_BOUND_SB;
+        consume(g0, va); g0 = ld(u + 4); TM_BOUND_SB;
+        read_unit<WIN>(g2, base, win, va); TM_BOUND_SB;
+        consume(g1, vb); g1 = ld(u + 5); TM_BOUND_SB;
+        read_unit<WIN>(g3, base, win, vb); TM_BOUND_SB;
+        consume(g2, va); g2 = ld(u + 6); TM_BOUND_SB;
+        read_unit<WIN>(g0, base, win, va); TM_BOUND_SB;
+        consume(g3, vb); g3 = ld(u + 7); TM_BOUND_SB;
+        read_unit<WIN>(g1, base, win, vb); TM_BOUND_SB;
+        consume(g0, va); g0 = ld(u + 8); TM_BOUND_SB;
+        read_unit<WIN>(g2, base, win, va); TM_BOUND_SB;
+        consume(g1, vb); g1 = ld(u + 9); TM_BOUND_SB;
+        read_unit<WIN>(g3, base, win, vb); TM_BOUND_SB;
+        consume(g2, va); g2 = ld(u + 10); TM_BOUND_SB;
+        consume(g3, vb); g3 = ld(u + 11); TM_BOUND_SB;
     }
+    // the last 0..7 units, one at a time
+    auto process = [&](u32x4 R) {
+        read_unit<WIN>(R, base, win, va);
+        consume(R, va);
+    };
+    for (; u + 4 <= u_end; u += 4) {
+        process(g0); g0 = ld(u + 4); TM_BOUND_SB;
+        process(g1); g1 = ld(u + 5); TM_BOUND_SB;
+        process(g2); g2 = ld(u + 6); TM_BOUND_SB;
+        process(g3); g3 = ld(u + 7); TM_BOUND_SB;
+    }
+#undef TM_BOUND_SB
     if (u < u_end) process(g0);
     if (u + 1 < u_end) process(g1);
     if (u + 2 < u_end) process(g2);
@@ -530,7 +563,12 @@ int tmlib::bound_scores_impl(const tm_library* L, const float* polar, const doub
     };
     // one workgroup per CU when the image fills the LDS: use every wave slot
     const bool whole = lds > 64 * 1024;
-    int r = whole ? launch(bound_kernel<16>, 16) : launch(bound_kernel<8>, 8);
+    // n_theta = 360 (windows of 90 columns) has its own instance
+    int r;
+    if (L->bnd_win == 90)
+        r = whole ? launch(bound_kernel<16, 90>, 16) : launch(bound_kernel<8, 90>, 8);
+    else
+        r = whole ? launch(bound_kernel<16, 0>, 16) : launch(bound_kernel<8, 0>, 8);
     if (template_order) {
         if (!r) {
             hipLaunchKernelGGL(bound_permute, dim3((n_cs + 255) / 256, B), dim3(256), 0, s, Qc,
