@@ -87,6 +87,10 @@ def parse():
                     help="skip the exact window-bound search leg")
     ap.add_argument("--no-c2", action="store_true",
                     help="skip the paper-scale FCC leg (run beside the default workload)")
+    ap.add_argument("--no-two-stage", action="store_true",
+                    help="skip the two-stage (masked second-phase) leg")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving leg (for a kernel trace of burst mode)")
     ap.add_argument("--serving-rows", type=int, default=1024,
                     help="scan rows replayed through the serving loop (0 = skip)")
     ap.add_argument("--serving-distinct", type=int, default=128,
@@ -563,6 +567,61 @@ def fourier_leg(tm, sc, plain_top, steps, warmup, cid):
     return res
 
 
+def two_stage_leg(tm, sc, steps, warmup):
+    """Two-stage indexing over the same scan (custom indexation procedures,
+    Section 4.3): after the dominant phase has been indexed (the timed step
+    of the line's value), the mask of its reflections is built from the
+    scan's mean pattern, and the masked patterns are indexed against a
+    second phase's library (the 2000-template FCC library, unit
+    intensities) with the window-bound exact search. Timed step: mask +
+    masked polar transform + stage-2 match; its top-N is checked against the
+    exhaustive scan of the same masked patterns."""
+    import torch
+    import synth
+    B, N = sc.B, sc.N
+    lib_np = synth.make_library(synth.WORKLOADS[2])
+    lib2 = tm.Library(lib_np["kx"], lib_np["ky"], lib_np["intensity"], lib_np["offsets"], sc.px,
+                      sc.grid, unit_intensity=True)
+    # threshold: the 98th percentile of the mean pattern (a parameter choice)
+    mean = sc.x[: min(B, 4096)].float().mean(0)
+    thr = float(torch.quantile(mean.flatten(), 0.98))
+    n_rows = lib2.rows()[0]
+    polar = torch.empty((B, n_rows, sc.cfg.n_theta), dtype=torch.float32, device=sc.x.device)
+    norms = torch.empty((B,), dtype=torch.float64, device=sc.x.device)
+    out = tuple(torch.empty((B, N), dtype=dt, device=sc.x.device)
+                for dt in (torch.int32, torch.int32, torch.float32))
+    keep = {}
+
+    def step(ev):
+        if ev is not None:
+            ev[0].record(sc.stream)
+        mask = tm.mask_from_mean(sc.x, thr, 1, 2)
+        tm.polar_transform(sc.x, sc.grid, polar_out=polar, norm_out=norms, want_profile=False,
+                           lib=lib2, mask=mask)
+        if ev is not None:
+            ev[1].record(sc.stream)
+        tm.match_batch(lib2, polar, norms, N, out=out, coarse="bound")
+        if ev is not None:
+            ev[2].record(sc.stream)
+        keep["mask"] = mask
+
+    wall, evs, per_step = time_steps(step, steps, warmup)
+    plain = [o.cpu() for o in tm.match_batch(lib2, polar, norms, N)]
+    same = all(bool(torch.equal(a.cpu(), p)) for a, p in zip(out, plain))
+    masked = float((keep["mask"] == 0).float().mean().item())
+    res = {"value": round(B * steps / wall, 1), "unit": "patterns/s",
+           "ms_per_step": round(wall / steps * 1e3, 4), "step_device_ms": step_stats(per_step),
+           "mask_and_polar_ms": round(float(np.mean([e[0].elapsed_time(e[1]) for e in evs])), 4),
+           "match_ms": round(float(np.mean([e[1].elapsed_time(e[2]) for e in evs])), 4),
+           "second_library_templates": lib2.n_total, "mask_threshold": thr,
+           "masked_pixel_fraction": round(masked, 4),
+           "top_n_identical_to_exhaustive_fp32": same}
+    say(f"two-stage: {res['ms_per_step']:.2f} ms/step for stage 2 (mask + polar "
+        f"{res['mask_and_polar_ms']:.2f}, match {res['match_ms']:.2f}), masked {masked:.3f}, "
+        f"identical top-N {same}")
+    return res
+
+
 def end_to_end(tm, sc, reps, chunk, paths):
     """Patterns from pinned host memory to top-N rows in pinned host memory,
     copies overlapped with compute (serve.PinnedIndexer); wall clock from the
@@ -593,8 +652,10 @@ def serving_bench(tm, n_rows, n_distinct, workers):
     (4000 patterns/s), each routed to one of three resident libraries (2000
     FCC, 8000 HCP, 20000 orthorhombic templates); continuous batching on 4
     stream slots with a 16 GiB in-flight budget; each library takes the
-    faster of two exact paths (measured on one row). Returns the paced
-    latency report and the burst-mode throughput."""
+    fastest of three exact paths (plain gather, window-bound search, Fourier
+    route; measured on one row). Returns the paced latency report, the
+    burst-mode throughput and, for comparison, the same burst run serially
+    (one slot, one row per launch: no overlap between rows)."""
     import multiprocessing as mp
 
     import torch
@@ -623,7 +684,7 @@ def serving_bench(tm, n_rows, n_distinct, workers):
         xr = rows[r].cuda()
         polar, norms, _ = tm.polar_transform(xr, grid, want_profile=False, lib=lib)
         ms = {}
-        for name, kw in (("plain", {}), ("fourier", {"coarse": "fft"})):
+        for name, kw in (("plain", {}), ("bound", {"coarse": "bound"}), ("fourier", {"coarse": "fft"})):
             tm.match_batch(lib, polar, norms, 5, **kw)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -634,24 +695,30 @@ def serving_bench(tm, n_rows, n_distinct, workers):
         paths[i] = min(ms, key=ms.get)
         timing[i] = {k: round(v, 3) for k, v in ms.items()}
     fourier = {i for i, p in paths.items() if p == "fourier"}
+    bound = {i for i, p in paths.items() if p == "bound"}
     budget = 16 << 30
     out = {"rows": n_rows, "distinct_rows": distinct, "patterns_per_row": synth.SERVING_ROW,
            "arrival_patterns_per_s": synth.SERVING_ROW / synth.SERVING_INTERVAL_S,
            "libraries": {i: libs[i].info()["n_templates_total"] for i in libs},
            "slots": 4, "max_batch_rows": 4, "budget_bytes": budget,
-           "path": "exact FP32 top-N per row: plain gather or Fourier route + certified "
-                   "rescoring, whichever is faster per library",
+           "path": "exact FP32 top-N per row: plain gather, window-bound search or Fourier "
+                   "route + certified rescoring, whichever is fastest per library",
            "library_paths": paths, "row_match_ms_by_path": timing}
     # warm up every library once
-    ex = GpuExecutor(libs, grid, N=5, slots=4, fourier=fourier)
+    ex = GpuExecutor(libs, grid, N=5, slots=4, fourier=fourier, bound=bound)
     srv = Server(ex, budget_bytes=budget, slots=4, max_batch_rows=4)
     run_stream(srv, rows[:3] * 1, rows_lib[:3], np.zeros(3))
-    for mode, arr in (("paced", arrivals), ("burst", np.zeros(n_rows))):
-        srv = Server(GpuExecutor(libs, grid, N=5, slots=4, fourier=fourier), budget_bytes=budget,
-                     slots=4, max_batch_rows=4)
+    modes = [("paced", arrivals, 4, 4), ("burst", np.zeros(n_rows), 4, 4),
+             ("serial", np.zeros(n_rows), 1, 1)]
+    for mode, arr, slots, max_rows in modes:
+        srv = Server(GpuExecutor(libs, grid, N=5, slots=slots, fourier=fourier, bound=bound),
+                     budget_bytes=budget, slots=slots, max_batch_rows=max_rows)
         res = run_stream(srv, rows, rows_lib, arr)
         out[mode] = latency_report(res)
         print(f"[bench] serving {mode}: {out[mode]}", file=sys.stderr, flush=True)
+    b, s_ = out["burst"].get("sustained_patterns_per_s"), out["serial"].get("sustained_patterns_per_s")
+    if b and s_:
+        out["burst_over_serial"] = round(b / s_, 3)
     return out
 
 
@@ -953,6 +1020,11 @@ def main():
         return 0
     if a.config == 5:
         return c5_bench(a)
+    if a.serving_only:
+        import paper_2111_07347_amd as tm
+        print(json.dumps({"serving": serving_bench(tm, a.serving_rows, a.serving_distinct,
+                                                   pool_size(a))}), flush=True)
+        return 0
     import paper_2111_07347_amd as tm
     import synth
 
@@ -977,6 +1049,7 @@ def main():
     keeps = [float(k) for k in a.keeps.split(",") if k]
     prec = precision_sweep(tm, sc, plain_top, precs, keeps, a.prec_steps, 1) if precs else {}
     fourier = None if a.no_fft else fourier_leg(tm, sc, plain_top, a.prec_steps, 1, a.config)
+    two_stage = None if a.no_two_stage else two_stage_leg(tm, sc, a.prec_steps, 1)
 
     e2e = None
     if a.e2e_reps > 0:
@@ -1094,6 +1167,7 @@ def main():
         "bound_search": bound,
         "precision_paths": prec,
         "fourier_path": fourier,
+        "two_stage": two_stage,
         "end_to_end": e2e,
         "paper_scale_fcc": c2,
         "orientation_accuracy": accuracy,

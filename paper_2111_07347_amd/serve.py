@@ -145,14 +145,15 @@ class Scheduler:
 
 class GpuExecutor:
     """Device work of a batch on the slot's stream: host-to-device copy of the
-    rows, polar transform, match (plain; or the Fourier route with certified
-    rescoring for the libraries listed in `fourier`, which gives the plain
-    path's top-N; or pre-filtered in reduced precision with exact
+    rows, polar transform, match (plain; or, for the libraries listed in
+    `bound`, the exact search with window upper bounds, or, for those in
+    `fourier`, the Fourier route with certified rescoring, both of which give
+    the plain path's top-N; or pre-filtered in reduced precision with exact
     rescoring), device-to-host copy of the top-N, completion event."""
 
     def __init__(self, libraries: dict, grid, N: int, slots: int, gamma: float = 1.0,
                  subtract: float = 0.0, prefilter_keep: float = 0.0, precision: str = "bf16",
-                 fourier=()):
+                 fourier=(), bound=()):
         import torch
 
         import paper_2111_07347_amd as tm
@@ -166,6 +167,7 @@ class GpuExecutor:
         self.keep = prefilter_keep
         self.precision = precision
         self.fourier = set(fourier)     # library ids loaded with spectra (Library(fft=True))
+        self.bound = set(bound)         # library ids searched with window bounds
         self.streams = [torch.cuda.Stream() for _ in range(slots)]   # default priority
         self.events = [None] * slots
         self.outputs = [None] * slots
@@ -175,7 +177,12 @@ class GpuExecutor:
         R, nt = self.grid.R, self.grid.n_theta
         rows = self.libraries[lib_id].rows()[0] or R       # compact polar: touched rows
         b = n_patterns * (H * W * itemsize + rows * nt * 4 + 8 + R * 4 + self.N * 12)
-        if lib_id in self.fourier:
+        if lib_id in self.bound:
+            # bounds in chunk-slot order, candidate lists (at most 10 % of
+            # T') and the split launches' partial lists
+            Tp = self.libraries[lib_id].n_total
+            b += n_patterns * (Tp + 64) * 4 + n_patterns * (Tp // 10 + 1) * 4 + (16384 * self.N * 12)
+        elif lib_id in self.fourier:
             # stored C(k) (float16 re/im per frequency and template, chunked
             # to 2 GiB), approximate scores and the certified candidate lists
             lib = self.libraries[lib_id]
@@ -201,7 +208,9 @@ class GpuExecutor:
                 o += h.shape[0]
             polar, norms, prof = tm.polar_transform(x, self.grid, self.gamma, self.subtract,
                                                     want_profile=self.keep > 0.0, lib=lib)
-            if batch.lib_id in self.fourier:
+            if batch.lib_id in self.bound:
+                tt, ts, tq = tm.match_batch(lib, polar, norms, self.N, coarse="bound")
+            elif batch.lib_id in self.fourier:
                 tt, ts, tq = tm.match_batch(lib, polar, norms, self.N, coarse="fft")
             elif self.keep > 0.0:
                 tt, ts, tq = tm.match_batch(lib, polar, norms, self.N, profiles=prof,

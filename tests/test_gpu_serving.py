@@ -102,3 +102,22 @@ def test_fourier_route_library_serves_the_plain_results(setup):
         assert np.array_equal(r.top_template, p.top_template), (r.req_id, lib_ids[r.req_id])
         assert np.array_equal(r.top_angle, p.top_angle), (r.req_id, lib_ids[r.req_id])
         assert np.array_equal(r.top_score, p.top_score), (r.req_id, lib_ids[r.req_id])
+
+
+def test_window_bound_libraries_serve_the_plain_results(setup):
+    """Every library served through the window-bound exact search returns
+    exactly the plain path's top-N, in the mix."""
+    tm, GpuExecutor, Server, grid, px, libs_np, libs, lib_ids, rows_np, rows = setup
+    from paper_2111_07347_amd.serve import run_stream
+    n = len(lib_ids)
+    _say("serving: all libraries through the window-bound search, mixed, 3 slots")
+    ex = GpuExecutor(libs, grid, N=5, slots=3, bound=set(libs))
+    srv = Server(ex, budget_bytes=16 << 30, slots=3, max_batch_rows=3)
+    res = run_stream(srv, rows, list(lib_ids), np.zeros(n))
+    assert all(r.error is None for r in res)
+    plain = _serve(setup, list(range(n)), slots=3, max_rows=3)
+    for r in res:
+        p = plain[r.req_id]
+        assert np.array_equal(r.top_template, p.top_template), (r.req_id, lib_ids[r.req_id])
+        assert np.array_equal(r.top_angle, p.top_angle), (r.req_id, lib_ids[r.req_id])
+        assert np.array_equal(r.top_score, p.top_score), (r.req_id, lib_ids[r.req_id])
