@@ -42,10 +42,20 @@ certify_select(const float* __restrict__ Qt, int Tp, const int32_t* __restrict__
     const float* row = Qt + static_cast<size_t>(b) * Tp;
     const int lo = static_cast<int>((static_cast<long long>(Tp) * wave) / W);
     const int hi = static_cast<int>((static_cast<long long>(Tp) * (wave + 1)) / W);
+    // 4 blocks of 64 columns per step, their loads issued together
+    constexpr int kBlocks = 4;
+    auto take_at = [&](int t, float v) { return t < hi && v >= thr && (!map || map[t] >= 0); };
     int c = 0;
-    for (int base = lo; base < hi; base += 64) {
-        const int t = base + lane;
-        c += __popcll(tmlib::ballot(t < hi && row[t] >= thr && (!map || map[t] >= 0)));
+    for (int base0 = lo; base0 < hi; base0 += 64 * kBlocks) {
+        float v[kBlocks];
+#pragma unroll
+        for (int k = 0; k < kBlocks; ++k) {
+            const int t = base0 + 64 * k + lane;
+            v[k] = t < hi ? row[t] : -INFINITY;
+        }
+#pragma unroll
+        for (int k = 0; k < kBlocks; ++k)
+            c += __popcll(tmlib::ballot(take_at(base0 + 64 * k + lane, v[k])));
     }
     if (lane == 0) wcount[wave] = c;
     __syncthreads();
@@ -58,12 +68,21 @@ certify_select(const float* __restrict__ Qt, int Tp, const int32_t* __restrict__
     if (!over) {
         int32_t* out = cand + static_cast<size_t>(b) * cap;
         int pos = before;
-        for (int base = lo; base < hi; base += 64) {
-            const int t = base + lane;
-            const bool take = t < hi && row[t] >= thr && (!map || map[t] >= 0);
-            const unsigned long long m = tmlib::ballot(take);
-            if (take) out[pos + __popcll(m & ((1ull << lane) - 1))] = map ? map[t] : t;
-            pos += __popcll(m);
+        for (int base0 = lo; base0 < hi; base0 += 64 * kBlocks) {
+            float v[kBlocks];
+#pragma unroll
+            for (int k = 0; k < kBlocks; ++k) {
+                const int t = base0 + 64 * k + lane;
+                v[k] = t < hi ? row[t] : -INFINITY;
+            }
+#pragma unroll
+            for (int k = 0; k < kBlocks; ++k) {
+                const int t = base0 + 64 * k + lane;
+                const bool take = take_at(t, v[k]);
+                const unsigned long long m = tmlib::ballot(take);
+                if (take) out[pos + __popcll(m & ((1ull << lane) - 1))] = map ? map[t] : t;
+                pos += __popcll(m);
+            }
         }
     }
     if (threadIdx.x == 0) {

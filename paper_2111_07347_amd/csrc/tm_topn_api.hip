@@ -3,9 +3,10 @@
 // best matching templates queried instead of only the best one).
 //
 // One workgroup per pattern, 4 waves; each wave streams a contiguous quarter
-// of the templates 64 at a time (coalesced loads), tests all 64 against its
-// running N-th best with one ballot, and inserts only the candidates that
-// beat it, in increasing template order. The waves' lists are merged in LDS.
+// of the templates, 4 blocks of 64 per step (coalesced loads, all four in
+// flight together), tests each block against its running N-th best with one
+// ballot, and inserts only the candidates that beat it, in increasing
+// template order. The waves' lists are merged in LDS.
 #include <algorithm>
 
 #include "tm_device.h"
@@ -29,18 +30,32 @@ topn_kernel(const float* __restrict__ best_q, const short* __restrict__ best_s, 
     const float* q_row = best_q + static_cast<size_t>(b) * T;
     const short* s_row = best_s ? best_s + static_cast<size_t>(b) * T : nullptr;
     tmlib::TopState st = tmlib::topn_init();
-    for (int base = lo; base < hi; base += 64) {
-        const int t = base + lane;
-        const bool ok = t < hi;
-        const float q = ok ? q_row[t] : -INFINITY;
-        const int s = (ok && best_s) ? s_row[t] : 0;
-        unsigned long long msk = tmlib::ballot(ok && (st.cnt < N || tmlib::topn_beats(st, q, t)));
-        while (msk) {
-            const int l = __ffsll(static_cast<long long>(msk)) - 1;
-            msk &= msk - 1;
-            const float Q = __shfl(q, l, 64);
-            const int S = __shfl(s, l, 64);
-            if (st.cnt < N || tmlib::topn_beats(st, Q, base + l)) tmlib::topn_insert(st, Q, base + l, S, lane, N);
+    // 4 blocks of 64 templates per step: their loads are issued together
+    constexpr int kBlocks = 4;
+    for (int base0 = lo; base0 < hi; base0 += 64 * kBlocks) {
+        float qv[kBlocks];
+        int sv[kBlocks];
+#pragma unroll
+        for (int k = 0; k < kBlocks; ++k) {
+            const int t = base0 + 64 * k + lane;
+            const bool ok = t < hi;
+            qv[k] = ok ? q_row[t] : -INFINITY;
+            sv[k] = (ok && best_s) ? s_row[t] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kBlocks; ++k) {
+            const int base = base0 + 64 * k;
+            const int t = base + lane;
+            const float q = qv[k];
+            unsigned long long msk =
+                tmlib::ballot(t < hi && (st.cnt < N || tmlib::topn_beats(st, q, t)));
+            while (msk) {
+                const int l = __ffsll(static_cast<long long>(msk)) - 1;
+                msk &= msk - 1;
+                const float Q = __shfl(q, l, 64);
+                const int S = __shfl(sv[k], l, 64);
+                if (st.cnt < N || tmlib::topn_beats(st, Q, base + l)) tmlib::topn_insert(st, Q, base + l, S, lane, N);
+            }
         }
     }
     tmlib::topn_merge_write<kTopnWaves>(st, lds, wave, lane, N, top_t + static_cast<size_t>(b) * N,
