@@ -63,13 +63,9 @@ struct Rec {
 // The records' scalar loads and all their LDS reads are in flight before
 // the first FMA.
 template <int K, int G, int CLS, int NB>
-__device__ __forceinline__ void accumulate_batch(const Rec<G>* __restrict__ rec, int i,
-                                                 const float* lds, int lane, int n_theta,
-                                                 float (&acc)[G][K]) {
-    Rec<G> r[NB];
+__device__ __forceinline__ void accumulate_recs(const Rec<G> (&r)[NB], const float* lds, int lane,
+                                                int n_theta, float (&acc)[G][K]) {
     float v[NB][K];
-#pragma unroll
-    for (int u = 0; u < NB; ++u) r[u] = rec[i + u];
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
         const float* pa = lds + r[u].off + lane;
@@ -85,15 +81,63 @@ __device__ __forceinline__ void accumulate_batch(const Rec<G>* __restrict__ rec,
             for (int k = 0; k < K; ++k) acc[g][k] = fmaf(r[u].w[g], v[u][k], acc[g][k]);
 }
 
+template <int K, int G, int CLS, int NB>
+__device__ __forceinline__ void accumulate_batch(const Rec<G>* __restrict__ rec, int i,
+                                                 const float* lds, int lane, int n_theta,
+                                                 float (&acc)[G][K]) {
+    Rec<G> r[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) r[u] = rec[i + u];
+    accumulate_recs<K, G, CLS, NB>(r, lds, lane, n_theta, acc);
+}
+
 // Accumulate records [i0, i1) in batches of NB (8 when a wave may hold the
 // registers, i.e. when a workgroup fills the CU), then 4, then singly. The
-// summation order per accumulator is the record order in every case.
+// summation order per accumulator is the record order in every case. With
+// one template per group (candidate lists: few templates per pattern, so
+// the record loads' latency is not hidden by other work) the next batch's
+// records are loaded while the current one is summed.
 template <int K, int G, int CLS, int NB>
 __device__ __forceinline__ void accumulate(const Rec<G>* __restrict__ rec, int i0, int i1,
                                            const float* lds, int lane, int n_theta,
                                            float (&acc)[G][K]) {
     int i = i0;
-    for (; i + NB <= i1; i += NB) accumulate_batch<K, G, CLS, NB>(rec, i, lds, lane, n_theta, acc);
+    if constexpr (G == 1 && NB == 8) {
+        if (i + NB <= i1) {
+            // Vector loads (every lane the same address; an opaque zero
+            // index keeps the compiler from turning them into scalar loads,
+            // whose results cannot be waited for apart from the LDS reads'):
+            // the loads of the next batch stay in flight while this one is
+            // summed.
+            int z;
+            asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+            const Rec<G>* vrec = rec + z;
+            Rec<G> ra[NB], rb[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) ra[u] = vrec[i + u];
+            for (; i + 3 * NB <= i1; i += 2 * NB) {
+#pragma unroll
+                for (int u = 0; u < NB; ++u) rb[u] = vrec[i + NB + u];
+                accumulate_recs<K, G, CLS, NB>(ra, lds, lane, n_theta, acc);
+#pragma unroll
+                for (int u = 0; u < NB; ++u) ra[u] = vrec[i + 2 * NB + u];
+                accumulate_recs<K, G, CLS, NB>(rb, lds, lane, n_theta, acc);
+            }
+            // ra holds the batch at i; one or two whole batches remain
+            if (i + 2 * NB <= i1) {
+#pragma unroll
+                for (int u = 0; u < NB; ++u) rb[u] = vrec[i + NB + u];
+                accumulate_recs<K, G, CLS, NB>(ra, lds, lane, n_theta, acc);
+                accumulate_recs<K, G, CLS, NB>(rb, lds, lane, n_theta, acc);
+                i += 2 * NB;
+            } else {
+                accumulate_recs<K, G, CLS, NB>(ra, lds, lane, n_theta, acc);
+                i += NB;
+            }
+        }
+    } else {
+        for (; i + NB <= i1; i += NB) accumulate_batch<K, G, CLS, NB>(rec, i, lds, lane, n_theta, acc);
+    }
     if constexpr (NB > 4) {
         if (i + 4 <= i1) {
             accumulate_batch<K, G, CLS, 4>(rec, i, lds, lane, n_theta, acc);
