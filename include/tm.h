@@ -506,7 +506,7 @@ int tm_ipf_deviation(const double* euler_a, int32_t stride_a, const double* eule
                      void* hip_stream);
 
 /* tm_simulate_library - kinematical template library on the device
- * (Section 2.1): a reciprocal-space grid within a limiting radius is rotated
+ * (Section 2.1): the reciprocal lattice points up to a maximum radius are rotated
  * by each orientation (phi1 = 0, Phi, phi2); each point's excitation error
  * (distance to the Ewald sphere) sets a shape factor; spot intensity is
  * F F* times the shape factor; the excited spots are projected onto kx-ky.
@@ -688,8 +688,8 @@ int tm_bound_layout(const tm_library* lib, int32_t* chunks, int64_t* units, int3
 int tm_fft_error_bound(const tm_library* lib, double* eps);
 
 /* tm_topn - sort per-template best scores and keep the N best per pattern
- * (Section 2.2, end: the list of correlations can be sorted and the N best
- * matching templates queried).
+ * (Section 2.2, end: sorting the per-template correlations gives the N
+ * best templates rather than only the best one).
  *
  * Arguments
  *   best_score   device, [B, T] float32.

@@ -3,7 +3,7 @@
 Test infrastructure only (see the package docstring).
 
 Section 2.1 builds each template in four steps:
-1. a reciprocal-space grid within a limiting radius;
+1. the reciprocal lattice points up to a maximum radius;
 2. the grid rotated by the orientation (phi1 = 0, Phi, phi2), and each
    point's distance to the surface of the Ewald sphere (the excitation
    error);

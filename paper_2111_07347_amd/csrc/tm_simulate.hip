@@ -1,5 +1,5 @@
 // Kinematical simulation of a template library on the device (Section 2.1):
-// a reciprocal-space grid within a limiting radius, rotated by each
+// the reciprocal lattice points up to a maximum radius, rotated by each
 // orientation (phi1 = 0, Phi, phi2); the excitation error (distance to the
 // Ewald sphere); spot intensity I = F F* times a shape factor of the
 // excitation error; projection of the excited spots onto kx-ky.

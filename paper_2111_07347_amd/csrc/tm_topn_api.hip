@@ -1,6 +1,6 @@
 // tm_topn: sort per-template best scores and keep the N best templates per
-// pattern (Section 2.2, end: the list of correlations can be sorted and the N
-// best matching templates queried instead of only the best one).
+// pattern (Section 2.2, end: sorting the per-template correlations gives the N
+// best templates rather than only the best one).
 //
 // One workgroup per pattern, 4 waves; each wave streams a contiguous quarter
 // of the templates, 4 blocks of 64 per step (coalesced loads, all four in
