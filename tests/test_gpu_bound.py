@@ -208,3 +208,76 @@ def test_bound_slots_order_equals_template_order(tm, c1, c1_lib):
     assert np.array_equal(us[:, slots >= 0], ub[:, slots[slots >= 0]])
     assert (us[:, slots < 0] == 0).all()
     assert lib.bound_layout()["chunks"] * 64 == len(slots)
+
+
+def _random_case(n_theta, seed, n_templates=40, R=48, H=104, W=100, B=12):
+    """Small random library (up to 25 spots, duplicates merged) and patterns
+    of rendered templates at random angles plus noise."""
+    rng = np.random.default_rng(seed)
+    lib = small_library(n_templates, seed, max_spots=25, g_min=0.08)
+    px_per = (R - 4) / 1.2
+    cx, cy = W / 2.0, H / 2.0
+    yy, xx = np.mgrid[0:H, 0:W]
+    imgs = np.zeros((B, H, W), dtype=np.float32)
+    for b in range(B):
+        t = int(rng.integers(0, n_templates))
+        a, e = lib["offsets"][t], lib["offsets"][t + 1]
+        phi = rng.uniform(0, 2 * np.pi)
+        c, s = np.cos(phi), np.sin(phi)
+        img = 0.02 * rng.standard_normal((H, W))
+        for kx, ky, w in zip(lib["kx"][a:e], lib["ky"][a:e], lib["intensity"][a:e]):
+            x = cx + px_per * (c * kx - s * ky)
+            y = cy + px_per * (s * kx + c * ky)
+            img += w * np.exp(-((xx - x) ** 2 + (yy - y) ** 2) / (2 * 1.5 ** 2))
+        imgs[b] = img
+    return lib, imgs, px_per, R, cx, cy
+
+
+@pytest.mark.parametrize("n_theta", [64, 90, 181, 361, 720, 768])
+def test_bound_search_theta_widths_layouts_and_sizes(tm, n_theta):
+    """Windows of ceil(n_theta / 4) columns at other widths (the kernel with a
+    runtime window stride; odd widths), full and compact polar layouts, N from
+    1 to min(64, T'), B = 1 and B = 0: bounds hold and equal their window
+    sums, the search equals the plain path bit for bit."""
+    import torch
+    _say(f"bound search, n_theta {n_theta}")
+    lib_np, imgs, px_per, R, cx, cy = _random_case(n_theta, 300 + n_theta)
+    grid = tm.PolarGrid(R=R, n_theta=n_theta, cx=cx, cy=cy)
+    lib = tm.Library(lib_np["kx"], lib_np["ky"], lib_np["intensity"], lib_np["offsets"], px_per,
+                     grid)
+    assert lib.bound_layout()["win"] == -(-n_theta // 4)
+    olib = oracle.OracleLibrary.build(lib_np, px_per, R, n_theta)
+    x = torch.from_numpy(imgs).cuda()
+    full, fnorms, _ = tm.polar_transform(x, grid)
+    comp, cnorms, _ = tm.polar_transform(x, grid, lib=lib)
+    ub_f = tm.bound_scores(lib, full, fnorms).cpu().numpy()
+    ub_c = tm.bound_scores(lib, comp, cnorms).cpu().numpy()
+    assert np.array_equal(ub_f, ub_c)
+    best = tm.match_batch(lib, full, fnorms, 1, with_best=True)[3].cpu().numpy()
+    assert (ub_f >= best).all(), float((best - ub_f).max())
+    rows = np.unique(olib.J)
+    P = full.cpu().numpy().astype(np.float64)
+    pn = fnorms.cpu().numpy()
+    A = np.abs(P[:, rows]).max(axis=(1, 2))
+    wsum = np.zeros(olib.n_total)
+    np.add.at(wsum, olib.tid, olib.Wt / olib.tnorm[olib.tid])
+    cnt = np.bincount(olib.tid, minlength=olib.n_total) + 1
+    gam = cnt * 2.0 ** -24 / (1 - cnt * 2.0 ** -24)
+    for b in range(len(imgs)):
+        u64 = _window_bounds64(P[b, rows], rows, olib, pn[b])
+        assert (ub_f[b] >= u64 * (1 - 1e-7)).all()
+        assert (ub_f[b] <= u64 * (1 + 2.5e-3) + 2.5 * gam * wsum * A[b] / pn[b] + 1e-12).all()
+    Tp = lib.n_total
+    for N in sorted({1, 4, min(64, Tp)}):
+        for polar, norms in ((full, fnorms), (comp, cnorms)):
+            pt, ps, pq = (o.cpu().numpy() for o in tm.match_batch(lib, polar, norms, N))
+            bt, bs, bq = (o.cpu().numpy() for o in tm.match_batch(lib, polar, norms, N,
+                                                                  coarse="bound"))
+            assert np.array_equal(bt, pt) and np.array_equal(bs, ps) and np.array_equal(bq, pq)
+    # one pattern alone gives the same rows; an empty batch is a no-op
+    b1 = [o.cpu().numpy()[0] for o in tm.match_batch(lib, comp[5:6].contiguous(),
+                                                       cnorms[5:6].contiguous(), 4, coarse="bound")]
+    ref = [o.cpu().numpy()[5] for o in tm.match_batch(lib, comp, cnorms, 4, coarse="bound")]
+    assert all(np.array_equal(u, v) for u, v in zip(b1, ref))
+    e = tm.match_batch(lib, comp[:0], cnorms[:0], 4, coarse="bound")
+    assert e[0].shape == (0, 4)
