@@ -4,8 +4,10 @@
 // bounds of tm_bound.hip, margin 0). The N templates with the best estimates
 // (or more: n_first) are scored exactly; the N-th best of their exact scores,
 // q_N, is a lower bound of the final N-th best, so every template of the
-// final top-N has an estimate of at least q_N - margin. Those templates are then scored exactly and ranked
-// again; a pattern with more candidates than a cap is scored in full.
+// final top-N has an estimate of at least q_N - margin. Those templates
+// (other than the ones already scored) are then scored exactly and their
+// top-N merged with the first one; a pattern with more candidates than a
+// cap is scored in full.
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -20,19 +22,24 @@ constexpr int kSelThreads = 256;
 // Candidates of the certified rescoring, one workgroup per pattern: every
 // column c with Qt[b, c] >= (N-th best exact score of the rescored
 // approximate top-N) - margin, written as its template (map[c], or c), in
-// ascending column order (columns without a template are skipped). More
-// than cap: the pattern is marked for a full
-// exact scan instead. Waves own contiguous quarters of the row and compact
-// with ballots (two passes: count, then write).
+// ascending column order (columns without a template are skipped), except
+// the n_first templates already scored exactly (first[b, :]). More than cap
+// such templates in all: the pattern is marked for a full exact scan
+// instead. Waves own contiguous quarters of the row and compact with
+// ballots (two passes: count, then write).
 __global__ void __launch_bounds__(kSelThreads)
 certify_select(const float* __restrict__ Qt, int Tp, const int32_t* __restrict__ map,
                const float* __restrict__ q_exact, int N, double margin, int cap,
                int32_t* __restrict__ cand, int32_t* __restrict__ cnt, int32_t* __restrict__ full,
-               int32_t* __restrict__ n_rescored, int n_templates) {
+               int32_t* __restrict__ n_rescored, int n_templates,
+               const int32_t* __restrict__ first, int n_first) {
     constexpr int W = kSelThreads / 64;
-    __shared__ int wcount[W];
+    __shared__ int wcount[W], wnew[W];
+    __shared__ int sfirst[tmlib::kMaxN];
     const int b = blockIdx.x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (threadIdx.x < n_first) sfirst[threadIdx.x] = first[static_cast<size_t>(b) * n_first + threadIdx.x];
+    __syncthreads();
     // threshold rounded toward -inf: a template whose approximate score could
     // reach the N-th best exact score within the bound is never dropped by
     // the rounding of the subtraction
@@ -45,7 +52,13 @@ certify_select(const float* __restrict__ Qt, int Tp, const int32_t* __restrict__
     // 4 blocks of 64 columns per step, their loads issued together
     constexpr int kBlocks = 4;
     auto take_at = [&](int t, float v) { return t < hi && v >= thr && (!map || map[t] >= 0); };
-    int c = 0;
+    auto is_first = [&](int t) {
+        const int tt = map ? map[t] : t;
+        bool f = false;
+        for (int i = 0; i < n_first; ++i) f |= (sfirst[i] == tt);
+        return f;
+    };
+    int c = 0, cn = 0;
     for (int base0 = lo; base0 < hi; base0 += 64 * kBlocks) {
         float v[kBlocks];
 #pragma unroll
@@ -54,15 +67,23 @@ certify_select(const float* __restrict__ Qt, int Tp, const int32_t* __restrict__
             v[k] = t < hi ? row[t] : -INFINITY;
         }
 #pragma unroll
-        for (int k = 0; k < kBlocks; ++k)
-            c += __popcll(tmlib::ballot(take_at(base0 + 64 * k + lane, v[k])));
+        for (int k = 0; k < kBlocks; ++k) {
+            const int t = base0 + 64 * k + lane;
+            const bool tk = take_at(t, v[k]);
+            c += __popcll(tmlib::ballot(tk));
+            cn += __popcll(tmlib::ballot(tk && !is_first(t)));
+        }
     }
-    if (lane == 0) wcount[wave] = c;
+    if (lane == 0) {
+        wcount[wave] = c;
+        wnew[wave] = cn;
+    }
     __syncthreads();
-    int before = 0, total = 0;
+    int before = 0, total = 0, total_new = 0;
     for (int w = 0; w < W; ++w) {
-        before += (w < wave) ? wcount[w] : 0;
+        before += (w < wave) ? wnew[w] : 0;
         total += wcount[w];
+        total_new += wnew[w];
     }
     const bool over = total > cap;
     if (!over) {
@@ -78,7 +99,7 @@ certify_select(const float* __restrict__ Qt, int Tp, const int32_t* __restrict__
 #pragma unroll
             for (int k = 0; k < kBlocks; ++k) {
                 const int t = base0 + 64 * k + lane;
-                const bool take = take_at(t, v[k]);
+                const bool take = take_at(t, v[k]) && !is_first(t);
                 const unsigned long long m = tmlib::ballot(take);
                 if (take) out[pos + __popcll(m & ((1ull << lane) - 1))] = map ? map[t] : t;
                 pos += __popcll(m);
@@ -86,9 +107,74 @@ certify_select(const float* __restrict__ Qt, int Tp, const int32_t* __restrict__
         }
     }
     if (threadIdx.x == 0) {
-        cnt[b] = over ? 0 : total;
+        cnt[b] = over ? 0 : total_new;
         full[b] = over ? 1 : 0;
         if (n_rescored) n_rescored[b] = over ? n_templates : total;
+    }
+}
+
+// The final top-N of a pattern not scanned in full: its candidates' top-N
+// (in the output rows) merged with the top-N of the templates scored first
+// (one wave per pattern; the scorer's ranking rule; a non-finite norm is
+// flagged as the scorer flags it).
+__global__ void __launch_bounds__(256)
+merge_first(const int32_t* __restrict__ full, int B, const double* __restrict__ norms, int N,
+            const int32_t* __restrict__ ft, const int32_t* __restrict__ fs,
+            const float* __restrict__ fq, int32_t* __restrict__ top_t, int32_t* __restrict__ top_s,
+            float* __restrict__ top_q) {
+    const int lane = threadIdx.x & 63;
+    const int b = (blockIdx.x * 256 + threadIdx.x) >> 6;
+    if (b >= B || full[b]) return;
+    const size_t o = static_cast<size_t>(b) * N;
+    const double pn = norms[b];
+    if ((__double_as_longlong(pn) & 0x7ff0000000000000LL) == 0x7ff0000000000000LL) {
+        for (int i = lane; i < N; i += 64) {
+            top_t[o + i] = -1;
+            top_s[o + i] = -1;
+            top_q[o + i] = __int_as_float(0x7fc00000);
+        }
+        return;
+    }
+    // entries: 0..N-1 the candidates' list, N..2N-1 the first list (N <= 64,
+    // so at most two per lane)
+    float q[2];
+    int t[2], sh[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int e = lane + 64 * k;
+        const bool c = e < N, f = e >= N && e < 2 * N;
+        q[k] = c ? top_q[o + e] : (f ? fq[o + e - N] : -INFINITY);
+        t[k] = c ? top_t[o + e] : (f ? ft[o + e - N] : INT_MAX);
+        sh[k] = c ? top_s[o + e] : (f ? fs[o + e - N] : 0);
+    }
+    float prev_q = INFINITY;
+    int prev_t = -1;
+    int out_t = 0, out_s = 0;
+    float out_q = 0.0f;
+    for (int r = 0; r < N; ++r) {
+        float bq = -INFINITY;
+        int bt = INT_MAX, bs = 0;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const bool after = (q[k] < prev_q) || (q[k] == prev_q && t[k] > prev_t);
+            const bool better = (q[k] > bq) || (q[k] == bq && t[k] < bt);
+            if (after && better) { bq = q[k]; bt = t[k]; bs = sh[k]; }
+        }
+#pragma unroll
+        for (int x = 32; x >= 1; x >>= 1) {
+            const float oq = __shfl_xor(bq, x, 64);
+            const int ot = __shfl_xor(bt, x, 64);
+            const int os = __shfl_xor(bs, x, 64);
+            if (oq > bq || (oq == bq && ot < bt)) { bq = oq; bt = ot; bs = os; }
+        }
+        if (lane == r) { out_t = bt; out_s = bs; out_q = bq; }
+        prev_q = bq;
+        prev_t = bt;
+    }
+    if (lane < N) {
+        top_t[o + lane] = out_t;
+        top_s[o + lane] = out_s;
+        top_q[o + lane] = out_q;
     }
 }
 
@@ -300,7 +386,7 @@ int tmlib::certified_rescore(const tm_library* lib, const float* polar, const do
     // 2. every template whose estimate reaches q_N - margin
     if (!r) {
         hipLaunchKernelGGL(certify_select, dim3(B), dim3(kSelThreads), 0, s, Qt, n_cols, map, q1, N,
-                           margin, cap, cand, cnt, full, n_rescored, Tp);
+                           margin, cap, cand, cnt, full, n_rescored, Tp, t0, n_first);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) r = tmlib::hip_fail(e, "certify_select launch");
     }
@@ -337,6 +423,12 @@ int tmlib::certified_rescore(const tm_library* lib, const float* polar, const do
         return TM_OK;
     };
     if (!r) r = pass(false);
+    if (!r) {
+        hipLaunchKernelGGL(merge_first, dim3(static_cast<unsigned>((B + 3) / 4)), dim3(256), 0, s, full,
+                           B, norms, N, t1, s1, q1, top_template, top_angle, top_score);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) r = tmlib::hip_fail(e, "merge_first launch");
+    }
     if (!r) r = pass(true);
     for (void* p : {static_cast<void*>(t0), static_cast<void*>(s0), static_cast<void*>(q0),
                     static_cast<void*>(t1), static_cast<void*>(s1), static_cast<void*>(q1),
