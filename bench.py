@@ -165,6 +165,7 @@ def time_steps(step, steps, warmup, n_marks=3):
 # Sources that define each kernel whose traffic the benchmark reports.
 KERNEL_SOURCES = {
     "match_kernel": ("tm_match.hip", "tm_library.hip", "tm_topn.h"),
+    "bound_kernel": ("tm_bound.hip",),
     "polar_kernel": ("tm_polar.hip",),
     "fft_": ("tm_fft.hip",),
 }
@@ -187,10 +188,16 @@ def recorded_traffic(cid, kernel_prefix):
         src = os.path.join(ROOT, "paper_2111_07347_amd", "csrc", f)
         if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != h:
             return None
-    for k, v in rec["traffic_bytes_per_launch"].items():
-        if k.startswith(kernel_prefix):
-            return v["fetch_bytes"] + v["write_bytes"]
-    return None
+    keys = [k for k in rec["traffic_bytes_per_launch"] if k.startswith(kernel_prefix)]
+    if kernel_prefix == "match_kernel":
+        # the exhaustive scan's launch: the grouped-record instance (G = 3),
+        # whose launches all cover the whole batch
+        grouped = [k for k in keys if k.split("<")[1].split(",")[1].strip() == "3"]
+        keys = grouped or keys
+    if not keys:
+        return None
+    v = rec["traffic_bytes_per_launch"][keys[0]]
+    return v["fetch_bytes"] + v["write_bytes"]
 
 
 def _angle_margins(args):
@@ -425,7 +432,9 @@ def bound_leg(tm, sc, plain_top, steps, warmup, cid):
                                  "full_scan_fraction": round(float(np.mean(nrn == sc.lib.n_total)), 6)},
         "roofline": {"bound": "alu", "kernel": "bound_kernel", "achieved": round(tf, 3),
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(tf / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(tf / FP32_PEAK_TFLOPS, 4),
+                     "traffic": recorded_traffic(cid, "bound_kernel"),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "kernel_ms": round(bound_ms, 4),
                      "work_per_launch": {"flops": flops, "patterns": B,
                                          "template_pixels": sc.info["n_spots"],
