@@ -414,11 +414,11 @@ def bound_leg(tm, sc, plain_top, steps, warmup, cid):
     polar_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     flops = 2.0 * B * sc.info["n_spots"] * 4
     tf = flops / (bound_ms * 1e-3) / 1e12
-    # LDS: per record unit and wave 16 two-byte window reads per lane (4
-    # records x 4 coarse shifts), each returning a 4-byte lane word; the
-    # algorithmic reads are one 2-byte value per template pixel and shift
+    # LDS: per record unit and wave 8 dword reads per lane (4 records x 2
+    # pairs of float16 window maxima); the algorithmic reads are one 2-byte
+    # value per template pixel and shift
     bl = sc.lib.bound_layout()
-    lds_phys = float(B) * bl["units"] * 16 * 64 * 4
+    lds_phys = float(B) * bl["units"] * 8 * 64 * 4
     lds_alg = float(B) * sc.info["n_spots"] * 4 * 2
     rec_bytes = float(B) * bl["units"] * 1024
     res = {
@@ -441,7 +441,7 @@ def bound_leg(tm, sc, plain_top, steps, warmup, cid):
                                          "coarse_shifts": 4},
                      "nonpacked_fp32": {"peak": FP32_NONPACKED_TFLOPS,
                                         "frac": round(tf / FP32_NONPACKED_TFLOPS, 4)},
-                     "lds": {"note": "the kernel is bound by LDS reads of window maxima",
+                     "lds": {"note": "LDS reads of paired window maxima (one read2 per record)",
                              "algorithmic_bytes": lds_alg,
                              "algorithmic_gbs": round(lds_alg / (bound_ms * 1e-3) / 1e9, 1),
                              "physical_bytes": lds_phys,

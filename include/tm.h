@@ -632,19 +632,23 @@ int tm_fft_scores(const tm_library* lib, const float* polar, const double* norms
  * lets the certified rescoring skip templates that cannot reach the top-N).
  *
  * With non-negative template weights, for the window of win = ceil(n_theta
- * / 4) consecutive shifts starting at S win (S = 0..3, shifts mod n_theta):
- *   C(s) = sum_i w_i P[j_i, k_i + s] <= sum_i w_i M[j_i, k_i + S win],
- *   M[j, x] = max(0, max_{0 <= d < win} P[j, (x + d) mod n_theta]),
- * and the largest of the 4 window sums bounds max_s Q(b, t, s) of Eq. (1).
+ * / 4) consecutive shifts starting at S win (S = 0..3, columns mod n_theta):
+ *   C(s) = sum_i w_i P[j_i, k_i + s] <= sum_i w_i M[j_i, k_i + S win - e_iS],
+ *   M[j, x] = max(0, max_{0 <= d < wlen} P[j, x + d]),
+ * where dl = 4 win - n_theta, wlen = min(win + dl, n_theta), and e_iS = dl
+ * for spots with k_i >= 2 win at S = 2, 3, else 0 (the window image pairs
+ * columns 2 win apart; with 4 | n_theta, dl = 0 and wlen = win). The
+ * largest of the 4 window sums bounds max_s Q(b, t, s) of Eq. (1).
  * The window maxima and weights are rounded up to float16 (scaled), summed
  * in float32, and the stored bound is widened by the worst-case float32
  * rounding of both the bound and the plain path's own sum, so that
  *   bound_out[b, t] >= the float32 Q that tm_match_batch computes.
  *
  * Arguments
- *   lib           loaded library (all weights >= 0; the window image of the
- *                 touched rows plus one, (rows + 1) x (n_theta + 3 win)
- *                 float16, must fit 128 KiB of LDS, else TM_EUNSUPPORTED).
+ *   lib           loaded library (all weights >= 0, n_theta >= 16; the
+ *                 window image of the touched rows plus one, (rows + 1) x
+ *                 3 win pairs of float16, must fit 128 KiB of LDS, else
+ *                 TM_EUNSUPPORTED).
  *   polar, norms  as in tm_match_batch; compact_rows as in tm_fft_scores.
  *   B             >= 0 (0 is a no-op).
  *   bound_out     device, [B, T'] float32, written. A pattern with a
@@ -670,11 +674,13 @@ int tm_bound_scores_slots(const tm_library* lib, const float* polar, const doubl
  * (the same exact-search aid as tm_bound_scores).
  *   chunks  out (nullable): chunks of 64 templates, one template per lane.
  *   units   out (nullable): record units per pattern (each 4 records per
- *           lane, 1 KiB per wave; a chunk's templates are padded to its
- *           largest pixel count plus the margin record).
+ *           lane, 1 KiB per wave; in a chunk each template's two half-turns
+ *           of pixels, the margin record joining the smaller, are padded to
+ *           the chunk's largest, in whole units).
  *   win     out (nullable): shifts per coarse window, ceil(n_theta / 4).
  * Errors: TM_EINVAL (lib NULL), TM_EUNSUPPORTED (no window bounds for this
- * library: a negative weight or an image over the LDS budget). */
+ * library: a negative weight, n_theta < 16 or an image over the LDS
+ * budget). */
 int tm_bound_layout(const tm_library* lib, int32_t* chunks, int64_t* units, int32_t* win);
 
 /* tm_fft_error_bound - a-priori bound eps with |Q~ - Q32| <= eps for every

@@ -5,14 +5,16 @@
 // n_theta columns of the polar image and keeps its best Q of Eq. (1). Most
 // templates are far from the best ones, and for them a cheap bound settles
 // the matter. With non-negative template weights w_i, for any window of
-// `win` consecutive shifts starting at coarse shift S (s = S win + d,
-// 0 <= d < win):
+// `win` = ceil(n_theta / 4) consecutive shifts starting at coarse shift S
+// (s = S win + d, 0 <= d < win; S = 0 .. 3 covers every shift):
 //
 //   C(s) = sum_i w_i P[j_i, k_i + s] <= sum_i w_i M[j_i, k_i + S win],
-//   M[j, x] = max(0, max_{0 <= d < win} P[j, (x + d) mod n_theta]),
+//   M[j, x] = max(0, max_{0 <= d < wlen} P[j, (x + d) mod n_theta]),
 //
-// so one product per spot and coarse shift bounds a whole window of shifts,
-// and the maximum over the coarse shifts bounds the template's best score.
+// (columns mod n_theta; wlen = win + 4 win - n_theta, i.e. win when 4
+// divides n_theta, see below), so one product per spot and coarse shift
+// bounds a whole window of shifts, and the maximum over the coarse shifts
+// bounds the template's best score.
 // The bounds feed the certified rescoring (tm_certify.hip) with margin 0:
 // the N templates with the largest bounds are scored exactly, every
 // template whose bound reaches their N-th best exact score is scored
@@ -36,31 +38,48 @@
 // rounded up, which is at least the plain path's float32 Q_t of every
 // template.
 //
+// Half-turn pairing. The shifts S and S + 2 of a pixel read columns 2 win
+// apart, so the window image is stored as pairs, one dword per column c in
+// [0, 3 win) of a row:
+//
+//   Y[j, c] = (M[j, c], M[j, c + 2 win])      (float16 each, columns mod n)
+//
+// A pixel in the first half-turn (k < 2 win) reads Y[c] and Y[c + win] at
+// c = k: their low halves are shifts 0 and 1, the high halves shifts 2 and
+// 3. A pixel in the second half-turn (c = k - 2 win) reads the same two
+// dwords with the halves' roles swapped: Y[c].hi is M[k] (shift 0),
+// Y[c + win].hi is M[k + win] (shift 1), and Y[c].lo = M[c] stands for
+// M[k + 2 win] = M[c + 4 win - n], which it covers because its window is
+// 4 win - n columns wider (the same for shift 3). So every record costs two
+// 32-bit LDS reads for its 4 window maxima, and a row takes 3 win dwords.
+// A lane processes one half-turn of its template, then the other (its
+// larger one first); between the two every lane swaps its shift-0/2 and
+// shift-1/3 accumulators, which keeps the update the same for all lanes.
+//
 // Kernel layout (one workgroup per pattern):
-//   * the window image M of the library's touched rows is built in LDS in
-//     float16, rows of n_theta + 3 win columns (a halo past n_theta), so the
-//     4 coarse shifts of a pixel at column k read columns k + win S without
-//     any modulo;
-//   * a lane scores one template over the 4 coarse shifts S (windows of
-//     win = ceil(n_theta / 4) columns), a wave 64 templates at a time:
-//     templates are sorted by pixel count and cut into chunks of 64, all
-//     lanes of a chunk running the same number of steps (zero-weight
-//     padding to whole units of 4 steps);
+//   * the window image Y of the library's touched rows is built in LDS;
+//   * a lane scores one template over the 4 coarse shifts S, a wave 64
+//     templates at a time: templates are sorted by the pixel counts of
+//     their half-turns and cut into chunks of 64; in a chunk all lanes run
+//     the same number of steps in each half (zero-weight padding to whole
+//     units of 4 steps);
 //   * a lane's records come 4 at a time in one 16-byte load (a wave loads
 //     1 KiB of consecutive bytes per unit, 3 units ahead of their use); the
-//     last unit of a chunk carries a flag (the sign bit of its last weights,
-//     cleared before use);
+//     last unit of a chunk's first half and of the chunk carry flags in
+//     the sign bits of their last weights (the multiply-adds take the
+//     weights' absolute values);
 //   * each template's margin term (below) is one more record: its weight
 //     the margin factor, its window maxima read from an extra image row
-//     that holds the largest |P| (scaled, rounded up) in every column;
-//   * per record: one address multiply-add, 4 LDS reads of a float16 window
-//     maximum and 4 mixed float16 x float16 + float32 multiply-adds; the
-//     library orders each step's records over the lanes so that the reads
-//     of a half-wave fall on distinct LDS banks (or the same dword) where
-//     possible, which sets the kernel's speed: it is bound by LDS reads;
+//     that holds the largest |P| (scaled, rounded up) in every half;
+//   * per record: one address multiply-add, 2 LDS reads of a pair of
+//     float16 window maxima and 4 mixed float16 x float16 + float32
+//     multiply-adds; the library orders each step's records over the
+//     lanes so that the reads of a half-wave fall on distinct LDS banks (or
+//     the same dword) where possible;
 //   * a chunk's bounds leave as one coalesced 256-byte store, in chunk-slot
 //     order (the library's slot -> template map goes with them).
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -80,7 +99,7 @@ constexpr int kImageExp = 14;              // window maxima scaled below 2^14
 constexpr size_t kLdsBudget = 128 * 1024;  // window image (16-bit offsets)
 constexpr int kFirst = 32;                 // best bounds scored exactly first
 constexpr int kMaxCols = 12;               // window columns per lane (n_theta <= 768)
-constexpr uint32_t kFlag = 0x80000000u;    // chunk end: sign bit of a unit's last weights
+constexpr uint32_t kFlag = 0x80000000u;    // a weight's sign bit: end of a half or a chunk
 
 // ---------------------------------------------------------------- host side
 
@@ -102,6 +121,7 @@ uint16_t half_up(float x) {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) const uint16_t lds_u16;
+typedef __attribute__((address_space(3))) const uint32_t lds_u32;
 
 __device__ __forceinline__ float h2f(uint32_t bits16) {
     return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(bits16)));
@@ -115,49 +135,56 @@ __device__ __forceinline__ uint16_t f16_up(float x) {
     return b;
 }
 
-// LDS byte address of a record's first window value: the record's 16-bit
-// half offset times 2 plus the image base, in one multiply-add of the low
-// 16 bits (v_mad_u32_u16).
+// LDS byte address of a record's first pair: the record's 16-bit dword
+// offset times 4 plus the image base, in one multiply-add of the low 16
+// bits (v_mad_u32_u16).
 __device__ __forceinline__ uint32_t rec_addr(uint32_t rec, uint32_t base) {
     uint32_t a;
-    asm("v_mad_u32_u16 %0, %1, 2, %2" : "=v"(a) : "v"(rec), "v"(base));
+    asm("v_mad_u32_u16 %0, %1, 4, %2" : "=v"(a) : "v"(rec), "v"(base));
     return a;
 }
 
-// The LDS reads of one unit of a lane's records (4 steps): the 4 coarse
-// shifts' window maxima of each record (win halves apart), issued without
-// waiting; the address uses only a record's low 16 bits (the end flag in
-// bit 31 does not matter here).
+constexpr int kPairs = 2;                  // 32-bit LDS reads per record
+
+// The LDS reads of one unit of a lane's records (4 steps): the two pairs of
+// each record (win dwords apart), issued without waiting; the address uses
+// only a record's low 16 bits.
 template <int WIN>
 __device__ __forceinline__ void read_unit(const u32x4 R, uint32_t base, int win,
-                                          float (&v)[kUnitSteps * kShifts]) {
+                                          uint32_t (&v)[kUnitSteps * kPairs]) {
 #pragma unroll
     for (int u = 0; u < kUnitSteps; ++u) {
-        lds_u16* p = reinterpret_cast<lds_u16*>(static_cast<uintptr_t>(rec_addr(R[u], base)));
-#pragma unroll
-        for (int S = 0; S < kShifts; ++S) v[u * kShifts + S] = h2f(p[S * (WIN ? WIN : win)]);
+        lds_u32* p = reinterpret_cast<lds_u32*>(static_cast<uintptr_t>(rec_addr(R[u], base)));
+        v[u * kPairs] = p[0];
+        v[u * kPairs + 1] = p[WIN ? WIN : win];
     }
 }
 
-// The multiply-adds of one unit (weights without the end flag).
-__device__ __forceinline__ void fma_unit(const u32x4 R, const float (&v)[kUnitSteps * kShifts],
+// The multiply-adds of one unit: acc[0], acc[2] from the first pair's low
+// and high halves, acc[1], acc[3] from the second's; weights by absolute
+// value (their sign bits carry the flags).
+__device__ __forceinline__ void fma_unit(const u32x4 R, const uint32_t (&v)[kUnitSteps * kPairs],
                                          float (&acc)[kShifts]) {
 #pragma unroll
-    for (int u = 0; u < kUnitSteps; ++u)
-#pragma unroll
-        for (int S = 0; S < kShifts; ++S)
-            acc[S] = fmaf(h2f(R[u] >> 16), v[u * kShifts + S], acc[S]);
+    for (int u = 0; u < kUnitSteps; ++u) {
+        const float w = fabsf(h2f(R[u] >> 16));
+        acc[0] = fmaf(w, h2f(v[u * kPairs]), acc[0]);
+        acc[2] = fmaf(w, h2f(v[u * kPairs] >> 16), acc[2]);
+        acc[1] = fmaf(w, h2f(v[u * kPairs + 1]), acc[1]);
+        acc[3] = fmaf(w, h2f(v[u * kPairs + 1] >> 16), acc[3]);
+    }
 }
 
-// WIN > 0: the window width as a constant (the reads' offsets become
-// immediates of the LDS instructions); 0: taken from win.
+// WIN > 0: win as a constant (the second read's offset becomes an
+// immediate of the LDS instruction); 0: taken from win. Image rows are Lrow
+// (= 3 win) dwords; wlen is the width of the window maxima.
 template <int NW, int WIN>
 __global__ void __launch_bounds__(NW * 64)
 bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, int Rs, int n,
-             const int* __restrict__ rows, int n_rows, int Lrow, int win,
+             const int* __restrict__ rows, int n_rows, int Lrow, int win, int wlen,
              const u32x4* __restrict__ recs, const int* __restrict__ chunk_end,
              const int* __restrict__ part, int n_cs, float dfac, float* __restrict__ Qc) {
-    extern __shared__ uint16_t m16[];        // window image
+    extern __shared__ uint16_t m16[];        // window image: pairs of halves
     __shared__ float red[NW];
     const int b = blockIdx.x;
     const int lane = threadIdx.x & 63;
@@ -185,16 +212,17 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
     int e = 0;
     (void)frexpf(A, &e);                        // A = m 2^e, m in [0.5, 1)
     const float scale = A > 0.0f ? ldexpf(1.0f, kImageExp - e) : 1.0f;
-    // 2. window maxima (clamped at 0), scaled, rounded up to float16. The
-    // image is periodic (M[x + n] = M[x]): lane l computes the o consecutive
-    // columns x0 = o l .. x0 + o - 1 of [0, n) from the o + win - 1 values
-    // they span: the maximum of the part every window shares, then the
-    // head's suffix maxima and the tail's prefix maxima; each column is
-    // stored at x and, inside the halo, at x + n (and x + 2n for n < 6).
+    // 2. window maxima (clamped at 0), scaled, rounded up to float16. M is
+    // periodic (M[x + n] = M[x]): lane l computes the o consecutive columns
+    // x0 = o l .. x0 + o - 1 of [0, n) from the o + wlen - 1 values they
+    // span: the maximum of the part every window shares, then the head's
+    // suffix maxima and the tail's prefix maxima. Column x is the low half
+    // of Y[x] (if x < Lrow) and the high half of Y[c], c + 2 win = x (mod
+    // n), if c < Lrow (Lrow = 3 win < n: at most one of each).
     const int o = (n + 63) / 64;                 // columns per lane (<= kMaxCols)
     for (int r = wave; r < n_rows; r += NW) {
         const float* row = src + static_cast<size_t>(rows ? rows[r] : r) * n;
-        uint16_t* dst = m16 + static_cast<size_t>(r) * Lrow;
+        uint16_t* dst = m16 + static_cast<size_t>(r) * Lrow * 2;
         const int x0 = o * lane;
         if (x0 < n) {
             auto at = [&](int j) {
@@ -203,11 +231,11 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
             };
             // loads are issued in independent batches (indices clamped, not
             // branched on), so they are in flight together
-            float common = 0.0f;                 // columns o - 1 .. win - 1 of the span
-            for (int j = o - 1; j < win; j += 8) {
+            float common = 0.0f;                 // columns o - 1 .. wlen - 1 of the span
+            for (int j = o - 1; j < wlen; j += 8) {
                 float v[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = at(min(j + u, win - 1));
+                for (int u = 0; u < 8; ++u) v[u] = at(min(j + u, wlen - 1));
 #pragma unroll
                 for (int u = 0; u < 8; ++u) common = fmaxf(common, v[u]);
             }
@@ -215,7 +243,7 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
 #pragma unroll
             for (int d = 0; d < kMaxCols; ++d) {
                 hv[d] = at(min(d, max(o - 2, 0)));          // head: columns 0 .. o - 2
-                tv[d] = at(win - 1 + min(max(d, 1), o - 1));  // tail: columns win .. win + o - 2
+                tv[d] = at(wlen - 1 + min(max(d, 1), o - 1));  // tail: columns wlen .. wlen + o - 2
             }
             float out[kMaxCols];
             float hmax = common, tmax = common;
@@ -234,7 +262,9 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
                 const int x = x0 + d;
                 if (d < o && x < n) {
                     const uint16_t h = f16_up(out[d] * scale);
-                    for (int xx = x; xx < Lrow; xx += n) dst[xx] = h;
+                    if (x < Lrow) dst[2 * x] = h;
+                    const int c = x - 2 * win + (x < 2 * win ? n : 0);
+                    if (c < Lrow) dst[2 * c + 1] = h;
                 }
             }
         }
@@ -243,8 +273,8 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
     // the extra row n_rows: A scaled, rounded up (the margin records' value)
     {
         const uint16_t h = f16_up(A * scale);
-        uint16_t* dst = m16 + static_cast<size_t>(n_rows) * Lrow;
-        for (int x = threadIdx.x; x < Lrow; x += NW * 64) dst[x] = h;
+        uint16_t* dst = m16 + static_cast<size_t>(n_rows) * Lrow * 2;
+        for (int x = threadIdx.x; x < 2 * Lrow; x += NW * 64) dst[x] = h;
     }
     __syncthreads();
     // 3. bounds: per template Q^ = ((m out_scale) dfac) invP (1 + 2^-19), m
@@ -271,21 +301,30 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
     float acc[kShifts];
 #pragma unroll
     for (int S = 0; S < kShifts; ++S) acc[S] = 0.0f;
-    // consume a unit whose reads are in v: multiply-adds, then at a chunk's
-    // end its bounds (one coalesced store) and fresh accumulators
-    auto consume = [&](u32x4 R, const float (&v)[kUnitSteps * kShifts]) {
+    // consume a unit whose reads are in v: multiply-adds; at the end of a
+    // chunk's first half (flag on the last weight only) the accumulators of
+    // shifts 0/2 and 1/3 trade places; at a chunk's end (flags on the last
+    // two weights) its bounds (one coalesced store) and fresh accumulators
+    auto consume = [&](const u32x4 R, const uint32_t (&v)[kUnitSteps * kPairs]) {
         const uint32_t flag = __builtin_amdgcn_readfirstlane(R[3]) & kFlag;
-        R[3] &= ~kFlag;
         fma_unit(R, v, acc);
         if (flag) {
-            float m = acc[0];
+            if (__builtin_amdgcn_readfirstlane(R[2]) & kFlag) {
+                float m = acc[0];
 #pragma unroll
-            for (int S = 1; S < kShifts; ++S) m = fmaxf(m, acc[S]);
-            qrow[static_cast<size_t>(c) * kLanes + lane] =
-                ((m * out_scale) * dfac) * invP * (1.0f + 0x1p-19f);
-            ++c;
+                for (int S = 1; S < kShifts; ++S) m = fmaxf(m, acc[S]);
+                qrow[static_cast<size_t>(c) * kLanes + lane] =
+                    ((m * out_scale) * dfac) * invP * (1.0f + 0x1p-19f);
+                ++c;
 #pragma unroll
-            for (int S = 0; S < kShifts; ++S) acc[S] = 0.0f;
+                for (int S = 0; S < kShifts; ++S) acc[S] = 0.0f;
+            } else {
+                const float t0 = acc[0], t1 = acc[1];
+                acc[0] = acc[2];
+                acc[1] = acc[3];
+                acc[2] = t0;
+                acc[3] = t1;
+            }
         }
     };
     // Units stream through four registers g0..g3, each reloaded with the
@@ -298,7 +337,7 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
     u32x4 g1 = U[static_cast<size_t>(min(u_begin + 1, last)) * kLanes];
     u32x4 g2 = U[static_cast<size_t>(min(u_begin + 2, last)) * kLanes];
     u32x4 g3 = U[static_cast<size_t>(min(u_begin + 3, last)) * kLanes];
-    float va[kUnitSteps * kShifts], vb[kUnitSteps * kShifts];
+    uint32_t va[kUnitSteps * kPairs], vb[kUnitSteps * kPairs];
     auto ld = [&](int k) { return U[static_cast<size_t>(min(k, last)) * kLanes]; };
 #define TM_BOUND_SB __builtin_amdgcn_sched_barrier(0)
     int u = u_begin;
@@ -360,122 +399,145 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
     for (const auto& v : pix)
         for (const HostPixel& p : v)
             if (!(p.w >= 0.0)) return TM_OK;           // bounds need non-negative weights
+    // (n_theta >= 16, so that 3 win < n_theta and 2 win <= n_theta)
+    if (n < 16) return TM_OK;
     const int win = (n + kShifts - 1) / kShifts;
-    // window image rows of n + 3 win columns (a halo past n), read at
-    // k + win S for the 4 coarse shifts S
-    const uint32_t sstride = static_cast<uint32_t>(win);
-    int Lrow = n + (kShifts - 1) * win;
-    Lrow += Lrow & 1;
+    // window image rows of 3 win dwords (pairs of float16 window maxima),
+    // read at c and c + win
+    const int Lrow = 3 * win;
     // rows: the touched ones, then one holding A (the margin records' value)
-    const size_t halves = static_cast<size_t>(L->n_rows + 1) * Lrow;
-    if (halves * 2 > kLdsBudget || halves > 65536) return TM_OK;   // window image too large
+    const size_t dwords = static_cast<size_t>(L->n_rows + 1) * Lrow;
+    if (dwords * 4 > kLdsBudget || dwords > 65536) return TM_OK;   // window image too large
     const uint32_t a_row = static_cast<uint32_t>(L->n_rows) * Lrow;
 
-    // per template: records (offset, float16 weight), pixel count, margin factor
-    std::vector<std::vector<uint32_t>> tr(Tp);
-    std::vector<int32_t> cnt(Tp, 0);
+    // per template and half-turn (k < 2 win, k >= 2 win): records (dword
+    // offset, float16 weight); the larger half comes first
+    std::vector<std::array<std::vector<uint32_t>, 2>> tr(Tp);
+    std::vector<int32_t> big(Tp, 0), small(Tp, 0);
     int nmax = 0;
     for (int32_t tt = 0; tt < Tp; ++tt) {
         const int32_t t = tt < T ? tt : tt - T;
         const bool is_mirror = tt >= T;
         const double nrm = L->tnorm[t];
         double wsum = 0.0;
+        std::array<std::vector<uint32_t>, 2> hv;
         for (const HostPixel& p : pix[t]) {
             const int k = is_mirror ? (n - p.k) % n : p.k;
+            const int h = k >= 2 * win ? 1 : 0;
             const float w32 = nrm > 0.0 ? static_cast<float>(p.w / nrm) : 0.0f;
             wsum += w32;
             const uint32_t off = static_cast<uint32_t>(row_index[p.j]) * Lrow +
-                                 static_cast<uint32_t>(k);
+                                 static_cast<uint32_t>(k - 2 * win * h);
             const uint32_t w16 = half_up(std::ldexp(w32, kWeightExp));
-            tr[tt].push_back(off | (w16 << 16));
+            hv[h].push_back(off | (w16 << 16));
         }
-        cnt[tt] = static_cast<int32_t>(pix[t].size());
-        nmax = std::max(nmax, cnt[tt]);
-        // the margin record: weight c_t 2^10 (rounded up), value A
-        const double cf = gamma32(cnt[tt]) * wsum * (1.0 + 0x1p-20);
+        const int cnt = static_cast<int>(pix[t].size());
+        nmax = std::max(nmax, cnt);
+        // the margin record: weight c_t 2^10 (rounded up), value A (one
+        // place for all: a broadcast read), in the smaller half
+        const double cf = gamma32(cnt) * wsum * (1.0 + 0x1p-20);
         const uint32_t c16 = half_up(static_cast<float>(std::ldexp(cf, kWeightExp) * (1.0 + 0x1p-20)));
-        tr[tt].push_back(a_row | (c16 << 16));   // one place for all: a broadcast read
-        ++cnt[tt];
+        hv[hv[0].size() <= hv[1].size() ? 0 : 1].push_back(a_row | (c16 << 16));
+        if (hv[0].size() < hv[1].size()) std::swap(hv[0], hv[1]);
+        big[tt] = static_cast<int32_t>(hv[0].size());
+        small[tt] = static_cast<int32_t>(hv[1].size());
+        tr[tt] = std::move(hv);
     }
-    // chunks of 64 templates of similar size
+    // chunks of 64 templates of similar half sizes
     std::vector<int32_t> order(Tp);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int32_t a, int32_t b) { return cnt[a] > cnt[b]; });
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return big[a] != big[b] ? big[a] > big[b] : small[a] > small[b];
+    });
     const int32_t n_chunks = (Tp + kLanes - 1) / kLanes;
     std::vector<int32_t> tid(static_cast<size_t>(n_chunks) * kLanes, -1);
     std::vector<int32_t> cend(n_chunks, 0);
     std::vector<uint32_t> recs;
-    // LDS bank model of the window reads: kBanks banks of 4 bytes, lanes
-    // grouped in half-waves; the dword of a record's read at shift S
+    // LDS bank model of the pair reads: kBanks banks of 4 bytes, lanes
+    // grouped in half-waves; the dword of a record's read r
     const int nbanks = kBanks, group = kLanes / 2;
-    auto dword = [&](uint32_t rec, int S) { return ((rec & 0xffffu) + S * sstride) / 2; };
+    auto dword = [&](uint32_t rec, int r) { return (rec & 0xffffu) + r * static_cast<uint32_t>(win); };
+    auto whole = [](int m) { return std::max(kUnitSteps, (m + kUnitSteps - 1) / kUnitSteps * kUnitSteps); };
     for (int32_t c = 0; c < n_chunks; ++c) {
-        int m = 0;
+        int mh[2] = {0, 0};
         for (int l = 0; l < kLanes; ++l) {
             const int32_t idx = c * kLanes + l;
             tid[idx] = idx < Tp ? order[idx] : -1;
-            if (tid[idx] >= 0) m = std::max(m, cnt[tid[idx]]);
-        }
-        m = std::max(kUnitSteps, (m + kUnitSteps - 1) / kUnitSteps * kUnitSteps);   // whole units
-        // per step one record per lane, chosen so that the lanes of each
-        // half-wave read distinct banks where possible (a template's records
-        // may come in any order: the bound's sum and its margin do not
-        // depend on it); padding (weight 0) reads a free bank of row 0
-        std::vector<std::vector<uint32_t>> left(kLanes);
-        for (int l = 0; l < kLanes; ++l)
-            if (tid[c * kLanes + l] >= 0) left[l] = tr[tid[c * kLanes + l]];
-        std::vector<uint32_t> step(static_cast<size_t>(m) * kLanes, 0u);
-        for (int i = 0; i < m; ++i) {
-            // per shift and bank: the first dword read there and the number
-            // of distinct dwords (a second lane on the same dword is free)
-            std::vector<uint32_t> first(static_cast<size_t>(kShifts) * nbanks);
-            std::vector<uint8_t> ndist(static_cast<size_t>(kShifts) * nbanks);
-            for (int l = 0; l < kLanes; ++l) {
-                if (l % group == 0) std::fill(ndist.begin(), ndist.end(), 0);
-                auto cost = [&](uint32_t rec) {
-                    int k = 0;
-                    for (int S = 0; S < kShifts; ++S) {
-                        const uint32_t d = dword(rec, S);
-                        const size_t ix = static_cast<size_t>(S) * nbanks + d % nbanks;
-                        if (ndist[ix] && first[ix] != d) k += ndist[ix];
-                    }
-                    return k;
-                };
-                auto take = [&](uint32_t rec) {
-                    for (int S = 0; S < kShifts; ++S) {
-                        const uint32_t d = dword(rec, S);
-                        const size_t ix = static_cast<size_t>(S) * nbanks + d % nbanks;
-                        if (!ndist[ix]) { first[ix] = d; ndist[ix] = 1; }
-                        else if (first[ix] != d && ndist[ix] < 255) ++ndist[ix];
-                    }
-                    step[static_cast<size_t>(i) * kLanes + l] = rec;
-                };
-                auto& L_ = left[l];
-                if (L_.empty()) {
-                    uint32_t pad = 0;
-                    int best_c = 99;
-                    for (uint32_t h = 0; h < 64 && h + (kShifts - 1) * sstride < static_cast<uint32_t>(Lrow); h += 2) {
-                        const int k = cost(h);
-                        if (k < best_c) { best_c = k; pad = h; }
-                        if (k == 0) break;
-                    }
-                    take(pad);
-                    continue;
-                }
-                size_t best = 0;
-                int best_c = 99;
-                const size_t lim = std::min<size_t>(L_.size(), kChoices);
-                for (size_t e = 0; e < lim && best_c > 0; ++e) {
-                    const int k = cost(L_[e]);
-                    if (k < best_c) { best_c = k; best = e; }
-                }
-                take(L_[best]);
-                L_.erase(L_.begin() + static_cast<long>(best));
+            if (tid[idx] >= 0) {
+                mh[0] = std::max(mh[0], big[tid[idx]]);
+                mh[1] = std::max(mh[1], small[tid[idx]]);
             }
         }
-        // the chunk's last records carry the flag (a weight's sign bit)
-        for (int l = 0; l < kLanes; ++l) step[static_cast<size_t>(m - 1) * kLanes + l] |= kFlag;
+        mh[0] = whole(mh[0]);                   // whole units per half
+        mh[1] = whole(mh[1]);
+        const int m = mh[0] + mh[1];
+        std::vector<uint32_t> step(static_cast<size_t>(m) * kLanes, 0u);
+        for (int h = 0; h < 2; ++h) {
+            // per step one record per lane, chosen so that the lanes of each
+            // half-wave read distinct banks where possible (a template's
+            // records may come in any order within a half: the bound's sum
+            // and its margin do not depend on it); padding (weight 0) reads
+            // a free bank of row 0
+            std::vector<std::vector<uint32_t>> left(kLanes);
+            for (int l = 0; l < kLanes; ++l)
+                if (tid[c * kLanes + l] >= 0) left[l] = tr[tid[c * kLanes + l]][h];
+            for (int i = h ? mh[0] : 0; i < (h ? m : mh[0]); ++i) {
+                // per read and bank: the first dword read there and the
+                // number of distinct dwords (a second lane on the same dword
+                // is free)
+                std::vector<uint32_t> first(static_cast<size_t>(kPairs) * nbanks);
+                std::vector<uint8_t> ndist(static_cast<size_t>(kPairs) * nbanks);
+                for (int l = 0; l < kLanes; ++l) {
+                    if (l % group == 0) std::fill(ndist.begin(), ndist.end(), 0);
+                    auto cost = [&](uint32_t rec) {
+                        int k = 0;
+                        for (int r = 0; r < kPairs; ++r) {
+                            const uint32_t d = dword(rec, r);
+                            const size_t ix = static_cast<size_t>(r) * nbanks + d % nbanks;
+                            if (ndist[ix] && first[ix] != d) k += ndist[ix];
+                        }
+                        return k;
+                    };
+                    auto take = [&](uint32_t rec) {
+                        for (int r = 0; r < kPairs; ++r) {
+                            const uint32_t d = dword(rec, r);
+                            const size_t ix = static_cast<size_t>(r) * nbanks + d % nbanks;
+                            if (!ndist[ix]) { first[ix] = d; ndist[ix] = 1; }
+                            else if (first[ix] != d && ndist[ix] < 255) ++ndist[ix];
+                        }
+                        step[static_cast<size_t>(i) * kLanes + l] = rec;
+                    };
+                    auto& L_ = left[l];
+                    if (L_.empty()) {
+                        uint32_t pad = 0;
+                        int best_c = 99;
+                        for (uint32_t x = 0; x < 64 && x + win < static_cast<uint32_t>(Lrow); ++x) {
+                            const int k = cost(x);
+                            if (k < best_c) { best_c = k; pad = x; }
+                            if (k == 0) break;
+                        }
+                        take(pad);
+                        continue;
+                    }
+                    size_t best = 0;
+                    int best_c = 99;
+                    const size_t lim = std::min<size_t>(L_.size(), kChoices);
+                    for (size_t e = 0; e < lim && best_c > 0; ++e) {
+                        const int k = cost(L_[e]);
+                        if (k < best_c) { best_c = k; best = e; }
+                    }
+                    take(L_[best]);
+                    L_.erase(L_.begin() + static_cast<long>(best));
+                }
+            }
+        }
+        // flags (weights' sign bits, in every lane): the first half's last
+        // record; the chunk's last two records
+        for (int l = 0; l < kLanes; ++l) {
+            step[static_cast<size_t>(mh[0] - 1) * kLanes + l] |= kFlag;
+            step[static_cast<size_t>(m - 1) * kLanes + l] |= kFlag;
+            step[static_cast<size_t>(m - 2) * kLanes + l] |= kFlag;
+        }
         for (int q = 0; q < m; q += kUnitSteps)
             for (int l = 0; l < kLanes; ++l)
                 for (int i = q; i < q + kUnitSteps; ++i)
@@ -542,7 +604,10 @@ void tmlib::bound_release(tm_library* L) {
 int tmlib::bound_scores_impl(const tm_library* L, const float* polar, const double* norms,
                              int32_t B, float* out, bool template_order, bool compact,
                              hipStream_t s) {
-    const size_t lds = static_cast<size_t>(L->n_rows + 1) * L->bnd_L * sizeof(uint16_t);
+    const size_t lds = static_cast<size_t>(L->n_rows + 1) * L->bnd_L * sizeof(uint32_t);
+    // window maxima over win + 4 win - n columns (see the header), at most a row
+    const int n = L->n_theta, win = L->bnd_win;
+    const int wlen = std::min(5 * win - n, n);
     const int Rs = compact ? L->n_rows : L->R;
     const int* rows = compact ? nullptr : L->d_rows;
     const int n_cs = L->bnd_chunks * kLanes;
@@ -555,7 +620,7 @@ int tmlib::bound_scores_impl(const tm_library* L, const float* polar, const doub
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    static_cast<int>(lds)));
         hipLaunchKernelGGL(kern, dim3(B), dim3(nw * 64), lds, s, polar, norms, Rs, L->n_theta, rows,
-                           L->n_rows, L->bnd_L, L->bnd_win,
+                           L->n_rows, L->bnd_L, win, wlen,
                            reinterpret_cast<const u32x4*>(L->d_bnd_recs), L->d_bnd_end,
                            L->d_bnd_part + (nw == 8 ? 0 : 9), n_cs, L->bnd_dfac, Qc);
         TM_HIP(hipGetLastError());

@@ -214,7 +214,7 @@ struct tm_library {
     bool bound = false;
     int32_t bnd_win = 0;        // polar columns per coarse shift window
     int32_t bnd_shifts = 0;     // coarse shifts per template
-    int32_t bnd_L = 0;          // window-image row length (halves) in LDS
+    int32_t bnd_L = 0;          // window-image row length (dwords: pairs of halves) in LDS
     int32_t bnd_chunks = 0;     // chunks of 64 templates (one per lane) scored by one wave
     int64_t bnd_units = 0;      // record units per pattern (all chunks)
     float bnd_dfac = 1.0f;      // 1 / (1 - gamma_n), rounded up, for the bound's float32 sums

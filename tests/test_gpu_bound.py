@@ -2,9 +2,12 @@
 (tm_bound_scores) and the exact search built on them (tm_match_batch with
 coarse = TM_COARSE_BOUND), which must return the plain path's top-N.
 
-The bound's definition: with M[j, x] = max(0, max_{0 <= d < win} P[j, x + d])
-(win = ceil(n_theta / 4), columns mod n_theta) the largest of the 4 window
-sums sum_i w_i M[j_i, k_i + S win] / ||P|| bounds max_s Q(t, s). The tests
+The bound's definition: with M[j, x] = max(0, max_{0 <= d < wlen} P[j, x + d])
+(win = ceil(n_theta / 4), wlen = min(win + dl, n_theta), dl = 4 win - n_theta,
+columns mod n_theta) the largest of the 4 window sums
+sum_i w_i M[j_i, k_i + S win - e_iS] / ||P|| bounds max_s Q(t, s), where
+e_iS = dl for spots with k_i >= 2 win at S = 2, 3 and 0 otherwise (the
+kernel pairs the columns 2 win apart; 0 whenever 4 divides n_theta). The tests
 check that every bound is at least the plain path's float32 best score of
 its template, and that it is that window sum (computed here in float64 from
 the same polar image) up to the documented float16 rounding up and float32
@@ -48,12 +51,14 @@ def _window_bounds64(P_rows, rows, olib, pn):
     """float64 window bounds [T'] of one pattern from its compact polar rows."""
     n = olib.n_theta
     win = -(-n // 4)
+    dl = 4 * win - n
     R = olib.R
     P = np.zeros((R, n))
     P[rows] = P_rows
-    M = np.max(np.stack([np.roll(P, -d, axis=1) for d in range(win)]), axis=0)
+    M = np.max(np.stack([np.roll(P, -d, axis=1) for d in range(min(win + dl, n))]), axis=0)
     M = np.maximum(M, 0.0)
-    cols = (olib.K[:, None] + win * np.arange(4)[None, :]) % n
+    S = np.arange(4)[None, :]
+    cols = (olib.K[:, None] + win * S - dl * ((olib.K[:, None] >= 2 * win) & (S >= 2))) % n
     vals = M[olib.J[:, None], cols] * (olib.Wt / olib.tnorm[olib.tid])[:, None]
     ub = np.zeros((olib.n_total, 4))
     np.add.at(ub, olib.tid, vals)
