@@ -117,6 +117,16 @@ uint16_t half_up(float x) {
     return b;
 }
 
+// Per-wave LDS scratch of the window-image build, in halves: a row of n
+// columns plus a halo of wlen + o, and its block maxima (blocks of o).
+size_t scratch_halves(int n, int win) {
+    const int o = (n + 63) / 64;
+    const int wlen = std::min(5 * win - n, n);
+    const int H = wlen + o;
+    const int nb = (n + H) / o;
+    return static_cast<size_t>(n + H + nb + 7) / 8 * 8;
+}
+
 // ---------------------------------------------------------------- device side
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -181,7 +191,7 @@ __device__ __forceinline__ void fma_unit(const u32x4 R, const uint32_t (&v)[kUni
 template <int NW, int WIN>
 __global__ void __launch_bounds__(NW * 64)
 bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, int Rs, int n,
-             const int* __restrict__ rows, int n_rows, int Lrow, int win, int wlen,
+             const int* __restrict__ rows, int n_rows, int Lrow, int win, int wlen, int scr_stride,
              const u32x4* __restrict__ recs, const int* __restrict__ chunk_end,
              const int* __restrict__ part, int n_cs, float dfac, float* __restrict__ Qc) {
     extern __shared__ uint16_t m16[];        // window image: pairs of halves
@@ -197,11 +207,27 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
         for (int i = threadIdx.x; i < n_cs; i += NW * 64) qrow[i] = 0.0f;
         return;
     }
-    // 1. A = max |P| over the touched rows, and the image scale
+    // 1. A = max |P| over the touched rows, and the image scale; a lane
+    // loads columns lane + 64 i of 4 rows at once (coalesced, in flight
+    // together)
+    constexpr int MC = WIN == 90 ? 6 : kMaxCols;  // bound on o = ceil(n / 64)
     float a = 0.0f;
-    for (int r = wave; r < n_rows; r += NW) {
-        const float* row = src + static_cast<size_t>(rows ? rows[r] : r) * n;
-        for (int c = lane; c < n; c += 64) a = fmaxf(a, fabsf(row[c]));
+    for (int r0 = wave; r0 < n_rows; r0 += 4 * NW) {
+        float v[4][MC];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int r = min(r0 + k * NW, n_rows - 1);
+            const float* row = src + static_cast<size_t>(rows ? rows[r] : r) * n;
+#pragma unroll
+            for (int i = 0; i < MC; ++i) {
+                const int c = lane + 64 * i;
+                v[k][i] = c < n ? row[c] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int i = 0; i < MC; ++i) a = fmaxf(a, fabsf(v[k][i]));
     }
     a = tmlib::wave_max(a);
     if (lane == 0) red[wave] = a;
@@ -212,62 +238,94 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
     int e = 0;
     (void)frexpf(A, &e);                        // A = m 2^e, m in [0.5, 1)
     const float scale = A > 0.0f ? ldexpf(1.0f, kImageExp - e) : 1.0f;
-    // 2. window maxima (clamped at 0), scaled, rounded up to float16. M is
-    // periodic (M[x + n] = M[x]): lane l computes the o consecutive columns
-    // x0 = o l .. x0 + o - 1 of [0, n) from the o + wlen - 1 values they
-    // span: the maximum of the part every window shares, then the head's
-    // suffix maxima and the tail's prefix maxima. Column x is the low half
-    // of Y[x] (if x < Lrow) and the high half of Y[c], c + 2 win = x (mod
-    // n), if c < Lrow (Lrow = 3 win < n: at most one of each).
-    const int o = (n + 63) / 64;                 // columns per lane (<= kMaxCols)
-    for (int r = wave; r < n_rows; r += NW) {
+    // 2. window maxima. Rounding up to float16 is monotone, so the maximum
+    // of the rounded values is the rounded maximum: each row goes once, as
+    // clamped (at 0), scaled, rounded-up float16 bits, into the wave's row
+    // buffer rb of n + H columns (the first H = wlen + o again past n), and
+    // its maxima over aligned blocks of o columns into bm; non-negative
+    // float16 bits order like their values. Lane l then takes the o
+    // consecutive columns x0 = o l .. x0 + o - 1: the part every window
+    // shares (column x0 + o - 1, q whole blocks, r more columns), then the
+    // head's suffix maxima and the tail's prefix maxima. Column x is the low
+    // half of Y[x] (if x < Lrow) and the high half of Y[c], c + 2 win = x
+    // (mod n), if c < Lrow (Lrow = 3 win < n: at most one of each). The
+    // next row's loads are issued before the current row is processed; the
+    // buffers are the wave's own (wave-level ordering only).
+    const int o = (n + 63) / 64;                 // columns per lane (<= MC)
+    const int H = wlen + o;
+    const int nb = (n + H) / o;                  // whole blocks in rb
+    const int q = (wlen - o) / o, rq = wlen - o - q * o;
+    uint16_t* rb = m16 + static_cast<size_t>(n_rows + 1) * Lrow * 2 +
+                   static_cast<size_t>(wave) * scr_stride;
+    uint16_t* bm = rb + n + H;
+    auto load_row = [&](int r, float (&v)[MC]) {
         const float* row = src + static_cast<size_t>(rows ? rows[r] : r) * n;
+#pragma unroll
+        for (int i = 0; i < MC; ++i) {
+            const int c = lane + 64 * i;
+            v[i] = c < n ? row[c] : 0.0f;
+        }
+    };
+    float nv[MC];
+    if (wave < n_rows) load_row(wave, nv);
+    for (int r = wave; r < n_rows; r += NW) {
+        float v[MC];
+#pragma unroll
+        for (int i = 0; i < MC; ++i) v[i] = nv[i];
+        if (r + NW < n_rows) load_row(r + NW, nv);
+#pragma unroll
+        for (int i = 0; i < MC; ++i) {
+            const int c = lane + 64 * i;
+            if (c < n) {
+                const uint16_t h = f16_up(fmaxf(v[i], 0.0f) * scale);
+                rb[c] = h;
+                if (c < H) rb[n + c] = h;
+            }
+        }
+        tmlib::wave_sync();
+        for (int bk = lane; bk < nb; bk += 64) {
+            uint32_t m = 0;
+            for (int d = 0; d < o; ++d) m = max(m, static_cast<uint32_t>(rb[bk * o + d]));
+            bm[bk] = static_cast<uint16_t>(m);
+        }
+        tmlib::wave_sync();
         uint16_t* dst = m16 + static_cast<size_t>(r) * Lrow * 2;
         const int x0 = o * lane;
         if (x0 < n) {
-            auto at = [&](int j) {
-                const int c = x0 + j;
-                return row[c < n ? c : c - n];
-            };
-            // loads are issued in independent batches (indices clamped, not
-            // branched on), so they are in flight together
-            float common = 0.0f;                 // columns o - 1 .. wlen - 1 of the span
-            for (int j = o - 1; j < wlen; j += 8) {
-                float v[8];
+            uint32_t hv[MC], tv[MC];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = at(min(j + u, wlen - 1));
-#pragma unroll
-                for (int u = 0; u < 8; ++u) common = fmaxf(common, v[u]);
+            for (int d = 0; d < MC; ++d) {
+                hv[d] = rb[x0 + min(d, o - 1)];                      // columns x0 .. x0 + o - 1
+                tv[d] = rb[x0 + wlen - 1 + min(max(d, 1), o - 1)];   // x0 + wlen .. x0 + wlen + o - 2
             }
-            float hv[kMaxCols], tv[kMaxCols];
+            uint32_t common = hv[MC - 1];               // column x0 + o - 1
+            for (int k = 1; k <= q; ++k) common = max(common, static_cast<uint32_t>(bm[lane + k]));
+            for (int k = 0; k < rq; ++k)
+                common = max(common, static_cast<uint32_t>(rb[x0 + o * (q + 1) + k]));
+            uint32_t out[MC];
+            uint32_t hmax = common, tmax = common;
 #pragma unroll
-            for (int d = 0; d < kMaxCols; ++d) {
-                hv[d] = at(min(d, max(o - 2, 0)));          // head: columns 0 .. o - 2
-                tv[d] = at(wlen - 1 + min(max(d, 1), o - 1));  // tail: columns wlen .. wlen + o - 2
-            }
-            float out[kMaxCols];
-            float hmax = common, tmax = common;
-#pragma unroll
-            for (int d = kMaxCols - 1; d >= 0; --d) {
-                if (d < o - 1) hmax = fmaxf(hmax, hv[d]);
+            for (int d = MC - 1; d >= 0; --d) {
+                if (d < o - 1) hmax = max(hmax, hv[d]);
                 out[d] = hmax;
             }
 #pragma unroll
-            for (int d = 1; d < kMaxCols; ++d) {
-                if (d < o) tmax = fmaxf(tmax, tv[d]);
-                out[d] = fmaxf(out[d], tmax);
+            for (int d = 1; d < MC; ++d) {
+                if (d < o) tmax = max(tmax, tv[d]);
+                out[d] = max(out[d], tmax);
             }
 #pragma unroll
-            for (int d = 0; d < kMaxCols; ++d) {
+            for (int d = 0; d < MC; ++d) {
                 const int x = x0 + d;
                 if (d < o && x < n) {
-                    const uint16_t h = f16_up(out[d] * scale);
+                    const uint16_t h = static_cast<uint16_t>(out[d]);
                     if (x < Lrow) dst[2 * x] = h;
                     const int c = x - 2 * win + (x < 2 * win ? n : 0);
                     if (c < Lrow) dst[2 * c + 1] = h;
                 }
             }
         }
+        tmlib::wave_sync();                     // rb and bm are rewritten next
     }
     __syncthreads();
     // the extra row n_rows: A scaled, rounded up (the margin records' value)
@@ -408,6 +466,14 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
     // rows: the touched ones, then one holding A (the margin records' value)
     const size_t dwords = static_cast<size_t>(L->n_rows + 1) * Lrow;
     if (dwords * 4 > kLdsBudget || dwords > 65536) return TM_OK;   // window image too large
+    // with 16 waves' row buffers the workgroup's LDS must fit the device's
+    {
+        int dev = 0, max_lds = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            return TM_OK;
+        if (dwords * 4 + 16 * 2 * scratch_halves(n, win) > static_cast<size_t>(max_lds)) return TM_OK;
+    }
     const uint32_t a_row = static_cast<uint32_t>(L->n_rows) * Lrow;
 
     // per template and half-turn (k < 2 win, k >= 2 win): records (dword
@@ -604,10 +670,11 @@ void tmlib::bound_release(tm_library* L) {
 int tmlib::bound_scores_impl(const tm_library* L, const float* polar, const double* norms,
                              int32_t B, float* out, bool template_order, bool compact,
                              hipStream_t s) {
-    const size_t lds = static_cast<size_t>(L->n_rows + 1) * L->bnd_L * sizeof(uint32_t);
+    const size_t image = static_cast<size_t>(L->n_rows + 1) * L->bnd_L * sizeof(uint32_t);
     // window maxima over win + 4 win - n columns (see the header), at most a row
     const int n = L->n_theta, win = L->bnd_win;
     const int wlen = std::min(5 * win - n, n);
+    const size_t scr = scratch_halves(n, win);
     const int Rs = compact ? L->n_rows : L->R;
     const int* rows = compact ? nullptr : L->d_rows;
     const int n_cs = L->bnd_chunks * kLanes;
@@ -616,18 +683,19 @@ int tmlib::bound_scores_impl(const tm_library* L, const float* polar, const doub
         TM_HIP(hipMallocAsync(reinterpret_cast<void**>(&Qc),
                               std::max<size_t>(static_cast<size_t>(B) * n_cs, 1) * sizeof(float), s));
     auto launch = [&](auto kern, int nw) -> int {
+        const size_t lds = image + nw * scr * sizeof(uint16_t);
         TM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    static_cast<int>(lds)));
         hipLaunchKernelGGL(kern, dim3(B), dim3(nw * 64), lds, s, polar, norms, Rs, L->n_theta, rows,
-                           L->n_rows, L->bnd_L, win, wlen,
+                           L->n_rows, L->bnd_L, win, wlen, static_cast<int>(scr),
                            reinterpret_cast<const u32x4*>(L->d_bnd_recs), L->d_bnd_end,
                            L->d_bnd_part + (nw == 8 ? 0 : 9), n_cs, L->bnd_dfac, Qc);
         TM_HIP(hipGetLastError());
         return TM_OK;
     };
     // one workgroup per CU when the image fills the LDS: use every wave slot
-    const bool whole = lds > 64 * 1024;
+    const bool whole = image > 64 * 1024;
     // n_theta = 360 (windows of 90 columns) has its own instance
     int r;
     if (L->bnd_win == 90)

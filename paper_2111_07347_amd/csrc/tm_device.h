@@ -24,4 +24,13 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 __device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p); }
 
+// Orders a wave's LDS accesses across its lanes: what a lane wrote before
+// is seen by the wave's reads after (the compiler may not move memory
+// operations across it; the hardware keeps a wave's LDS operations in order).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 }  // namespace tmlib
