@@ -16,10 +16,11 @@
 // bounds a whole window of shifts, and the maximum over the coarse shifts
 // bounds the template's best score.
 // The bounds feed the certified rescoring (tm_certify.hip) with margin 0:
-// the N templates with the largest bounds are scored exactly, every
-// template whose bound reaches their N-th best exact score is scored
-// exactly, and the result is the plain path's top-N (same float32 sums in
-// the same order, so the same bits).
+// a few templates with large bounds (the 32 best of the kernel's per-lane
+// largest bounds) are scored exactly, every template whose bound reaches
+// the N-th best of those exact scores is scored exactly, and the result is
+// the plain path's top-N (same float32 sums in the same order, so the same
+// bits); which templates come first only changes how many pass.
 //
 // Rigour in finite precision. The plain path's own float32 sum may exceed
 // the exact C(s) by gamma_n sum_i w_i |P_i| <= gamma_n (sum_i w_i) A, A =
@@ -193,7 +194,8 @@ __global__ void __launch_bounds__(NW * 64)
 bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, int Rs, int n,
              const int* __restrict__ rows, int n_rows, int Lrow, int win, int wlen, int scr_stride,
              const u32x4* __restrict__ recs, const int* __restrict__ chunk_end,
-             const int* __restrict__ part, int n_cs, float dfac, float* __restrict__ Qc) {
+             const int* __restrict__ part, int n_cs, float dfac, float* __restrict__ Qc,
+             float* __restrict__ lane_q, int32_t* __restrict__ lane_c) {
     extern __shared__ uint16_t m16[];        // window image: pairs of halves
     __shared__ float red[NW];
     const int b = blockIdx.x;
@@ -205,6 +207,10 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
     // a non-finite norm: the exact scorer flags the pattern; bounds 0
     if ((__double_as_longlong(pn) & 0x7ff0000000000000LL) == 0x7ff0000000000000LL) {
         for (int i = threadIdx.x; i < n_cs; i += NW * 64) qrow[i] = 0.0f;
+        if (lane_q) {
+            lane_q[static_cast<size_t>(b) * NW * 64 + threadIdx.x] = -INFINITY;
+            lane_c[static_cast<size_t>(b) * NW * 64 + threadIdx.x] = -1;
+        }
         return;
     }
     // 1. A = max |P| over the touched rows, and the image scale; a lane
@@ -349,8 +355,12 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
     const float out_scale = 1.0f / (scale * static_cast<float>(1 << kWeightExp));   // power of 2
     const uint32_t base = static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_u16*)m16));
     // the wave's chunks [c_begin, c_end) hold about 1/NW of the units
+    // each lane also keeps its largest bound and that bound's column (the
+    // first of equal ones), optionally written out at the end
     const int c_begin = part[wave], c_end = part[wave + 1];
-    if (c_begin >= c_end) return;
+    float best_q = -INFINITY;
+    int best_c = -1;
+    if (c_begin < c_end) {
     const int u_begin = (c_begin == 0) ? 0 : chunk_end[c_begin - 1];
     const int u_end = chunk_end[c_end - 1];
     const int last = u_end - 1;
@@ -371,8 +381,12 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
                 float m = acc[0];
 #pragma unroll
                 for (int S = 1; S < kShifts; ++S) m = fmaxf(m, acc[S]);
-                qrow[static_cast<size_t>(c) * kLanes + lane] =
-                    ((m * out_scale) * dfac) * invP * (1.0f + 0x1p-19f);
+                const float qv = ((m * out_scale) * dfac) * invP * (1.0f + 0x1p-19f);
+                qrow[static_cast<size_t>(c) * kLanes + lane] = qv;
+                if (qv > best_q) {
+                    best_q = qv;
+                    best_c = c * kLanes + lane;
+                }
                 ++c;
 #pragma unroll
                 for (int S = 0; S < kShifts; ++S) acc[S] = 0.0f;
@@ -432,6 +446,11 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
     if (u < u_end) process(g0);
     if (u + 1 < u_end) process(g1);
     if (u + 2 < u_end) process(g2);
+    }
+    if (lane_q) {
+        lane_q[static_cast<size_t>(b) * NW * 64 + threadIdx.x] = best_q;
+        lane_c[static_cast<size_t>(b) * NW * 64 + threadIdx.x] = best_c;
+    }
 }
 
 // Bounds from chunk-slot order to template order.
@@ -669,7 +688,7 @@ void tmlib::bound_release(tm_library* L) {
 
 int tmlib::bound_scores_impl(const tm_library* L, const float* polar, const double* norms,
                              int32_t B, float* out, bool template_order, bool compact,
-                             hipStream_t s) {
+                             hipStream_t s, float* lane_q, int32_t* lane_c, int* n_list) {
     const size_t image = static_cast<size_t>(L->n_rows + 1) * L->bnd_L * sizeof(uint32_t);
     // window maxima over win + 4 win - n columns (see the header), at most a row
     const int n = L->n_theta, win = L->bnd_win;
@@ -690,7 +709,9 @@ int tmlib::bound_scores_impl(const tm_library* L, const float* polar, const doub
         hipLaunchKernelGGL(kern, dim3(B), dim3(nw * 64), lds, s, polar, norms, Rs, L->n_theta, rows,
                            L->n_rows, L->bnd_L, win, wlen, static_cast<int>(scr),
                            reinterpret_cast<const u32x4*>(L->d_bnd_recs), L->d_bnd_end,
-                           L->d_bnd_part + (nw == 8 ? 0 : 9), n_cs, L->bnd_dfac, Qc);
+                           L->d_bnd_part + (nw == 8 ? 0 : 9), n_cs, L->bnd_dfac, Qc, lane_q,
+                           lane_c);
+        if (n_list) *n_list = nw * 64;
         TM_HIP(hipGetLastError());
         return TM_OK;
     };
@@ -721,18 +742,30 @@ int tmlib::bound_match(const tm_library* lib, const float* polar, const double* 
     const int Tp = lib->Tp;
     const int n_cs = lib->bnd_chunks * kLanes;
     float* Qc = nullptr;
+    float* lq = nullptr;
+    int32_t* lc = nullptr;
     TM_HIP(hipMallocAsync(reinterpret_cast<void**>(&Qc), static_cast<size_t>(B) * n_cs * sizeof(float), s));
-    int r = bound_scores_impl(lib, polar, norms, B, Qc, false, compact, s);
+    int r = TM_OK;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&lq), static_cast<size_t>(B) * 1024 * sizeof(float), s);
+    if (e == hipSuccess)
+        e = hipMallocAsync(reinterpret_cast<void**>(&lc), static_cast<size_t>(B) * 1024 * sizeof(int32_t), s);
+    if (e != hipSuccess) r = tmlib::hip_fail(e, "hipMallocAsync");
+    int n_list = 0;
+    if (!r) r = bound_scores_impl(lib, polar, norms, B, Qc, false, compact, s, lq, lc, &n_list);
     const double frac = cap_frac > 0.0 ? cap_frac : 0.1;
     int32_t cap = static_cast<int32_t>(std::ceil(frac * Tp - 1e-9));
     cap = std::max(N, std::min(cap, Tp));
-    // the bound ranks templates less sharply than the exact score: score the
-    // 32 best bounds exactly first, so that the threshold starts high
+    // the bound ranks templates less sharply than the exact score: the 32
+    // best of the lanes' largest bounds (at most one per lane) are scored
+    // exactly first, so that the threshold starts high
     if (!r) r = tmlib::certified_rescore(lib, polar, norms, B, N, std::max(N, kFirst), Qc, n_cs,
                                          lib->d_bnd_tid, 0.0, cap, n_rescored, top_template,
-                                         top_angle, top_score, compact, s);
-    hipError_t e = hipFreeAsync(Qc, s);
-    if (!r && e != hipSuccess) r = tmlib::hip_fail(e, "hipFreeAsync");
+                                         top_angle, top_score, compact, s, lq, lc, n_list);
+    for (void* p : {static_cast<void*>(lq), static_cast<void*>(lc), static_cast<void*>(Qc)}) {
+        if (!p) continue;
+        e = hipFreeAsync(p, s);
+        if (!r && e != hipSuccess) r = tmlib::hip_fail(e, "hipFreeAsync");
+    }
     return r;
 }
 

@@ -26,7 +26,8 @@ constexpr int kSelThreads = 256;
 // the n_first templates already scored exactly (first[b, :]). More than cap
 // such templates in all: the pattern is marked for a full exact scan
 // instead. Waves own contiguous quarters of the row and compact with
-// ballots (two passes: count, then write).
+// ballots (two passes: count, then write; the second reads again only the
+// steps of 256 columns that held a candidate, among a wave's first 64).
 __global__ void __launch_bounds__(kSelThreads)
 certify_select(const float* __restrict__ Qt, int Tp, const int32_t* __restrict__ map,
                const float* __restrict__ q_exact, int N, double margin, int cap,
@@ -59,20 +60,24 @@ certify_select(const float* __restrict__ Qt, int Tp, const int32_t* __restrict__
         return f;
     };
     int c = 0, cn = 0;
-    for (int base0 = lo; base0 < hi; base0 += 64 * kBlocks) {
+    unsigned long long hits = 0;                 // steps (< 64) with a candidate
+    for (int base0 = lo, st = 0; base0 < hi; base0 += 64 * kBlocks, ++st) {
         float v[kBlocks];
 #pragma unroll
         for (int k = 0; k < kBlocks; ++k) {
             const int t = base0 + 64 * k + lane;
             v[k] = t < hi ? row[t] : -INFINITY;
         }
+        int cs = 0;
 #pragma unroll
         for (int k = 0; k < kBlocks; ++k) {
             const int t = base0 + 64 * k + lane;
             const bool tk = take_at(t, v[k]);
-            c += __popcll(tmlib::ballot(tk));
+            cs += __popcll(tmlib::ballot(tk));
             cn += __popcll(tmlib::ballot(tk && !is_first(t)));
         }
+        c += cs;
+        if (cs && st < 64) hits |= 1ull << st;
     }
     if (lane == 0) {
         wcount[wave] = c;
@@ -89,7 +94,8 @@ certify_select(const float* __restrict__ Qt, int Tp, const int32_t* __restrict__
     if (!over) {
         int32_t* out = cand + static_cast<size_t>(b) * cap;
         int pos = before;
-        for (int base0 = lo; base0 < hi; base0 += 64 * kBlocks) {
+        for (int base0 = lo, st = 0; base0 < hi; base0 += 64 * kBlocks, ++st) {
+            if (st < 64 && !((hits >> st) & 1)) continue;   // uniform
             float v[kBlocks];
 #pragma unroll
             for (int k = 0; k < kBlocks; ++k) {
@@ -329,6 +335,19 @@ merge_split(const int4* __restrict__ merges, const int32_t* __restrict__ meta,
     }
 }
 
+// First-pass picks from a short list: entry t0[b, r] of row b of first_col
+// (n_list entries) to its column's template (-1 for none).
+__global__ void __launch_bounds__(256)
+map_listed(int32_t* __restrict__ idx, int B, int n_first, const int32_t* __restrict__ first_col,
+           int n_list, int n_cols, const int32_t* __restrict__ map) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= B * n_first) return;
+    const int b = i / n_first;
+    const int e = idx[i];
+    const int c = (e >= 0 && e < n_list) ? first_col[static_cast<size_t>(b) * n_list + e] : -1;
+    idx[i] = (c >= 0 && c < n_cols) ? (map ? map[c] : c) : -1;
+}
+
 // Column indices to templates, in place (-1 stays -1).
 __global__ void __launch_bounds__(256)
 map_columns(int32_t* __restrict__ idx, size_t n, const int32_t* __restrict__ map) {
@@ -354,7 +373,8 @@ int tmlib::certified_rescore(const tm_library* lib, const float* polar, const do
                              int32_t B, int32_t N, int32_t n_first, const float* Qt,
                              int32_t n_cols, const int32_t* map, double margin, int32_t cap,
                              int32_t* n_rescored, int32_t* top_template, int32_t* top_angle,
-                             float* top_score, bool compact, hipStream_t s) {
+                             float* top_score, bool compact, hipStream_t s, const float* first_q,
+                             const int32_t* first_col, int32_t n_list) {
     const int Tp = lib->Tp;
     n_first = std::max(N, std::min(n_first, std::min(tmlib::kMaxN, Tp)));
     int r = TM_OK;
@@ -372,9 +392,25 @@ int tmlib::certified_rescore(const tm_library* lib, const float* polar, const do
     if (!r) r = alloc_async(&cand, static_cast<size_t>(B) * cap, s);
     if (!r) r = alloc_async(&cnt, B, s);
     if (!r) r = alloc_async(&full, B, s);
-    // 1. the n_first best estimates, scored exactly: their N-th best, q_N
-    if (!r) r = tmlib::launch_topn(Qt, nullptr, B, n_cols, n_first, t0, s0, q0, s);
-    if (!r && map) {
+    // 1. the n_first best estimates (or of the caller's short list), scored
+    // exactly: their N-th best, q_N
+    if (first_q) {
+        if (n_list < n_first) {
+            tmlib::set_error("first-pass list of %d entries for %d picks", n_list, n_first);
+            r = TM_EINVAL;
+        }
+        if (!r) r = tmlib::launch_topn(first_q, nullptr, B, n_list, n_first, t0, s0, q0, s);
+        if (!r) {
+            const int n = B * n_first;
+            hipLaunchKernelGGL(map_listed, dim3((n + 255) / 256), dim3(256), 0, s, t0, B, n_first,
+                               first_col, n_list, n_cols, map);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) r = tmlib::hip_fail(e, "map_listed launch");
+        }
+    } else if (!r) {
+        r = tmlib::launch_topn(Qt, nullptr, B, n_cols, n_first, t0, s0, q0, s);
+    }
+    if (!r && map && !first_q) {
         const size_t n = bf;
         hipLaunchKernelGGL(map_columns, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s,
                            t0, n, map);

@@ -117,11 +117,16 @@ int fill_i32(int32_t* dst, int64_t n, int32_t value, hipStream_t s);
 // With map (optional) the estimates come in another column order: Qt is
 // [B, n_cols] and column c holds template map[c] (-1: no template, estimate
 // -inf); without it n_cols = T'.
+// With first_q / first_col (optional, device [B, n_list]) the first pass
+// scores the columns first_col of the n_first largest first_q values
+// instead of Qt's n_first largest (any choice keeps the result exact;
+// columns -1 are none).
 int certified_rescore(const tm_library* lib, const float* polar, const double* norms, int32_t B,
                       int32_t N, int32_t n_first, const float* Qt, int32_t n_cols,
                       const int32_t* map, double margin, int32_t cap, int32_t* n_rescored,
                       int32_t* top_template, int32_t* top_angle, float* top_score, bool compact,
-                      hipStream_t s);
+                      hipStream_t s, const float* first_q = nullptr,
+                      const int32_t* first_col = nullptr, int32_t n_list = 0);
 
 // Window upper bounds (tm_bound.hip): library data built at load (only when
 // every template weight is non-negative and the window image fits the LDS
@@ -133,8 +138,12 @@ void bound_release(tm_library* L);
 // Bounds in chunk-slot order (Qc [B, bnd_chunks * 64], -inf for empty
 // slots; d_bnd_tid maps slots to templates) or, with template_order, in
 // template order (Qt [B, T']).
+// lane_q, lane_c (optional, device, B x 1024): each lane's largest bound
+// and its chunk-slot column (-inf / -1 for none), in rows of *n_list
+// entries (the workgroup's lanes).
 int bound_scores_impl(const tm_library* L, const float* polar, const double* norms, int32_t B,
-                      float* out, bool template_order, bool compact, hipStream_t s);
+                      float* out, bool template_order, bool compact, hipStream_t s,
+                      float* lane_q = nullptr, int32_t* lane_c = nullptr, int* n_list = nullptr);
 int bound_match(const tm_library* lib, const float* polar, const double* norms, int32_t B,
                 int32_t N, double cap_frac, int32_t* n_rescored, int32_t* top_template,
                 int32_t* top_angle, float* top_score, bool compact, hipStream_t s);
