@@ -64,11 +64,10 @@
 //     their half-turns and cut into chunks of 64; in a chunk all lanes run
 //     the same number of steps in each half (zero-weight padding to whole
 //     units of 4 steps);
-//   * a lane's records come 4 at a time in one 16-byte load (a wave loads
-//     1 KiB of consecutive bytes per unit, 3 units ahead of their use); the
-//     last unit of a chunk's first half and of the chunk carry flags in
-//     the sign bits of their last weights (the multiply-adds take the
-//     weights' absolute values);
+//   * a lane's records come 4 at a time in one 16-byte buffer load (a wave
+//     loads 1 KiB of consecutive bytes per unit, 3 units ahead of their
+//     use); the units that end a chunk's first half and the chunk are known
+//     per chunk and compared with the unit counter on the scalar unit;
 //   * each template's margin term (below) is one more record: its weight
 //     the margin factor, its window maxima read from an extra image row
 //     that holds the largest |P| (scaled, rounded up) in every half;
@@ -100,7 +99,6 @@ constexpr int kImageExp = 14;              // window maxima scaled below 2^14
 constexpr size_t kLdsBudget = 128 * 1024;  // window image (16-bit offsets)
 constexpr int kFirst = 32;                 // best bounds scored exactly first
 constexpr int kMaxCols = 12;               // window columns per lane (n_theta <= 768)
-constexpr uint32_t kFlag = 0x80000000u;    // a weight's sign bit: end of a half or a chunk
 
 // ---------------------------------------------------------------- host side
 
@@ -172,13 +170,12 @@ __device__ __forceinline__ void read_unit(const u32x4 R, uint32_t base, int win,
 }
 
 // The multiply-adds of one unit: acc[0], acc[2] from the first pair's low
-// and high halves, acc[1], acc[3] from the second's; weights by absolute
-// value (their sign bits carry the flags).
+// and high halves, acc[1], acc[3] from the second's.
 __device__ __forceinline__ void fma_unit(const u32x4 R, const uint32_t (&v)[kUnitSteps * kPairs],
                                          float (&acc)[kShifts]) {
 #pragma unroll
     for (int u = 0; u < kUnitSteps; ++u) {
-        const float w = fabsf(h2f(R[u] >> 16));
+        const float w = h2f(R[u] >> 16);
         acc[0] = fmaf(w, h2f(v[u * kPairs]), acc[0]);
         acc[2] = fmaf(w, h2f(v[u * kPairs] >> 16), acc[2]);
         acc[1] = fmaf(w, h2f(v[u * kPairs + 1]), acc[1]);
@@ -193,8 +190,9 @@ template <int NW, int WIN>
 __global__ void __launch_bounds__(NW * 64)
 bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, int Rs, int n,
              const int* __restrict__ rows, int n_rows, int Lrow, int win, int wlen, int scr_stride,
-             const u32x4* __restrict__ recs, const int* __restrict__ chunk_end,
-             const int* __restrict__ part, int n_cs, float dfac, float* __restrict__ Qc,
+             const u32x4* __restrict__ recs, int rec_bytes, const int* __restrict__ chunk_end,
+             const int* __restrict__ half_end, const int* __restrict__ part, int n_cs,
+             float dfac, float* __restrict__ Qc,
              float* __restrict__ lane_q, int32_t* __restrict__ lane_c) {
     extern __shared__ uint16_t m16[];        // window image: pairs of halves
     __shared__ float red[NW];
@@ -364,38 +362,63 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
     const int u_begin = (c_begin == 0) ? 0 : chunk_end[c_begin - 1];
     const int u_end = chunk_end[c_end - 1];
     const int last = u_end - 1;
-    const u32x4* U = recs + lane;
+    // records through a buffer resource: lane offset in a register, unit
+    // offset (1 KiB per unit) in a scalar, no per-load address arithmetic
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<u32x4*>(recs), 0, rec_bytes, 0x00020000);
+    const int voff = lane * 16;
+    auto ld = [&](int k) {
+        return __builtin_bit_cast(
+            u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, min(k, last) * 1024, 0));
+    };
     int c = c_begin;
     float acc[kShifts];
 #pragma unroll
     for (int S = 0; S < kShifts; ++S) acc[S] = 0.0f;
-    // consume a unit whose reads are in v: multiply-adds; at the end of a
-    // chunk's first half (flag on the last weight only) the accumulators of
-    // shifts 0/2 and 1/3 trade places; at a chunk's end (flags on the last
-    // two weights) its bounds (one coalesced store) and fresh accumulators
-    auto consume = [&](const u32x4 R, const uint32_t (&v)[kUnitSteps * kPairs]) {
-        const uint32_t flag = __builtin_amdgcn_readfirstlane(R[3]) & kFlag;
+    // the units that end the current chunk's first half (nh) and the chunk
+    // (ne), from lane c - cb of two registers holding 64 chunks' entries
+    int cb = c_begin;
+    int vce = 0, vhe = 0;
+    auto load_events = [&]() {
+        const int cc = min(cb + lane, c_end - 1);
+        vce = chunk_end[cc];
+        vhe = half_end[cc];
+    };
+    load_events();
+    int ne = __builtin_amdgcn_readfirstlane(vce) - 1;
+    int nh = __builtin_amdgcn_readfirstlane(vhe) - 1;
+    // consume unit uu whose reads are in v: multiply-adds; after the
+    // chunk's first half the accumulators of shifts 0/2 and 1/3 trade
+    // places; at the chunk's end its bounds (one coalesced store) and fresh
+    // accumulators (each half holds at least one unit)
+    auto consume = [&](const u32x4 R, const uint32_t (&v)[kUnitSteps * kPairs], int uu) {
         fma_unit(R, v, acc);
-        if (flag) {
-            if (__builtin_amdgcn_readfirstlane(R[2]) & kFlag) {
-                float m = acc[0];
+        if (uu == nh) {
+            const float t0 = acc[0], t1 = acc[1];
+            acc[0] = acc[2];
+            acc[1] = acc[3];
+            acc[2] = t0;
+            acc[3] = t1;
+        } else if (uu == ne) {
+            float m = acc[0];
 #pragma unroll
-                for (int S = 1; S < kShifts; ++S) m = fmaxf(m, acc[S]);
-                const float qv = ((m * out_scale) * dfac) * invP * (1.0f + 0x1p-19f);
-                qrow[static_cast<size_t>(c) * kLanes + lane] = qv;
-                if (qv > best_q) {
-                    best_q = qv;
-                    best_c = c * kLanes + lane;
+            for (int S = 1; S < kShifts; ++S) m = fmaxf(m, acc[S]);
+            const float qv = ((m * out_scale) * dfac) * invP * (1.0f + 0x1p-19f);
+            qrow[static_cast<size_t>(c) * kLanes + lane] = qv;
+            if (qv > best_q) {
+                best_q = qv;
+                best_c = c * kLanes + lane;
+            }
+            ++c;
+#pragma unroll
+            for (int S = 0; S < kShifts; ++S) acc[S] = 0.0f;
+            if (c < c_end) {
+                if (c - cb == 64) {
+                    cb = c;
+                    load_events();
                 }
-                ++c;
-#pragma unroll
-                for (int S = 0; S < kShifts; ++S) acc[S] = 0.0f;
-            } else {
-                const float t0 = acc[0], t1 = acc[1];
-                acc[0] = acc[2];
-                acc[1] = acc[3];
-                acc[2] = t0;
-                acc[3] = t1;
+                ne = __builtin_amdgcn_readlane(vce, c - cb) - 1;
+                nh = __builtin_amdgcn_readlane(vhe, c - cb) - 1;
             }
         }
     };
@@ -405,47 +428,46 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
     // before unit u is consumed, into the other of two value sets; the
     // pipeline fills and drains within each 8-unit iteration, so no read is
     // in flight across the loop's back edge.
-    u32x4 g0 = U[static_cast<size_t>(u_begin) * kLanes];
-    u32x4 g1 = U[static_cast<size_t>(min(u_begin + 1, last)) * kLanes];
-    u32x4 g2 = U[static_cast<size_t>(min(u_begin + 2, last)) * kLanes];
-    u32x4 g3 = U[static_cast<size_t>(min(u_begin + 3, last)) * kLanes];
+    u32x4 g0 = ld(u_begin);
+    u32x4 g1 = ld(u_begin + 1);
+    u32x4 g2 = ld(u_begin + 2);
+    u32x4 g3 = ld(u_begin + 3);
     uint32_t va[kUnitSteps * kPairs], vb[kUnitSteps * kPairs];
-    auto ld = [&](int k) { return U[static_cast<size_t>(min(k, last)) * kLanes]; };
 #define TM_BOUND_SB __builtin_amdgcn_sched_barrier(0)
     int u = u_begin;
     for (; u + 8 <= u_end; u += 8) {
         read_unit<WIN>(g0, base, win, va); TM_BOUND_SB;
         read_unit<WIN>(g1, base, win, vb); TM_BOUND_SB;
-        consume(g0, va); g0 = ld(u + 4); TM_BOUND_SB;
+        consume(g0, va, u); g0 = ld(u + 4); TM_BOUND_SB;
         read_unit<WIN>(g2, base, win, va); TM_BOUND_SB;
-        consume(g1, vb); g1 = ld(u + 5); TM_BOUND_SB;
+        consume(g1, vb, u + 1); g1 = ld(u + 5); TM_BOUND_SB;
         read_unit<WIN>(g3, base, win, vb); TM_BOUND_SB;
-        consume(g2, va); g2 = ld(u + 6); TM_BOUND_SB;
+        consume(g2, va, u + 2); g2 = ld(u + 6); TM_BOUND_SB;
         read_unit<WIN>(g0, base, win, va); TM_BOUND_SB;
-        consume(g3, vb); g3 = ld(u + 7); TM_BOUND_SB;
+        consume(g3, vb, u + 3); g3 = ld(u + 7); TM_BOUND_SB;
         read_unit<WIN>(g1, base, win, vb); TM_BOUND_SB;
-        consume(g0, va); g0 = ld(u + 8); TM_BOUND_SB;
+        consume(g0, va, u + 4); g0 = ld(u + 8); TM_BOUND_SB;
         read_unit<WIN>(g2, base, win, va); TM_BOUND_SB;
-        consume(g1, vb); g1 = ld(u + 9); TM_BOUND_SB;
+        consume(g1, vb, u + 5); g1 = ld(u + 9); TM_BOUND_SB;
         read_unit<WIN>(g3, base, win, vb); TM_BOUND_SB;
-        consume(g2, va); g2 = ld(u + 10); TM_BOUND_SB;
-        consume(g3, vb); g3 = ld(u + 11); TM_BOUND_SB;
+        consume(g2, va, u + 6); g2 = ld(u + 10); TM_BOUND_SB;
+        consume(g3, vb, u + 7); g3 = ld(u + 11); TM_BOUND_SB;
     }
     // the last 0..7 units, one at a time
-    auto process = [&](u32x4 R) {
+    auto process = [&](u32x4 R, int uu) {
         read_unit<WIN>(R, base, win, va);
-        consume(R, va);
+        consume(R, va, uu);
     };
     for (; u + 4 <= u_end; u += 4) {
-        process(g0); g0 = ld(u + 4); TM_BOUND_SB;
-        process(g1); g1 = ld(u + 5); TM_BOUND_SB;
-        process(g2); g2 = ld(u + 6); TM_BOUND_SB;
-        process(g3); g3 = ld(u + 7); TM_BOUND_SB;
+        process(g0, u); g0 = ld(u + 4); TM_BOUND_SB;
+        process(g1, u + 1); g1 = ld(u + 5); TM_BOUND_SB;
+        process(g2, u + 2); g2 = ld(u + 6); TM_BOUND_SB;
+        process(g3, u + 3); g3 = ld(u + 7); TM_BOUND_SB;
     }
 #undef TM_BOUND_SB
-    if (u < u_end) process(g0);
-    if (u + 1 < u_end) process(g1);
-    if (u + 2 < u_end) process(g2);
+    if (u < u_end) process(g0, u);
+    if (u + 1 < u_end) process(g1, u + 1);
+    if (u + 2 < u_end) process(g2, u + 2);
     }
     if (lane_q) {
         lane_q[static_cast<size_t>(b) * NW * 64 + threadIdx.x] = best_q;
@@ -536,7 +558,7 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
     });
     const int32_t n_chunks = (Tp + kLanes - 1) / kLanes;
     std::vector<int32_t> tid(static_cast<size_t>(n_chunks) * kLanes, -1);
-    std::vector<int32_t> cend(n_chunks, 0);
+    std::vector<int32_t> cend(n_chunks, 0), hend(n_chunks, 0);
     std::vector<uint32_t> recs;
     // LDS bank model of the pair reads: kBanks banks of 4 bytes, lanes
     // grouped in half-waves; the dword of a record's read r
@@ -616,19 +638,15 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
                 }
             }
         }
-        // flags (weights' sign bits, in every lane): the first half's last
-        // record; the chunk's last two records
-        for (int l = 0; l < kLanes; ++l) {
-            step[static_cast<size_t>(mh[0] - 1) * kLanes + l] |= kFlag;
-            step[static_cast<size_t>(m - 1) * kLanes + l] |= kFlag;
-            step[static_cast<size_t>(m - 2) * kLanes + l] |= kFlag;
-        }
+        // the unit after the chunk's first half
+        hend[c] = static_cast<int32_t>(recs.size() / (kUnitSteps * kLanes) + mh[0] / kUnitSteps);
         for (int q = 0; q < m; q += kUnitSteps)
             for (int l = 0; l < kLanes; ++l)
                 for (int i = q; i < q + kUnitSteps; ++i)
                     recs.push_back(step[static_cast<size_t>(i) * kLanes + l]);
+        // (1 KiB per unit, addressed with 32-bit offsets)
         const int64_t units = static_cast<int64_t>(recs.size() / (kUnitSteps * kLanes));
-        if (units > INT32_MAX / kLanes) return TM_OK;
+        if (units >= INT32_MAX / 1024) return TM_OK;
         cend[c] = static_cast<int32_t>(units);
     }
     // chunk ranges of the waves of an 8-wave and a 16-wave workgroup, each
@@ -659,6 +677,7 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
     };
     if (int r = up(&L->d_bnd_recs, recs)) return r;
     if (int r = up(&L->d_bnd_end, cend)) return r;
+    if (int r = up(&L->d_bnd_half, hend)) return r;
     if (int r = up(&L->d_bnd_tid, tid)) return r;
     L->bnd_tid = tid;
     if (int r = up(&L->d_bnd_part, part)) return r;
@@ -675,10 +694,12 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
 void tmlib::bound_release(tm_library* L) {
     (void)hipFree(L->d_bnd_recs);
     (void)hipFree(L->d_bnd_end);
+    (void)hipFree(L->d_bnd_half);
     (void)hipFree(L->d_bnd_tid);
     (void)hipFree(L->d_bnd_part);
     L->d_bnd_recs = nullptr;
     L->d_bnd_end = nullptr;
+    L->d_bnd_half = nullptr;
     L->d_bnd_tid = nullptr;
     L->d_bnd_part = nullptr;
     L->bound = false;
@@ -708,7 +729,8 @@ int tmlib::bound_scores_impl(const tm_library* L, const float* polar, const doub
                                    static_cast<int>(lds)));
         hipLaunchKernelGGL(kern, dim3(B), dim3(nw * 64), lds, s, polar, norms, Rs, L->n_theta, rows,
                            L->n_rows, L->bnd_L, win, wlen, static_cast<int>(scr),
-                           reinterpret_cast<const u32x4*>(L->d_bnd_recs), L->d_bnd_end,
+                           reinterpret_cast<const u32x4*>(L->d_bnd_recs),
+                           static_cast<int>(L->bnd_units * 1024), L->d_bnd_end, L->d_bnd_half,
                            L->d_bnd_part + (nw == 8 ? 0 : 9), n_cs, L->bnd_dfac, Qc, lane_q,
                            lane_c);
         if (n_list) *n_list = nw * 64;
