@@ -636,8 +636,9 @@ int tm_fft_scores(const tm_library* lib, const float* polar, const double* norms
  *   C(s) = sum_i w_i P[j_i, k_i + s] <= sum_i w_i M[j_i, k_i + S win - e_iS],
  *   M[j, x] = max(0, max_{0 <= d < wlen} P[j, x + d]),
  * where dl = 4 win - n_theta, wlen = min(win + dl, n_theta), and e_iS = dl
- * for spots with k_i >= 2 win at S = 2, 3, else 0 (the window image pairs
- * columns 2 win apart; with 4 | n_theta, dl = 0 and wlen = win). The
+ * when floor(k_i / win) + S >= 4, else 0 (the window image holds a pixel's
+ * 4 maxima at columns k_i mod win + q win, q = 0..3; with 4 | n_theta,
+ * dl = 0 and wlen = win). The
  * largest of the 4 window sums bounds max_s Q(b, t, s) of Eq. (1).
  * The window maxima and weights are rounded up to float16 (scaled), summed
  * in float32, and the stored bound is widened by the worst-case float32
@@ -647,7 +648,7 @@ int tm_fft_scores(const tm_library* lib, const float* polar, const double* norms
  * Arguments
  *   lib           loaded library (all weights >= 0, n_theta >= 16; the
  *                 window image of the touched rows plus one, (rows + 1) x
- *                 3 win pairs of float16, must fit 128 KiB of LDS, else
+ *                 2 win pairs of float16, must fit 128 KiB of LDS, else
  *                 TM_EUNSUPPORTED).
  *   polar, norms  as in tm_match_batch; compact_rows as in tm_fft_scores.
  *   B             >= 0 (0 is a no-op).
@@ -674,9 +675,9 @@ int tm_bound_scores_slots(const tm_library* lib, const float* polar, const doubl
  * (the same exact-search aid as tm_bound_scores).
  *   chunks  out (nullable): chunks of 64 templates, one template per lane.
  *   units   out (nullable): record units per pattern (each 4 records per
- *           lane, 1 KiB per wave; in a chunk each template's two half-turns
- *           of pixels, the margin record joining the smaller, are padded to
- *           the chunk's largest, in whole units).
+ *           lane, 1 KiB per wave; in a chunk each template's four
+ *           quarter-turns of pixels, the margin record joining the smallest,
+ *           are padded to the chunk's largest, in whole units).
  *   win     out (nullable): shifts per coarse window, ceil(n_theta / 4).
  * Errors: TM_EINVAL (lib NULL), TM_EUNSUPPORTED (no window bounds for this
  * library: a negative weight, n_theta < 16 or an image over the LDS

@@ -39,38 +39,39 @@
 // rounded up, which is at least the plain path's float32 Q_t of every
 // template.
 //
-// Half-turn pairing. The shifts S and S + 2 of a pixel read columns 2 win
-// apart, so the window image is stored as pairs, one dword per column c in
-// [0, 3 win) of a row:
+// Quarter-turn pairing. A pixel at column k = q win + r (q = 0..3, r <
+// win) needs M at r + (q + S) win for S = 0..3, the 4 maxima M[r + i win],
+// i = 0..3, in some rotation. The window image stores them as two dwords,
 //
-//   Y[j, c] = (M[j, c], M[j, c + 2 win])      (float16 each, columns mod n)
+//   Y[j, r] = (M[j, r], M[j, r + 2 win]),  Y[j, r + win] = (M[j, r + win],
+//   M[j, r + 3 win])                         (float16 each, columns mod n),
 //
-// A pixel in the first half-turn (k < 2 win) reads Y[c] and Y[c + win] at
-// c = k: their low halves are shifts 0 and 1, the high halves shifts 2 and
-// 3. A pixel in the second half-turn (c = k - 2 win) reads the same two
-// dwords with the halves' roles swapped: Y[c].hi is M[k] (shift 0),
-// Y[c + win].hi is M[k + win] (shift 1), and Y[c].lo = M[c] stands for
-// M[k + 2 win] = M[c + 4 win - n], which it covers because its window is
-// 4 win - n columns wider (the same for shift 3). So every record costs two
-// 32-bit LDS reads for its 4 window maxima, and a row takes 3 win dwords.
-// A lane processes one half-turn of its template, then the other (its
-// larger one first); between the two every lane swaps its shift-0/2 and
-// shift-1/3 accumulators, which keeps the update the same for all lanes.
+// one row of 2 win dwords per touched row, read with one 2-dword LDS read
+// at r and r + win. acc[i] collects M[r + i win], which is shift S = i - q
+// (mod 4): the pixels of one quarter share the rotation. A lane takes its
+// template's quarters in cyclic order (its largest first); between two
+// quarters every lane moves the value of shift S from acc[S + q] to
+// acc[S + q + 1], the same operation in every lane. When 4 does not divide
+// n, i = q + S - 4 for q + S >= 4 stands for column r + (q + S) win - n =
+// r + i win + 4 win - n: read 4 win - n columns early, which the wider
+// windows cover.
 //
 // Kernel layout (one workgroup per pattern):
-//   * the window image Y of the library's touched rows is built in LDS;
+//   * the window image Y of the library's touched rows is built in LDS (8
+//     waves build rows); the image and those waves' row buffers fit two
+//     workgroups in a CU's LDS for most libraries;
 //   * a lane scores one template over the 4 coarse shifts S, a wave 64
 //     templates at a time: templates are sorted by the pixel counts of
-//     their half-turns and cut into chunks of 64; in a chunk all lanes run
-//     the same number of steps in each half (zero-weight padding to whole
-//     units of 4 steps);
+//     their quarter-turns (in the lane's order) and cut into chunks of 64;
+//     in a chunk all lanes run the same number of steps in each quarter slot
+//     (zero-weight padding to whole units of 4 steps);
 //   * a lane's records come 4 at a time in one 16-byte buffer load (a wave
 //     loads 1 KiB of consecutive bytes per unit, 3 units ahead of their
-//     use); the units that end a chunk's first half and the chunk are known
-//     per chunk and compared with the unit counter on the scalar unit;
+//     use); the units that end a chunk's quarter slots are known per chunk
+//     and compared with the unit counter on the scalar unit;
 //   * each template's margin term (below) is one more record: its weight
 //     the margin factor, its window maxima read from an extra image row
-//     that holds the largest |P| (scaled, rounded up) in every half;
+//     that holds the largest |P| (scaled, rounded up) everywhere;
 //   * per record: one address multiply-add, 2 LDS reads of a pair of
 //     float16 window maxima and 4 mixed float16 x float16 + float32
 //     multiply-adds; the library orders each step's records over the
@@ -98,6 +99,7 @@ constexpr int kWeightExp = 10;             // float16 weights carry w * 2^10
 constexpr int kImageExp = 14;              // window maxima scaled below 2^14
 constexpr size_t kLdsBudget = 128 * 1024;  // window image (16-bit offsets)
 constexpr int kFirst = 32;                 // best bounds scored exactly first
+constexpr int kBuildWaves = 8;             // waves that build the window image's rows
 constexpr int kMaxCols = 12;               // window columns per lane (n_theta <= 768)
 
 // ---------------------------------------------------------------- host side
@@ -185,13 +187,13 @@ __device__ __forceinline__ void fma_unit(const u32x4 R, const uint32_t (&v)[kUni
 
 // WIN > 0: win as a constant (the second read's offset becomes an
 // immediate of the LDS instruction); 0: taken from win. Image rows are Lrow
-// (= 3 win) dwords; wlen is the width of the window maxima.
+// (= 2 win) dwords; wlen is the width of the window maxima.
 template <int NW, int WIN>
-__global__ void __launch_bounds__(NW * 64)
+__global__ void __launch_bounds__(NW * 64, (NW == 16 && WIN) ? 8 : 1)
 bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, int Rs, int n,
              const int* __restrict__ rows, int n_rows, int Lrow, int win, int wlen, int scr_stride,
              const u32x4* __restrict__ recs, int rec_bytes, const int* __restrict__ chunk_end,
-             const int* __restrict__ half_end, const int* __restrict__ part, int n_cs,
+             const int4* __restrict__ slot_end, const int* __restrict__ part, int n_cs,
              float dfac, float* __restrict__ Qc,
              float* __restrict__ lane_q, int32_t* __restrict__ lane_c) {
     extern __shared__ uint16_t m16[];        // window image: pairs of halves
@@ -252,13 +254,14 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
     // shares (column x0 + o - 1, q whole blocks, r more columns), then the
     // head's suffix maxima and the tail's prefix maxima. Column x is the low
     // half of Y[x] (if x < Lrow) and the high half of Y[c], c + 2 win = x
-    // (mod n), if c < Lrow (Lrow = 3 win < n: at most one of each). The
+    // (mod n), if c < Lrow (Lrow = 2 win <= n: at most one of each). The
     // next row's loads are issued before the current row is processed; the
     // buffers are the wave's own (wave-level ordering only).
     const int o = (n + 63) / 64;                 // columns per lane (<= MC)
     const int H = wlen + o;
     const int nb = (n + H) / o;                  // whole blocks in rb
     const int q = (wlen - o) / o, rq = wlen - o - q * o;
+    constexpr int PW = NW < kBuildWaves ? NW : kBuildWaves;   // waves that build rows
     uint16_t* rb = m16 + static_cast<size_t>(n_rows + 1) * Lrow * 2 +
                    static_cast<size_t>(wave) * scr_stride;
     uint16_t* bm = rb + n + H;
@@ -271,12 +274,12 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
         }
     };
     float nv[MC];
-    if (wave < n_rows) load_row(wave, nv);
-    for (int r = wave; r < n_rows; r += NW) {
+    if (wave < PW && wave < n_rows) load_row(wave, nv);
+    for (int r = wave < PW ? wave : n_rows; r < n_rows; r += PW) {
         float v[MC];
 #pragma unroll
         for (int i = 0; i < MC; ++i) v[i] = nv[i];
-        if (r + NW < n_rows) load_row(r + NW, nv);
+        if (r + PW < n_rows) load_row(r + PW, nv);
 #pragma unroll
         for (int i = 0; i < MC; ++i) {
             const int c = lane + 64 * i;
@@ -375,51 +378,61 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
     float acc[kShifts];
 #pragma unroll
     for (int S = 0; S < kShifts; ++S) acc[S] = 0.0f;
-    // the units that end the current chunk's first half (nh) and the chunk
-    // (ne), from lane c - cb of two registers holding 64 chunks' entries
+    // the last units of the current chunk's quarter slots (s0 the current
+    // slot's, p its index), from lane c - cb of registers holding 64
+    // chunks' entries; an empty slot ends where the one before it does
     int cb = c_begin;
-    int vce = 0, vhe = 0;
-    auto load_events = [&]() {
-        const int cc = min(cb + lane, c_end - 1);
-        vce = chunk_end[cc];
-        vhe = half_end[cc];
+    int4 vse = make_int4(0, 0, 0, 0);
+    auto load_events = [&]() { vse = slot_end[min(cb + lane, c_end - 1)]; };
+    int s0 = 0, s1 = 0, s2 = 0, s3 = 0, p = 0;
+    auto chunk_events = [&]() {
+        if (c - cb == 64) {
+            cb = c;
+            load_events();
+        }
+        const int i = c - cb;
+        s0 = __builtin_amdgcn_readlane(vse.x, i) - 1;
+        s1 = __builtin_amdgcn_readlane(vse.y, i) - 1;
+        s2 = __builtin_amdgcn_readlane(vse.z, i) - 1;
+        s3 = __builtin_amdgcn_readlane(vse.w, i) - 1;
+        p = 0;
     };
     load_events();
-    int ne = __builtin_amdgcn_readfirstlane(vce) - 1;
-    int nh = __builtin_amdgcn_readfirstlane(vhe) - 1;
-    // consume unit uu whose reads are in v: multiply-adds; after the
-    // chunk's first half the accumulators of shifts 0/2 and 1/3 trade
-    // places; at the chunk's end its bounds (one coalesced store) and fresh
-    // accumulators (each half holds at least one unit)
+    chunk_events();
+    // consume unit uu whose reads are in v: multiply-adds; after each
+    // quarter slot but the last the accumulators rotate by one (the value of
+    // shift S moves from acc[S + q] to acc[S + q + 1], mod 4); at the chunk's
+    // end its bounds (one coalesced store) and fresh accumulators
     auto consume = [&](const u32x4 R, const uint32_t (&v)[kUnitSteps * kPairs], int uu) {
         fma_unit(R, v, acc);
-        if (uu == nh) {
-            const float t0 = acc[0], t1 = acc[1];
-            acc[0] = acc[2];
-            acc[1] = acc[3];
-            acc[2] = t0;
-            acc[3] = t1;
-        } else if (uu == ne) {
-            float m = acc[0];
+        if (uu == s0) {
+            do {
+                if (p == kShifts - 1) {
+                    float m = acc[0];
 #pragma unroll
-            for (int S = 1; S < kShifts; ++S) m = fmaxf(m, acc[S]);
-            const float qv = ((m * out_scale) * dfac) * invP * (1.0f + 0x1p-19f);
-            qrow[static_cast<size_t>(c) * kLanes + lane] = qv;
-            if (qv > best_q) {
-                best_q = qv;
-                best_c = c * kLanes + lane;
-            }
-            ++c;
+                    for (int S = 1; S < kShifts; ++S) m = fmaxf(m, acc[S]);
+                    const float qv = ((m * out_scale) * dfac) * invP * (1.0f + 0x1p-19f);
+                    qrow[static_cast<size_t>(c) * kLanes + lane] = qv;
+                    if (qv > best_q) {
+                        best_q = qv;
+                        best_c = c * kLanes + lane;
+                    }
+                    ++c;
 #pragma unroll
-            for (int S = 0; S < kShifts; ++S) acc[S] = 0.0f;
-            if (c < c_end) {
-                if (c - cb == 64) {
-                    cb = c;
-                    load_events();
+                    for (int S = 0; S < kShifts; ++S) acc[S] = 0.0f;
+                    if (c < c_end) chunk_events();
+                    break;
                 }
-                ne = __builtin_amdgcn_readlane(vce, c - cb) - 1;
-                nh = __builtin_amdgcn_readlane(vhe, c - cb) - 1;
-            }
+                const float t = acc[3];
+                acc[3] = acc[2];
+                acc[2] = acc[1];
+                acc[1] = acc[0];
+                acc[0] = t;
+                ++p;
+                s0 = s1;
+                s1 = s2;
+                s2 = s3;
+            } while (uu == s0);
         }
     };
     // Units stream through four registers g0..g3, each reloaded with the
@@ -498,97 +511,111 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
     for (const auto& v : pix)
         for (const HostPixel& p : v)
             if (!(p.w >= 0.0)) return TM_OK;           // bounds need non-negative weights
-    // (n_theta >= 16, so that 3 win < n_theta and 2 win <= n_theta)
+    // (n_theta >= 16, so that 2 win <= n_theta)
     if (n < 16) return TM_OK;
     const int win = (n + kShifts - 1) / kShifts;
-    // window image rows of 3 win dwords (pairs of float16 window maxima),
-    // read at c and c + win
-    const int Lrow = 3 * win;
+    // window image rows of 2 win dwords (pairs of float16 window maxima),
+    // read at r and r + win
+    const int Lrow = 2 * win;
     // rows: the touched ones, then one holding A (the margin records' value)
     const size_t dwords = static_cast<size_t>(L->n_rows + 1) * Lrow;
     if (dwords * 4 > kLdsBudget || dwords > 65536) return TM_OK;   // window image too large
-    // with 16 waves' row buffers the workgroup's LDS must fit the device's
+    // with the row buffers of the waves that build it, the workgroup's LDS
+    // must fit the device's
     {
         int dev = 0, max_lds = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
             return TM_OK;
-        if (dwords * 4 + 16 * 2 * scratch_halves(n, win) > static_cast<size_t>(max_lds)) return TM_OK;
+        if (dwords * 4 + kBuildWaves * 2 * scratch_halves(n, win) > static_cast<size_t>(max_lds))
+            return TM_OK;
     }
     const uint32_t a_row = static_cast<uint32_t>(L->n_rows) * Lrow;
 
-    // per template and half-turn (k < 2 win, k >= 2 win): records (dword
-    // offset, float16 weight); the larger half comes first
-    std::vector<std::array<std::vector<uint32_t>, 2>> tr(Tp);
-    std::vector<int32_t> big(Tp, 0), small(Tp, 0);
+    // per template and quarter-turn q = k / win: records (dword offset of
+    // column k - q win, float16 weight); the margin record joins the
+    // smallest quarter; the lane's order of quarters is the rotation
+    // (starting quarter o, then o + 1, ... mod 4) that puts the most
+    // records first (ties: the largest count vector)
+    std::vector<std::array<std::vector<uint32_t>, kShifts>> tr(Tp);
+    std::vector<std::array<int32_t, kShifts>> qc(Tp);
     int nmax = 0;
     for (int32_t tt = 0; tt < Tp; ++tt) {
         const int32_t t = tt < T ? tt : tt - T;
         const bool is_mirror = tt >= T;
         const double nrm = L->tnorm[t];
         double wsum = 0.0;
-        std::array<std::vector<uint32_t>, 2> hv;
+        std::array<std::vector<uint32_t>, kShifts> qv;
         for (const HostPixel& p : pix[t]) {
             const int k = is_mirror ? (n - p.k) % n : p.k;
-            const int h = k >= 2 * win ? 1 : 0;
+            const int q = k / win;
             const float w32 = nrm > 0.0 ? static_cast<float>(p.w / nrm) : 0.0f;
             wsum += w32;
             const uint32_t off = static_cast<uint32_t>(row_index[p.j]) * Lrow +
-                                 static_cast<uint32_t>(k - 2 * win * h);
+                                 static_cast<uint32_t>(k - q * win);
             const uint32_t w16 = half_up(std::ldexp(w32, kWeightExp));
-            hv[h].push_back(off | (w16 << 16));
+            qv[q].push_back(off | (w16 << 16));
         }
         const int cnt = static_cast<int>(pix[t].size());
         nmax = std::max(nmax, cnt);
         // the margin record: weight c_t 2^10 (rounded up), value A (one
-        // place for all: a broadcast read), in the smaller half
+        // place for all: a broadcast read)
         const double cf = gamma32(cnt) * wsum * (1.0 + 0x1p-20);
         const uint32_t c16 = half_up(static_cast<float>(std::ldexp(cf, kWeightExp) * (1.0 + 0x1p-20)));
-        hv[hv[0].size() <= hv[1].size() ? 0 : 1].push_back(a_row | (c16 << 16));
-        if (hv[0].size() < hv[1].size()) std::swap(hv[0], hv[1]);
-        big[tt] = static_cast<int32_t>(hv[0].size());
-        small[tt] = static_cast<int32_t>(hv[1].size());
-        tr[tt] = std::move(hv);
+        int qs = 0;
+        for (int q = 1; q < kShifts; ++q)
+            if (qv[q].size() < qv[qs].size()) qs = q;
+        qv[qs].push_back(a_row | (c16 << 16));
+        std::array<int32_t, kShifts> best{};
+        int bo = 0;
+        for (int o = 0; o < kShifts; ++o) {
+            std::array<int32_t, kShifts> v;
+            for (int p = 0; p < kShifts; ++p) v[p] = static_cast<int32_t>(qv[(o + p) % kShifts].size());
+            if (o == 0 || v > best) { best = v; bo = o; }
+        }
+        for (int p = 0; p < kShifts; ++p) tr[tt][p] = std::move(qv[(bo + p) % kShifts]);
+        qc[tt] = best;
     }
-    // chunks of 64 templates of similar half sizes
+    // chunks of 64 templates of similar slot sizes
     std::vector<int32_t> order(Tp);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        return big[a] != big[b] ? big[a] > big[b] : small[a] > small[b];
-    });
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return qc[a] > qc[b]; });
     const int32_t n_chunks = (Tp + kLanes - 1) / kLanes;
     std::vector<int32_t> tid(static_cast<size_t>(n_chunks) * kLanes, -1);
-    std::vector<int32_t> cend(n_chunks, 0), hend(n_chunks, 0);
+    std::vector<int32_t> cend(n_chunks, 0), send(static_cast<size_t>(n_chunks) * 4, 0);
     std::vector<uint32_t> recs;
     // LDS bank model of the pair reads: kBanks banks of 4 bytes, lanes
     // grouped in half-waves; the dword of a record's read r
     const int nbanks = kBanks, group = kLanes / 2;
     auto dword = [&](uint32_t rec, int r) { return (rec & 0xffffu) + r * static_cast<uint32_t>(win); };
-    auto whole = [](int m) { return std::max(kUnitSteps, (m + kUnitSteps - 1) / kUnitSteps * kUnitSteps); };
+    auto whole = [](int m) { return (m + kUnitSteps - 1) / kUnitSteps * kUnitSteps; };
     for (int32_t c = 0; c < n_chunks; ++c) {
-        int mh[2] = {0, 0};
+        int mh[kShifts] = {0, 0, 0, 0};
         for (int l = 0; l < kLanes; ++l) {
             const int32_t idx = c * kLanes + l;
             tid[idx] = idx < Tp ? order[idx] : -1;
-            if (tid[idx] >= 0) {
-                mh[0] = std::max(mh[0], big[tid[idx]]);
-                mh[1] = std::max(mh[1], small[tid[idx]]);
-            }
+            if (tid[idx] >= 0)
+                for (int p = 0; p < kShifts; ++p) mh[p] = std::max(mh[p], qc[tid[idx]][p]);
         }
-        mh[0] = whole(mh[0]);                   // whole units per half
-        mh[1] = whole(mh[1]);
-        const int m = mh[0] + mh[1];
+        // whole units per slot; the first slot holds every template's
+        // largest quarter (at least the margin record); later ones may be
+        // empty
+        int sb[kShifts + 1] = {0};
+        for (int p = 0; p < kShifts; ++p)
+            sb[p + 1] = sb[p] + (p == 0 ? std::max(kUnitSteps, whole(mh[0])) : whole(mh[p]));
+        const int m = sb[kShifts];
         std::vector<uint32_t> step(static_cast<size_t>(m) * kLanes, 0u);
-        for (int h = 0; h < 2; ++h) {
+        for (int p = 0; p < kShifts; ++p) {
             // per step one record per lane, chosen so that the lanes of each
             // half-wave read distinct banks where possible (a template's
-            // records may come in any order within a half: the bound's sum
+            // records may come in any order within a slot: the bound's sum
             // and its margin do not depend on it); padding (weight 0) reads
             // a free bank of row 0
             std::vector<std::vector<uint32_t>> left(kLanes);
             for (int l = 0; l < kLanes; ++l)
-                if (tid[c * kLanes + l] >= 0) left[l] = tr[tid[c * kLanes + l]][h];
-            for (int i = h ? mh[0] : 0; i < (h ? m : mh[0]); ++i) {
+                if (tid[c * kLanes + l] >= 0) left[l] = tr[tid[c * kLanes + l]][p];
+            for (int i = sb[p]; i < sb[p + 1]; ++i) {
                 // per read and bank: the first dword read there and the
                 // number of distinct dwords (a second lane on the same dword
                 // is free)
@@ -618,7 +645,7 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
                     if (L_.empty()) {
                         uint32_t pad = 0;
                         int best_c = 99;
-                        for (uint32_t x = 0; x < 64 && x + win < static_cast<uint32_t>(Lrow); ++x) {
+                        for (uint32_t x = 0; x < 64 && x < static_cast<uint32_t>(win); ++x) {
                             const int k = cost(x);
                             if (k < best_c) { best_c = k; pad = x; }
                             if (k == 0) break;
@@ -638,8 +665,9 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
                 }
             }
         }
-        // the unit after the chunk's first half
-        hend[c] = static_cast<int32_t>(recs.size() / (kUnitSteps * kLanes) + mh[0] / kUnitSteps);
+        // the first unit after each slot (the last one: after the chunk)
+        const int32_t u0 = static_cast<int32_t>(recs.size() / (kUnitSteps * kLanes));
+        for (int p = 0; p < kShifts; ++p) send[static_cast<size_t>(c) * 4 + p] = u0 + sb[p + 1] / kUnitSteps;
         for (int q = 0; q < m; q += kUnitSteps)
             for (int l = 0; l < kLanes; ++l)
                 for (int i = q; i < q + kUnitSteps; ++i)
@@ -677,7 +705,7 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
     };
     if (int r = up(&L->d_bnd_recs, recs)) return r;
     if (int r = up(&L->d_bnd_end, cend)) return r;
-    if (int r = up(&L->d_bnd_half, hend)) return r;
+    if (int r = up(&L->d_bnd_slots, send)) return r;
     if (int r = up(&L->d_bnd_tid, tid)) return r;
     L->bnd_tid = tid;
     if (int r = up(&L->d_bnd_part, part)) return r;
@@ -694,12 +722,12 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
 void tmlib::bound_release(tm_library* L) {
     (void)hipFree(L->d_bnd_recs);
     (void)hipFree(L->d_bnd_end);
-    (void)hipFree(L->d_bnd_half);
+    (void)hipFree(L->d_bnd_slots);
     (void)hipFree(L->d_bnd_tid);
     (void)hipFree(L->d_bnd_part);
     L->d_bnd_recs = nullptr;
     L->d_bnd_end = nullptr;
-    L->d_bnd_half = nullptr;
+    L->d_bnd_slots = nullptr;
     L->d_bnd_tid = nullptr;
     L->d_bnd_part = nullptr;
     L->bound = false;
@@ -723,14 +751,15 @@ int tmlib::bound_scores_impl(const tm_library* L, const float* polar, const doub
         TM_HIP(hipMallocAsync(reinterpret_cast<void**>(&Qc),
                               std::max<size_t>(static_cast<size_t>(B) * n_cs, 1) * sizeof(float), s));
     auto launch = [&](auto kern, int nw) -> int {
-        const size_t lds = image + nw * scr * sizeof(uint16_t);
+        const size_t lds = image + std::min(nw, kBuildWaves) * scr * sizeof(uint16_t);
         TM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    static_cast<int>(lds)));
         hipLaunchKernelGGL(kern, dim3(B), dim3(nw * 64), lds, s, polar, norms, Rs, L->n_theta, rows,
                            L->n_rows, L->bnd_L, win, wlen, static_cast<int>(scr),
                            reinterpret_cast<const u32x4*>(L->d_bnd_recs),
-                           static_cast<int>(L->bnd_units * 1024), L->d_bnd_end, L->d_bnd_half,
+                           static_cast<int>(L->bnd_units * 1024), L->d_bnd_end,
+                           reinterpret_cast<const int4*>(L->d_bnd_slots),
                            L->d_bnd_part + (nw == 8 ? 0 : 9), n_cs, L->bnd_dfac, Qc, lane_q,
                            lane_c);
         if (n_list) *n_list = nw * 64;

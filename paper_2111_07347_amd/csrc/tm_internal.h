@@ -230,7 +230,7 @@ struct tm_library {
     uint32_t* d_bnd_recs = nullptr;   // units of 4 steps x 64 lanes: LDS half offset | float16
                                       // weight << 16, 16 bytes per lane
     int32_t* d_bnd_end = nullptr;     // [bnd_chunks]: first unit after each chunk
-    int32_t* d_bnd_half = nullptr;    // [bnd_chunks]: first unit of each chunk's second half
+    int32_t* d_bnd_slots = nullptr;   // [bnd_chunks][4]: first unit after each quarter slot
     int32_t* d_bnd_tid = nullptr;     // [bnd_chunks * 64]: template of each chunk slot, -1 none
     std::vector<int32_t> bnd_tid;     // host copy
     float* d_bnd_cfac = nullptr;      // [bnd_chunks * 64]: margin factor, -1 for no template

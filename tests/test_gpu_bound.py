@@ -6,8 +6,9 @@ The bound's definition: with M[j, x] = max(0, max_{0 <= d < wlen} P[j, x + d])
 (win = ceil(n_theta / 4), wlen = min(win + dl, n_theta), dl = 4 win - n_theta,
 columns mod n_theta) the largest of the 4 window sums
 sum_i w_i M[j_i, k_i + S win - e_iS] / ||P|| bounds max_s Q(t, s), where
-e_iS = dl for spots with k_i >= 2 win at S = 2, 3 and 0 otherwise (the
-kernel pairs the columns 2 win apart; 0 whenever 4 divides n_theta). The tests
+e_iS = dl when floor(k_i / win) + S >= 4 and 0 otherwise (the kernel
+reads the 4 maxima of a pixel from columns k_i mod win + q win, q = 0..3;
+0 whenever 4 divides n_theta). The tests
 check that every bound is at least the plain path's float32 best score of
 its template, and that it is that window sum (computed here in float64 from
 the same polar image) up to the documented float16 rounding up and float32
@@ -58,7 +59,7 @@ def _window_bounds64(P_rows, rows, olib, pn):
     M = np.max(np.stack([np.roll(P, -d, axis=1) for d in range(min(win + dl, n))]), axis=0)
     M = np.maximum(M, 0.0)
     S = np.arange(4)[None, :]
-    cols = (olib.K[:, None] + win * S - dl * ((olib.K[:, None] >= 2 * win) & (S >= 2))) % n
+    cols = (olib.K[:, None] + win * S - dl * (olib.K[:, None] // win + S >= 4)) % n
     vals = M[olib.J[:, None], cols] * (olib.Wt / olib.tnorm[olib.tid])[:, None]
     ub = np.zeros((olib.n_total, 4))
     np.add.at(ub, olib.tid, vals)
