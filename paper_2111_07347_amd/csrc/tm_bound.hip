@@ -16,7 +16,7 @@
 // bounds a whole window of shifts, and the maximum over the coarse shifts
 // bounds the template's best score.
 // The bounds feed the certified rescoring (tm_certify.hip) with margin 0:
-// a few templates with large bounds (the 32 best of the kernel's per-lane
+// a few templates with large bounds (the 48 best of the kernel's per-lane
 // largest bounds) are scored exactly, every template whose bound reaches
 // the N-th best of those exact scores is scored exactly, and the result is
 // the plain path's top-N (same float32 sums in the same order, so the same
@@ -98,7 +98,7 @@ constexpr int kChoices = 64;               // records tried per lane and step
 constexpr int kWeightExp = 10;             // float16 weights carry w * 2^10
 constexpr int kImageExp = 14;              // window maxima scaled below 2^14
 constexpr size_t kLdsBudget = 128 * 1024;  // window image (16-bit offsets)
-constexpr int kFirst = 32;                 // best bounds scored exactly first
+constexpr int kFirst = 48;                 // best bounds scored exactly first
 constexpr int kBuildWaves = 8;             // waves that build the window image's rows
 constexpr int kMaxCols = 12;               // window columns per lane (n_theta <= 768)
 
@@ -806,7 +806,7 @@ int tmlib::bound_match(const tm_library* lib, const float* polar, const double* 
     const double frac = cap_frac > 0.0 ? cap_frac : 0.1;
     int32_t cap = static_cast<int32_t>(std::ceil(frac * Tp - 1e-9));
     cap = std::max(N, std::min(cap, Tp));
-    // the bound ranks templates less sharply than the exact score: the 32
+    // the bound ranks templates less sharply than the exact score: the 48
     // best of the lanes' largest bounds (at most one per lane) are scored
     // exactly first, so that the threshold starts high
     if (!r) r = tmlib::certified_rescore(lib, polar, norms, B, N, std::max(N, kFirst), Qc, n_cs,

@@ -21,13 +21,15 @@ constexpr int kSelThreads = 256;
 
 // Candidates of the certified rescoring, one workgroup per pattern: every
 // column c with Qt[b, c] >= (N-th best exact score of the rescored
-// approximate top-N) - margin, written as its template (map[c], or c), in
-// ascending column order (columns without a template are skipped), except
-// the n_first templates already scored exactly (first[b, :]). More than cap
+// approximate top-N) - margin, written as its template (map[c], or c)
+// (columns without a template are skipped), except the n_first templates
+// already scored exactly (first[b, :]); the order does not matter to the
+// scorer (its ranking rule decides). More than cap
 // such templates in all: the pattern is marked for a full exact scan
 // instead. Waves own contiguous quarters of the row and compact with
 // ballots (two passes: count, then write; the second reads again only the
-// steps of 256 columns that held a candidate, among a wave's first 64).
+// blocks of 64 loads that held a candidate, among a wave's first 64).
+template <int V>
 __global__ void __launch_bounds__(kSelThreads)
 certify_select(const float* __restrict__ Qt, int Tp, const int32_t* __restrict__ map,
                const float* __restrict__ q_exact, int N, double margin, int cap,
@@ -48,9 +50,13 @@ certify_select(const float* __restrict__ Qt, int Tp, const int32_t* __restrict__
     float thr = static_cast<float>(thr_d);
     if (static_cast<double>(thr) > thr_d) thr = nextafterf(thr, -INFINITY);
     const float* row = Qt + static_cast<size_t>(b) * Tp;
-    const int lo = static_cast<int>((static_cast<long long>(Tp) * wave) / W);
-    const int hi = static_cast<int>((static_cast<long long>(Tp) * (wave + 1)) / W);
-    // 4 blocks of 64 columns per step, their loads issued together
+    // waves own contiguous quarters, whole groups of V columns (V = 4: one
+    // 16-byte load per lane and block; the row length is a multiple of 4)
+    const int ng = Tp / V;
+    const int lo = V * static_cast<int>((static_cast<long long>(ng) * wave) / W);
+    const int hi = V * static_cast<int>((static_cast<long long>(ng) * (wave + 1)) / W);
+    // 4 blocks of 64 V columns per step, their loads issued together;
+    // column of (block k, component e) for this lane: base + V (64 k + lane) + e
     constexpr int kBlocks = 4;
     auto take_at = [&](int t, float v) { return t < hi && v >= thr && (!map || map[t] >= 0); };
     auto is_first = [&](int t) {
@@ -59,25 +65,49 @@ certify_select(const float* __restrict__ Qt, int Tp, const int32_t* __restrict__
         for (int i = 0; i < n_first; ++i) f |= (sfirst[i] == tt);
         return f;
     };
+    auto load = [&](int base0, float (&v)[kBlocks][V]) {
+#pragma unroll
+        for (int k = 0; k < kBlocks; ++k) {
+            const int t = base0 + V * (64 * k + lane);
+            if constexpr (V == 4) {
+                const float4 x = t < hi ? *reinterpret_cast<const float4*>(row + t)
+                                        : make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
+                v[k][0] = x.x; v[k][1] = x.y; v[k][2] = x.z; v[k][3] = x.w;
+            } else {
+                v[k][0] = t < hi ? row[t] : -INFINITY;
+            }
+        }
+    };
     int c = 0, cn = 0;
-    unsigned long long hits = 0;                 // steps (< 64) with a candidate
-    for (int base0 = lo, st = 0; base0 < hi; base0 += 64 * kBlocks, ++st) {
-        float v[kBlocks];
+    unsigned long long hits = 0;                 // blocks (< 64) with a candidate
+    // the next step's loads are issued before this step's values are tested
+    constexpr int kStep = V * 64 * kBlocks;
+    float nv[kBlocks][V];
+    load(lo, nv);
+    for (int base0 = lo, st = 0; base0 < hi; base0 += kStep, ++st) {
+        float v[kBlocks][V];
+#pragma unroll
+        for (int k = 0; k < kBlocks; ++k)
+#pragma unroll
+            for (int e = 0; e < V; ++e) v[k][e] = nv[k][e];
+        load(base0 + kStep, nv);
 #pragma unroll
         for (int k = 0; k < kBlocks; ++k) {
-            const int t = base0 + 64 * k + lane;
-            v[k] = t < hi ? row[t] : -INFINITY;
-        }
-        int cs = 0;
+            int cs = 0;
 #pragma unroll
-        for (int k = 0; k < kBlocks; ++k) {
-            const int t = base0 + 64 * k + lane;
-            const bool tk = take_at(t, v[k]);
-            cs += __popcll(tmlib::ballot(tk));
-            cn += __popcll(tmlib::ballot(tk && !is_first(t)));
+            for (int e = 0; e < V; ++e) {
+                const int t = base0 + V * (64 * k + lane) + e;
+                const bool tk = take_at(t, v[k][e]);
+                const unsigned long long mk = tmlib::ballot(tk);
+                if (mk) {                                // uniform; rare
+                    cs += __popcll(mk);
+                    cn += __popcll(tmlib::ballot(tk && !is_first(t)));
+                }
+            }
+            c += cs;
+            const int blk = st * kBlocks + k;
+            if (cs && blk < 64) hits |= 1ull << blk;
         }
-        c += cs;
-        if (cs && st < 64) hits |= 1ull << st;
     }
     if (lane == 0) {
         wcount[wave] = c;
@@ -94,22 +124,38 @@ certify_select(const float* __restrict__ Qt, int Tp, const int32_t* __restrict__
     if (!over) {
         int32_t* out = cand + static_cast<size_t>(b) * cap;
         int pos = before;
-        for (int base0 = lo, st = 0; base0 < hi; base0 += 64 * kBlocks, ++st) {
-            if (st < 64 && !((hits >> st) & 1)) continue;   // uniform
-            float v[kBlocks];
+        for (int base0 = lo, st = 0; base0 < hi; base0 += V * 64 * kBlocks, ++st) {
+            // the step's blocks that held a candidate (all from block 64 on)
+            const unsigned sel = st * kBlocks + kBlocks <= 64
+                                     ? static_cast<unsigned>(hits >> (st * kBlocks)) & ((1u << kBlocks) - 1)
+                                     : (1u << kBlocks) - 1;
+            if (!sel) continue;                                  // uniform
+            float v[kBlocks][V];
 #pragma unroll
             for (int k = 0; k < kBlocks; ++k) {
-                const int t = base0 + 64 * k + lane;
-                v[k] = t < hi ? row[t] : -INFINITY;
+                const int t = base0 + V * (64 * k + lane);
+                if (!((sel >> k) & 1) || t >= hi) {
+#pragma unroll
+                    for (int e = 0; e < V; ++e) v[k][e] = -INFINITY;
+                } else if constexpr (V == 4) {
+                    const float4 x = *reinterpret_cast<const float4*>(row + t);
+                    v[k][0] = x.x; v[k][1] = x.y; v[k][2] = x.z; v[k][3] = x.w;
+                } else {
+                    v[k][0] = row[t];
+                }
             }
 #pragma unroll
-            for (int k = 0; k < kBlocks; ++k) {
-                const int t = base0 + 64 * k + lane;
-                const bool take = take_at(t, v[k]) && !is_first(t);
-                const unsigned long long m = tmlib::ballot(take);
-                if (take) out[pos + __popcll(m & ((1ull << lane) - 1))] = map ? map[t] : t;
-                pos += __popcll(m);
-            }
+            for (int k = 0; k < kBlocks; ++k)
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const int t = base0 + V * (64 * k + lane) + e;
+                    const bool tk = take_at(t, v[k][e]);
+                    if (!tmlib::ballot(tk)) continue;    // uniform; rare
+                    const bool take = tk && !is_first(t);
+                    const unsigned long long m = tmlib::ballot(take);
+                    if (take) out[pos + __popcll(m & ((1ull << lane) - 1))] = map ? map[t] : t;
+                    pos += __popcll(m);
+                }
         }
     }
     if (threadIdx.x == 0) {
@@ -335,17 +381,46 @@ merge_split(const int4* __restrict__ merges, const int32_t* __restrict__ meta,
     }
 }
 
-// First-pass picks from a short list: entry t0[b, r] of row b of first_col
-// (n_list entries) to its column's template (-1 for none).
+// First-pass picks from a short list: the n_first best entries of row b of
+// first_q (n_list <= 1024 entries; value descending, list index ascending),
+// each as the template of its column first_col[b, i] (-1 for none). One
+// workgroup per pattern sorts the row in LDS (bitonic, padded to 1024 with
+// -inf entries that rank after every real one).
+constexpr int kPickN = 1024;
 __global__ void __launch_bounds__(256)
-map_listed(int32_t* __restrict__ idx, int B, int n_first, const int32_t* __restrict__ first_col,
-           int n_list, int n_cols, const int32_t* __restrict__ map) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= B * n_first) return;
-    const int b = i / n_first;
-    const int e = idx[i];
-    const int c = (e >= 0 && e < n_list) ? first_col[static_cast<size_t>(b) * n_list + e] : -1;
-    idx[i] = (c >= 0 && c < n_cols) ? (map ? map[c] : c) : -1;
+pick_listed(const float* __restrict__ first_q, const int32_t* __restrict__ first_col, int n_list,
+            int n_first, int n_cols, const int32_t* __restrict__ map, int32_t* __restrict__ out) {
+    __shared__ float sq[kPickN];
+    __shared__ int si[kPickN];
+    const int b = blockIdx.x;
+    for (int i = threadIdx.x; i < kPickN; i += 256) {
+        sq[i] = i < n_list ? first_q[static_cast<size_t>(b) * n_list + i] : -INFINITY;
+        si[i] = i;
+    }
+    __syncthreads();
+    auto better = [](float qa, int ia, float qb, int ib) { return qa > qb || (qa == qb && ia < ib); };
+    for (int k = 2; k <= kPickN; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < kPickN; i += 256) {
+                const int p = i ^ j;
+                if (p > i) {
+                    const float qa = sq[i], qb = sq[p];
+                    const int ia = si[i], ib = si[p];
+                    // blocks with bit k clear end best-first, the others best-last
+                    const bool swap = (i & k) == 0 ? better(qb, ib, qa, ia) : better(qa, ia, qb, ib);
+                    if (swap) {
+                        sq[i] = qb; sq[p] = qa;
+                        si[i] = ib; si[p] = ia;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int r = threadIdx.x; r < n_first; r += 256) {
+        const int e = si[r];
+        const int c = e < n_list ? first_col[static_cast<size_t>(b) * n_list + e] : -1;
+        out[static_cast<size_t>(b) * n_first + r] = (c >= 0 && c < n_cols) ? (map ? map[c] : c) : -1;
+    }
 }
 
 // Column indices to templates, in place (-1 stays -1).
@@ -399,13 +474,15 @@ int tmlib::certified_rescore(const tm_library* lib, const float* polar, const do
             tmlib::set_error("first-pass list of %d entries for %d picks", n_list, n_first);
             r = TM_EINVAL;
         }
-        if (!r) r = tmlib::launch_topn(first_q, nullptr, B, n_list, n_first, t0, s0, q0, s);
+        if (!r && n_list > kPickN) {
+            tmlib::set_error("first-pass list of %d entries (at most %d)", n_list, kPickN);
+            r = TM_EINVAL;
+        }
         if (!r) {
-            const int n = B * n_first;
-            hipLaunchKernelGGL(map_listed, dim3((n + 255) / 256), dim3(256), 0, s, t0, B, n_first,
-                               first_col, n_list, n_cols, map);
+            hipLaunchKernelGGL(pick_listed, dim3(B), dim3(256), 0, s, first_q, first_col, n_list,
+                               n_first, n_cols, map, t0);
             hipError_t e = hipGetLastError();
-            if (e != hipSuccess) r = tmlib::hip_fail(e, "map_listed launch");
+            if (e != hipSuccess) r = tmlib::hip_fail(e, "pick_listed launch");
         }
     } else if (!r) {
         r = tmlib::launch_topn(Qt, nullptr, B, n_cols, n_first, t0, s0, q0, s);
@@ -421,8 +498,13 @@ int tmlib::certified_rescore(const tm_library* lib, const float* polar, const do
                                     n_first, nullptr, nullptr, compact, s);
     // 2. every template whose estimate reaches q_N - margin
     if (!r) {
-        hipLaunchKernelGGL(certify_select, dim3(B), dim3(kSelThreads), 0, s, Qt, n_cols, map, q1, N,
-                           margin, cap, cand, cnt, full, n_rescored, Tp, t0, n_first);
+        // 16-byte loads when every row starts 16-byte aligned
+        if (n_cols % 4 == 0 && reinterpret_cast<uintptr_t>(Qt) % 16 == 0)
+            hipLaunchKernelGGL(certify_select<4>, dim3(B), dim3(kSelThreads), 0, s, Qt, n_cols, map,
+                               q1, N, margin, cap, cand, cnt, full, n_rescored, Tp, t0, n_first);
+        else
+            hipLaunchKernelGGL(certify_select<1>, dim3(B), dim3(kSelThreads), 0, s, Qt, n_cols, map,
+                               q1, N, margin, cap, cand, cnt, full, n_rescored, Tp, t0, n_first);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) r = tmlib::hip_fail(e, "certify_select launch");
     }
