@@ -46,8 +46,8 @@
 //   Y[j, r] = (M[j, r], M[j, r + 2 win]),  Y[j, r + win] = (M[j, r + win],
 //   M[j, r + 3 win])                         (float16 each, columns mod n),
 //
-// one row of 2 win dwords per touched row, read with one 2-dword LDS read
-// at r and r + win. acc[i] collects M[r + i win], which is shift S = i - q
+// one row of 2 win dwords (plus one unused, for an odd pitch) per touched
+// row, read with one 2-dword LDS read at r and r + win. acc[i] collects M[r + i win], which is shift S = i - q
 // (mod 4): the pixels of one quarter share the rotation. A lane takes its
 // template's quarters in cyclic order (its largest first); between two
 // quarters every lane moves the value of shift S from acc[S + q] to
@@ -187,11 +187,13 @@ __device__ __forceinline__ void fma_unit(const u32x4 R, const uint32_t (&v)[kUni
 
 // WIN > 0: win as a constant (the second read's offset becomes an
 // immediate of the LDS instruction); 0: taken from win. Image rows are Lrow
-// (= 2 win) dwords; wlen is the width of the window maxima.
+// (= 2 win + 1) dwords, place r holding compact row rowat[r]; wlen is the
+// width of the window maxima.
 template <int NW, int WIN>
 __global__ void __launch_bounds__(NW * 64, (NW == 16 && WIN) ? 8 : 1)
 bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, int Rs, int n,
-             const int* __restrict__ rows, int n_rows, int Lrow, int win, int wlen, int scr_stride,
+             const int* __restrict__ rows, const int* __restrict__ rowat, int n_rows, int Lrow,
+             int win, int wlen, int scr_stride,
              const u32x4* __restrict__ recs, int rec_bytes, const int* __restrict__ chunk_end,
              const int4* __restrict__ slot_end, const int* __restrict__ part, int n_cs,
              float dfac, float* __restrict__ Qc,
@@ -265,8 +267,10 @@ bound_kernel(const float* __restrict__ polar, const double* __restrict__ norms, 
     uint16_t* rb = m16 + static_cast<size_t>(n_rows + 1) * Lrow * 2 +
                    static_cast<size_t>(wave) * scr_stride;
     uint16_t* bm = rb + n + H;
+    // image row place r holds compact row rowat[r]
     auto load_row = [&](int r, float (&v)[MC]) {
-        const float* row = src + static_cast<size_t>(rows ? rows[r] : r) * n;
+        const int cr = rowat[r];
+        const float* row = src + static_cast<size_t>(rows ? rows[cr] : cr) * n;
 #pragma unroll
         for (int i = 0; i < MC; ++i) {
             const int c = lane + 64 * i;
@@ -515,8 +519,10 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
     if (n < 16) return TM_OK;
     const int win = (n + kShifts - 1) / kShifts;
     // window image rows of 2 win dwords (pairs of float16 window maxima),
-    // read at r and r + win
-    const int Lrow = 2 * win;
+    // read at r and r + win, plus one unused dword: an odd pitch, so that a
+    // row's place in the image sets the LDS bank of its column 0 to any of
+    // the 32 (rows are placed below to even out the banks)
+    const int Lrow = 2 * win + 1;
     // rows: the touched ones, then one holding A (the margin records' value)
     const size_t dwords = static_cast<size_t>(L->n_rows + 1) * Lrow;
     if (dwords * 4 > kLdsBudget || dwords > 65536) return TM_OK;   // window image too large
@@ -551,6 +557,8 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
             const int q = k / win;
             const float w32 = nrm > 0.0 ? static_cast<float>(p.w / nrm) : 0.0f;
             wsum += w32;
+            // (compact row) * Lrow + column for now; rows move to their
+            // places in the image below
             const uint32_t off = static_cast<uint32_t>(row_index[p.j]) * Lrow +
                                  static_cast<uint32_t>(k - q * win);
             const uint32_t w16 = half_up(std::ldexp(w32, kWeightExp));
@@ -583,6 +591,83 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
                      [&](int32_t a, int32_t b) { return qc[a] > qc[b]; });
     const int32_t n_chunks = (Tp + kLanes - 1) / kLanes;
     std::vector<int32_t> tid(static_cast<size_t>(n_chunks) * kLanes, -1);
+    for (int32_t i = 0; i < n_chunks * kLanes; ++i) tid[i] = i < Tp ? order[i] : -1;
+    // Row places. The pixels of one (chunk, slot, half-wave) are read in
+    // its steps, one per lane and step; their columns' banks, (place * Lrow
+    // + r) mod 32, should be spread evenly. Rows are placed in decreasing
+    // order of pixel count, each at the free place whose bank shift meets
+    // the least load already placed in the groups where the row has pixels
+    // (sum of products of the two bank histograms).
+    const int n_rows = L->n_rows;
+    std::vector<int32_t> rowat(n_rows), place(n_rows, -1);
+    {
+        const int n_groups = n_chunks * kShifts * 2;
+        std::vector<std::vector<std::pair<int, std::array<uint16_t, kBanks>>>> hist(n_rows);
+        std::vector<int64_t> rowcnt(n_rows, 0);
+        std::vector<std::array<uint16_t, kBanks>> acc(n_rows);
+        std::vector<int> touched;
+        for (int32_t c = 0; c < n_chunks; ++c)
+            for (int p = 0; p < kShifts; ++p)
+                for (int h = 0; h < 2; ++h) {
+                    const int g = (c * kShifts + p) * 2 + h;
+                    touched.clear();
+                    for (int l = h * 32; l < h * 32 + 32; ++l) {
+                        const int32_t t = tid[c * kLanes + l];
+                        if (t < 0) continue;
+                        for (uint32_t rec : tr[t][p]) {
+                            const uint32_t off = rec & 0xffffu;
+                            if (off == a_row) continue;
+                            const int row = static_cast<int>(off / Lrow);
+                            bool seen = false;
+                            for (int x : touched) seen |= (x == row);
+                            if (!seen) { touched.push_back(row); acc[row].fill(0); }
+                            ++acc[row][(off % Lrow) % kBanks];
+                            ++rowcnt[row];
+                        }
+                    }
+                    for (int row : touched) hist[row].push_back({g, acc[row]});
+                }
+        std::vector<int32_t> byc(n_rows);
+        std::iota(byc.begin(), byc.end(), 0);
+        std::stable_sort(byc.begin(), byc.end(), [&](int a, int b) { return rowcnt[a] > rowcnt[b]; });
+        std::vector<std::array<int32_t, kBanks>> load(n_groups);
+        for (auto& a : load) a.fill(0);
+        std::vector<char> used(n_rows, 0);
+        for (int row : byc) {
+            // one free place per bank shift
+            int cand[kBanks];
+            std::fill(cand, cand + kBanks, -1);
+            for (int pl = 0; pl < n_rows; ++pl)
+                if (!used[pl]) {
+                    const int s = static_cast<int>((static_cast<int64_t>(pl) * Lrow) % kBanks);
+                    if (cand[s] < 0) cand[s] = pl;
+                }
+            int64_t best = -1;
+            int bs = 0;
+            for (int s = 0; s < kBanks; ++s) {
+                if (cand[s] < 0) continue;
+                int64_t cost = 0;
+                for (const auto& [g, hb] : hist[row])
+                    for (int b = 0; b < kBanks; ++b)
+                        if (hb[b]) cost += static_cast<int64_t>(hb[b]) * load[g][(b + s) % kBanks];
+                if (best < 0 || cost < best) { best = cost; bs = s; }
+            }
+            place[row] = cand[bs];
+            used[cand[bs]] = 1;
+            rowat[cand[bs]] = row;
+            for (const auto& [g, hb] : hist[row])
+                for (int b = 0; b < kBanks; ++b) load[g][(b + bs) % kBanks] += hb[b];
+        }
+        // records to image offsets
+        for (int32_t tt = 0; tt < Tp; ++tt)
+            for (int p = 0; p < kShifts; ++p)
+                for (uint32_t& rec : tr[tt][p]) {
+                    const uint32_t off = rec & 0xffffu;
+                    if (off == a_row) continue;
+                    const uint32_t row = off / Lrow, col = off % Lrow;
+                    rec = (rec & 0xffff0000u) | (static_cast<uint32_t>(place[row]) * Lrow + col);
+                }
+    }
     std::vector<int32_t> cend(n_chunks, 0), send(static_cast<size_t>(n_chunks) * 4, 0);
     std::vector<uint32_t> recs;
     // LDS bank model of the pair reads: kBanks banks of 4 bytes, lanes
@@ -594,7 +679,6 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
         int mh[kShifts] = {0, 0, 0, 0};
         for (int l = 0; l < kLanes; ++l) {
             const int32_t idx = c * kLanes + l;
-            tid[idx] = idx < Tp ? order[idx] : -1;
             if (tid[idx] >= 0)
                 for (int p = 0; p < kShifts; ++p) mh[p] = std::max(mh[p], qc[tid[idx]][p]);
         }
@@ -706,6 +790,7 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
     if (int r = up(&L->d_bnd_recs, recs)) return r;
     if (int r = up(&L->d_bnd_end, cend)) return r;
     if (int r = up(&L->d_bnd_slots, send)) return r;
+    if (int r = up(&L->d_bnd_rowat, rowat)) return r;
     if (int r = up(&L->d_bnd_tid, tid)) return r;
     L->bnd_tid = tid;
     if (int r = up(&L->d_bnd_part, part)) return r;
@@ -723,11 +808,13 @@ void tmlib::bound_release(tm_library* L) {
     (void)hipFree(L->d_bnd_recs);
     (void)hipFree(L->d_bnd_end);
     (void)hipFree(L->d_bnd_slots);
+    (void)hipFree(L->d_bnd_rowat);
     (void)hipFree(L->d_bnd_tid);
     (void)hipFree(L->d_bnd_part);
     L->d_bnd_recs = nullptr;
     L->d_bnd_end = nullptr;
     L->d_bnd_slots = nullptr;
+    L->d_bnd_rowat = nullptr;
     L->d_bnd_tid = nullptr;
     L->d_bnd_part = nullptr;
     L->bound = false;
@@ -756,7 +843,7 @@ int tmlib::bound_scores_impl(const tm_library* L, const float* polar, const doub
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    static_cast<int>(lds)));
         hipLaunchKernelGGL(kern, dim3(B), dim3(nw * 64), lds, s, polar, norms, Rs, L->n_theta, rows,
-                           L->n_rows, L->bnd_L, win, wlen, static_cast<int>(scr),
+                           L->d_bnd_rowat, L->n_rows, L->bnd_L, win, wlen, static_cast<int>(scr),
                            reinterpret_cast<const u32x4*>(L->d_bnd_recs),
                            static_cast<int>(L->bnd_units * 1024), L->d_bnd_end,
                            reinterpret_cast<const int4*>(L->d_bnd_slots),

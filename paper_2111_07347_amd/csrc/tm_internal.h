@@ -231,6 +231,7 @@ struct tm_library {
                                       // weight << 16, 16 bytes per lane
     int32_t* d_bnd_end = nullptr;     // [bnd_chunks]: first unit after each chunk
     int32_t* d_bnd_slots = nullptr;   // [bnd_chunks][4]: first unit after each quarter slot
+    int32_t* d_bnd_rowat = nullptr;   // [n_rows]: the compact row held at each image row place
     int32_t* d_bnd_tid = nullptr;     // [bnd_chunks * 64]: template of each chunk slot, -1 none
     std::vector<int32_t> bnd_tid;     // host copy
     float* d_bnd_cfac = nullptr;      // [bnd_chunks * 64]: margin factor, -1 for no template
