@@ -584,11 +584,20 @@ int tmlib::bound_prepare(tm_library* L, const std::vector<std::vector<HostPixel>
         for (int p = 0; p < kShifts; ++p) tr[tt][p] = std::move(qv[(bo + p) % kShifts]);
         qc[tt] = best;
     }
-    // chunks of 64 templates of similar slot sizes
+    // chunks of 64 templates of similar slot sizes: ordered by the slot
+    // sizes in whole units first (a chunk pays each slot's largest, rounded
+    // up to whole units), then by the sizes themselves
     std::vector<int32_t> order(Tp);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int32_t a, int32_t b) { return qc[a] > qc[b]; });
+    auto units_of = [](const std::array<int32_t, kShifts>& v) {
+        std::array<int32_t, kShifts> u;
+        for (int p = 0; p < kShifts; ++p) u[p] = (v[p] + kUnitSteps - 1) / kUnitSteps;
+        return u;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const auto ua = units_of(qc[a]), ub = units_of(qc[b]);
+        return ua != ub ? ua > ub : qc[a] > qc[b];
+    });
     const int32_t n_chunks = (Tp + kLanes - 1) / kLanes;
     std::vector<int32_t> tid(static_cast<size_t>(n_chunks) * kLanes, -1);
     for (int32_t i = 0; i < n_chunks * kLanes; ++i) tid[i] = i < Tp ? order[i] : -1;
