@@ -382,44 +382,113 @@ merge_split(const int4* __restrict__ merges, const int32_t* __restrict__ meta,
 }
 
 // First-pass picks from a short list: the n_first best entries of row b of
-// first_q (n_list <= 1024 entries; value descending, list index ascending),
-// each as the template of its column first_col[b, i] (-1 for none). One
-// workgroup per pattern sorts the row in LDS (bitonic, padded to 1024 with
-// -inf entries that rank after every real one).
+// first_q (n_list <= 1024 entries; value descending, list index ascending
+// among equal values; NaN ranks last), each written as the template of its
+// column first_col[b, i] (-1 for none), in list order. One workgroup per
+// pattern: a radix select over order-preserving 32-bit keys finds the
+// n_first-th largest key T in four 8-bit passes (LDS histograms), then the
+// entries above T and the first entries equal to T are compacted with
+// ballots.
 constexpr int kPickN = 1024;
+__device__ __forceinline__ uint32_t order_key(float v) {
+    const uint32_t u = __float_as_uint(v);
+    if (v != v) return 0u;
+    return (u >> 31) ? ~u : (u | 0x80000000u);
+}
+
 __global__ void __launch_bounds__(256)
 pick_listed(const float* __restrict__ first_q, const int32_t* __restrict__ first_col, int n_list,
             int n_first, int n_cols, const int32_t* __restrict__ map, int32_t* __restrict__ out) {
-    __shared__ float sq[kPickN];
-    __shared__ int si[kPickN];
+    constexpr int KP = kPickN / 256;             // entries per thread: i = 256 k + thread
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t sel[2];                  // digit, entries above it in the bucket
+    __shared__ int ceq[KP][4], ctk[KP][4];       // per (k, wave): equal to T, taken
     const int b = blockIdx.x;
-    for (int i = threadIdx.x; i < kPickN; i += 256) {
-        sq[i] = i < n_list ? first_q[static_cast<size_t>(b) * n_list + i] : -INFINITY;
-        si[i] = i;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t key[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        const int i = 256 * k + tid;
+        key[k] = i < n_list ? order_key(first_q[static_cast<size_t>(b) * n_list + i]) : 0u;
+    }
+    // T: the n_first-th largest key, one 8-bit digit per pass
+    uint32_t prefix = 0, mask = 0;
+    int need = n_first;                          // entries still to take inside the bucket
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        hist[tid] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KP; ++k)
+            if ((key[k] & mask) == prefix) atomicAdd(&hist[(key[k] >> shift) & 255u], 1u);
+        __syncthreads();
+        if (wave == 0) {
+            // lane l holds digits 4 l .. 4 l + 3; above = entries with a
+            // larger digit in higher lanes
+            uint32_t h[4], sum = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                h[e] = hist[4 * lane + e];
+                sum += h[e];
+            }
+            uint32_t x = sum;                    // inclusive suffix sum over lanes
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t o = __shfl_down(x, d, 64);
+                if (lane + d < 64) x += o;
+            }
+            uint32_t above = x - sum;
+#pragma unroll
+            for (int e = 3; e >= 0; --e) {
+                if (above < static_cast<uint32_t>(need) && static_cast<uint32_t>(need) <= above + h[e]) {
+                    sel[0] = 4 * lane + e;
+                    sel[1] = above;
+                }
+                above += h[e];
+            }
+        }
+        __syncthreads();
+        need -= static_cast<int>(sel[1]);
+        prefix |= sel[0] << shift;
+        mask |= 255u << shift;
+        __syncthreads();                         // sel and hist are rewritten next
+    }
+    // every key above T, and the first `need` keys equal to T in list order
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    bool eq[KP];
+    unsigned long long meq[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        eq[k] = key[k] == prefix;
+        meq[k] = tmlib::ballot(eq[k]);
+        if (lane == 0) ceq[k][wave] = __popcll(meq[k]);
     }
     __syncthreads();
-    auto better = [](float qa, int ia, float qb, int ib) { return qa > qb || (qa == qb && ia < ib); };
-    for (int k = 2; k <= kPickN; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < kPickN; i += 256) {
-                const int p = i ^ j;
-                if (p > i) {
-                    const float qa = sq[i], qb = sq[p];
-                    const int ia = si[i], ib = si[p];
-                    // blocks with bit k clear end best-first, the others best-last
-                    const bool swap = (i & k) == 0 ? better(qb, ib, qa, ia) : better(qa, ia, qb, ib);
-                    if (swap) {
-                        sq[i] = qb; sq[p] = qa;
-                        si[i] = ib; si[p] = ia;
-                    }
-                }
-            }
-            __syncthreads();
+    bool take[KP];
+    unsigned long long mtk[KP];
+    int base = 0;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        int before = base;
+        for (int w = 0; w < wave; ++w) before += ceq[k][w];
+        for (int w = 0; w < 4; ++w) base += ceq[k][w];
+        before += __popcll(meq[k] & lt);
+        take[k] = key[k] > prefix || (eq[k] && before < need);
+        mtk[k] = tmlib::ballot(take[k]);
+        if (lane == 0) ctk[k][wave] = __popcll(mtk[k]);
+    }
+    __syncthreads();
+    int tb = 0;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        int pos = tb;
+        for (int w = 0; w < wave; ++w) pos += ctk[k][w];
+        for (int w = 0; w < 4; ++w) tb += ctk[k][w];
+        pos += __popcll(mtk[k] & lt);
+        if (take[k] && pos < n_first) {
+            const int i = 256 * k + tid;
+            const int c = i < n_list ? first_col[static_cast<size_t>(b) * n_list + i] : -1;
+            out[static_cast<size_t>(b) * n_first + pos] = (c >= 0 && c < n_cols) ? (map ? map[c] : c) : -1;
         }
-    for (int r = threadIdx.x; r < n_first; r += 256) {
-        const int e = si[r];
-        const int c = e < n_list ? first_col[static_cast<size_t>(b) * n_list + e] : -1;
-        out[static_cast<size_t>(b) * n_first + r] = (c >= 0 && c < n_cols) ? (map ? map[c] : c) : -1;
     }
 }
 
