@@ -27,11 +27,15 @@ constexpr int kSelThreads = 256;
 // scorer (its ranking rule decides). More than cap
 // such templates in all: the pattern is marked for a full exact scan
 // instead. Waves own contiguous quarters of the row and compact with
-// ballots (two passes: count, then write; the second reads again only the
-// blocks of 64 loads that held a candidate, among a wave's first 64).
+// ballots: a counting pass over the row that touches no other memory (so
+// the next step's loads stay in flight), then, reading again only the
+// blocks of 64 loads that held a column at or above the threshold, a pass
+// counting the new candidates and one writing them. With a map, columns
+// from T' on are taken to hold no template (as the window bounds' slot map
+// has it).
 template <int V>
 __global__ void __launch_bounds__(kSelThreads)
-certify_select(const float* __restrict__ Qt, int Tp, const int32_t* __restrict__ map,
+certify_select(const float* __restrict__ Qt, int Tp, int n_valid, const int32_t* __restrict__ map,
                const float* __restrict__ q_exact, int N, double margin, int cap,
                int32_t* __restrict__ cand, int32_t* __restrict__ cnt, int32_t* __restrict__ full,
                int32_t* __restrict__ n_rescored, int n_templates,
@@ -40,9 +44,8 @@ certify_select(const float* __restrict__ Qt, int Tp, const int32_t* __restrict__
     __shared__ int wcount[W], wnew[W];
     __shared__ int sfirst[tmlib::kMaxN];
     const int b = blockIdx.x;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = tmlib::uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (threadIdx.x < n_first) sfirst[threadIdx.x] = first[static_cast<size_t>(b) * n_first + threadIdx.x];
-    __syncthreads();
     // threshold rounded toward -inf: a template whose approximate score could
     // reach the N-th best exact score within the bound is never dropped by
     // the rounding of the subtraction
@@ -55,109 +58,119 @@ certify_select(const float* __restrict__ Qt, int Tp, const int32_t* __restrict__
     const int ng = Tp / V;
     const int lo = V * static_cast<int>((static_cast<long long>(ng) * wave) / W);
     const int hi = V * static_cast<int>((static_cast<long long>(ng) * (wave + 1)) / W);
+    const int lim = min(hi, n_valid);           // columns past n_valid hold no template
     // 4 blocks of 64 V columns per step, their loads issued together;
     // column of (block k, component e) for this lane: base + V (64 k + lane) + e
     constexpr int kBlocks = 4;
-    auto take_at = [&](int t, float v) { return t < hi && v >= thr && (!map || map[t] >= 0); };
+    constexpr int kStep = V * 64 * kBlocks;
     auto is_first = [&](int t) {
         const int tt = map ? map[t] : t;
         bool f = false;
         for (int i = 0; i < n_first; ++i) f |= (sfirst[i] == tt);
         return f;
     };
-    auto load = [&](int base0, float (&v)[kBlocks][V]) {
-#pragma unroll
-        for (int k = 0; k < kBlocks; ++k) {
-            const int t = base0 + V * (64 * k + lane);
-            if constexpr (V == 4) {
-                const float4 x = t < hi ? *reinterpret_cast<const float4*>(row + t)
-                                        : make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
-                v[k][0] = x.x; v[k][1] = x.y; v[k][2] = x.z; v[k][3] = x.w;
-            } else {
-                v[k][0] = t < hi ? row[t] : -INFINITY;
-            }
+    auto load_block = [&](int t, float (&v)[V]) {
+        if constexpr (V == 4) {
+            const float4 x = t < hi ? *reinterpret_cast<const float4*>(row + t)
+                                    : make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
+            v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+        } else {
+            v[0] = t < hi ? row[t] : -INFINITY;
         }
     };
-    int c = 0, cn = 0;
-    unsigned long long hits = 0;                 // blocks (< 64) with a candidate
-    // the next step's loads are issued before this step's values are tested
-    constexpr int kStep = V * 64 * kBlocks;
-    float nv[kBlocks][V];
-    load(lo, nv);
-    for (int base0 = lo, st = 0; base0 < hi; base0 += kStep, ++st) {
-        float v[kBlocks][V];
-#pragma unroll
-        for (int k = 0; k < kBlocks; ++k)
-#pragma unroll
-            for (int e = 0; e < V; ++e) v[k][e] = nv[k][e];
-        load(base0 + kStep, nv);
-#pragma unroll
-        for (int k = 0; k < kBlocks; ++k) {
-            int cs = 0;
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const int t = base0 + V * (64 * k + lane) + e;
-                const bool tk = take_at(t, v[k][e]);
-                const unsigned long long mk = tmlib::ballot(tk);
-                if (mk) {                                // uniform; rare
-                    cs += __popcll(mk);
-                    cn += __popcll(tmlib::ballot(tk && !is_first(t)));
-                }
-            }
-            c += cs;
-            const int blk = st * kBlocks + k;
-            if (cs && blk < 64) hits |= 1ull << blk;
-        }
-    }
-    if (lane == 0) {
-        wcount[wave] = c;
-        wnew[wave] = cn;
-    }
-    __syncthreads();
-    int before = 0, total = 0, total_new = 0;
-    for (int w = 0; w < W; ++w) {
-        before += (w < wave) ? wnew[w] : 0;
-        total += wcount[w];
-        total_new += wnew[w];
-    }
-    const bool over = total > cap;
-    if (!over) {
-        int32_t* out = cand + static_cast<size_t>(b) * cap;
-        int pos = before;
-        for (int base0 = lo, st = 0; base0 < hi; base0 += V * 64 * kBlocks, ++st) {
-            // the step's blocks that held a candidate (all from block 64 on)
-            const unsigned sel = st * kBlocks + kBlocks <= 64
-                                     ? static_cast<unsigned>(hits >> (st * kBlocks)) & ((1u << kBlocks) - 1)
-                                     : (1u << kBlocks) - 1;
-            if (!sel) continue;                                  // uniform
-            float v[kBlocks][V];
+    // 1. count the columns at or above the threshold (no memory access but
+    // the row) and mark the blocks (among a wave's first 64) that hold one.
+    // Two value sets alternate, so a step's loads are in flight while the
+    // one before is tested; loads past the wave's columns repeat its last
+    // group (the test masks them)
+    int c = 0;
+    unsigned long long hits = 0;
+    if (hi > lo) {
+        auto ld = [&](int base0, float (&v)[kBlocks][V]) {
 #pragma unroll
             for (int k = 0; k < kBlocks; ++k) {
-                const int t = base0 + V * (64 * k + lane);
-                if (!((sel >> k) & 1) || t >= hi) {
-#pragma unroll
-                    for (int e = 0; e < V; ++e) v[k][e] = -INFINITY;
-                } else if constexpr (V == 4) {
+                const int t = min(base0 + V * (64 * k + lane), hi - V);
+                if constexpr (V == 4) {
                     const float4 x = *reinterpret_cast<const float4*>(row + t);
                     v[k][0] = x.x; v[k][1] = x.y; v[k][2] = x.z; v[k][3] = x.w;
                 } else {
                     v[k][0] = row[t];
                 }
             }
+        };
+        auto test = [&](const float (&v)[kBlocks][V], int base0, int st) {
 #pragma unroll
-            for (int k = 0; k < kBlocks; ++k)
+            for (int k = 0; k < kBlocks; ++k) {
+                int cs = 0;
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
                     const int t = base0 + V * (64 * k + lane) + e;
-                    const bool tk = take_at(t, v[k][e]);
-                    if (!tmlib::ballot(tk)) continue;    // uniform; rare
-                    const bool take = tk && !is_first(t);
-                    const unsigned long long m = tmlib::ballot(take);
-                    if (take) out[pos + __popcll(m & ((1ull << lane) - 1))] = map ? map[t] : t;
-                    pos += __popcll(m);
+                    cs += __popcll(tmlib::ballot(t < lim && v[k][e] >= thr));
                 }
+                c += cs;
+                const int blk = st * kBlocks + k;
+                if (cs && blk < 64) hits |= 1ull << blk;
+            }
+        };
+        float va[kBlocks][V], vb[kBlocks][V];
+        ld(lo, va);
+        for (int base0 = lo, st = 0; base0 < hi; base0 += 2 * kStep, st += 2) {
+            ld(base0 + kStep, vb);
+            test(va, base0, st);
+            if (base0 + kStep >= hi) break;                  // uniform
+            ld(base0 + 2 * kStep, va);
+            test(vb, base0 + kStep, st + 1);
         }
     }
+    // the blocks of a step to read again: those that held a column at or
+    // above the threshold (all from block 64 on)
+    auto step_sel = [&](int st) -> unsigned {
+        return st * kBlocks + kBlocks <= 64
+                   ? static_cast<unsigned>(hits >> (st * kBlocks)) & ((1u << kBlocks) - 1)
+                   : (1u << kBlocks) - 1;
+    };
+    // 2. in those blocks: the candidates (a template, not scored first)
+    auto visit = [&](auto&& fn) {
+        for (int base0 = lo, st = 0; base0 < hi; base0 += kStep, ++st) {
+            const unsigned sel = step_sel(st);
+            if (!sel) continue;                                  // uniform
+#pragma unroll
+            for (int k = 0; k < kBlocks; ++k) {
+                if (!((sel >> k) & 1)) continue;                 // uniform
+                float v[V];
+                load_block(base0 + V * (64 * k + lane), v);
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const int t = base0 + V * (64 * k + lane) + e;
+                    const bool tk = t < lim && v[e] >= thr;
+                    if (!tmlib::ballot(tk)) continue;           // uniform
+                    fn(t, tk && (!map || map[t] >= 0) && !is_first(t));
+                }
+            }
+        }
+    };
+    // 3. one more pass over those blocks writes the candidates (at most cap)
+    // at places taken from a workgroup counter: their order is not
+    // deterministic, which no result depends on (every merge ranks by the
+    // scorer's rule)
+    if (threadIdx.x == 0) wcount[0] = 0;
+    __syncthreads();                             // sfirst and the counter are set
+    int32_t* out = cand + static_cast<size_t>(b) * cap;
+    visit([&](int t, bool take) {
+        const unsigned long long m = tmlib::ballot(take);
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&wcount[0], __popcll(m));
+        base = __shfl(base, 0, 64);
+        const int pos = base + __popcll(m & ((1ull << lane) - 1));
+        if (take && pos < cap) out[pos] = map ? map[t] : t;
+    });
+    __syncthreads();
+    const int total_new = wcount[0];
+    if (lane == 0) wnew[wave] = c;
+    __syncthreads();
+    int total = 0;
+    for (int w = 0; w < W; ++w) total += wnew[w];
+    const bool over = total > cap;
     if (threadIdx.x == 0) {
         cnt[b] = over ? 0 : total_new;
         full[b] = over ? 1 : 0;
@@ -568,12 +581,16 @@ int tmlib::certified_rescore(const tm_library* lib, const float* polar, const do
     // 2. every template whose estimate reaches q_N - margin
     if (!r) {
         // 16-byte loads when every row starts 16-byte aligned
+        // with a map, the columns past T' hold no template (map -1)
+        const int n_valid = map ? std::min(n_cols, Tp) : n_cols;
         if (n_cols % 4 == 0 && reinterpret_cast<uintptr_t>(Qt) % 16 == 0)
-            hipLaunchKernelGGL(certify_select<4>, dim3(B), dim3(kSelThreads), 0, s, Qt, n_cols, map,
-                               q1, N, margin, cap, cand, cnt, full, n_rescored, Tp, t0, n_first);
+            hipLaunchKernelGGL(certify_select<4>, dim3(B), dim3(kSelThreads), 0, s, Qt, n_cols,
+                               n_valid, map, q1, N, margin, cap, cand, cnt, full, n_rescored, Tp,
+                               t0, n_first);
         else
-            hipLaunchKernelGGL(certify_select<1>, dim3(B), dim3(kSelThreads), 0, s, Qt, n_cols, map,
-                               q1, N, margin, cap, cand, cnt, full, n_rescored, Tp, t0, n_first);
+            hipLaunchKernelGGL(certify_select<1>, dim3(B), dim3(kSelThreads), 0, s, Qt, n_cols,
+                               n_valid, map, q1, N, margin, cap, cand, cnt, full, n_rescored, Tp,
+                               t0, n_first);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) r = tmlib::hip_fail(e, "certify_select launch");
     }

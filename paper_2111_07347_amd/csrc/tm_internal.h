@@ -115,8 +115,8 @@ int fill_i32(int32_t* dst, int64_t n, int32_t value, hipStream_t s);
 // n_rescored (optional, [B]) receives the number of templates scored
 // exactly in the second pass. Enqueued on s.
 // With map (optional) the estimates come in another column order: Qt is
-// [B, n_cols] and column c holds template map[c] (-1: no template, estimate
-// -inf); without it n_cols = T'.
+// [B, n_cols] and column c holds template map[c] (c < T'; the columns from
+// T' on hold none, map -1); without it n_cols = T'.
 // With first_q / first_col (optional, device [B, n_list]) the first pass
 // scores the columns first_col of the n_first largest first_q values
 // instead of Qt's n_first largest (any choice keeps the result exact;
