@@ -541,8 +541,8 @@ int tmlib::certified_rescore(const tm_library* lib, const float* polar, const do
     const size_t bn = static_cast<size_t>(B) * N;
     const size_t bf = static_cast<size_t>(B) * n_first;
     if (!r) r = alloc_async(&t0, bf, s);
-    if (!r) r = alloc_async(&s0, bf, s);
-    if (!r) r = alloc_async(&q0, bf, s);
+    if (!r && !first_q) r = alloc_async(&s0, bf, s);   // the top-n's angles and scores
+    if (!r && !first_q) r = alloc_async(&q0, bf, s);
     if (!r) r = alloc_async(&t1, bn, s);
     if (!r) r = alloc_async(&s1, bn, s);
     if (!r) r = alloc_async(&q1, bn, s);
