@@ -11,8 +11,8 @@
 //   C(s) = sum_i w_i P[j_i, k_i + s] <= sum_i w_i M[j_i, k_i + S win],
 //   M[j, x] = max(0, max_{0 <= d < wlen} P[j, (x + d) mod n_theta]),
 //
-// (columns mod n_theta; wlen = win + 4 win - n_theta, i.e. win when 4
-// divides n_theta, see below), so one product per spot and coarse shift
+// (columns mod n_theta; wlen = min(win + 4 win - n_theta, n_theta), i.e.
+// win when 4 divides n_theta, see below), so one product per spot and coarse shift
 // bounds a whole window of shifts, and the maximum over the coarse shifts
 // bounds the template's best score.
 // The bounds feed the certified rescoring (tm_certify.hip) with margin 0:
@@ -47,8 +47,9 @@
 //   M[j, r + 3 win])                         (float16 each, columns mod n),
 //
 // one row of 2 win dwords (plus one unused, for an odd pitch) per touched
-// row, read with one 2-dword LDS read at r and r + win. acc[i] collects M[r + i win], which is shift S = i - q
-// (mod 4): the pixels of one quarter share the rotation. A lane takes its
+// row, read with one 2-dword LDS read at r and r + win. acc[i] collects
+// M[r + i win], which is shift S = i - q (mod 4): the pixels of one quarter
+// share the rotation. A lane takes its
 // template's quarters in cyclic order (its largest first); between two
 // quarters every lane moves the value of shift S from acc[S + q] to
 // acc[S + q + 1], the same operation in every lane. When 4 does not divide
@@ -62,9 +63,11 @@
 //     workgroups in a CU's LDS for most libraries;
 //   * a lane scores one template over the 4 coarse shifts S, a wave 64
 //     templates at a time: templates are sorted by the pixel counts of
-//     their quarter-turns (in the lane's order) and cut into chunks of 64;
-//     in a chunk all lanes run the same number of steps in each quarter slot
-//     (zero-weight padding to whole units of 4 steps);
+//     their quarter slots (in the lane's order; in whole units first) and
+//     cut into chunks of 64; in a chunk all lanes run the same number of
+//     steps in each slot (zero-weight padding to whole units of 4 steps);
+//     image rows are placed so that the LDS banks the slots read are loaded
+//     evenly;
 //   * a lane's records come 4 at a time in one 16-byte buffer load (a wave
 //     loads 1 KiB of consecutive bytes per unit, 3 units ahead of their
 //     use); the units that end a chunk's quarter slots are known per chunk
@@ -72,9 +75,9 @@
 //   * each template's margin term (below) is one more record: its weight
 //     the margin factor, its window maxima read from an extra image row
 //     that holds the largest |P| (scaled, rounded up) everywhere;
-//   * per record: one address multiply-add, 2 LDS reads of a pair of
-//     float16 window maxima and 4 mixed float16 x float16 + float32
-//     multiply-adds; the library orders each step's records over the
+//   * per record: one address multiply-add, one 2-dword LDS read (two
+//     pairs of float16 window maxima) and 4 mixed float16 x float16 +
+//     float32 multiply-adds; the library orders each step's records over the
 //     lanes so that the reads of a half-wave fall on distinct LDS banks (or
 //     the same dword) where possible;
 //   * a chunk's bounds leave as one coalesced 256-byte store, in chunk-slot
